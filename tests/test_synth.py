@@ -1,0 +1,69 @@
+"""Checks of the seeded synthetic workload generator (CPU only)."""
+import numpy as np
+
+from paper_2007_08576_amd import synth
+
+
+def test_config1_template_is_the_height_field():
+    sc = synth.make_config1(1)
+    K = sc.intr
+    P = sc.pts.astype(np.float64)
+    u = K.fx * P[:, 0] / P[:, 2] + K.cx
+    v = K.fy * P[:, 1] / P[:, 2] + K.cy
+    assert np.allclose(u, np.round(u), atol=1e-3) and np.allclose(v, np.round(v), atol=1e-3)
+    z = 80 + 6 * np.sin(np.round(u) / 15) * np.cos(np.round(v) / 20)
+    assert np.allclose(P[:, 2], z, atol=1e-4)
+    assert len(sc.pts) == 3000 and len(sc.feat_xyz) == 400
+    pix = np.round(v) * K.width + np.round(u)
+    assert np.all(np.diff(pix) > 0)  # raster order, no repeats
+
+
+def test_config1_features_outliers_and_bit_flips():
+    sc = synth.make_config1(1)
+    fr = sc.frame(1)
+    assert (fr.inlier_of < 0).sum() == 100 and (fr.inlier_of >= 0).sum() == 300
+    inl = fr.inlier_of >= 0
+    d = np.unpackbits(fr.feat_desc[inl] ^ sc.feat_desc[fr.inlier_of[inl]], axis=1).sum(1)
+    assert np.all(d == 8)
+    # exact mode: inlier positions are the warped template features
+    ok = np.isfinite(fr.feat_xyz[:, 0])
+    assert ok.all()
+    assert fr.depth.shape == (96, 128) and (fr.depth > 0).mean() > 0.9
+
+
+def test_determinism_and_seed_sensitivity():
+    a = synth.make_config1(1).frame(1)
+    b = synth.make_config1(1).frame(1)
+    c = synth.make_config1(2).frame(1)
+    assert np.array_equal(a.depth, b.depth) and np.array_equal(a.feat_desc, b.feat_desc)
+    assert not np.array_equal(a.feat_desc, c.feat_desc)
+
+
+def test_render_depth_of_a_plane():
+    K = synth.Intrinsics(40, 30, 50.0, 50.0, 20.0, 15.0)
+    depth = np.full((30, 40), 100.0, np.float32)
+    P = synth.backproject_grid(depth, K)
+    P = P + np.array([3.0, -2.0, 5.0])  # shifted plane z = 105
+    out = synth.render_depth(P, K)
+    cov = out > 0
+    assert cov.mean() > 0.7
+    assert np.allclose(out[cov], 105.0, atol=1e-4)
+
+
+def test_sequence_step_is_scaled_to_the_stated_maximum():
+    sc = synth.make_small_sequence(seed=3, n_frames=6, max_step_mm=3.0)
+    prev = sc.pts.astype(np.float64)
+    steps = []
+    for t in range(1, 7):
+        g = sc.frame(t).gt_vertices
+        steps.append(np.linalg.norm(g - prev, axis=1).max())
+        prev = g
+    assert max(steps) <= 3.0 + 1e-9 and max(steps) > 2.999
+
+
+def test_rng_uniform_range_and_choice():
+    r = synth.Rng(5, "x")
+    u = r.uniform(10000)
+    assert u.min() >= 0 and u.max() < 1 and abs(u.mean() - 0.5) < 0.02
+    c = synth.Rng(5, "y").choice(100, 30)
+    assert len(set(c.tolist())) == 30
