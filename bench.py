@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-frame deformation solve on one MI355X.
+
+Workload: the paper-scale single stream (config 2): 640 x 480 synthetic depth of 20 Gaussian dents
+over a 100 mm plane, 30,000 template points, 400 control points (79,800 dense ARAP pairs, a
+2,400-unknown normal system), 2,000 ORB features with 30 % outliers, 10 LM iterations per frame,
+plain FP32 path. A step is one frame through the whole solve (normal map, Hamming matching, 1-point
+RANSAC pre-selection, 10 x [rows, ARAP and data assembly, Cholesky solve, update, FP64 cost,
+accept]). Frames are generated once, uploaded to HBM, and replayed in ping-pong order (a continuous
+deformation) through tt_track_frame_device; the timed region contains only queued device work.
+
+Prints one JSON line (see the "roofline" and "cpu_baseline" fields for the kernel-level bound and
+the FP64 oracle timed on the host).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "deform-solve frames/s + p50/p99 latency, batched vs plain, RMS<=0.01 mm"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(n_frames):
+    from paper_2007_08576_amd import synth
+    sc = synth.make_config2(seed=2, n_frames=300)
+    frames = [sc.frame(t) for t in range(1, n_frames + 1)]
+    return sc, frames
+
+
+def cpu_baseline(sc, frame, lm_sample):
+    """The FP64 oracle on one frame of the same workload, with lm_sample LM iterations (and
+    separately 1), timed on one host core; frames/s extrapolated to the full 10 iterations."""
+    from oracle import oracle as O
+    K = O.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy)
+    times = {}
+    verts = None
+    for iters in (1, lm_sample):
+        s = O.Stream(O.default_params(num_control_points=sc.num_control_points, seed=2, lm_iters=iters), K)
+        s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        t0 = time.perf_counter()
+        v, _, _ = s.track_frame(frame.depth, frame.feat_xyz, frame.feat_desc)
+        times[iters] = time.perf_counter() - t0
+        if iters == lm_sample:
+            verts = v
+    t_iter = (times[lm_sample] - times[1]) / (lm_sample - 1)
+    t_front = max(times[1] - t_iter, 0.0)
+    per_frame = t_front + 10 * t_iter
+    total = times[1] + times[lm_sample]
+    return dict(value=1.0 / per_frame, unit="frames/s", cores=1, kind="oracle",
+                sample=f"config 2 frame 1 tracked twice by the FP64 oracle (1 and {lm_sample} LM iterations, "
+                       f"{total:.1f} s on one core); per-frame time = front + 10 x per-iteration "
+                       f"({t_front * 1e3:.0f} ms + 10 x {t_iter * 1e3:.0f} ms)"), verts
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=8, help="distinct synthetic frames (replayed ping-pong)")
+    ap.add_argument("--cpu-lm-sample", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the solve of one stream runs on one device, and streams are "
+              "independent (no cross-GPU work); run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2007_08576_amd import tt
+
+    t0 = time.time()
+    sc, frames = make_workload(args.frames)
+    log(f"workload generated in {time.time() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    dframes = [(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.feat_xyz).to(dev),
+                torch.from_numpy(f.feat_desc).to(dev)) for f in frames]
+    order = list(range(len(frames))) + list(range(len(frames) - 2, 0, -1))
+    stream = torch.cuda.Stream()
+    N, M = sc.num_control_points, sc.pts.shape[0]
+    params = tt.default_params(num_control_points=N, seed=2)
+    intr = tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy)
+    s = tt.Stream(params, intr, hip_stream=stream.cuda_stream)
+    s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    ov = torch.empty((M, 3), dtype=torch.float32, device=dev)
+    oq = torch.empty((N, 8), dtype=torch.float32, device=dev)
+
+    def step(k):
+        d = dframes[order[k % len(order)]]
+        s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], ov, oq)
+
+    for k in range(args.warmup):
+        step(k)
+    s.sync()
+    torch.cuda.synchronize()
+    s.get_timing()  # reset
+    s.set_timing(True)
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev0[k].record(stream)
+        step(args.warmup + k)
+        ev1[k].record(stream)
+    s.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.set_timing(False)
+    wall = t1 - t0
+    fps = args.steps / wall
+    lat = np.array([ev0[k].elapsed_time(ev1[k]) for k in range(args.steps)])
+    stage_ms, stage_n = s.get_timing()
+    stages = {name: dict(ms_per_call=float(stage_ms[i] / max(stage_n[i], 1)), calls=int(stage_n[i]))
+              for i, name in enumerate(tt.STAGES)}
+    log(f"{fps:.1f} frames/s, p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
+    for name, v in stages.items():
+        log(f"  {name:7s} {v['ms_per_call'] * 1e3:9.1f} us x {v['calls']}")
+
+    # roofline of the dominant kernel (measured live above on the library's HIP stream)
+    n = 6 * N
+    pairs = N * (N - 1) // 2
+    solve_ms = stages["solve"]["ms_per_call"]
+    arap_ms = stages["arap"]["ms_per_call"]
+    if solve_ms >= arap_ms:
+        flops = n ** 3 / 3.0 + 2.0 * n * n  # factorisation + both substitutions per solve
+        achieved = flops / (solve_ms * 1e-3) / 1e12
+        roof = dict(kernel="Cholesky solve (k_chol_panel + k_chol_update + k_chol_backsolve + k_damp, one LM step)",
+                    bound="mfma", achieved=achieved, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=achieved / FP32_PEAK_TFLOPS, traffic=None,
+                    algorithmic=f"n^3/3 + 2 n^2 = {flops:.3e} FLOP per solve, n = {n}",
+                    avg_duration_us=solve_ms * 1e3)
+    else:
+        nbytes = (n * (n + 1) // 2) * 4 + N * (16 + 32 + 16)
+        achieved = nbytes / (arap_ms * 1e-3) / 1e9
+        roof = dict(kernel="k_arap_assemble", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=None,
+                    algorithmic=f"lower-triangular FP32 normal matrix {n}x{n} written once + node state",
+                    avg_duration_us=arap_ms * 1e3)
+
+    out = {
+        "metric": METRIC,
+        "value": fps,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 / fps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "config2: plain FP32 single stream; 640x480 depth, M=30000 template points, "
+                               "N=400 control points (79800 ARAP pairs, 2400x2400 normal matrix), "
+                               "K=2000 features (30% outliers), 10 LM iterations per frame",
+                   "mode": "plain", "frames_replayed": len(frames)},
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "gn_iters_per_s": fps * params.lm_iters,
+        "arap_pairs_per_s": fps * params.lm_iters * pairs,
+        "stage_us": {k: v["ms_per_call"] * 1e3 for k, v in stages.items()},
+        "roofline": roof,
+    }
+
+    if not args.no_cpu_baseline:
+        # same frame, same reduced iteration count on the GPU: the full-size accuracy check
+        s2 = tt.Stream(tt.default_params(num_control_points=N, seed=2, lm_iters=args.cpu_lm_sample), intr)
+        s2.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        vg, _, _ = s2.track_frame(frames[0].depth, frames[0].feat_xyz, frames[0].feat_desc)
+        t0 = time.time()
+        cb, vo = cpu_baseline(sc, frames[0], args.cpu_lm_sample)
+        log(f"cpu baseline {cb['value']:.4f} frames/s ({time.time() - t0:.1f} s)")
+        out["cpu_baseline"] = cb
+        out["rms_vs_oracle_mm"] = float(np.sqrt(((vg - vo) ** 2).sum(1).mean()))
+        out["rms_vs_oracle_note"] = f"frame 1 from identity, {args.cpu_lm_sample} LM iterations on both sides"
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

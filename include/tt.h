@@ -1,0 +1,181 @@
+/*
+ * tt.h -- C ABI of the MI355X (gfx950) per-frame deformation solve of
+ * H. Zhou and J. Jagadeesan, "Real-time Surface Deformation Recovery from Stereo Videos"
+ * (arXiv:2007.08576).
+ *
+ * The problem (Sec. 2): a template surface, made from the first stereo frame, carries N sparse
+ * control points, each with a dual-quaternion warp W_i; the template follows the blend of its
+ * neighbouring control points. For every new frame (a depth map from stereo matching plus ORB
+ * features with 3D positions) the library estimates all W_i by Levenberg-Marquardt on
+ *   f_ICP + w_ORB f_ORB + w_ARAP f_ARAP                                    (Eq. 1)
+ * with projective point-to-plane ICP under Tukey's penalty (Sec. 2), ORB matches weighted by
+ * the 1-point RANSAC + reweighting pre-selection (Sec. 2.1, Eqs. 2-4) and the dense-connection
+ * as-rigid-as-possible cost (Sec. 2.2, Eqs. 5-6).
+ *
+ * Conventions. Millimetres and radians. Depth maps are row-major float32 (index v*width + u);
+ * a value that is not finite or not > 0 is invalid. Pixel centres sit at integer (u, v), and a
+ * camera-frame point projects to u = fx x / z + cx, v = fy y / z + cy. 3D points are packed
+ * x, y, z float32 triples. ORB descriptors are 32 bytes (256 bits) each. Dual quaternions are
+ * [qr.w qr.x qr.y qr.z qd.w qd.x qd.y qd.z], mapping x -> R(qr) x + 2 vec(qd conj(qr)), with
+ * qr.w >= 0.
+ *
+ * Ownership. Host-pointer arguments are caller-owned and used only during the call; the
+ * library keeps no caller pointer. A stream and everything resident on the device for it
+ * (template, blend tables, descriptors, warps, scratch) are owned by the library until
+ * tt_destroy. Device-pointer arguments (tt_track_frame_device) must stay valid until the work
+ * queued on the stream's HIP stream has completed.
+ *
+ * Errors. Every call returns 0 on success or a negative TT_E* code; tt_strerror names it.
+ * Nothing else crosses the ABI (no exceptions). Calls on one stream must not overlap
+ * (TT_EBUSY); different streams may be driven from different host threads.
+ */
+#ifndef TT_H
+#define TT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TT_OK 0
+#define TT_EINVAL (-1)  /* NULL pointer, bad size, non-finite template, N > M, bad params */
+#define TT_ENOMEM (-2)  /* device allocation failed or the stream's HBM budget is exceeded  */
+#define TT_ESTATE (-3)  /* frame before template                                           */
+#define TT_EDEVICE (-4) /* a HIP call failed, or a device-side bound was hit               */
+#define TT_EBUSY (-5)   /* another call is running on the same stream                       */
+
+#define TT_FP32 0 /* FP32 assembly and FP32 Cholesky (the only precision of this version) */
+
+typedef struct tt_stream tt_stream;
+
+typedef struct {
+  int width, height;     /* depth map size, >= 3 each */
+  double fx, fy, cx, cy; /* pinhole intrinsics in pixels */
+} tt_intrinsics;
+
+typedef struct {
+  int num_control_points;  /* N >= 1, chosen by farthest-point sampling over the template   */
+  int knn;                 /* control points blended per template point; must be 4           */
+  double w_orb;            /* weight of f_ORB in Eq. (1); paper: 10                          */
+  double w_angle;          /* weight of f_angle in Eq. (5); paper: 20                        */
+  double w_rotation;       /* weight of f_rotation in Eq. (5); paper: 100                    */
+  double lambda_arap;      /* scale of the dynamic ARAP weight (Sec. 2): 1                   */
+  double tukey_c;          /* Tukey constant of f_ICP, mm: 5                                 */
+  double H;                /* reweighting threshold of Eq. (4), mm: 3                        */
+  int ransac_refs;         /* reference matches per frame (Sec. 2.1): 30                     */
+  int ransac_iters;        /* R/w alternations per reference (Sec. 2.1): 10                  */
+  int lm_iters;            /* Levenberg-Marquardt iterations per frame: 10                   */
+  int max_hamming;         /* matches farther than this are unusable; 256 keeps all          */
+  double lm_lambda0;       /* initial Marquardt damping of each frame: 1e-4                  */
+  int precision;           /* TT_FP32                                                        */
+  uint64_t seed;           /* seed of the reference-match sampler                            */
+  uint64_t hbm_budget_bytes; /* 0 = unlimited; otherwise a cap on the stream's device bytes  */
+} tt_params;
+
+/* Optional per-frame outputs of tt_track_frame; each pointer may be NULL. Sizes: K1 template
+ * features, M template points, R = ransac_refs, T = lm_iters, n = 6 N. */
+typedef struct {
+  int32_t* match_idx;   /* [K1] nearest frame feature by Hamming distance (ties: lower index), -1 if none */
+  int32_t* match_dist;  /* [K1] its distance (256 if none) */
+  double* wstar;        /* [K1] pre-selection weight: max of w_k over kept hypotheses, 0 if unusable */
+  uint8_t* preselected; /* [K1] 1 if w* >= 1/2 */
+  int32_t* hyp_k0;      /* [R] reference match of each hypothesis, -1 if fewer usable matches */
+  double* hyp_W;        /* [R] sum of w_k after the last reweighting */
+  int32_t* hyp_nin;     /* [R] matches with d_k <= H */
+  uint8_t* hyp_kept;    /* [R] 1 kept, 0 dropped, 2 degenerate rotation fit */
+  int32_t* corr0;       /* [M] iteration-0 pixel of each template point, -1 if none */
+  double* r0;           /* [M] iteration-0 point-to-plane residual (0 without a pixel) */
+  double* omega0;       /* [M] iteration-0 Tukey weight */
+  double* orbw0;        /* [K1] iteration-0 feature weight */
+  double* A0;           /* [n*n] iteration-0 J^T J (undamped), row-major, symmetric */
+  double* g0;           /* [n] iteration-0 J^T r */
+  double* w_arap;       /* [1] dynamic ARAP weight of the frame */
+  double* cost_old;     /* [T] cost at the iterate (correspondences of that iteration) */
+  double* cost_new;     /* [T] cost at the candidate (NaN if the factorisation failed) */
+  double* lambda;       /* [T] damping used */
+  uint8_t* accepted;    /* [T] 1 if the candidate was accepted */
+} tt_frame_debug;
+
+/* Fills every field with the paper's constants and this library's defaults. */
+void tt_default_params(tt_params* p);
+
+/* Creates a stream. hip_stream is a hipStream_t to queue work on (NULL: the library creates
+ * its own at default priority). Allocates the frame-size device buffers. */
+int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_stream, tt_stream** out);
+
+/* Template (Sec. 2, generated from the first frame): pts_xyz [M][3], feat_xyz [K1][3] and
+ * feat_desc [K1][32], host memory. Chooses the N control points by farthest-point sampling
+ * (start at point 0, ties to the lower index), the 4 nearest control points and Gaussian blend
+ * weights of every template point and feature, and the ARAP pair weights; uploads all of it
+ * and resets the warps to identity and the frame counter to 0. Synchronous.
+ * TT_EINVAL: NULL, M < 1, K1 < 0, N > M, non-finite coordinates, fewer distinct points than N. */
+int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat_xyz,
+                    const uint8_t* feat_desc, int K1);
+
+/* One frame from host memory: depth [height][width], feat_xyz [K2][3] (NaN = no depth),
+ * feat_desc [K2][32]. Runs matching, pre-selection and lm_iters LM iterations, then writes the
+ * deformed template out_vertices [M][3] and the warps out_dq [N][8] (either may be NULL) and
+ * the optional debug taps. Synchronous; advances the frame counter. */
+int tt_track_frame(tt_stream* s, const float* depth, const float* feat_xyz, const uint8_t* feat_desc,
+                   int K2, double* out_vertices, double* out_dq, tt_frame_debug* dbg);
+
+/* Same solve with every array in device memory (d_depth [height][width], d_feat_xyz [K2][3],
+ * d_feat_desc [K2][32]; outputs d_out_vertices [M][3] and d_out_dq [N][8] float32, either may
+ * be NULL). Queued on the stream's HIP stream and returns without waiting. */
+int tt_track_frame_device(tt_stream* s, const float* d_depth, const float* d_feat_xyz,
+                          const uint8_t* d_feat_desc, int K2, float* d_out_vertices, float* d_out_dq);
+
+/* Waits for the stream's queued work; returns TT_EDEVICE if a device-side check failed. */
+int tt_sync(tt_stream* s);
+
+/* The hipStream_t the stream queues on. */
+void* tt_hip_stream(tt_stream* s);
+
+/* Template queries: node_idx [N], knn_pts [M][4], alpha_pts [M][4], knn_feat [K1][4],
+ * alpha_feat [K1][4], sbar and s_arap (scalars); any may be NULL. */
+int tt_get_template_info(tt_stream* s, int32_t* node_idx, int32_t* knn_pts, float* alpha_pts,
+                         int32_t* knn_feat, float* alpha_feat, double* sbar, double* s_arap);
+
+/* Warp state (N x 8, double on the host) and frame counter: read, or set for teacher forcing. */
+int tt_get_state(tt_stream* s, double* dq, int64_t* frame);
+int tt_set_state(tt_stream* s, const double* dq, int64_t frame);
+
+/* Per-stage GPU timers (hipEvents recorded on the stream's HIP stream around each stage). */
+#define TT_STAGE_FRONT 0  /* normal map, Hamming matching, 1-point RANSAC pre-selection */
+#define TT_STAGE_ROWS 1   /* per-point / per-feature residual and Jacobian rows          */
+#define TT_STAGE_ARAP 2   /* dense ARAP assembly into the normal matrix                  */
+#define TT_STAGE_DATA 3   /* data-term block assembly (block-CSR)                        */
+#define TT_STAGE_SOLVE 4  /* damping, Cholesky factorisation, substitutions             */
+#define TT_STAGE_UPDATE 5 /* candidate warps, FP64 costs, accept / reject               */
+#define TT_NSTAGES 6
+
+/* Enables (1) or disables (0) the stage timers. */
+int tt_set_timing(tt_stream* s, int enable);
+
+/* Waits for the stream, then returns the GPU milliseconds accumulated per stage since the last
+ * call (ms [TT_NSTAGES]) and how many times each stage ran (count [TT_NSTAGES]); either may be
+ * NULL. Resets the accumulators. */
+int tt_get_timing(tt_stream* s, double* ms, int64_t* count);
+
+/* Diagnostic: solves A x = b with the library's dense FP32 Cholesky path (the same kernels as the
+ * LM step: blocked factorisation with the right-hand side carried along, then back substitution).
+ * A is n x n row-major (symmetric; the lower triangle is read), b and x have n entries, host
+ * memory. *fail receives 1 if a pivot was not positive. Allocates and frees its own device
+ * memory; synchronous. */
+int tt_debug_cholesky_solve(int n, const float* A, const float* b, float* x, int* fail);
+
+/* Device bytes held by the stream. */
+int tt_device_bytes(tt_stream* s, uint64_t* bytes);
+
+/* Destroys the stream and frees its device memory. */
+int tt_destroy(tt_stream* s);
+
+const char* tt_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

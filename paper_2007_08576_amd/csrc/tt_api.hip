@@ -1,0 +1,775 @@
+// tt_api.hip -- the C ABI of include/tt.h: stream objects, device memory, template set-up and
+// the per-frame driver that queues the whole solve on one HIP stream (no host round trip between
+// the LM iterations: the accept/reject decision and the damping live on the device).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "tt_internal.h"
+
+int partial_count(int M, int K1, int N);
+
+namespace {
+
+#define HIPCHK(x)                        \
+  do {                                   \
+    hipError_t e_ = (x);                 \
+    if (e_ != hipSuccess) return TT_EDEVICE; \
+  } while (0)
+
+bool finite3(const float* p) { return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]); }
+
+Intr intr_of(const tt_stream* s) { return Intr{s->K.width, s->K.height, s->K.fx, s->K.fy, s->K.cx, s->K.cy}; }
+
+template <typename T>
+int dalloc(tt_stream* s, std::vector<void*>& list, uint64_t& bytes, T** out, size_t count) {
+  size_t nbytes = sizeof(T) * (count ? count : 1);
+  uint64_t total = s->bytes_template + s->bytes_frame + s->bytes_k2 + nbytes;
+  if (s->P.hbm_budget_bytes && total > s->P.hbm_budget_bytes) return TT_ENOMEM;
+  void* p = nullptr;
+  if (hipMalloc(&p, nbytes) != hipSuccess) return TT_ENOMEM;
+  list.push_back(p);
+  bytes += nbytes;
+  *out = static_cast<T*>(p);
+  return TT_OK;
+}
+
+#define ALLOC(list, bytes, ptr, count)                       \
+  do {                                                       \
+    int rc_ = dalloc(s, s->list, s->bytes, &(ptr), (count)); \
+    if (rc_) return rc_;                                     \
+  } while (0)
+
+void free_list(std::vector<void*>& list, uint64_t& bytes) {
+  for (void* p : list) (void)hipFree(p);
+  list.clear();
+  bytes = 0;
+}
+
+void free_template(tt_stream* s) {
+  if (s->st) (void)hipStreamSynchronize(s->st);
+  free_list(s->allocs_template, s->bytes_template);
+  DevState& d = s->d;
+  int HW = d.HW, K2cap = d.K2cap;
+  float* depth = d.depth;
+  float4* nmap = d.nmap;
+  float* f2xyz = d.f2xyz;
+  uint32_t* f2desc = d.f2desc;
+  LMScalars* sc = d.sc;
+  double *lo = d.log_cost_old, *ln = d.log_cost_new, *ll = d.log_lambda;
+  int* la = d.log_accept;
+  d = DevState();
+  d.HW = HW; d.K2cap = K2cap; d.depth = depth; d.nmap = nmap; d.f2xyz = f2xyz; d.f2desc = f2desc;
+  d.sc = sc; d.log_cost_old = lo; d.log_cost_new = ln; d.log_lambda = ll; d.log_accept = la;
+  s->has_template = false;
+}
+
+struct Busy {
+  tt_stream* s;
+  bool ok;
+  explicit Busy(tt_stream* s_) : s(s_), ok(s_->mu.try_lock()) {}
+  ~Busy() {
+    if (ok) s->mu.unlock();
+  }
+};
+
+// Build the static block-CSR of data-term node pairs: for each template point (kind 0) and
+// feature (kind 1) and each ordered slot pair (s, t) with node[s] >= node[t], one entry in
+// block (node[s], node[t]). Entries of a block are in (kind, index, s, t) order.
+void build_csr(const std::vector<int4>& knn, const std::vector<int4>& fknn, int N, std::vector<int2>& blk_ab,
+               std::vector<int>& blk_ptr, std::vector<uint32_t>& ent) {
+  struct E {
+    uint64_t key;
+    uint32_t e;
+  };
+  std::vector<E> all;
+  all.reserve(10 * (knn.size() + fknn.size()));
+  auto add = [&](const int4& nb, int kind, int idx) {
+    const int n[4] = {nb.x, nb.y, nb.z, nb.w};
+    for (int s = 0; s < 4; s++)
+      for (int t = 0; t < 4; t++) {
+        if (n[s] < n[t]) continue;
+        uint64_t key = (uint64_t)n[s] * (uint64_t)N + (uint64_t)n[t];
+        uint32_t e = ((uint32_t)idx << 5) | ((uint32_t)kind << 4) | ((uint32_t)s << 2) | (uint32_t)t;
+        all.push_back(E{key, e});
+      }
+  };
+  for (size_t j = 0; j < knn.size(); j++) add(knn[j], 0, (int)j);
+  for (size_t k = 0; k < fknn.size(); k++) add(fknn[k], 1, (int)k);
+  std::stable_sort(all.begin(), all.end(), [](const E& a, const E& b) { return a.key < b.key; });
+  blk_ab.clear();
+  blk_ptr.clear();
+  ent.clear();
+  ent.reserve(all.size());
+  for (size_t i = 0; i < all.size(); i++) {
+    if (i == 0 || all[i].key != all[i - 1].key) {
+      blk_ab.push_back(make_int2((int)(all[i].key / N), (int)(all[i].key % N)));
+      blk_ptr.push_back((int)i);
+    }
+    ent.push_back(all[i].e);
+  }
+  blk_ptr.push_back((int)all.size());
+}
+
+int ensure_k2(tt_stream* s, int K2) {
+  DevState& d = s->d;
+  if (K2 <= d.K2cap) return TT_OK;
+  (void)hipStreamSynchronize(s->st);
+  free_list(s->allocs_k2, s->bytes_k2);
+  int cap = std::max(K2, 2 * d.K2cap);
+  ALLOC(allocs_k2, bytes_k2, d.f2xyz, (size_t)3 * cap);
+  ALLOC(allocs_k2, bytes_k2, d.f2desc, (size_t)8 * cap);
+  d.K2cap = cap;
+  return TT_OK;
+}
+
+// ---- stage timers
+hipError_t ev_get(tt_stream* s, hipEvent_t* e) {
+  if (!s->ev_pool.empty()) {
+    *e = s->ev_pool.back();
+    s->ev_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+int timing_flush(tt_stream* s) {
+  if (s->ev_pending.empty()) return TT_OK;
+  HIPCHK(hipStreamSynchronize(s->st));
+  for (auto& pe : s->ev_pending) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, pe.second.first, pe.second.second));
+    s->stage_ms[pe.first] += ms;
+    s->stage_n[pe.first] += 1;
+    s->ev_pool.push_back(pe.second.first);
+    s->ev_pool.push_back(pe.second.second);
+  }
+  s->ev_pending.clear();
+  return TT_OK;
+}
+
+struct StageTimer {
+  tt_stream* s;
+  int stage;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(tt_stream* s_, int stage_) : s(s_), stage(stage_) {
+    if (!s->timing) return;
+    if (ev_get(s, &a) != hipSuccess || ev_get(s, &b) != hipSuccess) {
+      s->timing = false;
+      return;
+    }
+    (void)hipEventRecord(a, s->st);
+  }
+  ~StageTimer() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, s->st);
+    s->ev_pending.push_back({stage, {a, b}});
+    if (s->ev_pending.size() > 16384) (void)timing_flush(s);
+  }
+};
+
+// Queue the whole frame. depth/xyz/desc are device pointers.
+int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint8_t* desc, int K2, float* out_xyz,
+                  float* out_dq, bool dbg) {
+  DevState& d = s->d;
+  const tt_params& P = s->P;
+  Intr K = intr_of(s);
+  hipStream_t st = s->st;
+  DevState dd = d;  // launchers read the frame inputs from these fields
+  dd.depth = const_cast<float*>(depth);
+  dd.f2xyz = const_cast<float*>(xyz);
+  dd.f2desc = reinterpret_cast<uint32_t*>(const_cast<uint8_t*>(desc));
+  {
+    StageTimer tm(s, TT_STAGE_FRONT);
+    HIPCHK(launch_normal_map(dd, K, st));
+    if (d.K1 > 0) {
+      HIPCHK(launch_match(dd, K2, P.max_hamming, st));  // K2 == 0: every feature unmatched
+      HIPCHK(launch_preselect(dd, P.ransac_refs, P.ransac_iters, P.H, P.seed, s->frame, st));
+    }
+    HIPCHK(launch_lm_begin(d, P.lm_lambda0, st));
+  }
+  for (int it = 0; it < P.lm_iters; it++) {
+    {
+      StageTimer tm(s, TT_STAGE_ROWS);
+      HIPCHK(launch_lm_rows(dd, P, K, it, st));
+    }
+    {
+      StageTimer tm(s, TT_STAGE_ARAP);
+      HIPCHK(launch_lm_arap(dd, P, st));
+    }
+    {
+      StageTimer tm(s, TT_STAGE_DATA);
+      HIPCHK(launch_lm_data(dd, st));
+    }
+    if (dbg && it == 0) {
+      HIPCHK(hipMemcpyAsync(d.A_dbg, d.A, sizeof(float) * (size_t)d.npad * d.ld, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(d.g_dbg, d.g, sizeof(float) * d.npad, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(d.corr_dbg, d.corr, sizeof(int) * d.M, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(d.rres_dbg, d.rres, sizeof(float) * d.M, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(d.omega_dbg, d.omega, sizeof(float) * d.M, hipMemcpyDeviceToDevice, st));
+      if (d.K1)
+        HIPCHK(hipMemcpyAsync(d.orbw_dbg, d.orbw, sizeof(float) * d.K1, hipMemcpyDeviceToDevice, st));
+    }
+    {
+      StageTimer tm(s, TT_STAGE_SOLVE);
+      HIPCHK(launch_lm_damp(dd, st));
+      s->solve_epoch = (s->solve_epoch == 0x7FFFFFFF) ? 1 : s->solve_epoch + 1;
+      HIPCHK(launch_cholesky_solve(dd, s->solve_epoch, st));
+    }
+    {
+      StageTimer tm(s, TT_STAGE_UPDATE);
+      HIPCHK(launch_lm_finish(dd, P, K, st));
+    }
+  }
+  HIPCHK(launch_deform_out(d, out_xyz, out_dq, st));
+  s->frame += 1;
+  return TT_OK;
+}
+
+int ensure_debug_buffers(tt_stream* s) {
+  DevState& d = s->d;
+  if (d.A_dbg) return TT_OK;
+  ALLOC(allocs_template, bytes_template, d.A_dbg, (size_t)d.npad * d.ld);
+  ALLOC(allocs_template, bytes_template, d.g_dbg, (size_t)d.npad);
+  ALLOC(allocs_template, bytes_template, d.corr_dbg, (size_t)d.M);
+  ALLOC(allocs_template, bytes_template, d.rres_dbg, (size_t)d.M);
+  ALLOC(allocs_template, bytes_template, d.omega_dbg, (size_t)d.M);
+  ALLOC(allocs_template, bytes_template, d.orbw_dbg, (size_t)(d.K1 ? d.K1 : 1));
+  return TT_OK;
+}
+
+template <typename T>
+int d2h(T* host, const T* dev, size_t count, hipStream_t st) {
+  if (!host || !count) return TT_OK;
+  HIPCHK(hipMemcpyAsync(host, dev, sizeof(T) * count, hipMemcpyDeviceToHost, st));
+  return TT_OK;
+}
+
+int copy_debug(tt_stream* s, tt_frame_debug* dbg) {
+  DevState& d = s->d;
+  hipStream_t st = s->st;
+  const int K1 = d.K1, M = d.M, R = s->P.ransac_refs, T = s->P.lm_iters, n = d.n;
+  std::vector<int> hs(R), refs(R);
+  std::vector<float> fbuf;
+  HIPCHK(hipStreamSynchronize(st));
+  if (K1 > 0) {
+    if (d2h(dbg->match_idx, d.midx, K1, st)) return TT_EDEVICE;
+    if (d2h(dbg->match_dist, d.mdist, K1, st)) return TT_EDEVICE;
+    if (d2h(dbg->wstar, d.wstar, K1, st)) return TT_EDEVICE;
+    if (d2h(dbg->preselected, d.presel, K1, st)) return TT_EDEVICE;
+    if (d2h(dbg->hyp_W, d.hyp_W, R, st)) return TT_EDEVICE;
+    if (d2h(dbg->hyp_nin, d.hyp_nin, R, st)) return TT_EDEVICE;
+    if (d2h(hs.data(), d.hyp_state, R, st)) return TT_EDEVICE;
+    if (d2h(refs.data(), d.refs, R, st)) return TT_EDEVICE;
+  } else {
+    for (int h = 0; h < R; h++) { hs[h] = -1; refs[h] = -1; }
+    if (dbg->hyp_W) for (int h = 0; h < R; h++) dbg->hyp_W[h] = 0.0;
+    if (dbg->hyp_nin) for (int h = 0; h < R; h++) dbg->hyp_nin[h] = 0;
+  }
+  if (d2h(dbg->corr0, d.corr_dbg, M, st)) return TT_EDEVICE;
+  std::vector<float> rr(M), om(M), ow(K1 ? K1 : 1), gg(d.npad);
+  if (d2h(rr.data(), d.rres_dbg, M, st)) return TT_EDEVICE;
+  if (d2h(om.data(), d.omega_dbg, M, st)) return TT_EDEVICE;
+  if (K1 && d2h(ow.data(), d.orbw_dbg, K1, st)) return TT_EDEVICE;
+  if (d2h(gg.data(), d.g_dbg, d.npad, st)) return TT_EDEVICE;
+  if (dbg->A0) {
+    fbuf.resize((size_t)d.npad * d.ld);
+    if (d2h(fbuf.data(), d.A_dbg, fbuf.size(), st)) return TT_EDEVICE;
+  }
+  LMScalars sc;
+  HIPCHK(hipMemcpyAsync(&sc, d.sc, sizeof(sc), hipMemcpyDeviceToHost, st));
+  std::vector<double> lo(T), ln(T), ll(T);
+  std::vector<int> la(T);
+  if (T > 0) {
+    if (d2h(lo.data(), d.log_cost_old, T, st)) return TT_EDEVICE;
+    if (d2h(ln.data(), d.log_cost_new, T, st)) return TT_EDEVICE;
+    if (d2h(ll.data(), d.log_lambda, T, st)) return TT_EDEVICE;
+    if (d2h(la.data(), d.log_accept, T, st)) return TT_EDEVICE;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  for (int h = 0; h < R; h++) {
+    if (dbg->hyp_k0) dbg->hyp_k0[h] = refs[h];
+    if (dbg->hyp_kept) dbg->hyp_kept[h] = (uint8_t)(hs[h] == 1 ? 1 : (hs[h] == 2 ? 2 : 0));
+  }
+  for (int j = 0; j < M; j++) {
+    if (dbg->r0) dbg->r0[j] = rr[j];
+    if (dbg->omega0) dbg->omega0[j] = om[j];
+  }
+  for (int k = 0; k < K1; k++)
+    if (dbg->orbw0) dbg->orbw0[k] = ow[k];
+  if (dbg->g0)
+    for (int i = 0; i < n; i++) dbg->g0[i] = gg[i];
+  if (dbg->A0)
+    for (int i = 0; i < n; i++)
+      for (int j = 0; j <= i; j++) {
+        double v = fbuf[(size_t)i * d.ld + j];
+        dbg->A0[(size_t)i * n + j] = v;
+        dbg->A0[(size_t)j * n + i] = v;
+      }
+  if (dbg->w_arap) *dbg->w_arap = sc.w_arap;
+  for (int t = 0; t < T; t++) {
+    if (dbg->cost_old) dbg->cost_old[t] = lo[t];
+    if (dbg->cost_new) dbg->cost_new[t] = ln[t];
+    if (dbg->lambda) dbg->lambda[t] = ll[t];
+    if (dbg->accepted) dbg->accepted[t] = (uint8_t)la[t];
+  }
+  return TT_OK;
+}
+
+}  // namespace
+
+// =============================================================================================
+
+extern "C" {
+
+void tt_default_params(tt_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->num_control_points = 64;
+  p->knn = 4;
+  p->w_orb = 10.0;
+  p->w_angle = 20.0;
+  p->w_rotation = 100.0;
+  p->lambda_arap = 1.0;
+  p->tukey_c = 5.0;
+  p->H = 3.0;
+  p->ransac_refs = 30;
+  p->ransac_iters = 10;
+  p->lm_iters = 10;
+  p->max_hamming = 256;
+  p->lm_lambda0 = 1e-4;
+  p->precision = TT_FP32;
+  p->seed = 0;
+  p->hbm_budget_bytes = 0;
+}
+
+const char* tt_strerror(int code) {
+  switch (code) {
+    case TT_OK: return "ok";
+    case TT_EINVAL: return "invalid argument";
+    case TT_ENOMEM: return "out of device memory or over the stream's HBM budget";
+    case TT_ESTATE: return "frame before template";
+    case TT_EDEVICE: return "device error";
+    case TT_EBUSY: return "stream busy";
+    default: return "unknown error";
+  }
+}
+
+int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_stream, tt_stream** out) {
+  if (!p || !K || !out) return TT_EINVAL;
+  *out = nullptr;
+  if (p->num_control_points < 1 || p->knn != 4 || p->ransac_refs < 1 || p->ransac_refs > 1024 ||
+      p->ransac_iters < 1 || p->lm_iters < 0 || p->lm_iters > 1000 || !(p->H > 0) || !(p->tukey_c > 0) ||
+      !(p->w_orb >= 0) || !(p->w_angle >= 0) || !(p->w_rotation >= 0) || !(p->lambda_arap >= 0) ||
+      !(p->lm_lambda0 > 0) || p->precision != TT_FP32)
+    return TT_EINVAL;
+  if (K->width < 3 || K->height < 3 || !(K->fx > 0) || !(K->fy > 0) || !isfinite(K->cx) || !isfinite(K->cy) ||
+      (int64_t)K->width * K->height > (1 << 28))
+    return TT_EINVAL;
+  tt_stream* s = new (std::nothrow) tt_stream();
+  if (!s) return TT_ENOMEM;
+  s->P = *p;
+  s->K = *K;
+  if (hip_stream) {
+    s->st = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess) {
+      delete s;
+      return TT_EDEVICE;
+    }
+    s->own_stream = true;
+  }
+  DevState& d = s->d;
+  d.HW = K->width * K->height;
+  int T = p->lm_iters > 0 ? p->lm_iters : 1;
+  int rc = TT_OK;
+  rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.depth, (size_t)d.HW);
+  rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.nmap, (size_t)d.HW);
+  rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.sc, 1);
+  rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_cost_old, (size_t)T);
+  rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_cost_new, (size_t)T);
+  rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_lambda, (size_t)T);
+  rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_accept, (size_t)T);
+  if (rc) {
+    tt_destroy(s);
+    return rc;
+  }
+  if (hipMemsetAsync(d.sc, 0, sizeof(LMScalars), s->st) != hipSuccess) {
+    tt_destroy(s);
+    return TT_EDEVICE;
+  }
+  *out = s;
+  return TT_OK;
+}
+
+int tt_set_timing(tt_stream* s, int enable) {
+  if (!s) return TT_EINVAL;
+  Busy busy(s);
+  if (!busy.ok) return TT_EBUSY;
+  s->timing = enable != 0;
+  return TT_OK;
+}
+
+int tt_get_timing(tt_stream* s, double* ms, int64_t* count) {
+  if (!s) return TT_EINVAL;
+  Busy busy(s);
+  if (!busy.ok) return TT_EBUSY;
+  int rc = timing_flush(s);
+  if (rc) return rc;
+  for (int i = 0; i < TT_NSTAGES; i++) {
+    if (ms) ms[i] = s->stage_ms[i];
+    if (count) count[i] = s->stage_n[i];
+    s->stage_ms[i] = 0.0;
+    s->stage_n[i] = 0;
+  }
+  return TT_OK;
+}
+
+int tt_debug_cholesky_solve(int n, const float* A, const float* b, float* x, int* fail) {
+  if (n < 1 || n > 65536 || !A || !b || !x || !fail) return TT_EINVAL;
+  DevState d;
+  d.n = n;
+  d.npad = ((n + TT_NB - 1) / TT_NB) * TT_NB;
+  d.nb = d.npad / TT_NB;
+  d.ld = d.npad;
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return TT_EDEVICE;
+  std::vector<void*> mem;
+  auto al = [&](void** p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) return false;
+    mem.push_back(*p);
+    return true;
+  };
+  int rc = TT_OK;
+  const size_t rows = (size_t)d.npad + TT_NB;
+  if (!al((void**)&d.A, sizeof(float) * rows * d.ld) || !al((void**)&d.x, sizeof(float) * d.npad) ||
+      !al((void**)&d.Linv, sizeof(float) * (size_t)d.nb * TT_NB * TT_NB) || !al((void**)&d.flags, sizeof(int) * d.nb) ||
+      !al((void**)&d.sc, sizeof(LMScalars)) || !al((void**)&d.dscale, sizeof(float) * d.npad)) {
+    rc = TT_ENOMEM;
+  } else {
+    std::vector<float> h(rows * d.ld, 0.0f);
+    for (int i = 0; i < n; i++)
+      for (int j = 0; j <= i; j++) h[(size_t)i * d.ld + j] = A[(size_t)i * n + j];
+    for (int i = n; i < d.npad; i++) h[(size_t)i * d.ld + i] = 1.0f;
+    for (int j = 0; j < n; j++) h[(size_t)d.npad * d.ld + j] = b[j];
+    std::vector<float> hx(d.npad), ones(d.npad, 1.0f);  // no equilibration in this diagnostic
+    LMScalars sc;
+    memset(&sc, 0, sizeof(sc));
+    if (hipMemcpyAsync(d.A, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemsetAsync(d.flags, 0, sizeof(int) * d.nb, st) != hipSuccess ||
+        hipMemcpyAsync(d.dscale, ones.data(), sizeof(float) * d.npad, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, st) != hipSuccess ||
+        launch_cholesky_solve(d, 1, st) != hipSuccess ||
+        hipMemcpyAsync(hx.data(), d.x, sizeof(float) * d.npad, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&sc, d.sc, sizeof(sc), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = TT_EDEVICE;
+    } else {
+      for (int i = 0; i < n; i++) x[i] = hx[i];
+      *fail = sc.chol_fail;
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  for (void* p : mem) (void)hipFree(p);
+  (void)hipStreamDestroy(st);
+  return rc;
+}
+
+int tt_destroy(tt_stream* s) {
+  if (!s) return TT_EINVAL;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    (void)timing_flush(s);
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+    s->ev_pool.clear();
+    free_template(s);
+    free_list(s->allocs_k2, s->bytes_k2);
+    free_list(s->allocs_frame, s->bytes_frame);
+    if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);
+    s->st = nullptr;
+  }
+  delete s;
+  return TT_OK;
+}
+
+void* tt_hip_stream(tt_stream* s) { return s ? static_cast<void*>(s->st) : nullptr; }
+
+int tt_device_bytes(tt_stream* s, uint64_t* bytes) {
+  if (!s || !bytes) return TT_EINVAL;
+  *bytes = s->bytes_template + s->bytes_frame + s->bytes_k2;
+  return TT_OK;
+}
+
+int tt_sync(tt_stream* s) {
+  if (!s) return TT_EINVAL;
+  return hipStreamSynchronize(s->st) == hipSuccess ? TT_OK : TT_EDEVICE;
+}
+
+int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat_xyz, const uint8_t* feat_desc,
+                    int K1) {
+  if (!s || !pts_xyz || M < 1 || K1 < 0 || (K1 > 0 && (!feat_xyz || !feat_desc))) return TT_EINVAL;
+  const int N = s->P.num_control_points;
+  if (N > M || M > (1 << 26) || K1 > (1 << 23)) return TT_EINVAL;
+  for (int j = 0; j < M; j++)
+    if (!finite3(pts_xyz + 3 * j)) return TT_EINVAL;
+  for (int k = 0; k < K1; k++)
+    if (!finite3(feat_xyz + 3 * k)) return TT_EINVAL;
+  Busy busy(s);
+  if (!busy.ok) return TT_EBUSY;
+  free_template(s);
+  DevState& d = s->d;
+  hipStream_t st = s->st;
+  d.M = M;
+  d.N = N;
+  d.K1 = K1;
+  d.n = 6 * N;
+  d.npad = ((d.n + TT_NB - 1) / TT_NB) * TT_NB;
+  d.nb = d.npad / TT_NB;
+  d.ld = d.npad;
+  const int R = s->P.ransac_refs;
+  const size_t K1a = K1 ? K1 : 1;
+  ALLOC(allocs_template, bytes_template, d.px, (size_t)M);
+  ALLOC(allocs_template, bytes_template, d.py, (size_t)M);
+  ALLOC(allocs_template, bytes_template, d.pz, (size_t)M);
+  ALLOC(allocs_template, bytes_template, d.knn, (size_t)M);
+  ALLOC(allocs_template, bytes_template, d.alpha, (size_t)M);
+  ALLOC(allocs_template, bytes_template, d.fpx, K1a);
+  ALLOC(allocs_template, bytes_template, d.fpy, K1a);
+  ALLOC(allocs_template, bytes_template, d.fpz, K1a);
+  ALLOC(allocs_template, bytes_template, d.fknn, K1a);
+  ALLOC(allocs_template, bytes_template, d.falpha, K1a);
+  ALLOC(allocs_template, bytes_template, d.desc, 8 * K1a);
+  ALLOC(allocs_template, bytes_template, d.c0, (size_t)N);
+  ALLOC(allocs_template, bytes_template, d.node_idx, (size_t)N);
+  ALLOC(allocs_template, bytes_template, d.mind, (size_t)std::max(M, N));
+  ALLOC(allocs_template, bytes_template, d.W, (size_t)8 * N);
+  ALLOC(allocs_template, bytes_template, d.Wc, (size_t)8 * N);
+  ALLOC(allocs_template, bytes_template, d.pos, (size_t)N);
+  ALLOC(allocs_template, bytes_template, d.posc, (size_t)N);
+  ALLOC(allocs_template, bytes_template, d.ndisp, (size_t)N);
+  ALLOC(allocs_template, bytes_template, d.ndispc, (size_t)N);
+  ALLOC(allocs_template, bytes_template, d.midx, K1a);
+  ALLOC(allocs_template, bytes_template, d.mdist, K1a);
+  ALLOC(allocs_template, bytes_template, d.o2, K1a);
+  ALLOC(allocs_template, bytes_template, d.ulist, K1a);
+  ALLOC(allocs_template, bytes_template, d.refs, (size_t)R);
+  ALLOC(allocs_template, bytes_template, d.hyp_w, (size_t)R * K1a);
+  ALLOC(allocs_template, bytes_template, d.hyp_W, (size_t)R);
+  ALLOC(allocs_template, bytes_template, d.hyp_nin, (size_t)R);
+  ALLOC(allocs_template, bytes_template, d.hyp_state, (size_t)R);
+  ALLOC(allocs_template, bytes_template, d.wstar, K1a);
+  ALLOC(allocs_template, bytes_template, d.presel, K1a);
+  ALLOC(allocs_template, bytes_template, d.corr, (size_t)M);
+  ALLOC(allocs_template, bytes_template, d.rres, (size_t)M);
+  ALLOC(allocs_template, bytes_template, d.omega, (size_t)M);
+  ALLOC(allocs_template, bytes_template, d.jac, (size_t)24 * M);
+  ALLOC(allocs_template, bytes_template, d.wres, (size_t)M);
+  ALLOC(allocs_template, bytes_template, d.orbw, K1a);
+  ALLOC(allocs_template, bytes_template, d.jacF, 72 * K1a);
+  ALLOC(allocs_template, bytes_template, d.wresF, 3 * K1a);
+  ALLOC(allocs_template, bytes_template, d.A, (size_t)(d.npad + TT_NB) * d.ld);
+  ALLOC(allocs_template, bytes_template, d.g, (size_t)d.npad);
+  ALLOC(allocs_template, bytes_template, d.x, (size_t)d.npad);
+  ALLOC(allocs_template, bytes_template, d.Linv, (size_t)d.nb * TT_NB * TT_NB);
+  ALLOC(allocs_template, bytes_template, d.flags, (size_t)d.nb);
+  ALLOC(allocs_template, bytes_template, d.dscale, (size_t)d.npad);
+  d.npartial = partial_count(M, K1, N) + 8;
+  ALLOC(allocs_template, bytes_template, d.partial, (size_t)d.npartial);
+  int* d_err = nullptr;
+  ALLOC(allocs_template, bytes_template, d_err, 1);
+
+  // upload the template as SoA
+  {
+    std::vector<float> x(M), y(M), z(M);
+    for (int j = 0; j < M; j++) {
+      x[j] = pts_xyz[3 * j];
+      y[j] = pts_xyz[3 * j + 1];
+      z[j] = pts_xyz[3 * j + 2];
+    }
+    HIPCHK(hipMemcpyAsync(d.px, x.data(), sizeof(float) * M, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.py, y.data(), sizeof(float) * M, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.pz, z.data(), sizeof(float) * M, hipMemcpyHostToDevice, st));
+    std::vector<float> fx(K1a, 0.f), fy(K1a, 0.f), fz(K1a, 0.f);
+    for (int k = 0; k < K1; k++) {
+      fx[k] = feat_xyz[3 * k];
+      fy[k] = feat_xyz[3 * k + 1];
+      fz[k] = feat_xyz[3 * k + 2];
+    }
+    HIPCHK(hipMemcpyAsync(d.fpx, fx.data(), sizeof(float) * K1a, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.fpy, fy.data(), sizeof(float) * K1a, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.fpz, fz.data(), sizeof(float) * K1a, hipMemcpyHostToDevice, st));
+    if (K1) HIPCHK(hipMemcpyAsync(d.desc, feat_desc, 32 * (size_t)K1, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(d_err, 0, sizeof(int), st));
+    HIPCHK(launch_fps(d, M, N, d_err, st));
+    int err = 0;
+    HIPCHK(hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (err) {
+      free_template(s);
+      return TT_EINVAL;
+    }
+  }
+  double sbar = 1.0, sarap = 0.0;
+  HIPCHK(launch_template_tables(d, st, &sbar, &sarap));
+  d.sbar = sbar;
+  d.s_arap = sarap;
+  HIPCHK(launch_knn(d, sbar, st));
+  // static block-CSR of the data-term node pairs
+  {
+    std::vector<int4> knn(M), fknn(K1);
+    HIPCHK(hipMemcpyAsync(knn.data(), d.knn, sizeof(int4) * M, hipMemcpyDeviceToHost, st));
+    if (K1) HIPCHK(hipMemcpyAsync(fknn.data(), d.fknn, sizeof(int4) * K1, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<int2> ab;
+    std::vector<int> ptr;
+    std::vector<uint32_t> ent;
+    build_csr(knn, fknn, N, ab, ptr, ent);
+    d.nblk = (int)ab.size();
+    ALLOC(allocs_template, bytes_template, d.blk_ab, ab.size());
+    ALLOC(allocs_template, bytes_template, d.blk_ptr, ptr.size());
+    ALLOC(allocs_template, bytes_template, d.blk_ent, ent.size());
+    HIPCHK(hipMemcpyAsync(d.blk_ab, ab.data(), sizeof(int2) * ab.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.blk_ptr, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.blk_ent, ent.data(), sizeof(uint32_t) * ent.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  // warps = identity; normal matrix zero with an identity on the padding
+  {
+    std::vector<float> W(8 * (size_t)N, 0.0f);
+    for (int i = 0; i < N; i++) W[8 * i] = 1.0f;
+    HIPCHK(hipMemcpyAsync(d.W, W.data(), sizeof(float) * W.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(d.A, 0, sizeof(float) * (size_t)(d.npad + TT_NB) * d.ld, st));
+    std::vector<float> one(1, 1.0f);
+    for (int k = d.n; k < d.npad; k++)
+      HIPCHK(hipMemcpyAsync(d.A + (size_t)k * d.ld + k, one.data(), sizeof(float), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(d.x, 0, sizeof(float) * d.npad, st));
+    HIPCHK(hipMemsetAsync(d.flags, 0, sizeof(int) * d.nb, st));
+    s->solve_epoch = 0;
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  s->frame = 0;
+  s->has_template = true;
+  return TT_OK;
+}
+
+int tt_track_frame_device(tt_stream* s, const float* d_depth, const float* d_feat_xyz, const uint8_t* d_feat_desc,
+                          int K2, float* d_out_vertices, float* d_out_dq) {
+  if (!s || !d_depth || K2 < 0 || K2 > (1 << 23) || (K2 > 0 && (!d_feat_xyz || !d_feat_desc))) return TT_EINVAL;
+  if (K2 > 0 && ((uintptr_t)d_feat_desc % 16 != 0)) return TT_EINVAL;
+  Busy busy(s);
+  if (!busy.ok) return TT_EBUSY;
+  if (!s->has_template) return TT_ESTATE;
+  return enqueue_frame(s, d_depth, d_feat_xyz, d_feat_desc, K2, d_out_vertices, d_out_dq, false);
+}
+
+int tt_track_frame(tt_stream* s, const float* depth, const float* feat_xyz, const uint8_t* feat_desc, int K2,
+                   double* out_vertices, double* out_dq, tt_frame_debug* dbg) {
+  if (!s || !depth || K2 < 0 || K2 > (1 << 23) || (K2 > 0 && (!feat_xyz || !feat_desc))) return TT_EINVAL;
+  Busy busy(s);
+  if (!busy.ok) return TT_EBUSY;
+  if (!s->has_template) return TT_ESTATE;
+  DevState& d = s->d;
+  hipStream_t st = s->st;
+  int rc = ensure_k2(s, K2);
+  if (rc) return rc;
+  if (dbg) {
+    rc = ensure_debug_buffers(s);
+    if (rc) return rc;
+  }
+  HIPCHK(hipMemcpyAsync(d.depth, depth, sizeof(float) * d.HW, hipMemcpyHostToDevice, st));
+  if (K2 > 0) {
+    HIPCHK(hipMemcpyAsync(d.f2xyz, feat_xyz, sizeof(float) * 3 * (size_t)K2, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.f2desc, feat_desc, 32 * (size_t)K2, hipMemcpyHostToDevice, st));
+  }
+  // outputs in float on the device, widened on the host
+  float *ov = nullptr, *oq = nullptr;
+  std::vector<void*> tmp;
+  uint64_t tmpb = 0;
+  if (out_vertices) {
+    if (hipMalloc(&ov, sizeof(float) * 3 * (size_t)d.M) != hipSuccess) return TT_ENOMEM;
+    tmp.push_back(ov);
+  }
+  if (out_dq) {
+    if (hipMalloc(&oq, sizeof(float) * 8 * (size_t)d.N) != hipSuccess) {
+      free_list(tmp, tmpb);
+      return TT_ENOMEM;
+    }
+    tmp.push_back(oq);
+  }
+  rc = enqueue_frame(s, d.depth, d.f2xyz, reinterpret_cast<const uint8_t*>(d.f2desc), K2, ov, oq, dbg != nullptr);
+  if (rc == TT_OK) {
+    std::vector<float> hv(out_vertices ? 3 * (size_t)d.M : 0), hq(out_dq ? 8 * (size_t)d.N : 0);
+    if (ov && hipMemcpyAsync(hv.data(), ov, sizeof(float) * hv.size(), hipMemcpyDeviceToHost, st) != hipSuccess)
+      rc = TT_EDEVICE;
+    if (oq && hipMemcpyAsync(hq.data(), oq, sizeof(float) * hq.size(), hipMemcpyDeviceToHost, st) != hipSuccess)
+      rc = TT_EDEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) rc = TT_EDEVICE;
+    if (rc == TT_OK) {
+      for (size_t i = 0; i < hv.size(); i++) out_vertices[i] = hv[i];
+      for (size_t i = 0; i < hq.size(); i++) out_dq[i] = hq[i];
+      if (dbg) rc = copy_debug(s, dbg);
+    }
+  }
+  free_list(tmp, tmpb);
+  return rc;
+}
+
+int tt_get_template_info(tt_stream* s, int32_t* node_idx, int32_t* knn_pts, float* alpha_pts, int32_t* knn_feat,
+                         float* alpha_feat, double* sbar, double* s_arap) {
+  if (!s) return TT_EINVAL;
+  Busy busy(s);
+  if (!busy.ok) return TT_EBUSY;
+  if (!s->has_template) return TT_ESTATE;
+  DevState& d = s->d;
+  hipStream_t st = s->st;
+  if (node_idx) HIPCHK(hipMemcpyAsync(node_idx, d.node_idx, sizeof(int) * d.N, hipMemcpyDeviceToHost, st));
+  if (knn_pts) HIPCHK(hipMemcpyAsync(knn_pts, d.knn, sizeof(int4) * d.M, hipMemcpyDeviceToHost, st));
+  if (alpha_pts) HIPCHK(hipMemcpyAsync(alpha_pts, d.alpha, sizeof(float4) * d.M, hipMemcpyDeviceToHost, st));
+  if (knn_feat && d.K1) HIPCHK(hipMemcpyAsync(knn_feat, d.fknn, sizeof(int4) * d.K1, hipMemcpyDeviceToHost, st));
+  if (alpha_feat && d.K1)
+    HIPCHK(hipMemcpyAsync(alpha_feat, d.falpha, sizeof(float4) * d.K1, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (sbar) *sbar = d.sbar;
+  if (s_arap) *s_arap = d.s_arap;
+  return TT_OK;
+}
+
+int tt_get_state(tt_stream* s, double* dq, int64_t* frame) {
+  if (!s) return TT_EINVAL;
+  Busy busy(s);
+  if (!busy.ok) return TT_EBUSY;
+  if (!s->has_template) return TT_ESTATE;
+  DevState& d = s->d;
+  if (dq) {
+    std::vector<float> W(8 * (size_t)d.N);
+    HIPCHK(hipMemcpyAsync(W.data(), d.W, sizeof(float) * W.size(), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    for (size_t i = 0; i < W.size(); i++) dq[i] = W[i];
+  }
+  if (frame) *frame = s->frame;
+  return TT_OK;
+}
+
+int tt_set_state(tt_stream* s, const double* dq, int64_t frame) {
+  if (!s || frame < 0) return TT_EINVAL;
+  Busy busy(s);
+  if (!busy.ok) return TT_EBUSY;
+  if (!s->has_template) return TT_ESTATE;
+  DevState& d = s->d;
+  if (dq) {
+    std::vector<float> W(8 * (size_t)d.N);
+    for (size_t i = 0; i < W.size(); i++) {
+      if (!isfinite(dq[i])) return TT_EINVAL;
+      W[i] = (float)dq[i];
+    }
+    HIPCHK(hipMemcpyAsync(d.W, W.data(), sizeof(float) * W.size(), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+  }
+  s->frame = frame;
+  return TT_OK;
+}
+
+}  // extern "C"

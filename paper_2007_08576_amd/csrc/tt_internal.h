@@ -1,0 +1,164 @@
+// tt_internal.h -- device-side state of one tracked stream and the kernel launchers.
+//
+// Data layout in HBM (all resident for the life of the stream unless marked per frame):
+//   template points   px, py, pz          f32 [M]        (SoA, coalesced per point)
+//                     knn                 int4 [M]       (4 nearest control points)
+//                     alpha               float4 [M]     (Gaussian blend weights)
+//   template features fpx, fpy, fpz       f32 [K1]; fknn int4 [K1]; falpha float4 [K1]
+//                     desc                uint32 [8][K1] (256-bit descriptors as 8 word planes)
+//   control points    c0                  float4 [N]     (rest position p_i^0)
+//                     W, Wc               f32 [N][8]     (current / candidate dual quaternion)
+//                     pos                 float4 [N]     (p_i^t of the current warps)
+//   data-term blocks  blk_ab, blk_ptr, blk_ent: static block-CSR of node pairs (a >= b) that
+//                     share a template point or feature, with the contributing rows
+//   per frame         depth f32 [H*W]; nmap float4 [H*W] = (n, z) of the target surface
+//   per iteration     jac f32 [24][M], wres f32 [M] (weighted ICP rows); jacF f32 [72][K1],
+//                     wresF f32 [3][K1] (weighted feature rows)
+//   normal matrix     A f32 [(npad + 64) x npad] row-major, lower triangle; rows npad..npad+63
+//                     hold the right-hand side row(s) so that the forward substitution runs
+//                     inside the blocked factorisation; Linv f32 [nb][64][64] inverse diagonal
+//                     blocks for the back substitution.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/tt.h"
+
+#define TT_NB 64  // Cholesky block size
+
+struct LMScalars {
+  double lambda;     // Marquardt damping of the current iteration
+  double e_old;      // cost at the iterate
+  double e_new;      // cost at the candidate
+  double w_arap;     // dynamic ARAP weight of the frame
+  double sum_omega;  // sum of Tukey weights (iteration 0)
+  double sum_orbw;   // sum of feature weights (iteration 0)
+  double eps;        // diagonal shift of the damping
+  int chol_fail;     // set by the factorisation when a pivot is not positive
+  int accept;        // decision of the last iteration
+  int it;            // iteration counter
+  int err;           // device-side error bits
+};
+
+struct DevState {
+  // sizes
+  int M = 0, N = 0, K1 = 0, HW = 0, n = 0, npad = 0, nb = 0, ld = 0;
+  int K2cap = 0;
+  // template
+  float *px = nullptr, *py = nullptr, *pz = nullptr;
+  int4* knn = nullptr;
+  float4* alpha = nullptr;
+  float *fpx = nullptr, *fpy = nullptr, *fpz = nullptr;
+  int4* fknn = nullptr;
+  float4* falpha = nullptr;
+  uint32_t* desc = nullptr;
+  float4* c0 = nullptr;
+  int* node_idx = nullptr;
+  double* mind = nullptr;  // FPS scratch [M]
+  int nblk = 0;
+  int2* blk_ab = nullptr;
+  int* blk_ptr = nullptr;
+  uint32_t* blk_ent = nullptr;
+  double sbar = 0.0, s_arap = 0.0;
+  // warps
+  float *W = nullptr, *Wc = nullptr;
+  float4 *pos = nullptr, *posc = nullptr;    // p_i^t
+  float4 *ndisp = nullptr, *ndispc = nullptr;  // p_i^t - p_i^0
+  // frame inputs (staging)
+  float* depth = nullptr;
+  float4* nmap = nullptr;
+  float* f2xyz = nullptr;    // [K2cap][3]
+  uint32_t* f2desc = nullptr;  // [8][K2cap]
+  // matching + pre-selection
+  int* midx = nullptr;
+  int* mdist = nullptr;
+  float4* o2 = nullptr;      // [K1] matched frame point, w = 1 if usable
+  int* ulist = nullptr;      // [K1] usable list / shuffle workspace
+  int* refs = nullptr;       // [R]
+  double* hyp_w = nullptr;   // [R][K1]
+  double* hyp_W = nullptr;   // [R]
+  int* hyp_nin = nullptr;    // [R]
+  int* hyp_state = nullptr;  // [R] 1 kept, 0 dropped, 2 degenerate, -1 not drawn
+  double* wstar = nullptr;   // [K1]
+  uint8_t* presel = nullptr; // [K1]
+  // LM
+  int* corr = nullptr;
+  float* rres = nullptr;
+  float* omega = nullptr;
+  float* jac = nullptr;      // [24][M]
+  float* wres = nullptr;     // [M]
+  float* orbw = nullptr;     // [K1]
+  float* jacF = nullptr;     // [72][K1]
+  float* wresF = nullptr;    // [3][K1]
+  float* A = nullptr;        // [(npad + TT_NB) * ld]
+  float* g = nullptr;        // [npad]
+  float* x = nullptr;        // [npad] solution of the equilibrated system
+  float* dscale = nullptr;   // [npad] symmetric diagonal equilibration d_k = 1/sqrt(damped A_kk)
+  float* Linv = nullptr;     // [nb][TT_NB][TT_NB]
+  int* flags = nullptr;      // [nb] back-substitution block flags (epoch of the solve)
+  double* partial = nullptr; // reduction partials
+  int npartial = 0;
+  LMScalars* sc = nullptr;
+  double* log_cost_old = nullptr;
+  double* log_cost_new = nullptr;
+  double* log_lambda = nullptr;
+  int* log_accept = nullptr;
+  // debug copies
+  float* A_dbg = nullptr;
+  float* g_dbg = nullptr;
+  int* corr_dbg = nullptr;
+  float* rres_dbg = nullptr;
+  float* omega_dbg = nullptr;
+  float* orbw_dbg = nullptr;
+};
+
+struct tt_stream {
+  tt_params P;
+  tt_intrinsics K;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  bool has_template = false;
+  int64_t frame = 0;
+  int solve_epoch = 0;  // increments per Cholesky solve; flags of the back substitution match it
+  std::mutex mu;
+  DevState d;
+  std::vector<void*> allocs_template;  // freed on re-template / destroy
+  std::vector<void*> allocs_frame;     // frame-size buffers (created with the stream)
+  std::vector<void*> allocs_k2;        // grows with K2
+  uint64_t bytes_template = 0, bytes_frame = 0, bytes_k2 = 0;
+  // stage timers
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  double stage_ms[TT_NSTAGES] = {0, 0, 0, 0, 0, 0};
+  int64_t stage_n[TT_NSTAGES] = {0, 0, 0, 0, 0, 0};
+};
+
+// ---- launchers (each queues kernels on st and returns hipGetLastError()) --------------------
+struct Intr {
+  int W, H;
+  double fx, fy, cx, cy;
+};
+
+hipError_t launch_fps(const DevState& d, int M, int N, int* err_flag, hipStream_t st);
+hipError_t launch_template_tables(DevState& d, hipStream_t st, double* sbar_out, double* sarap_out);
+hipError_t launch_knn(const DevState& d, double sbar, hipStream_t st);
+
+hipError_t launch_normal_map(const DevState& d, const Intr& K, hipStream_t st);
+hipError_t launch_match(const DevState& d, int K2, int max_hamming, hipStream_t st);
+hipError_t launch_preselect(const DevState& d, int R, int iters, double H, uint64_t seed, int64_t frame,
+                            hipStream_t st);
+
+hipError_t launch_lm_begin(DevState& d, double lambda0, hipStream_t st);
+hipError_t launch_lm_rows(DevState& d, const tt_params& P, const Intr& K, int it, hipStream_t st);
+hipError_t launch_lm_arap(DevState& d, const tt_params& P, hipStream_t st);
+hipError_t launch_lm_data(DevState& d, hipStream_t st);
+hipError_t launch_lm_damp(DevState& d, hipStream_t st);
+hipError_t launch_lm_finish(DevState& d, const tt_params& P, const Intr& K, hipStream_t st);
+hipError_t launch_deform_out(const DevState& d, float* out_xyz, float* out_dq, hipStream_t st);
+
+hipError_t launch_cholesky_solve(DevState& d, int epoch, hipStream_t st);

@@ -1,0 +1,917 @@
+// tt_lm.hip -- one Levenberg-Marquardt iteration of Eq. (1) on the device (Sec. 2):
+//
+//   k_node_prep        node positions p_i^t = W_i(p_i^0)
+//   k_data_rows        per template point: dual-quaternion blend, nearest-pixel re-projection
+//                      (FP64 index math), point-to-plane residual along the target normal, Tukey
+//                      weight and the weighted 1x24 Jacobian row; per template feature: the
+//                      feature residual, its weight (pre-selected: w*, else the 1 - d/(5H) ramp,
+//                      Sec. 2.1) and the weighted 3x24 rows
+//   k_lm_scalars       dynamic ARAP weight (Sec. 2): summed data weights over summed pair weights
+//   k_arap_assemble    dense ARAP (Sec. 2.2, Eqs. (5)-(6)) over all control-point pairs: one
+//                      workgroup per node row writes the row's off-diagonal 6x6 blocks once and
+//                      reduces its diagonal block and gradient in LDS
+//   k_data_assemble    adds the ICP and feature rows into the node-pair blocks through the
+//                      static block-CSR (deterministic, no atomics)
+//   k_damp             Marquardt damping A + lambda diag(A) + eps I and the right-hand side
+//   (Cholesky + solves: tt_chol.hip)
+//   k_update           candidate warps W' = Delta(delta_i) W_i (node-centred increments)
+//   k_cost_data/arap   FP64 cost of the candidate with correspondences and weights frozen
+//   k_accept           accept if the cost drops (lambda / 10), else reject (lambda * 10)
+//
+// Residual rows (all weights frozen within an iteration):
+//   ICP     sqrt(omega_j) n . (v_j - q)
+//   feature sqrt(w_ORB w_k) (DQB(o1_k) - o2_k)
+//   ARAP    per ordered pair (a, b): sqrt(w) (|b| - |e0|), sqrt(w w_angle) (a_hat - b_hat),
+//           sqrt(w w_rotation) (qr_a - qr_b), with w = w_ARAP w_ab, e0 = p_b^0 - p_a^0,
+//           a = R_a e0, b = p_b^t - p_a^t (the angle of Eq. (6) in chordal form |a_hat - b_hat|).
+#include <float.h>
+
+#include "tt_internal.h"
+#include "tt_math.h"
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kRowThreads = 256;
+
+struct Parts {
+  int pts, feat, arap, cdata, carap;  // offsets into the partial-sum buffer
+  int nbp, nbf;                       // blocks over points / features
+};
+
+__host__ __device__ inline Parts parts_of(int M, int K1, int N) {
+  Parts p;
+  p.nbp = (M + kRowThreads - 1) / kRowThreads;
+  p.nbf = (K1 + kRowThreads - 1) / kRowThreads;
+  p.pts = 0;                      // 2 per point block: sum omega, sum omega r^2
+  p.feat = p.pts + 2 * p.nbp;     // 2 per feature block: sum w, sum w_orb w |e|^2
+  p.arap = p.feat + 2 * p.nbf;    // 1 per node row
+  p.cdata = p.arap + N;           // 1 per point/feature block of the candidate
+  p.carap = p.cdata + p.nbp + p.nbf;
+  return p;
+}
+
+template <int BS>
+__device__ double block_sum_d(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = BS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void load_dq(const float* W, int i, float* q) {
+  const float4* p = reinterpret_cast<const float4*>(W + 8 * i);
+  float4 a = p[0], b = p[1];
+  q[0] = a.x; q[1] = a.y; q[2] = a.z; q[3] = a.w;
+  q[4] = b.x; q[5] = b.y; q[6] = b.z; q[7] = b.w;
+}
+
+// h(q, y) = G(q)^T y = -u y_w + w y_v + u x y_v
+__device__ __forceinline__ f3 gT(const float* q, const float* y) {
+  f3 u = mk3(q[1], q[2], q[3]);
+  f3 yv = mk3(y[1], y[2], y[3]);
+  return (-y[0]) * u + q[0] * yv + cross(u, yv);
+}
+
+// y (1x8) times dW/dxi (8x6) of node (q, p): omega part (G(qr)^T y_r + G(qd)^T y_d
+// - p x G(qr)^T y_d) / 2, tau part G(qr)^T y_d / 2.
+__device__ __forceinline__ void row_times_Q(const float* y, const float* q, f3 p, float coef, float* out6) {
+  f3 hr = gT(q, y);
+  f3 hd = gT(q + 4, y + 4);
+  f3 hrd = gT(q, y + 4);
+  f3 om = hr + hd - cross(p, hrd);
+  float k = 0.5f * coef;
+  out6[0] = k * om.x; out6[1] = k * om.y; out6[2] = k * om.z;
+  out6[3] = k * hrd.x; out6[4] = k * hrd.y; out6[5] = k * hrd.z;
+}
+
+// ---------------------------------------------------------------------------------------------
+
+__global__ void k_node_prep(const float* __restrict__ W, const float4* __restrict__ c0, int N,
+                            float4* __restrict__ pos, float4* __restrict__ ndisp) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float q[8];
+  load_dq(W, i, q);
+  float4 c = c0[i];
+  f3 dp = dq_disp(q, mk3(c.x, c.y, c.z));
+  pos[i] = make_float4(c.x + dp.x, c.y + dp.y, c.z + dp.z, 0.0f);
+  ndisp[i] = make_float4(dp.x, dp.y, dp.z, 0.0f);
+}
+
+struct RowArgs {
+  // template points
+  const float *px, *py, *pz;
+  const int4* knn;
+  const float4* alpha;
+  int M;
+  // template features
+  const float *fpx, *fpy, *fpz;
+  const int4* fknn;
+  const float4* falpha;
+  int K1;
+  const float4* o2;
+  const uint8_t* presel;
+  const double* wstar;
+  // warps
+  const float* W;
+  const float4* pos;
+  // target
+  const float4* nmap;
+  int Wd, Hd;
+  double fx, fy, cx, cy;
+  float tukey_c, w_orb, H;
+  // outputs
+  int* corr;
+  float *rres, *omega, *jac, *wres;
+  float *orbw, *jacF, *wresF;
+  double* part;
+  Parts P;
+};
+
+// Nearest-pixel re-projection in FP64 of v = p + d: u = floor(fx x / z + cx + 1/2). Returns
+// the pixel or -1.
+__device__ __forceinline__ int project_pixel(f3 p, f3 d, const RowArgs& a) {
+#pragma clang fp contract(off)
+  double x = (double)p.x + (double)d.x, y = (double)p.y + (double)d.y, z = (double)p.z + (double)d.z;
+  if (!(z > 0.0)) return -1;
+  double uf = a.fx * x / z + a.cx;
+  double vf = a.fy * y / z + a.cy;
+  double ur = floor(uf + 0.5), vr = floor(vf + 0.5);
+  if (!(ur >= 0.0 && ur < (double)a.Wd && vr >= 0.0 && vr < (double)a.Hd)) return -1;
+  return (int)vr * a.Wd + (int)ur;
+}
+
+// n . (v - q) for v = p + d and the target point q of pixel pix (depth z): p - q is formed in
+// FP64 so that only the small residual is rounded to FP32.
+__device__ __forceinline__ float plane_residual(f3 p, f3 d, int pix, float4 nm, const RowArgs& a) {
+  int vv = pix / a.Wd, uu = pix - vv * a.Wd;
+  double z = (double)nm.w;
+  double qx = ((double)uu - a.cx) / a.fx * z;
+  double qy = ((double)vv - a.cy) / a.fy * z;
+  f3 pq = mk3((float)((double)p.x - qx), (float)((double)p.y - qy), (float)((double)p.z - z));
+  return dot(mk3(nm.x, nm.y, nm.z), d + pq);
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_data_rows(RowArgs a, int it) {
+  __shared__ double sh[kRowThreads];
+  const int tid = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  if ((int)blockIdx.x < a.P.nbp) {
+    // ---- ICP rows of template points
+    int j = blockIdx.x * kRowThreads + tid;
+    if (j < a.M) {
+      int4 nb = a.knn[j];
+      float4 al = a.alpha[j];
+      float q0[8], q1[8], q2[8], q3[8];
+      load_dq(a.W, nb.x, q0);
+      load_dq(a.W, nb.y, q1);
+      load_dq(a.W, nb.z, q2);
+      load_dq(a.W, nb.w, q3);
+      const float alv[4] = {al.x, al.y, al.z, al.w};
+      float b[8], sg[4];
+      dq_blend4(q0, q1, q2, q3, alv, b, sg);
+      f3 p = mk3(a.px[j], a.py[j], a.pz[j]);
+      f3 dp = dq_disp(b, p);
+      int pix = project_pixel(p, dp, a);
+      float r = 0.0f, om = 0.0f;
+      f3 n = mk3(0.f, 0.f, 0.f);
+      if (pix >= 0) {
+        float4 nm = a.nmap[pix];
+        if (nm.x != 0.0f || nm.y != 0.0f || nm.z != 0.0f) {
+          n = mk3(nm.x, nm.y, nm.z);
+          r = plane_residual(p, dp, pix, nm, a);
+          if (fabsf(r) < a.tukey_c) {
+            float t = r / a.tukey_c;
+            om = (1.0f - t * t) * (1.0f - t * t);
+          }
+        } else {
+          pix = -1;
+        }
+      }
+      a.corr[j] = pix;
+      a.rres[j] = r;
+      a.omega[j] = om;
+      float sw = sqrtf(om);
+      a.wres[j] = sw * r;
+      float J[24];
+#pragma unroll
+      for (int c = 0; c < 24; c++) J[c] = 0.0f;
+      if (om > 0.0f) {
+        float Jb[24];
+        dq_apply_jac(b, p, Jb);
+        float y[8];
+#pragma unroll
+        for (int c = 0; c < 8; c++) y[c] = n.x * Jb[c] + n.y * Jb[8 + c] + n.z * Jb[16 + c];
+        const int nodes[4] = {nb.x, nb.y, nb.z, nb.w};
+        const float* qs[4] = {q0, q1, q2, q3};
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+          float4 ps = a.pos[nodes[s]];
+          row_times_Q(y, qs[s], mk3(ps.x, ps.y, ps.z), sw * sg[s] * alv[s], J + 6 * s);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 24; c++) a.jac[(size_t)c * a.M + j] = J[c];
+      s0 = (double)om;
+      s1 = (double)om * (double)r * (double)r;
+    }
+    double t0 = block_sum_d<kRowThreads>(s0, sh);
+    double t1 = block_sum_d<kRowThreads>(s1, sh);
+    if (tid == 0) {
+      a.part[a.P.pts + 2 * blockIdx.x] = t0;
+      a.part[a.P.pts + 2 * blockIdx.x + 1] = t1;
+    }
+  } else {
+    // ---- feature rows of template features
+    int fb = blockIdx.x - a.P.nbp;
+    int k = fb * kRowThreads + tid;
+    if (k < a.K1) {
+      float4 o = a.o2[k];
+      float w = 0.0f;
+      float e[3] = {0.f, 0.f, 0.f};
+      float J[72];
+#pragma unroll
+      for (int c = 0; c < 72; c++) J[c] = 0.0f;
+      if (o.w > 0.0f) {
+        int4 nb = a.fknn[k];
+        float4 al = a.falpha[k];
+        float q0[8], q1[8], q2[8], q3[8];
+        load_dq(a.W, nb.x, q0);
+        load_dq(a.W, nb.y, q1);
+        load_dq(a.W, nb.z, q2);
+        load_dq(a.W, nb.w, q3);
+        const float alv[4] = {al.x, al.y, al.z, al.w};
+        float b[8], sg[4];
+        dq_blend4(q0, q1, q2, q3, alv, b, sg);
+        f3 p = mk3(a.fpx[k], a.fpy[k], a.fpz[k]);
+        f3 d = dq_disp(b, p) + (p - mk3(o.x, o.y, o.z));  // DQB(o1) - o2
+        if (a.presel[k]) {
+          w = (float)a.wstar[k];
+        } else {
+          float wk = 1.0f - len(d) / (5.0f * a.H);
+          w = fminf(fmaxf(wk, 0.0f), 1.0f);
+        }
+        e[0] = d.x; e[1] = d.y; e[2] = d.z;
+        if (w > 0.0f) {
+          float sw = sqrtf(a.w_orb * w);
+          float Jb[24];
+          dq_apply_jac(b, p, Jb);
+          const int nodes[4] = {nb.x, nb.y, nb.z, nb.w};
+          const float* qs[4] = {q0, q1, q2, q3};
+#pragma unroll
+          for (int rr = 0; rr < 3; rr++) {
+#pragma unroll
+            for (int s = 0; s < 4; s++) {
+              float4 ps = a.pos[nodes[s]];
+              row_times_Q(Jb + 8 * rr, qs[s], mk3(ps.x, ps.y, ps.z), sw * sg[s] * alv[s], J + rr * 24 + 6 * s);
+            }
+          }
+        }
+      }
+      float sw = sqrtf(a.w_orb * w);
+      a.orbw[k] = w;
+#pragma unroll
+      for (int c = 0; c < 3; c++) a.wresF[(size_t)c * a.K1 + k] = sw * e[c];
+#pragma unroll
+      for (int c = 0; c < 72; c++) a.jacF[(size_t)c * a.K1 + k] = J[c];
+      s0 = (double)w;
+      s1 = (double)a.w_orb * (double)w * ((double)e[0] * e[0] + (double)e[1] * e[1] + (double)e[2] * e[2]);
+    }
+    double t0 = block_sum_d<kRowThreads>(s0, sh);
+    double t1 = block_sum_d<kRowThreads>(s1, sh);
+    if (tid == 0) {
+      a.part[a.P.feat + 2 * fb] = t0;
+      a.part[a.P.feat + 2 * fb + 1] = t1;
+    }
+  }
+}
+
+// Dynamic ARAP weight, once per frame (iteration 0): lambda_arap times the summed ICP (Tukey)
+// and feature (w_ORB w_k) weights over the summed pair weights.
+__global__ __launch_bounds__(256) void k_lm_scalars(const double* __restrict__ part, Parts P, double lambda_arap,
+                                                    double w_orb, double s_arap, LMScalars* sc) {
+  __shared__ double sh[256];
+  double so = 0.0, sw = 0.0;
+  for (int b = threadIdx.x; b < P.nbp; b += 256) so += part[P.pts + 2 * b];
+  for (int b = threadIdx.x; b < P.nbf; b += 256) sw += part[P.feat + 2 * b];
+  so = block_sum_d<256>(so, sh);
+  sw = block_sum_d<256>(sw, sh);
+  if (threadIdx.x == 0) {
+    sc->sum_omega = so;
+    sc->sum_orbw = sw;
+    sc->w_arap = (s_arap > 0.0) ? lambda_arap * (so + w_orb * sw) / s_arap : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Dense ARAP pair block. For the unordered pair (i, j) both orderings enter; with
+// W2 = w_ARAP w_ij, a_hat = R_i e0 / |.|, ap_hat = R_j (-e0) / |.|, b_hat = b / |b|,
+// Pb = (I - b_hat b_hat^T) / |b|, Sa = [a_hat]x, Sb = [ap_hat]x:
+//   diag (i,i):  omega-omega  W2 wg (I - a a^T) + W2 wr |q_i|^2 I / 2
+//                omega-tau    W2 wg Sa Pb
+//                tau-tau      2 W2 (b b^T + wg Pb^2)
+//   g_i:         omega        -W2 wg (a_hat x b_hat) + W2 wr G(q_i)^T (q_i - q_j)
+//                tau          -2 W2 (|b| - |e0|) b_hat + W2 wg Pb (a_hat - ap_hat)
+//   off (i,j):   omega-omega  -W2 wr G(q_i)^T G(q_j) / 2
+//                omega-tau    -W2 wg Sa Pb
+//                tau-omega    W2 wg Pb Sb
+//                tau-tau      -2 W2 (b b^T + wg Pb^2)
+//   cost:        2 W2 (|b| - |e0|)^2 + W2 wg (|a_hat - b_hat|^2 + |ap_hat + b_hat|^2)
+//                + 2 W2 wr |q_i - q_j|^2
+struct PairGeom {
+  float W2;
+  bool geo;
+  f3 ah, aph, bh;
+  float lb, rlen;
+};
+
+// b = p_j - p_i is formed as e0 + (d_j - d_i) from the rest offset and the node displacements,
+// and |b| - |e0| as (2 e0 . D + D . D) / (|b| + |e0|), D = d_j - d_i, so that small stretches
+// keep their relative precision.
+__device__ __forceinline__ PairGeom pair_geom(float4 ci, float4 cj, float4 di, float4 dj, const float* qi,
+                                              const float* qj, float w_arap, float inv8s2) {
+  PairGeom g;
+  f3 e0 = mk3(cj.x - ci.x, cj.y - ci.y, cj.z - ci.z);
+  f3 D = mk3(dj.x - di.x, dj.y - di.y, dj.z - di.z);
+  f3 bv = e0 + D;
+  float e2 = dot(e0, e0);
+  g.W2 = w_arap * expf(-e2 * inv8s2);
+  f3 av = q_rotate(qi, e0);
+  f3 avp = q_rotate(qj, (-1.0f) * e0);
+  float la = len(av), lap = len(avp), lb = len(bv), l0 = sqrtf(e2);
+  g.geo = (la > 0.0f && lap > 0.0f && lb > 0.0f);
+  g.lb = lb;
+  g.rlen = g.geo ? (2.0f * dot(e0, D) + dot(D, D)) / (lb + l0) : 0.0f;
+  g.ah = g.geo ? (1.0f / la) * av : mk3(0.f, 0.f, 0.f);
+  g.aph = g.geo ? (1.0f / lap) * avp : mk3(0.f, 0.f, 0.f);
+  g.bh = g.geo ? (1.0f / lb) * bv : mk3(0.f, 0.f, 0.f);
+  return g;
+}
+
+__device__ __forceinline__ double pair_cost(const PairGeom& g, const float* qi, const float* qj, float wg, float wr) {
+  double c = 0.0;
+  if (g.geo) {
+    f3 d1 = g.ah - g.bh, d2 = g.aph + g.bh;
+    c += 2.0 * (double)g.W2 * (double)g.rlen * (double)g.rlen;
+    c += (double)g.W2 * (double)wg * ((double)dot(d1, d1) + (double)dot(d2, d2));
+  }
+  double dq = 0.0;
+#pragma unroll
+  for (int t = 0; t < 4; t++) dq += (double)(qi[t] - qj[t]) * (double)(qi[t] - qj[t]);
+  c += 2.0 * (double)g.W2 * (double)wr * dq;
+  return c;
+}
+
+// [s]x M for 3x3 M (row-major)
+__device__ __forceinline__ void skew_mul(f3 s, const float* M, float* out) {
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    float m0 = M[0 * 3 + c], m1 = M[1 * 3 + c], m2 = M[2 * 3 + c];
+    out[0 * 3 + c] = -s.z * m1 + s.y * m2;
+    out[1 * 3 + c] = s.z * m0 - s.x * m2;
+    out[2 * 3 + c] = -s.y * m0 + s.x * m1;
+  }
+}
+
+struct ArapArgs {
+  const float4* c0;
+  const float4* ndisp;
+  const float* W;
+  int N, n, ld;
+  float wg, wr, inv8s2;
+  const LMScalars* sc;
+  float* A;
+  float* g;
+  double* part;
+  Parts P;
+};
+
+constexpr int kArapThreads = 256;
+constexpr int kArapAcc = 36 + 6;
+
+__global__ __launch_bounds__(kArapThreads) void k_arap_assemble(ArapArgs a) {
+  __shared__ float red[kArapAcc][kArapThreads];
+  __shared__ double shd[kArapThreads];
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const float w_arap = (float)a.sc->w_arap;
+  float qi[8];
+  load_dq(a.W, i, qi);
+  const float4 ci = a.c0[i], pi = a.ndisp[i];
+  float D[36], gi[6];
+#pragma unroll
+  for (int t = 0; t < 36; t++) D[t] = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 6; t++) gi[t] = 0.0f;
+  double cost = 0.0;
+  float Gi[12];
+  gmat(qi, Gi);
+  const float qi2 = qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3];
+  for (int j = tid; j < a.N; j += kArapThreads) {
+    if (j == i) continue;
+    float qj[8];
+    load_dq(a.W, j, qj);
+    const float4 cj = a.c0[j], pj = a.ndisp[j];
+    PairGeom pg = pair_geom(ci, cj, pi, pj, qi, qj, w_arap, a.inv8s2);
+    const float W2 = pg.W2, wg = a.wg, wr = a.wr;
+    if (j > i) cost += pair_cost(pg, qi, qj, wg, wr);
+    float Gj[12];
+    gmat(qj, Gj);
+    // rotation part
+    float dqv[4] = {qi[0] - qj[0], qi[1] - qj[1], qi[2] - qj[2], qi[3] - qj[3]};
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      D[c * 6 + c] += 0.5f * W2 * wr * qi2;
+      gi[c] += W2 * wr * (Gi[0 * 3 + c] * dqv[0] + Gi[1 * 3 + c] * dqv[1] + Gi[2 * 3 + c] * dqv[2] + Gi[3 * 3 + c] * dqv[3]);
+    }
+    float B[36];
+#pragma unroll
+    for (int t = 0; t < 36; t++) B[t] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+      for (int c = 0; c < 3; c++)
+        B[r * 6 + c] = -0.5f * W2 * wr *
+                       (Gi[0 * 3 + r] * Gj[0 * 3 + c] + Gi[1 * 3 + r] * Gj[1 * 3 + c] + Gi[2 * 3 + r] * Gj[2 * 3 + c] +
+                        Gi[3 * 3 + r] * Gj[3 * 3 + c]);
+    if (pg.geo) {
+      const f3 ah = pg.ah, aph = pg.aph, bh = pg.bh;
+      const float ilb = 1.0f / pg.lb;
+      const float bb[3] = {bh.x, bh.y, bh.z}, aa[3] = {ah.x, ah.y, ah.z};
+      float Pb[9], Pb2[9];
+#pragma unroll
+      for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          float P = ((r == c) ? 1.0f : 0.0f) - bb[r] * bb[c];
+          Pb[r * 3 + c] = P * ilb;
+          Pb2[r * 3 + c] = P * ilb * ilb;
+        }
+      float SaPb[9], SbPb[9], PbSb[9];
+      skew_mul(ah, Pb, SaPb);   // Sa Pb
+      skew_mul(aph, Pb, SbPb);  // Sb Pb ; Pb Sb = (Sb^T Pb)^T = -(Sb Pb)^T
+#pragma unroll
+      for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) PbSb[r * 3 + c] = -SbPb[c * 3 + r];
+      // diagonal block
+#pragma unroll
+      for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          float I = (r == c) ? 1.0f : 0.0f;
+          D[r * 6 + c] += W2 * wg * (I - aa[r] * aa[c]);
+          float wt = W2 * wg * SaPb[r * 3 + c];
+          D[r * 6 + 3 + c] += wt;
+          D[(3 + c) * 6 + r] += wt;
+          D[(3 + r) * 6 + 3 + c] += 2.0f * W2 * (bb[r] * bb[c] + wg * Pb2[r * 3 + c]);
+        }
+      // gradient
+      f3 axb = cross(ah, bh);
+      f3 da = ah - aph;
+      gi[0] += -W2 * wg * axb.x;
+      gi[1] += -W2 * wg * axb.y;
+      gi[2] += -W2 * wg * axb.z;
+#pragma unroll
+      for (int r = 0; r < 3; r++)
+        gi[3 + r] += -2.0f * W2 * pg.rlen * bb[r] +
+                     W2 * wg * (Pb[r * 3 + 0] * da.x + Pb[r * 3 + 1] * da.y + Pb[r * 3 + 2] * da.z);
+      // off-diagonal block (rows i, columns j)
+#pragma unroll
+      for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          B[r * 6 + 3 + c] = -W2 * wg * SaPb[r * 3 + c];
+          B[(3 + r) * 6 + c] = W2 * wg * PbSb[r * 3 + c];
+          B[(3 + r) * 6 + 3 + c] = -2.0f * W2 * (bb[r] * bb[c] + wg * Pb2[r * 3 + c]);
+        }
+    }
+    if (j < i) {
+      float* dst = a.A + (size_t)(6 * i) * a.ld + 6 * j;
+#pragma unroll
+      for (int r = 0; r < 6; r++) {
+        float2* d2 = reinterpret_cast<float2*>(dst + (size_t)r * a.ld);
+        d2[0] = make_float2(B[r * 6 + 0], B[r * 6 + 1]);
+        d2[1] = make_float2(B[r * 6 + 2], B[r * 6 + 3]);
+        d2[2] = make_float2(B[r * 6 + 4], B[r * 6 + 5]);
+      }
+    }
+  }
+  // reduce the diagonal block, gradient and cost over the workgroup (fixed tree)
+#pragma unroll
+  for (int t = 0; t < 36; t++) red[t][tid] = D[t];
+#pragma unroll
+  for (int t = 0; t < 6; t++) red[36 + t][tid] = gi[t];
+  shd[tid] = cost;
+  __syncthreads();
+  for (int s = kArapThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+#pragma unroll
+      for (int t = 0; t < kArapAcc; t++) red[t][tid] += red[t][tid + s];
+      shd[tid] += shd[tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid < 36) {
+    int r = tid / 6, c = tid % 6;
+    a.A[(size_t)(6 * i + r) * a.ld + 6 * i + c] = red[tid][0];
+  } else if (tid < 42) {
+    a.g[6 * i + tid - 36] = red[tid][0];
+  }
+  if (tid == 0) a.part[a.P.arap + i] = shd[0];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Data-term blocks through the static block-CSR. Entry = (row index << 5) | (kind << 4) |
+// (slot_a << 2) | slot_b; kind 0 = template point (1 row), 1 = template feature (3 rows).
+// One wavefront per node-pair block (a >= b): sums J_a^T J_b (and J_a^T r on diagonal blocks
+// with slot_a == slot_b), then adds into A and g.
+
+constexpr int kDataThreads = 64;
+
+__global__ __launch_bounds__(kDataThreads) void k_data_assemble(const int2* __restrict__ blk_ab,
+                                                                const int* __restrict__ blk_ptr,
+                                                                const uint32_t* __restrict__ ent,
+                                                                const float* __restrict__ jac,
+                                                                const float* __restrict__ wres, int M,
+                                                                const float* __restrict__ jacF,
+                                                                const float* __restrict__ wresF, int K1,
+                                                                float* __restrict__ A, float* __restrict__ g, int ld) {
+  __shared__ float fin[42];
+  const int blk = blockIdx.x;
+  const int2 ab = blk_ab[blk];
+  const int lane = threadIdx.x;
+  float S[36], G[6];
+#pragma unroll
+  for (int t = 0; t < 36; t++) S[t] = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 6; t++) G[t] = 0.0f;
+  const int e0 = blk_ptr[blk], e1 = blk_ptr[blk + 1];
+  for (int e = e0 + lane; e < e1; e += kDataThreads) {
+    uint32_t en = ent[e];
+    int sb = en & 3, sa = (en >> 2) & 3, kind = (en >> 4) & 1;
+    int idx = (int)(en >> 5);
+    if (kind == 0) {
+      float Ja[6], Jb[6];
+#pragma unroll
+      for (int c = 0; c < 6; c++) {
+        Ja[c] = jac[(size_t)(6 * sa + c) * M + idx];
+        Jb[c] = jac[(size_t)(6 * sb + c) * M + idx];
+      }
+#pragma unroll
+      for (int r = 0; r < 6; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) S[r * 6 + c] += Ja[r] * Jb[c];
+      if (sa == sb) {
+        float rr = wres[idx];
+#pragma unroll
+        for (int r = 0; r < 6; r++) G[r] += Ja[r] * rr;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        float Ja[6], Jb[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+          Ja[c] = jacF[(size_t)(q * 24 + 6 * sa + c) * K1 + idx];
+          Jb[c] = jacF[(size_t)(q * 24 + 6 * sb + c) * K1 + idx];
+        }
+#pragma unroll
+        for (int r = 0; r < 6; r++)
+#pragma unroll
+          for (int c = 0; c < 6; c++) S[r * 6 + c] += Ja[r] * Jb[c];
+        if (sa == sb) {
+          float rr = wresF[(size_t)q * K1 + idx];
+#pragma unroll
+          for (int r = 0; r < 6; r++) G[r] += Ja[r] * rr;
+        }
+      }
+    }
+  }
+  // wavefront butterfly reduction (fixed pattern, deterministic)
+#pragma unroll
+  for (int t = 0; t < 36; t++)
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) S[t] += __shfl_xor(S[t], off, kWave);
+#pragma unroll
+  for (int t = 0; t < 6; t++)
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) G[t] += __shfl_xor(G[t], off, kWave);
+  if (lane == 0) {
+#pragma unroll
+    for (int t = 0; t < 36; t++) fin[t] = S[t];
+#pragma unroll
+    for (int t = 0; t < 6; t++) fin[36 + t] = G[t];
+  }
+  __syncthreads();
+  if (lane < 36) {
+    int r = lane / 6, c = lane % 6;
+    A[(size_t)(6 * ab.x + r) * ld + 6 * ab.y + c] += fin[lane];
+  } else if (lane < 42 && ab.x == ab.y) {
+    g[6 * ab.x + lane - 36] += fin[lane];
+  }
+}
+
+// Damping A_kk (1 + lambda) + eps, the symmetric diagonal equilibration d_k = 1/sqrt(that) (the
+// factorisation scales every entry by d_i d_j when it first reads it, so it factors D A D) and the
+// equilibrated right-hand side -d_k g_k. Also totals the cost of the iterate (FP64, fixed order).
+__global__ __launch_bounds__(1024) void k_damp(float* __restrict__ A, const float* __restrict__ g, int n, int npad,
+                                               int ld, float* __restrict__ dscale, const double* __restrict__ part,
+                                               Parts P, LMScalars* sc) {
+  __shared__ float shm[1024];
+  __shared__ double shd[1024];
+  float m = 0.0f;
+  for (int k = threadIdx.x; k < n; k += 1024) m = fmaxf(m, A[(size_t)k * ld + k]);
+  shm[threadIdx.x] = m;
+  double e = 0.0;
+  for (int b = threadIdx.x; b < P.nbp; b += 1024) e += part[P.pts + 2 * b + 1];
+  for (int b = threadIdx.x; b < P.nbf; b += 1024) e += part[P.feat + 2 * b + 1];
+  for (int b = threadIdx.x; b < P.cdata - P.arap; b += 1024) e += part[P.arap + b];
+  shd[threadIdx.x] = e;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      shm[threadIdx.x] = fmaxf(shm[threadIdx.x], shm[threadIdx.x + s]);
+      shd[threadIdx.x] += shd[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  const float eps = 1e-12f * shm[0];
+  const float lam = (float)sc->lambda;
+  for (int k = threadIdx.x; k < npad; k += 1024) {
+    float d = 1.0f;
+    if (k < n) {
+      float* dk = A + (size_t)k * ld + k;
+      const float a = *dk * (1.0f + lam) + eps;
+      *dk = a;
+      d = (a > 0.0f) ? 1.0f / sqrtf(a) : 1.0f;
+    }
+    dscale[k] = d;
+    A[(size_t)npad * ld + k] = (k < n) ? -g[k] * d : 0.0f;
+  }
+  if (threadIdx.x == 0) {
+    sc->e_old = shd[0];
+    sc->eps = (double)eps;
+    sc->chol_fail = 0;
+  }
+}
+
+// Candidate warps from the solution D y of (A + damping) x = -g (y solves the equilibrated system).
+__global__ void k_update(const float* __restrict__ W, const float4* __restrict__ pos, const float4* __restrict__ c0,
+                         const float* __restrict__ x, const float* __restrict__ dscale, int N, float* __restrict__ Wc,
+                         float4* __restrict__ posc, float4* __restrict__ ndispc) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float q[8], out[8];
+  load_dq(W, i, q);
+  float4 p = pos[i];
+  float xi[6];
+#pragma unroll
+  for (int c = 0; c < 6; c++) xi[c] = x[6 * i + c] * dscale[6 * i + c];
+  dq_increment(q, mk3(p.x, p.y, p.z), xi, out);
+  float4* d = reinterpret_cast<float4*>(Wc + 8 * i);
+  d[0] = make_float4(out[0], out[1], out[2], out[3]);
+  d[1] = make_float4(out[4], out[5], out[6], out[7]);
+  float4 c = c0[i];
+  f3 dc = dq_disp(out, mk3(c.x, c.y, c.z));
+  posc[i] = make_float4(c.x + dc.x, c.y + dc.y, c.z + dc.z, 0.0f);
+  ndispc[i] = make_float4(dc.x, dc.y, dc.z, 0.0f);
+}
+
+// FP64 cost of the candidate with the correspondences, Tukey weights and feature weights of the
+// iterate (points: omega (n . (v' - q))^2; features: w_ORB w |DQB(o1) - o2|^2).
+__global__ __launch_bounds__(kRowThreads) void k_cost_data(RowArgs a, const float* __restrict__ Wc) {
+  __shared__ double sh[kRowThreads];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  if ((int)blockIdx.x < a.P.nbp) {
+    int j = blockIdx.x * kRowThreads + tid;
+    if (j < a.M) {
+      int pix = a.corr[j];
+      float om = a.omega[j];
+      if (pix >= 0 && om > 0.0f) {
+        int4 nb = a.knn[j];
+        float4 al = a.alpha[j];
+        float q0[8], q1[8], q2[8], q3[8];
+        load_dq(Wc, nb.x, q0);
+        load_dq(Wc, nb.y, q1);
+        load_dq(Wc, nb.z, q2);
+        load_dq(Wc, nb.w, q3);
+        const float alv[4] = {al.x, al.y, al.z, al.w};
+        float b[8], sg[4];
+        dq_blend4(q0, q1, q2, q3, alv, b, sg);
+        f3 p = mk3(a.px[j], a.py[j], a.pz[j]);
+        float r = plane_residual(p, dq_disp(b, p), pix, a.nmap[pix], a);
+        s = (double)om * (double)r * (double)r;
+      }
+    }
+  } else {
+    int k = (blockIdx.x - a.P.nbp) * kRowThreads + tid;
+    if (k < a.K1) {
+      float w = a.orbw[k];
+      float4 o = a.o2[k];
+      if (o.w > 0.0f && w > 0.0f) {
+        int4 nb = a.fknn[k];
+        float4 al = a.falpha[k];
+        float q0[8], q1[8], q2[8], q3[8];
+        load_dq(Wc, nb.x, q0);
+        load_dq(Wc, nb.y, q1);
+        load_dq(Wc, nb.z, q2);
+        load_dq(Wc, nb.w, q3);
+        const float alv[4] = {al.x, al.y, al.z, al.w};
+        float b[8], sg[4];
+        dq_blend4(q0, q1, q2, q3, alv, b, sg);
+        f3 p = mk3(a.fpx[k], a.fpy[k], a.fpz[k]);
+        f3 d = dq_disp(b, p) + (p - mk3(o.x, o.y, o.z));
+        s = (double)a.w_orb * (double)w * ((double)d.x * d.x + (double)d.y * d.y + (double)d.z * d.z);
+      }
+    }
+  }
+  double t = block_sum_d<kRowThreads>(s, sh);
+  if (tid == 0) a.part[a.P.cdata + blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kArapThreads) void k_cost_arap(ArapArgs a, const float* __restrict__ Wc,
+                                                            const float4* __restrict__ ndispc) {
+  __shared__ double sh[kArapThreads];
+  const int i = blockIdx.x;
+  const float w_arap = (float)a.sc->w_arap;
+  float qi[8];
+  load_dq(Wc, i, qi);
+  const float4 ci = a.c0[i], pi = ndispc[i];
+  double cost = 0.0;
+  for (int j = i + 1 + threadIdx.x; j < a.N; j += kArapThreads) {
+    float qj[8];
+    load_dq(Wc, j, qj);
+    PairGeom pg = pair_geom(ci, a.c0[j], pi, ndispc[j], qi, qj, w_arap, a.inv8s2);
+    cost += pair_cost(pg, qi, qj, a.wg, a.wr);
+  }
+  double t = block_sum_d<kArapThreads>(cost, sh);
+  if (threadIdx.x == 0) a.part[a.P.carap + i] = t;
+}
+
+// Accept / reject on the device: accept iff the factorisation succeeded and the candidate's
+// cost is lower. lambda / 10 (>= 1e-10) on accept, * 10 (<= 1e10) on reject.
+__global__ __launch_bounds__(256) void k_accept(const double* __restrict__ part, Parts P, int N, LMScalars* sc,
+                                                float* __restrict__ W, const float* __restrict__ Wc,
+                                                float4* __restrict__ pos, const float4* __restrict__ posc,
+                                                float4* __restrict__ ndisp, const float4* __restrict__ ndispc,
+                                                double* log_old, double* log_new, double* log_lambda,
+                                                int* log_acc) {
+  __shared__ double sh[256];
+  __shared__ int acc_s;
+  double e = 0.0;
+  for (int b = threadIdx.x; b < P.nbp + P.nbf; b += 256) e += part[P.cdata + b];
+  for (int b = threadIdx.x; b < N; b += 256) e += part[P.carap + b];
+  e = block_sum_d<256>(e, sh);
+  if (threadIdx.x == 0) {
+    int it = sc->it;
+    bool fail = sc->chol_fail != 0;
+    double e_new = fail ? NAN : e;
+    bool acc = !fail && isfinite(e_new) && e_new < sc->e_old;
+    log_old[it] = sc->e_old;
+    log_new[it] = e_new;
+    log_lambda[it] = sc->lambda;
+    log_acc[it] = acc ? 1 : 0;
+    sc->e_new = e_new;
+    sc->accept = acc ? 1 : 0;
+    sc->lambda = acc ? fmax(sc->lambda / 10.0, 1e-10) : fmin(sc->lambda * 10.0, 1e10);
+    sc->it = it + 1;
+    acc_s = acc ? 1 : 0;
+  }
+  __syncthreads();
+  if (acc_s) {
+    for (int t = threadIdx.x; t < 8 * N; t += 256) W[t] = Wc[t];
+    for (int t = threadIdx.x; t < N; t += 256) {
+      pos[t] = posc[t];
+      ndisp[t] = ndispc[t];
+    }
+  }
+}
+
+__global__ void k_lm_begin(LMScalars* sc, double lambda0) {
+  sc->lambda = lambda0;
+  sc->it = 0;
+  sc->chol_fail = 0;
+  sc->accept = 0;
+}
+
+// Final deformed template (Sec. 2: interpolation of neighbouring control points) and warps.
+__global__ void k_deform_out(const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
+                             const int4* __restrict__ knn, const float4* __restrict__ alpha, int M,
+                             const float* __restrict__ W, int N, float* __restrict__ out_xyz,
+                             float* __restrict__ out_dq) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (out_dq && j < 8 * N) out_dq[j] = W[j];
+  if (!out_xyz || j >= M) return;
+  int4 nb = knn[j];
+  float4 al = alpha[j];
+  float q0[8], q1[8], q2[8], q3[8];
+  load_dq(W, nb.x, q0);
+  load_dq(W, nb.y, q1);
+  load_dq(W, nb.z, q2);
+  load_dq(W, nb.w, q3);
+  const float alv[4] = {al.x, al.y, al.z, al.w};
+  float b[8], sg[4];
+  dq_blend4(q0, q1, q2, q3, alv, b, sg);
+  f3 v = dq_apply(b, mk3(px[j], py[j], pz[j]));
+  out_xyz[3 * j] = v.x;
+  out_xyz[3 * j + 1] = v.y;
+  out_xyz[3 * j + 2] = v.z;
+}
+
+RowArgs row_args(DevState& d, const tt_params& P, const Intr& K) {
+  RowArgs a;
+  a.px = d.px; a.py = d.py; a.pz = d.pz; a.knn = d.knn; a.alpha = d.alpha; a.M = d.M;
+  a.fpx = d.fpx; a.fpy = d.fpy; a.fpz = d.fpz; a.fknn = d.fknn; a.falpha = d.falpha; a.K1 = d.K1;
+  a.o2 = d.o2; a.presel = d.presel; a.wstar = d.wstar;
+  a.W = d.W; a.pos = d.pos; a.nmap = d.nmap; a.Wd = K.W; a.Hd = K.H;
+  a.fx = K.fx; a.fy = K.fy; a.cx = K.cx; a.cy = K.cy;
+  a.tukey_c = (float)P.tukey_c; a.w_orb = (float)P.w_orb; a.H = (float)P.H;
+  a.corr = d.corr; a.rres = d.rres; a.omega = d.omega; a.jac = d.jac; a.wres = d.wres;
+  a.orbw = d.orbw; a.jacF = d.jacF; a.wresF = d.wresF;
+  a.part = d.partial;
+  a.P = parts_of(d.M, d.K1, d.N);
+  return a;
+}
+
+ArapArgs arap_args(DevState& d, const tt_params& P) {
+  ArapArgs a;
+  a.c0 = d.c0; a.ndisp = d.ndisp; a.W = d.W; a.N = d.N; a.n = d.n; a.ld = d.ld;
+  a.wg = (float)P.w_angle; a.wr = (float)P.w_rotation;
+  double sa = 2.0 * d.sbar;
+  a.inv8s2 = (float)(1.0 / (2.0 * sa * sa));
+  a.sc = d.sc; a.A = d.A; a.g = d.g; a.part = d.partial;
+  a.P = parts_of(d.M, d.K1, d.N);
+  return a;
+}
+
+}  // namespace
+
+int partial_count(int M, int K1, int N) {
+  Parts p = parts_of(M, K1, N);
+  return p.carap + N;
+}
+
+hipError_t launch_lm_begin(DevState& d, double lambda0, hipStream_t st) {
+  hipLaunchKernelGGL(k_lm_begin, dim3(1), dim3(1), 0, st, d.sc, lambda0);
+  hipLaunchKernelGGL(k_node_prep, dim3((d.N + 63) / 64), dim3(64), 0, st, d.W, d.c0, d.N, d.pos, d.ndisp);
+  return hipGetLastError();
+}
+
+// Assembly part of an iteration: rows (+ the ARAP weight at iteration 0), dense ARAP blocks,
+// data blocks.
+hipError_t launch_lm_rows(DevState& d, const tt_params& P, const Intr& K, int it, hipStream_t st) {
+  RowArgs ra = row_args(d, P, K);
+  hipLaunchKernelGGL(k_data_rows, dim3(ra.P.nbp + ra.P.nbf), dim3(kRowThreads), 0, st, ra, it);
+  if (it == 0)
+    hipLaunchKernelGGL(k_lm_scalars, dim3(1), dim3(256), 0, st, d.partial, ra.P, P.lambda_arap, P.w_orb, d.s_arap,
+                       d.sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_lm_arap(DevState& d, const tt_params& P, hipStream_t st) {
+  ArapArgs aa = arap_args(d, P);
+  hipLaunchKernelGGL(k_arap_assemble, dim3(d.N), dim3(kArapThreads), 0, st, aa);
+  return hipGetLastError();
+}
+
+hipError_t launch_lm_data(DevState& d, hipStream_t st) {
+  if (d.nblk > 0)
+    hipLaunchKernelGGL(k_data_assemble, dim3(d.nblk), dim3(kDataThreads), 0, st, d.blk_ab, d.blk_ptr, d.blk_ent,
+                       d.jac, d.wres, d.M, d.jacF, d.wresF, d.K1, d.A, d.g, d.ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_lm_damp(DevState& d, hipStream_t st) {
+  Parts p = parts_of(d.M, d.K1, d.N);
+  hipLaunchKernelGGL(k_damp, dim3(1), dim3(1024), 0, st, d.A, d.g, d.n, d.npad, d.ld, d.dscale, d.partial, p,
+                     d.sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_lm_finish(DevState& d, const tt_params& P, const Intr& K, hipStream_t st) {
+  hipLaunchKernelGGL(k_update, dim3((d.N + 63) / 64), dim3(64), 0, st, d.W, d.pos, d.c0, d.x, d.dscale, d.N, d.Wc,
+                     d.posc, d.ndispc);
+  RowArgs ra = row_args(d, P, K);
+  hipLaunchKernelGGL(k_cost_data, dim3(ra.P.nbp + ra.P.nbf), dim3(kRowThreads), 0, st, ra, d.Wc);
+  ArapArgs aa = arap_args(d, P);
+  hipLaunchKernelGGL(k_cost_arap, dim3(d.N), dim3(kArapThreads), 0, st, aa, d.Wc, d.ndispc);
+  hipLaunchKernelGGL(k_accept, dim3(1), dim3(256), 0, st, d.partial, ra.P, d.N, d.sc, d.W, d.Wc, d.pos, d.posc,
+                     d.ndisp, d.ndispc, d.log_cost_old, d.log_cost_new, d.log_lambda, d.log_accept);
+  return hipGetLastError();
+}
+
+hipError_t launch_deform_out(const DevState& d, float* out_xyz, float* out_dq, hipStream_t st) {
+  int n = d.M > 8 * d.N ? d.M : 8 * d.N;
+  hipLaunchKernelGGL(k_deform_out, dim3((n + 255) / 256), dim3(256), 0, st, d.px, d.py, d.pz, d.knn, d.alpha, d.M,
+                     d.W, d.N, out_xyz, out_dq);
+  return hipGetLastError();
+}

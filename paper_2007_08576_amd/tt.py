@@ -1,0 +1,250 @@
+"""Thin ctypes binding of the HIP library (include/tt.h). Argument marshalling only: every step of
+the solve runs in the library's kernels. Raises if the library has not been built.
+
+Names follow the C ABI: default_params, create_stream, Stream.set_template, Stream.track_frame,
+Stream.track_frame_device, Stream.destroy, strerror.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtt.so")
+
+TT_OK, TT_EINVAL, TT_ENOMEM, TT_ESTATE, TT_EDEVICE, TT_EBUSY = 0, -1, -2, -3, -4, -5
+TT_FP32 = 0
+STAGES = ("front", "rows", "arap", "data", "solve", "update")
+
+_lib = None
+
+
+class TTError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class Intrinsics(C.Structure):
+    _fields_ = [("width", C.c_int), ("height", C.c_int), ("fx", C.c_double), ("fy", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("num_control_points", C.c_int), ("knn", C.c_int), ("w_orb", C.c_double),
+                ("w_angle", C.c_double), ("w_rotation", C.c_double), ("lambda_arap", C.c_double),
+                ("tukey_c", C.c_double), ("H", C.c_double), ("ransac_refs", C.c_int),
+                ("ransac_iters", C.c_int), ("lm_iters", C.c_int), ("max_hamming", C.c_int),
+                ("lm_lambda0", C.c_double), ("precision", C.c_int), ("seed", C.c_uint64),
+                ("hbm_budget_bytes", C.c_uint64)]
+
+
+_DEBUG_FIELDS = ("match_idx", "match_dist", "wstar", "preselected", "hyp_k0", "hyp_W", "hyp_nin",
+                 "hyp_kept", "corr0", "r0", "omega0", "orbw0", "A0", "g0", "w_arap", "cost_old",
+                 "cost_new", "lambda_", "accepted")
+
+
+class FrameDebug(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in _DEBUG_FIELDS]
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2007_08576_amd.build")
+        # torch (which owns device memory and streams here) ships its own HIP runtime; loading it
+        # first lets the library bind to that same runtime instead of a second copy
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.tt_default_params.argtypes = [C.POINTER(Params)]
+        L.tt_default_params.restype = None
+        L.tt_create_stream.argtypes = [C.POINTER(Params), C.POINTER(Intrinsics), vp, C.POINTER(vp)]
+        L.tt_set_template.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int]
+        L.tt_track_frame.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp, C.POINTER(FrameDebug)]
+        L.tt_track_frame_device.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
+        L.tt_sync.argtypes = [vp]
+        L.tt_hip_stream.argtypes = [vp]
+        L.tt_hip_stream.restype = vp
+        L.tt_get_template_info.argtypes = [vp] + [vp] * 7
+        L.tt_get_state.argtypes = [vp, vp, vp]
+        L.tt_set_state.argtypes = [vp, vp, C.c_int64]
+        L.tt_device_bytes.argtypes = [vp, C.POINTER(C.c_uint64)]
+        L.tt_set_timing.argtypes = [vp, C.c_int]
+        L.tt_debug_cholesky_solve.argtypes = [C.c_int, vp, vp, vp, C.POINTER(C.c_int)]
+        L.tt_get_timing.argtypes = [vp, vp, vp]
+        L.tt_destroy.argtypes = [vp]
+        L.tt_strerror.argtypes = [C.c_int]
+        L.tt_strerror.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    return lib().tt_strerror(int(code)).decode()
+
+
+def _check(rc, what):
+    if rc != TT_OK:
+        raise TTError(rc, what)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def default_params(**kw):
+    p = Params()
+    lib().tt_default_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def intrinsics(width, height, fx, fy, cx, cy):
+    return Intrinsics(int(width), int(height), float(fx), float(fy), float(cx), float(cy))
+
+
+def _dev_ptr(t):
+    """Device address of a torch tensor (or an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return C.c_void_p(t)
+    return C.c_void_p(t.data_ptr())
+
+
+class Stream:
+    """A tracked surface: library-owned device state behind the C ABI."""
+
+    def __init__(self, params, intr, hip_stream=None):
+        self.params = params
+        self.intr = intr
+        h = C.c_void_p()
+        _check(lib().tt_create_stream(C.byref(params), C.byref(intr),
+                                      None if hip_stream is None else C.c_void_p(hip_stream), C.byref(h)),
+               "tt_create_stream")
+        self.h = h
+        self.M = self.N = self.K1 = 0
+
+    def destroy(self):
+        if self.h:
+            lib().tt_destroy(self.h)
+            self.h = None
+
+    close = destroy
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def set_template(self, pts, feat_xyz, feat_desc):
+        pts = _c(pts, np.float32).reshape(-1, 3)
+        feat_xyz = _c(feat_xyz, np.float32).reshape(-1, 3)
+        feat_desc = _c(feat_desc, np.uint8).reshape(-1, 32)
+        _check(lib().tt_set_template(self.h, _ptr(pts), pts.shape[0], _ptr(feat_xyz), _ptr(feat_desc),
+                                     feat_xyz.shape[0]), "tt_set_template")
+        self.M, self.K1, self.N = pts.shape[0], feat_xyz.shape[0], self.params.num_control_points
+
+    def track_frame(self, depth, feat_xyz, feat_desc, debug=False):
+        """Host-memory frame; returns (vertices [M,3] f64, dq [N,8] f64, debug dict)."""
+        depth = _c(depth, np.float32)
+        feat_xyz = _c(feat_xyz, np.float32).reshape(-1, 3)
+        feat_desc = _c(feat_desc, np.uint8).reshape(-1, 32)
+        verts = np.zeros((self.M, 3))
+        dq = np.zeros((self.N, 8))
+        out = {}
+        dbg = None
+        if debug:
+            K1, M, R, T, n = self.K1, self.M, self.params.ransac_refs, self.params.lm_iters, 6 * self.N
+            out = dict(match_idx=np.zeros(K1, np.int32), match_dist=np.zeros(K1, np.int32),
+                       wstar=np.zeros(K1), preselected=np.zeros(K1, np.uint8),
+                       hyp_k0=np.zeros(R, np.int32), hyp_W=np.zeros(R), hyp_nin=np.zeros(R, np.int32),
+                       hyp_kept=np.zeros(R, np.uint8), corr0=np.zeros(M, np.int32), r0=np.zeros(M),
+                       omega0=np.zeros(M), orbw0=np.zeros(K1), A0=np.zeros((n, n)), g0=np.zeros(n),
+                       w_arap=np.zeros(1), cost_old=np.zeros(T), cost_new=np.zeros(T),
+                       lambda_=np.zeros(T), accepted=np.zeros(T, np.uint8))
+            dbg = FrameDebug(**{k: _ptr(v) for k, v in out.items()})
+        rc = lib().tt_track_frame(self.h, _ptr(depth), _ptr(feat_xyz), _ptr(feat_desc), feat_xyz.shape[0],
+                                  _ptr(verts), _ptr(dq), C.byref(dbg) if dbg is not None else None)
+        _check(rc, "tt_track_frame")
+        if debug:
+            out["w_arap"] = float(out["w_arap"][0])
+            out["lambda"] = out.pop("lambda_")
+        return verts, dq, out
+
+    def track_frame_device(self, depth, feat_xyz, feat_desc, K2, out_vertices=None, out_dq=None):
+        """Device-memory frame (torch tensors or raw addresses); queued, not waited for."""
+        _check(lib().tt_track_frame_device(self.h, _dev_ptr(depth), _dev_ptr(feat_xyz), _dev_ptr(feat_desc),
+                                           int(K2), _dev_ptr(out_vertices), _dev_ptr(out_dq)),
+               "tt_track_frame_device")
+
+    def sync(self):
+        _check(lib().tt_sync(self.h), "tt_sync")
+
+    def hip_stream(self):
+        return lib().tt_hip_stream(self.h)
+
+    def template_info(self):
+        node_idx = np.zeros(self.N, np.int32)
+        knn_pts = np.zeros((self.M, 4), np.int32)
+        alpha_pts = np.zeros((self.M, 4), np.float32)
+        knn_feat = np.zeros((max(self.K1, 1), 4), np.int32)
+        alpha_feat = np.zeros((max(self.K1, 1), 4), np.float32)
+        sbar = np.zeros(1)
+        sarap = np.zeros(1)
+        _check(lib().tt_get_template_info(self.h, _ptr(node_idx), _ptr(knn_pts), _ptr(alpha_pts), _ptr(knn_feat),
+                                          _ptr(alpha_feat), _ptr(sbar), _ptr(sarap)), "tt_get_template_info")
+        return dict(node_idx=node_idx, knn_pts=knn_pts, alpha_pts=alpha_pts, knn_feat=knn_feat[:self.K1],
+                    alpha_feat=alpha_feat[:self.K1], sbar=float(sbar[0]), s_arap=float(sarap[0]))
+
+    def get_state(self):
+        dq = np.zeros((self.N, 8))
+        fr = np.zeros(1, np.int64)
+        _check(lib().tt_get_state(self.h, _ptr(dq), _ptr(fr)), "tt_get_state")
+        return dq, int(fr[0])
+
+    def set_state(self, dq, frame):
+        dq = None if dq is None else _c(dq, np.float64).reshape(self.N, 8)
+        _check(lib().tt_set_state(self.h, _ptr(dq), int(frame)), "tt_set_state")
+
+    def set_timing(self, enable=True):
+        _check(lib().tt_set_timing(self.h, 1 if enable else 0), "tt_set_timing")
+
+    def get_timing(self):
+        """(ms per stage, count per stage) accumulated since the last call; stage order as STAGES."""
+        ms = np.zeros(len(STAGES))
+        n = np.zeros(len(STAGES), np.int64)
+        _check(lib().tt_get_timing(self.h, _ptr(ms), _ptr(n)), "tt_get_timing")
+        return ms, n
+
+    def device_bytes(self):
+        b = C.c_uint64()
+        _check(lib().tt_device_bytes(self.h, C.byref(b)), "tt_device_bytes")
+        return int(b.value)
+
+
+def debug_cholesky_solve(A, b):
+    """Solve A x = b with the library's FP32 Cholesky kernels; returns (x, failed)."""
+    A = _c(A, np.float32)
+    b = _c(b, np.float32)
+    x = np.zeros(b.shape[0], np.float32)
+    fail = C.c_int(0)
+    _check(lib().tt_debug_cholesky_solve(int(b.shape[0]), _ptr(A), _ptr(b), _ptr(x), C.byref(fail)),
+           "tt_debug_cholesky_solve")
+    return x, bool(fail.value)
+
+
+def create_stream(params, intr, hip_stream=None):
+    return Stream(params, intr, hip_stream)

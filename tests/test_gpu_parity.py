@@ -1,0 +1,299 @@
+"""Parity of the HIP library with the FP64 oracle, step by step through the debug taps.
+
+Bars: bit-exact for Hamming distances, match indices, pre-selected sets, hypothesis records and
+projective-correspondence indices (the projection is taken in FP64 on both sides; at a state where
+the two sides' vertices coincide exactly -- the identity warps of a first frame -- the pixel must
+be identical); floating point within the stated tolerances (normal equations 1e-5 relative in
+Frobenius norm, deformed vertices <= 0.01 mm RMS after the frame's LM iterations from the same
+initial warps).
+"""
+import numpy as np
+import pytest
+
+from paper_2007_08576_amd import synth
+from tests import scenes
+
+pytestmark = pytest.mark.gpu
+
+RMS_TOL_MM = 0.01
+NE_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2007_08576_amd import tt
+    tt.lib()
+    return tt
+
+
+def _params(mod, **kw):
+    return mod.default_params(**kw)
+
+
+def _intr(mod, K):
+    return mod.intrinsics(K.width, K.height, K.fx, K.fy, K.cx, K.cy)
+
+
+def _pair(O, T, sc, **kw):
+    """Oracle and GPU streams with the same template."""
+    so = O.Stream(_params(O, num_control_points=sc.num_control_points, **kw), _intr(O, sc.intr))
+    sg = T.Stream(_params(T, num_control_points=sc.num_control_points, **kw), _intr(T, sc.intr))
+    so.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    sg.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    return so, sg
+
+
+def _rms(a, b):
+    return float(np.sqrt(((np.asarray(a) - np.asarray(b)) ** 2).sum(1).mean()))
+
+
+def _near_threshold(x, thr, rel=1e-9):
+    return np.abs(x - thr) <= rel * thr
+
+
+@pytest.fixture(scope="module")
+def c1(O, T):
+    sc = synth.make_config1(1)
+    fr = sc.frame(1)
+    so, sg = _pair(O, T, sc, seed=1)
+    vo, qo, do = so.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+    vg, qg, dg = sg.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+    return dict(sc=sc, fr=fr, so=so, sg=sg, vo=vo, qo=qo, do=do, vg=vg, qg=qg, dg=dg)
+
+
+def test_template_setup(c1):
+    io, ig = c1["so"].template_info(), c1["sg"].template_info()
+    assert np.array_equal(io["node_idx"], ig["node_idx"])
+    assert np.array_equal(io["knn_pts"], ig["knn_pts"])
+    assert np.array_equal(io["knn_feat"], ig["knn_feat"])
+    assert np.abs(io["alpha_pts"] - ig["alpha_pts"]).max() < 1e-6
+    assert np.abs(io["alpha_feat"] - ig["alpha_feat"]).max() < 1e-6
+    assert abs(io["sbar"] - ig["sbar"]) <= 1e-12 * io["sbar"]
+    assert abs(io["s_arap"] - ig["s_arap"]) <= 1e-9 * io["s_arap"]
+
+
+def test_hamming_bit_exact(c1):
+    do, dg = c1["do"], c1["dg"]
+    assert np.array_equal(do["match_idx"], dg["match_idx"])
+    assert np.array_equal(do["match_dist"], dg["match_dist"])
+
+
+def test_preselection_bit_exact(c1):
+    do, dg = c1["do"], c1["dg"]
+    assert np.array_equal(do["hyp_k0"], dg["hyp_k0"])
+    assert np.array_equal(do["hyp_nin"], dg["hyp_nin"])
+    assert np.array_equal(do["hyp_kept"], dg["hyp_kept"])
+    assert np.allclose(do["hyp_W"], dg["hyp_W"], rtol=1e-10, atol=0)
+    amb = _near_threshold(do["wstar"], 0.5)
+    assert np.array_equal(do["preselected"][~amb], dg["preselected"][~amb])
+    assert np.abs(do["wstar"] - dg["wstar"]).max() < 1e-9
+    assert do["preselected"].sum() > 250
+
+
+def test_association_iteration0(c1):
+    do, dg = c1["do"], c1["dg"]
+    assert np.array_equal(do["corr0"], dg["corr0"])  # identity warps: vertices coincide exactly
+    assert np.abs(do["r0"] - dg["r0"]).max() < 1e-4
+    assert np.abs(do["omega0"] - dg["omega0"]).max() < 1e-4
+    assert np.abs(do["orbw0"] - dg["orbw0"]).max() < 1e-5
+
+
+def test_normal_equations_iteration0(c1):
+    do, dg = c1["do"], c1["dg"]
+    Ao, Ag, go, gg = do["A0"], dg["A0"], do["g0"], dg["g0"]
+    assert abs(do["w_arap"] - dg["w_arap"]) <= 1e-6 * do["w_arap"]
+    ea = np.linalg.norm(Ao - Ag) / np.linalg.norm(Ao)
+    eg = np.linalg.norm(go - gg) / np.linalg.norm(go)
+    assert ea < NE_TOL, ea
+    assert eg < NE_TOL, eg
+    # per 6x6 node block, against the block's own size plus a floor relative to the largest block
+    N = c1["so"].N
+    blk = lambda A, i, j: A[6 * i:6 * i + 6, 6 * j:6 * j + 6]
+    big = max(np.linalg.norm(blk(Ao, i, i)) for i in range(N))
+    worst = 0.0
+    for i in range(N):
+        for j in range(i + 1):
+            e = np.linalg.norm(blk(Ao, i, j) - blk(Ag, i, j))
+            worst = max(worst, e / (np.linalg.norm(blk(Ao, i, j)) + 1e-6 * big))
+    assert worst < NE_TOL, worst
+
+
+def test_vertices_after_lm(c1):
+    rms = _rms(c1["vo"], c1["vg"])
+    assert rms <= RMS_TOL_MM, rms
+    assert np.abs(c1["qo"] - c1["qg"]).max() < 1e-3
+    # both moved well away from the identity towards the truth
+    gt = c1["fr"].gt_vertices
+    assert _rms(c1["vg"], gt) < 0.25 * _rms(c1["sc"].pts, gt)
+
+
+def test_lm_bookkeeping(c1):
+    dg = c1["dg"]
+    lam = dg["lambda"]
+    assert lam[0] == 1e-4
+    for t in range(len(lam) - 1):
+        if dg["accepted"][t]:
+            assert dg["cost_new"][t] < dg["cost_old"][t]
+            assert np.isclose(lam[t + 1], max(lam[t] / 10, 1e-10))
+        else:
+            assert np.isclose(lam[t + 1], min(lam[t] * 10, 1e10))
+    assert np.allclose(c1["do"]["cost_old"][0], dg["cost_old"][0], rtol=1e-5)
+
+
+def test_repeatable_bit_for_bit(c1, T):
+    sc, fr = c1["sc"], c1["fr"]
+    sg = T.Stream(_params(T, num_control_points=sc.num_control_points, seed=1), _intr(T, sc.intr))
+    sg.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    v1, q1, _ = sg.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc)
+    sg.set_state(np.tile(np.r_[1.0, 0, 0, 0, 0, 0, 0, 0], (sc.num_control_points, 1)), 0)
+    v2, q2, _ = sg.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc)
+    assert np.array_equal(v1, c1["vg"]) and np.array_equal(v1, v2) and np.array_equal(q1, q2)
+
+
+def test_device_path_matches_host_path(c1, T):
+    import torch
+    sc, fr = c1["sc"], c1["fr"]
+    sg = T.Stream(_params(T, num_control_points=sc.num_control_points, seed=1), _intr(T, sc.intr))
+    sg.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    dev = torch.device("cuda:0")
+    depth = torch.from_numpy(fr.depth).to(dev)
+    xyz = torch.from_numpy(fr.feat_xyz).to(dev)
+    desc = torch.from_numpy(fr.feat_desc).to(dev)
+    ov = torch.empty((sc.pts.shape[0], 3), dtype=torch.float32, device=dev)
+    oq = torch.empty((sc.num_control_points, 8), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    sg.track_frame_device(depth, xyz, desc, xyz.shape[0], ov, oq)
+    sg.sync()
+    assert np.array_equal(ov.cpu().numpy().astype(np.float64), c1["vg"])
+    assert np.array_equal(oq.cpu().numpy().astype(np.float64), c1["qg"])
+
+
+# ------------------------------------------------------------------------------------------------
+# a reduced sequence (several Cholesky blocks and a ragged last block), warm-started frames with
+# the GPU teacher-forced to the oracle's state before each frame
+
+def test_sequence_teacher_forced(O, T):
+    sc = synth.make_small_sequence(seed=11, M=2500, N=45, K1=300, width=160, height=120, n_frames=3,
+                                   max_step_mm=3.0)
+    so, sg = _pair(O, T, sc, seed=5)
+    for t in range(1, 4):
+        fr = sc.frame(t)
+        dq, f = so.get_state()
+        sg.set_state(dq, f)
+        vo, qo, do = so.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+        vg, qg, dg = sg.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+        print(f"frame {t}: rms {_rms(vo, vg):.2e} mm, truth rms gpu {_rms(vg, fr.gt_vertices):.3f}", flush=True)
+        assert np.array_equal(do["match_idx"], dg["match_idx"])
+        amb = _near_threshold(do["wstar"], 0.5)
+        assert np.array_equal(do["preselected"][~amb], dg["preselected"][~amb])
+        assert np.array_equal(do["hyp_k0"], dg["hyp_k0"])
+        # warm-started vertices differ at the float rounding of the warps: a pixel may change only
+        # where the FP64 projection falls next to a pixel boundary
+        same = do["corr0"] == dg["corr0"]
+        assert same.mean() > 0.995, same.mean()
+        ea = np.linalg.norm(do["A0"] - dg["A0"]) / np.linalg.norm(do["A0"])
+        assert ea < 1e-4, ea
+        assert _rms(vo, vg) <= RMS_TOL_MM
+
+
+# ------------------------------------------------------------------------------------------------
+# degenerate inputs
+
+def _run_both(O, T, sc, depth, fxyz, fdesc, **kw):
+    so, sg = _pair(O, T, sc, **kw)
+    vo, qo, do = so.track_frame(depth, fxyz, fdesc, debug=True)
+    vg, qg, dg = sg.track_frame(depth, fxyz, fdesc, debug=True)
+    return vo, vg, do, dg
+
+
+def test_no_frame_features(O, T):
+    sc = synth.make_config1(1)
+    fr = sc.frame(1)
+    vo, vg, do, dg = _run_both(O, T, sc, fr.depth, np.zeros((0, 3), np.float32), np.zeros((0, 32), np.uint8))
+    assert np.all(dg["match_idx"] == -1) and np.all(dg["match_dist"] == 256)
+    assert not dg["preselected"].any() and np.all(dg["hyp_k0"] == -1)
+    assert _rms(vo, vg) <= RMS_TOL_MM
+
+
+def test_all_depth_invalid(O, T):
+    sc = synth.make_config1(1)
+    fr = sc.frame(1)
+    depth = np.full_like(fr.depth, np.nan)
+    vo, vg, do, dg = _run_both(O, T, sc, depth, fr.feat_xyz, fr.feat_desc, seed=1)
+    assert np.all(dg["corr0"] == -1)
+    assert _rms(vo, vg) <= RMS_TOL_MM
+
+
+def test_no_template_features_and_nan_frame_points(O, T):
+    sc = synth.make_config1(1)
+    fr = sc.frame(1)
+    sc2 = synth.Scene(sc.name, sc.intr, 64, sc.pts, np.zeros((0, 3), np.float32), np.zeros((0, 32), np.uint8), 1,
+                      sc._frame_fn)
+    vo, vg, do, dg = _run_both(O, T, sc2, fr.depth, fr.feat_xyz, fr.feat_desc)
+    assert _rms(vo, vg) <= RMS_TOL_MM
+    xyz = fr.feat_xyz.copy()
+    xyz[::3] = np.nan  # a third of the frame features without depth
+    vo, vg, do, dg = _run_both(O, T, sc, fr.depth, xyz, fr.feat_desc, seed=1)
+    assert np.array_equal(do["preselected"], dg["preselected"])
+    assert _rms(vo, vg) <= RMS_TOL_MM
+
+
+def test_rigid_lattice_exact_recovery_on_gpu(O, T):
+    pts, feats, R, t = scenes.lattice_scene()
+    o2 = (feats @ R.T + t).astype(np.float32)
+    K = synth.Intrinsics(16, 16, 20.0, 20.0, 8.0, 8.0)
+    desc = np.random.default_rng(23).integers(0, 256, (25, 32), dtype=np.uint8)
+    sg = T.Stream(_params(T, num_control_points=12), _intr(T, K))
+    sg.set_template(pts.astype(np.float32), feats.astype(np.float32), desc)
+    v, q, d = sg.track_frame(np.zeros((16, 16), np.float32), o2, desc, debug=True)
+    assert d["preselected"].all()
+    want = pts @ R.T + t
+    assert np.abs(v - want).max() < 1e-3  # FP32 at 400-2000 mm coordinates
+
+
+def test_api_errors(T):
+    sc = synth.make_config1(1)
+    sg = T.Stream(_params(T, num_control_points=64), _intr(T, sc.intr))
+    fr = sc.frame(1)
+    with pytest.raises(T.TTError) as e:
+        sg.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc)
+    assert e.value.code == T.TT_ESTATE
+    with pytest.raises(T.TTError) as e:
+        sg.set_template(sc.pts[:10], sc.feat_xyz, sc.feat_desc)  # N > M
+    assert e.value.code == T.TT_EINVAL
+    bad = sc.pts.copy()
+    bad[5, 0] = np.inf
+    with pytest.raises(T.TTError) as e:
+        sg.set_template(bad, sc.feat_xyz, sc.feat_desc)
+    assert e.value.code == T.TT_EINVAL
+    dup = np.tile(sc.pts[:1], (100, 1))
+    with pytest.raises(T.TTError) as e:
+        sg.set_template(dup, sc.feat_xyz, sc.feat_desc)
+    assert e.value.code == T.TT_EINVAL
+    small = T.Stream(_params(T, num_control_points=64, hbm_budget_bytes=400 << 10), _intr(T, sc.intr))
+    with pytest.raises(T.TTError) as e:
+        small.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    assert e.value.code == T.TT_ENOMEM
+
+
+# ------------------------------------------------------------------------------------------------
+# full size: config 2 (640 x 480, M = 30,000, N = 400, K = 2,000, 30 % outliers), frame 1 from the
+# identity, in the same launch configuration the benchmark times (the oracle takes ~40 s here)
+
+def test_config2_full_size(O, T):
+    sc = synth.make_config2(seed=2, n_frames=300)
+    fr = sc.frame(1)
+    so, sg = _pair(O, T, sc, seed=2)
+    vg, qg, dg = sg.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+    vo, qo, do = so.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+    assert np.array_equal(do["match_idx"], dg["match_idx"])
+    assert np.array_equal(do["match_dist"], dg["match_dist"])
+    amb = _near_threshold(do["wstar"], 0.5)
+    assert np.array_equal(do["preselected"][~amb], dg["preselected"][~amb])
+    assert np.array_equal(do["hyp_k0"], dg["hyp_k0"]) and np.array_equal(do["hyp_kept"], dg["hyp_kept"])
+    assert np.array_equal(do["corr0"], dg["corr0"])
+    ea = np.linalg.norm(do["A0"] - dg["A0"]) / np.linalg.norm(do["A0"])
+    eg = np.linalg.norm(do["g0"] - dg["g0"]) / np.linalg.norm(do["g0"])
+    print(f"config 2: |dA|/|A| {ea:.2e}, |dg|/|g| {eg:.2e}, vertex rms {_rms(vo, vg):.2e} mm", flush=True)
+    assert ea < NE_TOL and eg < NE_TOL
+    assert _rms(vo, vg) <= RMS_TOL_MM
