@@ -147,9 +147,10 @@ int tt_set_state(tt_stream* s, const double* dq, int64_t frame);
 #define TT_STAGE_ROWS 1   /* per-point / per-feature residual and Jacobian rows          */
 #define TT_STAGE_ARAP 2   /* dense ARAP assembly into the normal matrix                  */
 #define TT_STAGE_DATA 3   /* data-term block assembly (block-CSR)                        */
-#define TT_STAGE_SOLVE 4  /* damping, Cholesky factorisation, substitutions             */
+#define TT_STAGE_SOLVE 4  /* damping and equilibration, back substitution               */
 #define TT_STAGE_UPDATE 5 /* candidate warps, FP64 costs, accept / reject               */
-#define TT_NSTAGES 6
+#define TT_STAGE_FACTOR 6 /* blocked Cholesky factorisation with the forward substitution */
+#define TT_NSTAGES 7
 
 /* Enables (1) or disables (0) the stage timers. */
 int tt_set_timing(tt_stream* s, int enable);

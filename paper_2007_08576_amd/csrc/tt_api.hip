@@ -213,11 +213,18 @@ int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint
       if (d.K1)
         HIPCHK(hipMemcpyAsync(d.orbw_dbg, d.orbw, sizeof(float) * d.K1, hipMemcpyDeviceToDevice, st));
     }
+    s->solve_epoch = (s->solve_epoch == 0x7FFFFFFF) ? 1 : s->solve_epoch + 1;
     {
       StageTimer tm(s, TT_STAGE_SOLVE);
       HIPCHK(launch_lm_damp(dd, st));
-      s->solve_epoch = (s->solve_epoch == 0x7FFFFFFF) ? 1 : s->solve_epoch + 1;
-      HIPCHK(launch_cholesky_solve(dd, s->solve_epoch, st));
+    }
+    {
+      StageTimer tm(s, TT_STAGE_FACTOR);
+      HIPCHK(launch_cholesky_factor(dd, s->solve_epoch, st));
+    }
+    {
+      StageTimer tm(s, TT_STAGE_SOLVE);
+      HIPCHK(launch_cholesky_backsolve(dd, s->solve_epoch, st));
     }
     {
       StageTimer tm(s, TT_STAGE_UPDATE);
@@ -358,6 +365,14 @@ const char* tt_strerror(int code) {
   }
 }
 
+// Compute units of the current device (0 if the query fails; the launcher then assumes 256).
+static int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return cus;
+}
+
 int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_stream, tt_stream** out) {
   if (!p || !K || !out) return TT_EINVAL;
   *out = nullptr;
@@ -384,6 +399,7 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
   }
   DevState& d = s->d;
   d.HW = K->width * K->height;
+  d.num_cus = device_cus();
   int T = p->lm_iters > 0 ? p->lm_iters : 1;
   int rc = TT_OK;
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.depth, (size_t)d.HW);
@@ -431,6 +447,7 @@ int tt_get_timing(tt_stream* s, double* ms, int64_t* count) {
 int tt_debug_cholesky_solve(int n, const float* A, const float* b, float* x, int* fail) {
   if (n < 1 || n > 65536 || !A || !b || !x || !fail) return TT_EINVAL;
   DevState d;
+  d.num_cus = device_cus();
   d.n = n;
   d.npad = ((n + TT_NB - 1) / TT_NB) * TT_NB;
   d.nb = d.npad / TT_NB;
@@ -446,7 +463,7 @@ int tt_debug_cholesky_solve(int n, const float* A, const float* b, float* x, int
   int rc = TT_OK;
   const size_t rows = (size_t)d.npad + TT_NB;
   if (!al((void**)&d.A, sizeof(float) * rows * d.ld) || !al((void**)&d.x, sizeof(float) * d.npad) ||
-      !al((void**)&d.Linv, sizeof(float) * (size_t)d.nb * TT_NB * TT_NB) || !al((void**)&d.flags, sizeof(int) * d.nb) ||
+      !al((void**)&d.Linv, sizeof(float) * (size_t)d.nb * TT_NB * TT_NB) || !al((void**)&d.flags, sizeof(int) * chol_flag_ints(d.nb)) ||
       !al((void**)&d.sc, sizeof(LMScalars)) || !al((void**)&d.dscale, sizeof(float) * d.npad)) {
     rc = TT_ENOMEM;
   } else {
@@ -459,10 +476,10 @@ int tt_debug_cholesky_solve(int n, const float* A, const float* b, float* x, int
     LMScalars sc;
     memset(&sc, 0, sizeof(sc));
     if (hipMemcpyAsync(d.A, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemsetAsync(d.flags, 0, sizeof(int) * d.nb, st) != hipSuccess ||
+        hipMemsetAsync(d.flags, 0, sizeof(int) * chol_flag_ints(d.nb), st) != hipSuccess ||
         hipMemcpyAsync(d.dscale, ones.data(), sizeof(float) * d.npad, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(d.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, st) != hipSuccess ||
-        launch_cholesky_solve(d, 1, st) != hipSuccess ||
+        launch_cholesky_factor(d, 1, st) != hipSuccess || launch_cholesky_backsolve(d, 1, st) != hipSuccess ||
         hipMemcpyAsync(hx.data(), d.x, sizeof(float) * d.npad, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(&sc, d.sc, sizeof(sc), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
@@ -503,9 +520,23 @@ int tt_device_bytes(tt_stream* s, uint64_t* bytes) {
   return TT_OK;
 }
 
+// After the stream has drained: TT_EDEVICE if a kernel raised a device-side error bit (then cleared).
+static int take_device_error(tt_stream* s) {
+  int err = 0;
+  if (hipMemcpyAsync(&err, &s->d.sc->err, sizeof(int), hipMemcpyDeviceToHost, s->st) != hipSuccess ||
+      hipStreamSynchronize(s->st) != hipSuccess)
+    return TT_EDEVICE;
+  if (err == 0) return TT_OK;
+  const int zero = 0;
+  (void)hipMemcpyAsync(&s->d.sc->err, &zero, sizeof(int), hipMemcpyHostToDevice, s->st);
+  (void)hipStreamSynchronize(s->st);
+  return TT_EDEVICE;
+}
+
 int tt_sync(tt_stream* s) {
   if (!s) return TT_EINVAL;
-  return hipStreamSynchronize(s->st) == hipSuccess ? TT_OK : TT_EDEVICE;
+  if (hipStreamSynchronize(s->st) != hipSuccess) return TT_EDEVICE;
+  return take_device_error(s);
 }
 
 int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat_xyz, const uint8_t* feat_desc,
@@ -574,7 +605,7 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
   ALLOC(allocs_template, bytes_template, d.g, (size_t)d.npad);
   ALLOC(allocs_template, bytes_template, d.x, (size_t)d.npad);
   ALLOC(allocs_template, bytes_template, d.Linv, (size_t)d.nb * TT_NB * TT_NB);
-  ALLOC(allocs_template, bytes_template, d.flags, (size_t)d.nb);
+  ALLOC(allocs_template, bytes_template, d.flags, chol_flag_ints(d.nb));
   ALLOC(allocs_template, bytes_template, d.dscale, (size_t)d.npad);
   d.npartial = partial_count(M, K1, N) + 8;
   ALLOC(allocs_template, bytes_template, d.partial, (size_t)d.npartial);
@@ -646,7 +677,7 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
     for (int k = d.n; k < d.npad; k++)
       HIPCHK(hipMemcpyAsync(d.A + (size_t)k * d.ld + k, one.data(), sizeof(float), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemsetAsync(d.x, 0, sizeof(float) * d.npad, st));
-    HIPCHK(hipMemsetAsync(d.flags, 0, sizeof(int) * d.nb, st));
+    HIPCHK(hipMemsetAsync(d.flags, 0, sizeof(int) * chol_flag_ints(d.nb), st));
     s->solve_epoch = 0;
     HIPCHK(hipStreamSynchronize(st));
   }
@@ -707,6 +738,7 @@ int tt_track_frame(tt_stream* s, const float* depth, const float* feat_xyz, cons
     if (oq && hipMemcpyAsync(hq.data(), oq, sizeof(float) * hq.size(), hipMemcpyDeviceToHost, st) != hipSuccess)
       rc = TT_EDEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) rc = TT_EDEVICE;
+    if (rc == TT_OK) rc = take_device_error(s);
     if (rc == TT_OK) {
       for (size_t i = 0; i < hv.size(); i++) out_vertices[i] = hv[i];
       for (size_t i = 0; i < hq.size(); i++) out_dq[i] = hq[i];

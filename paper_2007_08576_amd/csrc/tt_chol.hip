@@ -4,21 +4,17 @@
 // Layout: A is row-major with leading dimension ld = npad (n rounded up to the 64-wide block),
 // lower triangle only; the padding rows/columns carry an identity so no block is ragged.
 // Rows npad..npad+63 form one extra "right-hand-side" row block whose first row holds b^T: the
-// right-looking blocked factorisation treats it like any other row block below the diagonal,
-// which leaves y = L^{-1} b in that row when the factorisation ends (the forward substitution
-// comes for free). The back substitution L^T x = y then walks the block columns from the last.
+// blocked factorisation treats it like any other row block below the diagonal, which leaves
+// y = L^{-1} b in that row when the factorisation ends (the forward substitution comes for free).
+// The back substitution L^T x = y then walks the block columns from the last.
 //
-// Per block column k:
-//   k_chol_panel   every workgroup factors the 64 x 64 diagonal block in LDS (16-wide blocked,
-//                  leaves in registers) and inverts the factor (2 x 2 block recursion);
-//                  workgroup 0 stores L_kk and L_kk^{-1}; the others form L_ik = A_ik L_kk^{-T}
-//                  as a 64x64x64 product on the matrix cores
-//   k_chol_update  trailing tiles A_ij -= L_ik L_jk^T, k < j <= i (plus the right-hand-side row
-//                  block), 64 x 64 tiles on the matrix cores (v_mfma_f32_16x16x4_f32)
-// then one k_chol_backsolve launch: workgroup b owns block row j = nb-1-b of L^T x = y, folds in
-// x_k of every later block as it is published (flag per block), and publishes x_j. Workgroups only
-// wait on lower-numbered ones, which the hardware dispatches first, so the waits always end; a
-// bounded spin marks the solve failed instead of waiting forever.
+// k_chol_dataflow factors the whole matrix in one persistent launch (tile tasks with flags, see
+// below); 64 x 64 x 64 tile products run on the matrix cores (v_mfma_f32_16x16x4_f32) and the
+// diagonal blocks are factored and inverted inside one workgroup. Then one k_chol_backsolve
+// launch: workgroup b owns block row j = nb-1-b of L^T x = y, folds in x_k of every later block as
+// it is published (flag per block), and publishes x_j. Workgroups only wait on lower-numbered
+// ones, which the hardware dispatches first, so the waits always end; a bounded spin marks the
+// solve failed instead of waiting forever.
 #include "tt_internal.h"
 
 namespace {
@@ -27,18 +23,319 @@ constexpr int NB = TT_NB;
 constexpr int LDS_LD = NB + 2;  // conflict-free for the 16 x 4 MFMA operand reads
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// C (64 x 64) = X Y^T for X, Y in LDS (64 x 64, leading dimension LDS_LD). Four wavefronts each
-// compute a 32 x 32 quadrant as 2 x 2 MFMA 16x16x4 accumulators; acc[a][b][r] holds
-// C[qr + 16a + 4 (lane/16) + r][qc + 16b + lane%16].
-__device__ __forceinline__ void mma64_xyT(const float (*X)[LDS_LD], const float (*Y)[LDS_LD], floatx4 acc[2][2],
-                                          int& qr, int& qc) {
+#define MFMA16(a, b, c) __builtin_amdgcn_mfma_f32_16x16x4f32((a), (b), (c), 0, 0, 0)
+
+// Broadcast of lane n of each 16-lane row to the whole row (DPP row_newbcast, a VALU operand
+// modifier: no LDS traffic). n must fold to a constant (the callers' loops are fully unrolled).
+__device__ __forceinline__ float bcast16(float v, int n) {
+  int x = __float_as_int(v);
+  switch (n) {
+    case 0: x = __builtin_amdgcn_mov_dpp(x, 0x150, 0xF, 0xF, false); break;
+    case 1: x = __builtin_amdgcn_mov_dpp(x, 0x151, 0xF, 0xF, false); break;
+    case 2: x = __builtin_amdgcn_mov_dpp(x, 0x152, 0xF, 0xF, false); break;
+    case 3: x = __builtin_amdgcn_mov_dpp(x, 0x153, 0xF, 0xF, false); break;
+    case 4: x = __builtin_amdgcn_mov_dpp(x, 0x154, 0xF, 0xF, false); break;
+    case 5: x = __builtin_amdgcn_mov_dpp(x, 0x155, 0xF, 0xF, false); break;
+    case 6: x = __builtin_amdgcn_mov_dpp(x, 0x156, 0xF, 0xF, false); break;
+    case 7: x = __builtin_amdgcn_mov_dpp(x, 0x157, 0xF, 0xF, false); break;
+    case 8: x = __builtin_amdgcn_mov_dpp(x, 0x158, 0xF, 0xF, false); break;
+    case 9: x = __builtin_amdgcn_mov_dpp(x, 0x159, 0xF, 0xF, false); break;
+    case 10: x = __builtin_amdgcn_mov_dpp(x, 0x15a, 0xF, 0xF, false); break;
+    case 11: x = __builtin_amdgcn_mov_dpp(x, 0x15b, 0xF, 0xF, false); break;
+    case 12: x = __builtin_amdgcn_mov_dpp(x, 0x15c, 0xF, 0xF, false); break;
+    case 13: x = __builtin_amdgcn_mov_dpp(x, 0x15d, 0xF, 0xF, false); break;
+    case 14: x = __builtin_amdgcn_mov_dpp(x, 0x15e, 0xF, 0xF, false); break;
+    case 15: x = __builtin_amdgcn_mov_dpp(x, 0x15f, 0xF, 0xF, false); break;
+  }
+  return __int_as_float(x);
+}
+
+// 16 x 16 leaf on one wavefront: factors the block at (o, o) of L in place (lower, zeros above)
+// and writes its inverse to Li at (o, o). Lane r (mod 16) keeps row r in registers; pivots and
+// column entries move between lanes by row broadcasts. 1/sqrt(pivot) comes from one v_rsq. The
+// inverse is built column-oriented (lane r holds column r): x_i = p_i / L_ii, then
+// p_k -= L_ki x_i for k > i.
+__device__ __forceinline__ void leaf16(float (*L)[LDS_LD], float (*Li)[LDS_LD], int o, bool& ok) {
+  const int lane = threadIdx.x & 63, r = lane & 15;
+  const bool writer = lane < 16;
+  float a[16];
+#pragma unroll
+  for (int c = 0; c < 16; c++) {
+    const float v = L[o + r][o + c];
+    a[c] = (c <= r) ? v : 0.0f;
+  }
+  float invd[16];
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const float d = bcast16(a[j], j);
+    ok = ok && (d > 0.0f);
+    const float il = __builtin_amdgcn_rsqf(d);
+    invd[j] = il;
+    const float lr = (r > j) ? a[j] * il : 0.0f;
+    const float nlr = -lr;
+    a[j] = (r > j) ? lr : ((r == j) ? d * il : 0.0f);
+#pragma unroll
+    for (int m = j + 1; m < 16; m++) a[m] = fmaf(bcast16(lr, m), nlr, a[m]);
+  }
+  if (writer) {
+#pragma unroll
+    for (int c = 0; c < 16; c++) L[o + r][o + c] = (c <= r) ? a[c] : 0.0f;
+  }
+  float p[16], x[16];
+#pragma unroll
+  for (int i = 0; i < 16; i++) p[i] = (i == r) ? 1.0f : 0.0f;
+#pragma unroll
+  for (int i = 0; i < 16; i++) {
+    x[i] = p[i] * invd[i];
+    const float nx = -x[i];
+#pragma unroll
+    for (int k = i + 1; k < 16; k++) p[k] = fmaf(bcast16(a[i], k), nx, p[k]);
+  }
+  if (writer) {
+#pragma unroll
+    for (int i = 0; i < 16; i++) Li[o + i][o + r] = (i >= r) ? x[i] : 0.0f;
+  }
+}
+
+// Cholesky factor (in place, lower, zeros above) and inverse Li of the 64 x 64 block in LDS,
+// blocked by 16: per block column a leaf (above), then the rows below are solved against the
+// leaf inverse and the trailing lower triangle is updated, both as 16 x 16 x 16 products on the
+// matrix cores; finally the inverse is assembled by the 2 x 2 block recursion
+// [[A, 0], [C, D]]^{-1} = [[A^{-1}, 0], [-D^{-1} C A^{-1}, D^{-1}]] (16 -> 32 -> 64), also on the
+// matrix cores. Returns false if a pivot is not positive. All 256 threads must call it.
+__device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LDS_LD], float* T /* 32 x 32 */) {
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int li = lane % 16, lk = lane / 16;
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < NB * NB; e += blockDim.x) Li[e / NB][e % NB] = 0.0f;
+  __syncthreads();
+#pragma unroll 1
+  for (int kb = 0; kb < 4; kb++) {
+    const int o = 16 * kb;
+    if (wave == 0) {
+      bool ok = true;
+      leaf16(L, Li, o, ok);
+      if (lane == 0 && !ok) bad = 1;
+    }
+    __syncthreads();
+    const int nt = 3 - kb;  // 16-row tiles below the leaf
+    if (nt == 0) break;
+    // rows below: X = B D^{-T}, one 16 x 16 tile per wavefront
+    if (wave < nt) {
+      const int rb = o + 16 + 16 * wave;
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) acc = MFMA16(L[rb + li][o + kk + lk], Li[o + li][o + kk + lk], acc);
+#pragma unroll
+      for (int q = 0; q < 4; q++) L[rb + 4 * lk + q][o + li] = acc[q];
+    }
+    __syncthreads();
+    // trailing lower triangle -= X X^T (K = 16); diagonal tiles keep their upper part zero
+    const int ntiles = nt * (nt + 1) / 2;
+    for (int t = wave; t < ntiles; t += 4) {
+      int ti = 0;
+      while ((ti + 1) * (ti + 2) / 2 <= t) ti++;
+      const int tj = t - ti * (ti + 1) / 2;
+      const int r0 = o + 16 + 16 * ti, c0 = o + 16 + 16 * tj;
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) acc = MFMA16(L[r0 + li][o + kk + lk], L[c0 + li][o + kk + lk], acc);
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int rr = r0 + 4 * lk + q, cc = c0 + li;
+        if (cc <= rr) L[rr][cc] -= acc[q];
+      }
+    }
+    __syncthreads();
+  }
+  // inverse 16 -> 32: wavefronts 0 and 1 take one 32-block each
+  if (wave < 2) {
+    const int o = 32 * wave;
+    float* Tw = T + wave * 256;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) acc = MFMA16(L[o + 16 + li][o + kk + lk], Li[o + kk + lk][o + li], acc);
+#pragma unroll
+    for (int q = 0; q < 4; q++) Tw[(4 * lk + q) * 16 + li] = acc[q];
+    __builtin_amdgcn_wave_barrier();
+    floatx4 acc2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) acc2 = MFMA16(Li[o + 16 + li][o + 16 + kk + lk], Tw[(kk + lk) * 16 + li], acc2);
+#pragma unroll
+    for (int q = 0; q < 4; q++) Li[o + 16 + 4 * lk + q][o + li] = -acc2[q];
+  }
+  __syncthreads();
+  // 32 -> 64: wavefront w computes output tile (w / 2, w % 2) of T = C A^{-1}, then of -D^{-1} T
+  {
+    const int ti = wave / 2, tj = wave % 2;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4) acc = MFMA16(L[32 + 16 * ti + li][kk + lk], Li[kk + lk][16 * tj + li], acc);
+#pragma unroll
+    for (int q = 0; q < 4; q++) T[(16 * ti + 4 * lk + q) * 32 + 16 * tj + li] = acc[q];
+  }
+  __syncthreads();
+  {
+    const int ti = wave / 2, tj = wave % 2;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4) acc = MFMA16(Li[32 + 16 * ti + li][32 + kk + lk], T[(kk + lk) * 32 + 16 * tj + li], acc);
+#pragma unroll
+    for (int q = 0; q < 4; q++) Li[32 + 16 * ti + 4 * lk + q][16 * tj + li] = -acc[q];
+  }
+  __syncthreads();
+  return bad == 0;
+}
+
+// ---- dataflow factorisation: one persistent launch per solve ---------------------------------
+//
+// Left-looking tile tasks, handed out in a fixed order through an atomic ticket counter. Task
+// kinds, for block column c (tiles are 64 x 64; row block nb is the right-hand side):
+//   CRIT(j)      the critical chain: L_{j,j-1} = C_{j,j-1} Linv_{j-1}^T, C_jj -= L_{j,j-1} L_{j,j-1}^T,
+//                then factor and invert C_jj (publishes L_{j,j-1} and Linv_j)
+//   DIAGP(j)     C_jj = A_jj - sum_{k <= j-2} L_jk L_jk^T            (j >= 2; finished by CRIT(j))
+//   SUBP(j)      C_{j,j-1} = A_{j,j-1} - sum_{k <= j-2} L_jk L_{j-1,k}^T  (j >= 2; finished by CRIT(j))
+//   FULL(i, c)   L_ic = (A_ic - sum_{k < c} L_ik L_ck^T) Linv_c^T   (i >= c + 2, and the right-hand side)
+// Order: for j = 0, 1, ...: DIAGP(j), SUBP(j), CRIT(j), FULL(j+2 .. nb-1, j), FULL(nb, j). Every task
+// waits only on tasks with smaller tickets, which were claimed by running workgroups, so the waits
+// always end whatever the number of resident workgroups. Only CRIT tasks lie on the critical path:
+// the accumulations run ahead on the other workgroups.
+//
+// Hand-over: a producer's stores complete (s_waitcnt), then one thread releases at agent scope
+// (L2 write-back) and stores the tile's flag (the solve's epoch); a consumer polls the flag with
+// agent-scope loads and acquires at agent scope before reading the tile. A wait that outlasts a
+// deadline aborts the whole solve (all workgroups drain, the step is marked failed).
+enum { TASK_CRIT = 0, TASK_DIAGP = 1, TASK_SUBP = 2, TASK_FULL = 3 };
+
+struct CholSync {
+  int* bflag;   // [nb] back substitution
+  int* fin;     // [(nb + 1) * nb] final L tile (i, c) at fin[i * nb + c]
+  int* pdiag;   // [nb] partial diagonal tile of DIAGP(j)
+  int* psub;    // [nb] partial sub-diagonal tile of SUBP(j)
+  int* dinv;    // [nb] Linv_j published
+  int* ctr;     // [1] ticket counter (0 between solves)
+  int* abort_;  // [1] epoch of an aborted solve
+};
+
+__host__ __device__ inline CholSync chol_sync(int* base, int nb) {
+  CholSync S;
+  S.bflag = base;
+  S.fin = S.bflag + nb;
+  S.pdiag = S.fin + (size_t)(nb + 1) * nb;
+  S.psub = S.pdiag + nb;
+  S.dinv = S.psub + nb;
+  S.ctr = S.dinv + nb;
+  S.abort_ = S.ctr + 1;
+  return S;
+}
+
+__host__ __device__ inline int chol_task_count(int nb) {
+  int t = 0;
+  for (int j = 0; j < nb; j++) t += (j >= 2 ? 2 : 0) + 1 + (nb - j - 2 > 0 ? nb - j - 2 : 0) + 1;
+  return t;
+}
+
+__device__ __forceinline__ void decode_task(int t, int nb, int& kind, int& i, int& c) {
+  int t0 = 0;
+  for (int j = 0; j < nb; j++) {
+    const int nfull = (nb - j - 2 > 0 ? nb - j - 2 : 0) + 1;
+    const int gsz = (j >= 2 ? 2 : 0) + 1 + nfull;
+    if (t < t0 + gsz) {
+      int r = t - t0;
+      if (j >= 2) {
+        if (r == 0) { kind = TASK_DIAGP; i = j; c = j; return; }
+        if (r == 1) { kind = TASK_SUBP; i = j; c = j - 1; return; }
+        r -= 2;
+      }
+      if (r == 0) { kind = TASK_CRIT; i = j; c = j; return; }
+      r -= 1;
+      kind = TASK_FULL;
+      i = (r < nfull - 1) ? j + 2 + r : nb;
+      c = j;
+      return;
+    }
+    t0 += gsz;
+  }
+  kind = -1;
+  i = c = 0;
+}
+
+constexpr uint64_t kDeadlineTicks = 25000000ull;  // 0.25 s of the 100 MHz constant clock
+
+__device__ __forceinline__ int ld_flag(const int* f) {
+  return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 waits until every non-null flag equals epoch, then acquires; the block learns the result.
+__device__ bool block_wait(const int* f0, const int* f1, const int* f2, int epoch, const CholSync& S,
+                           uint64_t deadline, int* s_ok) {
+  if (threadIdx.x == 0) {
+    bool ok = true;
+    const int* fs[3] = {f0, f1, f2};
+    for (int q = 0; q < 3 && ok; q++) {
+      if (!fs[q]) continue;
+      int spins = 0;
+      while (ld_flag(fs[q]) != epoch) {
+        if ((++spins & 15) == 0 &&
+            (ld_flag(S.abort_) == epoch || __builtin_amdgcn_s_memrealtime() > deadline)) {
+          ok = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    if (!ok) __hip_atomic_store(S.abort_, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_ok = ok ? 1 : 0;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+// Wavefront 0 finds how many consecutive k >= k0 (< nk) have both tiles fi[k] and fc[k] final,
+// waiting until at least one has; then acquires. Returns 0 if the solve was aborted.
+__device__ int block_ready_prefix(const int* fi, const int* fc, int k0, int nk, int epoch, const CholSync& S,
+                                  uint64_t deadline, int* s_val) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int pre = 0, spins = 0;
+    for (;;) {
+      const int k = k0 + lane;
+      const bool r = (k >= nk) || (ld_flag(fi + k) == epoch && ld_flag(fc + k) == epoch);
+      const unsigned long long m = __ballot(r);
+      pre = (~m == 0ull) ? 64 : __builtin_ctzll(~m);
+      if (pre > nk - k0) pre = nk - k0;
+      if (pre > 0) break;
+      if ((++spins & 15) == 0 &&
+          (ld_flag(S.abort_) == epoch || __builtin_amdgcn_s_memrealtime() > deadline)) {
+        if (lane == 0) __hip_atomic_store(S.abort_, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    if (lane == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      *s_val = pre;
+    }
+  }
+  __syncthreads();
+  return *s_val;
+}
+
+// All stores of the block complete, then thread 0 releases at agent scope and raises the flag.
+__device__ __forceinline__ void block_publish(int* f, int epoch) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(f, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// acc += X Y^T for 64 x 64 tiles X, Y in LDS (leading dimension LDS_LD). Four wavefronts each
+// own a 32 x 32 quadrant as 2 x 2 MFMA 16x16x4 accumulators; acc[a][b][r] holds element
+// (qr + 16 a + 4 (lane / 16) + r, qc + 16 b + lane % 16) with (qr, qc) = 32 (w / 2, w % 2).
+__device__ __forceinline__ void mma64_acc(const float (*X)[LDS_LD], const float (*Y)[LDS_LD], floatx4 acc[2][2]) {
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-  qr = 32 * (w / 2);
-  qc = 32 * (w % 2);
-#pragma unroll
-  for (int a = 0; a < 2; a++)
-#pragma unroll
-    for (int b = 0; b < 2; b++) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int qr = 32 * (w / 2), qc = 32 * (w % 2);
   const int li = lane % 16, lk = lane / 16;
 #pragma unroll 4
   for (int kk = 0; kk < NB; kk += 4) {
@@ -54,249 +351,247 @@ __device__ __forceinline__ void mma64_xyT(const float (*X)[LDS_LD], const float 
   }
 }
 
-// Lane broadcast of a float (the readlane builtin moves 32-bit integers: pass the bits).
-__device__ __forceinline__ float readlane_f(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+// Row / column of element r of accumulator (a, b) of this thread (quadrant layout).
+__device__ __forceinline__ int acc_row(int a, int r) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  return 32 * (w / 2) + 16 * a + 4 * (lane / 16) + r;
+}
+__device__ __forceinline__ int acc_col(int b) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  return 32 * (w % 2) + 16 * b + lane % 16;
 }
 
-// In-LDS Cholesky of the 64 x 64 lower triangle L, blocked by 16: wavefront 0 factors each 16 x 16
-// diagonal block with rows in registers (readlane broadcasts, no barriers), then the rows below
-// are solved against it and the trailing lower triangle is updated. Returns false if a pivot is
-// not positive.
-__device__ bool potrf64(float (*L)[LDS_LD]) {
-  const int tid = threadIdx.x;
-  const int lane = tid % 64, wave = tid / 64;
-  __shared__ int bad;
-  if (tid == 0) bad = 0;
-  __syncthreads();
-#pragma unroll 1
-  for (int kb = 0; kb < 4; kb++) {
-    const int o = 16 * kb;
-    if (wave == 0) {
-      const int r = lane;
-      float a[16];
+// 64 x 64 tile at (r0, c0) of a row-major matrix into registers, 4 float4 per thread.
+__device__ __forceinline__ void tile_load(const float* __restrict__ M, int ld, size_t r0, size_t c0, float4 v[4]) {
 #pragma unroll
-      for (int c = 0; c < 16; c++) a[c] = (r < 16 && c <= r) ? L[o + r][o + c] : 0.0f;
-      bool ok = true;
-#pragma unroll
-      for (int j = 0; j < 16; j++) {
-        float djj = readlane_f(a[j], j);
-        ok = ok && (djj > 0.0f);
-        float ljj = sqrtf(djj);
-        float lrj = a[j] / ljj;
-        a[j] = (r > j) ? lrj : ((r == j) ? ljj : 0.0f);
-#pragma unroll
-        for (int m = j + 1; m < 16; m++) {
-          float lmj = readlane_f(a[j], m);
-          if (r > j && m <= r) a[m] -= a[j] * lmj;
-        }
-      }
-      if (r < 16) {
-#pragma unroll
-        for (int c = 0; c < 16; c++)
-          if (c <= r) L[o + r][o + c] = a[c];
-      }
-      if (lane == 0 && !ok) bad = 1;
-    }
-    __syncthreads();
-    const int rows = NB - o - 16;
-    if (rows == 0) break;
-    // rows below: x D^T = b, forward substitution over the 16 columns, one thread per row
-    if (tid < rows) {
-      const int r = o + 16 + tid;
-      float x[16];
-#pragma unroll
-      for (int c = 0; c < 16; c++) {
-        float s = L[r][o + c];
-#pragma unroll
-        for (int m = 0; m < c; m++) s -= x[m] * L[o + c][o + m];
-        x[c] = s / L[o + c][o + c];
-      }
-#pragma unroll
-      for (int c = 0; c < 16; c++) L[r][o + c] = x[c];
-    }
-    __syncthreads();
-    // trailing lower triangle: L[i][m] -= sum_c L[i][o+c] L[m][o+c], o+16 <= m <= i < 64
-    const int base = o + 16;
-    const int cnt = rows * rows;
-    for (int e = tid; e < cnt; e += blockDim.x) {
-      const int i = base + e / rows, m = base + e % rows;
-      if (m > i) continue;
-      float s = 0.0f;
-#pragma unroll
-      for (int c = 0; c < 16; c++) s += L[i][o + c] * L[m][o + c];
-      L[i][m] -= s;
-    }
-    __syncthreads();
+  for (int q = 0; q < 4; q++) {
+    const int e = threadIdx.x + 256 * q;
+    v[q] = *reinterpret_cast<const float4*>(M + (r0 + (e >> 4)) * ld + c0 + 4 * (e & 15));
   }
-  return bad == 0;
+}
+__device__ __forceinline__ void tile_to_lds(float (*X)[LDS_LD], const float4 v[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const int e = threadIdx.x + 256 * q;
+    const int r = e >> 4, c = 4 * (e & 15);
+    X[r][c] = v[q].x;
+    X[r][c + 1] = v[q].y;
+    X[r][c + 2] = v[q].z;
+    X[r][c + 3] = v[q].w;
+  }
 }
 
-// Li = L^{-1} for the 64 x 64 lower-triangular L, by 2 x 2 block recursion
-// [[A, 0], [C, D]]^{-1} = [[A^{-1}, 0], [-D^{-1} C A^{-1}, D^{-1}]] from 16 x 16 leaves.
-__device__ void trtri64(const float (*L)[LDS_LD], float (*Li)[LDS_LD], float* T /* 32*32 */) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += blockDim.x) Li[e / NB][e % NB] = 0.0f;
-  __syncthreads();
-  {
-    const int b = tid / 64, c = tid % 64;
-    if (b < 4 && c < 16) {
-      const int o = 16 * b;
-      float x[16];
+// Tile (r0, c0) in the accumulator layout, equilibrated by dscale when scale is set.
+__device__ __forceinline__ void acc_load(const float* __restrict__ A, int ld, size_t r0, size_t c0,
+                                         const float* __restrict__ dscale, bool scale, floatx4 v[2][2]) {
 #pragma unroll
-      for (int i = 0; i < 16; i++) {
-        float s = (i == c) ? 1.0f : 0.0f;
+  for (int a = 0; a < 2; a++)
 #pragma unroll
-        for (int m = 0; m < i; m++) s -= L[o + i][o + m] * x[m];
-        x[i] = s / L[o + i][o + i];
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const size_t row = r0 + acc_row(a, r), col = c0 + acc_col(b);
+        const float s0 = scale ? dscale[row] * dscale[col] : 1.0f;
+        v[a][b][r] = A[row * ld + col] * s0;
       }
+}
+__device__ __forceinline__ void acc_store(float* __restrict__ A, int ld, size_t r0, size_t c0, const floatx4 v[2][2]) {
 #pragma unroll
-      for (int i = 0; i < 16; i++)
-        if (i >= c) Li[o + i][o + c] = x[i];
-    }
-  }
-  __syncthreads();
-  // 16 -> 32: two independent blocks; T = C A^{-1}; X21 = -D^{-1} T (zeros above the diagonals
-  // make the full-length sums exact)
-  for (int e = tid; e < 2 * 16 * 16; e += blockDim.x) {
-    const int bb = e / 256, r = (e / 16) % 16, c = e % 16, o = 32 * bb;
-    float s = 0.0f;
+  for (int a = 0; a < 2; a++)
 #pragma unroll
-    for (int m = 0; m < 16; m++) s += L[o + 16 + r][o + m] * Li[o + m][o + c];
-    T[bb * 256 + r * 16 + c] = s;
-  }
-  __syncthreads();
-  for (int e = tid; e < 2 * 16 * 16; e += blockDim.x) {
-    const int bb = e / 256, r = (e / 16) % 16, c = e % 16, o = 32 * bb;
-    float s = 0.0f;
+    for (int b = 0; b < 2; b++)
 #pragma unroll
-    for (int m = 0; m < 16; m++) s += Li[o + 16 + r][o + 16 + m] * T[bb * 256 + m * 16 + c];
-    Li[o + 16 + r][o + c] = -s;
-  }
-  __syncthreads();
-  // 32 -> 64
-  for (int e = tid; e < 32 * 32; e += blockDim.x) {
-    const int r = e / 32, c = e % 32;
-    float s = 0.0f;
+      for (int r = 0; r < 4; r++) A[(r0 + acc_row(a, r)) * ld + c0 + acc_col(b)] = v[a][b][r];
+}
+__device__ __forceinline__ void acc_to_lds(float (*X)[LDS_LD], const floatx4 v[2][2], bool lower_only) {
 #pragma unroll
-    for (int m = 0; m < 32; m++) s += L[32 + r][m] * Li[m][c];
-    T[r * 32 + c] = s;
-  }
-  __syncthreads();
-  for (int e = tid; e < 32 * 32; e += blockDim.x) {
-    const int r = e / 32, c = e % 32;
-    float s = 0.0f;
+  for (int a = 0; a < 2; a++)
 #pragma unroll
-    for (int m = 0; m < 32; m++) s += Li[32 + r][32 + m] * T[m * 32 + c];
-    Li[32 + r][c] = -s;
-  }
-  __syncthreads();
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int row = acc_row(a, r), col = acc_col(b);
+        X[row][col] = (!lower_only || col <= row) ? v[a][b][r] : 0.0f;
+      }
+}
+__device__ __forceinline__ void acc_zero(floatx4 v[2][2]) {
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++) v[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 }
 
-__global__ __launch_bounds__(256) void k_chol_panel(float* __restrict__ A, int ld, int npad, int nb, int k,
-                                                    const float* __restrict__ dscale, float* __restrict__ Linv,
-                                                    LMScalars* sc) {
-  __shared__ float L[NB][LDS_LD];
-  __shared__ float Li[NB][LDS_LD];
-  __shared__ float B[NB][LDS_LD];
+struct CholArgs {
+  float* A;
+  int ld, npad, nb, ntasks, epoch;
+  const float* dscale;
+  float* Linv;
+  int* flags;
+  LMScalars* sc;
+};
+
+__global__ __launch_bounds__(256) void k_chol_dataflow(CholArgs P) {
+  __shared__ float X[NB][LDS_LD];
+  __shared__ float Y[NB][LDS_LD];
   __shared__ float T[32 * 32];
+  __shared__ int s_task, s_val;
   const int tid = threadIdx.x;
-  const size_t dk = (size_t)(NB * k);
-  const int ib = k + blockIdx.x;  // row block (== nb for the right-hand-side block)
-  const size_t r0 = (ib < nb) ? (size_t)(NB * ib) : (size_t)npad;
-  // block column 0 is read here for the first time: apply the equilibration D A D on the way in
-  // (the right-hand-side row arrives already scaled)
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int r = e / NB, c = e % NB;
-    const float dc = (k == 0) ? dscale[dk + c] : 1.0f;
-    L[r][c] = (c <= r) ? A[(dk + r) * ld + dk + c] * ((k == 0) ? dscale[dk + r] * dc : 1.0f) : 0.0f;
-    if (blockIdx.x > 0) {
-      const float s = (k == 0 && ib < nb) ? dscale[r0 + r] * dc : 1.0f;
-      B[r][c] = A[(r0 + r) * ld + dk + c] * s;
+  const int nb = P.nb, ld = P.ld, epoch = P.epoch;
+  const CholSync S = chol_sync(P.flags, nb);
+  int* ctr = S.ctr;
+  const uint64_t deadline = __builtin_amdgcn_s_memrealtime() + kDeadlineTicks;
+  for (;;) {
+    __syncthreads();  // every thread is done with the shared scalars of the previous task
+    if (tid == 0) {
+      const int t = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_task = t;
+      s_val = ld_flag(S.abort_) == epoch;
+      // every workgroup ends on exactly one claim >= ntasks, so this claim is the solve's last one:
+      // rearm the counter for the next solve (queued after this launch on the stream)
+      if (t == P.ntasks + (int)gridDim.x - 1) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-  }
-  __syncthreads();
-  const bool ok = potrf64(L);
-  if (blockIdx.x == 0 && tid == 0 && !ok) sc->chol_fail = 1;
-  trtri64(L, Li, T);
-  if (blockIdx.x == 0) {
-    for (int e = tid; e < NB * NB; e += blockDim.x) {
-      const int r = e / NB, c = e % NB;
-      if (c <= r) A[(dk + r) * ld + dk + c] = L[r][c];
-      Linv[(size_t)k * NB * NB + e] = Li[r][c];
+    __syncthreads();
+    const int t = s_task;
+    const bool aborted = s_val != 0;
+    if (t >= P.ntasks) break;
+    if (aborted) {
+      if (tid == 0) {
+        P.sc->chol_fail = 1;
+        P.sc->err = TT_DEVERR_CHOL_SYNC;
+      }
+      continue;
     }
-    return;
-  }
-  // L_ik = A_ik L_kk^{-T}: C[r][c] = sum_m B[r][m] Li[c][m]
-  floatx4 acc[2][2];
-  int qr, qc;
-  mma64_xyT(B, Li, acc, qr, qc);
-  const int lane = tid % 64;
+    int kind, i, c;
+    decode_task(t, nb, kind, i, c);
+    floatx4 acc[2][2], cpre[2][2];
+    if (kind == TASK_CRIT) {
+      const int j = i;
+      const size_t rj = (size_t)NB * j;
+      if (!block_wait(j >= 1 ? S.dinv + j - 1 : nullptr, j >= 2 ? S.pdiag + j : nullptr,
+                      j >= 2 ? S.psub + j : nullptr, epoch, S, deadline, &s_val))
+        continue;
+      if (j >= 1) {
+        float4 va[4], vb[4];
+        tile_load(P.A, ld, rj, rj - NB, va);
+        tile_load(P.Linv + (size_t)(j - 1) * NB * NB, NB, 0, 0, vb);
+        acc_load(P.A, ld, rj, rj, P.dscale, j <= 1, cpre);
+        if (j == 1) {  // raw tile: equilibrate here
 #pragma unroll
-  for (int a = 0; a < 2; a++)
+          for (int q = 0; q < 4; q++) {
+            const int e = tid + 256 * q;
+            const float sr = P.dscale[NB + (e >> 4)];
+            const int cc = 4 * (e & 15);
+            va[q].x *= sr * P.dscale[cc];
+            va[q].y *= sr * P.dscale[cc + 1];
+            va[q].z *= sr * P.dscale[cc + 2];
+            va[q].w *= sr * P.dscale[cc + 3];
+          }
+        }
+        tile_to_lds(X, va);
+        tile_to_lds(Y, vb);
+        __syncthreads();
+        acc_zero(acc);
+        mma64_acc(X, Y, acc);  // L_{j,j-1}
+        __syncthreads();
+        acc_store(P.A, ld, rj, rj - NB, acc);
+        acc_to_lds(X, acc, false);
+        block_publish(S.fin + (size_t)j * nb + (j - 1), epoch);
+        __syncthreads();
+        acc_zero(acc);
+        mma64_acc(X, X, acc);
 #pragma unroll
-    for (int b = 0; b < 2; b++)
+        for (int a = 0; a < 2; a++)
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int row = qr + 16 * a + 4 * (lane / 16) + r, col = qc + 16 * b + lane % 16;
-        A[(r0 + row) * ld + dk + col] = acc[a][b][r];
+          for (int b = 0; b < 2; b++) cpre[a][b] -= acc[a][b];
+        __syncthreads();
+      } else {
+        acc_load(P.A, ld, 0, 0, P.dscale, true, cpre);
       }
-}
-
-// trailing update A_ij -= L_ik L_jk^T over 64 x 64 tiles
-__global__ __launch_bounds__(256) void k_chol_update(float* __restrict__ A, int ld, int npad, int nb, int k,
-                                                     const float* __restrict__ dscale) {
-  __shared__ float Si[NB][LDS_LD];
-  __shared__ float Sj[NB][LDS_LD];
-  const int m = nb - 1 - k;  // trailing block columns
-  const int tri = m * (m + 1) / 2;
-  const int t = blockIdx.x;
-  int ii, jj;
-  if (t < tri) {
-    ii = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
-    while ((ii + 1) * (ii + 2) / 2 <= t) ii++;
-    while (ii * (ii + 1) / 2 > t) ii--;
-    jj = t - ii * (ii + 1) / 2;
-  } else {
-    ii = m;  // right-hand-side block
-    jj = t - tri;
-  }
-  const int bi = k + 1 + ii, bj = k + 1 + jj;
-  const size_t ri = (bi < nb) ? (size_t)(NB * bi) : (size_t)npad;
-  const size_t rj = (size_t)(NB * bj);
-  const size_t ck = (size_t)(NB * k);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB / 4; e += 256) {
-    const int r = e / (NB / 4), c4 = (e % (NB / 4)) * 4;
-    const float4 a = *reinterpret_cast<const float4*>(A + (ri + r) * ld + ck + c4);
-    const float4 b = *reinterpret_cast<const float4*>(A + (rj + r) * ld + ck + c4);
-    Si[r][c4] = a.x; Si[r][c4 + 1] = a.y; Si[r][c4 + 2] = a.z; Si[r][c4 + 3] = a.w;
-    Sj[r][c4] = b.x; Sj[r][c4 + 1] = b.y; Sj[r][c4 + 2] = b.z; Sj[r][c4 + 3] = b.w;
-  }
-  __syncthreads();
-  floatx4 acc[2][2];
-  int qr, qc;
-  mma64_xyT(Si, Sj, acc, qr, qc);
-  const int lane = tid % 64;
-#pragma unroll
-  for (int a = 0; a < 2; a++)
-#pragma unroll
-    for (int b = 0; b < 2; b++)
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const size_t row = ri + qr + 16 * a + 4 * (lane / 16) + r;
-        const size_t c = rj + qc + 16 * b + lane % 16;
-        // step 0 is the first touch of every trailing tile: equilibrate it (not the rhs row)
-        const float s = (k == 0 && bi < nb) ? dscale[row] * dscale[c] : 1.0f;
-        A[row * ld + c] = A[row * ld + c] * s - acc[a][b][r];
+      acc_to_lds(Y, cpre, true);
+      __syncthreads();
+      const bool ok = potrf_trtri64(Y, X, T);
+      float* Lj = P.Linv + (size_t)j * NB * NB;
+      for (int e = tid; e < NB * NB / 4; e += 256) {
+        const int r = e >> 4, cc = 4 * (e & 15);
+        *reinterpret_cast<float4*>(Lj + r * NB + cc) = make_float4(X[r][cc], X[r][cc + 1], X[r][cc + 2], X[r][cc + 3]);
       }
+      block_publish(S.dinv + j, epoch);
+      if (tid == 0 && !ok) P.sc->chol_fail = 1;
+      continue;
+    }
+    // DIAGP / SUBP / FULL: accumulate the finished columns k < nk into the tile
+    const int nk = (kind == TASK_DIAGP) ? c - 1 : c;
+    const size_t ri = (i < nb) ? (size_t)NB * i : (size_t)P.npad;
+    const size_t rc = (size_t)NB * c;
+    const bool same = (i == c);
+    acc_load(P.A, ld, ri, rc, P.dscale, i < nb, cpre);
+    acc_zero(acc);
+    const int* fi = S.fin + (size_t)i * nb;
+    const int* fc = S.fin + (size_t)c * nb;
+    bool ok = true;
+    if (nk > 0) {
+      int kr = block_ready_prefix(fi, fc, 0, nk, epoch, S, deadline, &s_val);
+      ok = kr > 0;
+      float4 va[4], vb[4];
+      if (ok) {
+        tile_load(P.A, ld, ri, 0, va);
+        if (!same) tile_load(P.A, ld, rc, 0, vb);
+      }
+      for (int k = 0; ok && k < nk; k++) {
+        __syncthreads();
+        tile_to_lds(X, va);
+        if (!same) tile_to_lds(Y, vb);
+        __syncthreads();
+        if (k + 1 < nk) {
+          if (k + 1 >= kr) {
+            const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, deadline, &s_val);
+            if (more == 0) {
+              ok = false;
+              break;
+            }
+            kr = k + 1 + more;
+          }
+          tile_load(P.A, ld, ri, (size_t)NB * (k + 1), va);
+          if (!same) tile_load(P.A, ld, rc, (size_t)NB * (k + 1), vb);
+        }
+        if (same) mma64_acc(X, X, acc);
+        else mma64_acc(X, Y, acc);
+      }
+    }
+    if (!ok) continue;
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int b = 0; b < 2; b++) cpre[a][b] -= acc[a][b];
+    if (kind != TASK_FULL) {
+      acc_store(P.A, ld, ri, rc, cpre);
+      block_publish(kind == TASK_DIAGP ? S.pdiag + i : S.psub + i, epoch);
+      continue;
+    }
+    if (!block_wait(S.dinv + c, nullptr, nullptr, epoch, S, deadline, &s_val)) continue;
+    {
+      float4 vb[4];
+      tile_load(P.Linv + (size_t)c * NB * NB, NB, 0, 0, vb);
+      acc_to_lds(X, cpre, false);
+      tile_to_lds(Y, vb);
+    }
+    __syncthreads();
+    acc_zero(acc);
+    mma64_acc(X, Y, acc);
+    acc_store(P.A, ld, ri, rc, acc);
+    block_publish(S.fin + (size_t)i * nb + c, epoch);
+  }
 }
 
 constexpr long long kSpinLimit = 1ll << 22;
 
+// Hand-over between workgroups of the back substitution: results and flags are written and read
+// with agent-scope atomics (coherent across the whole device, not held in one XCD's L2); a
+// producer waits for its result stores to complete before raising the flag, and a consumer reads
+// the results only after it has seen the flag.
 __device__ __forceinline__ bool wait_flag(const int* flag, int epoch) {
   long long spins = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
     if (++spins > kSpinLimit) return false;
     __builtin_amdgcn_s_sleep(1);
   }
@@ -312,50 +607,67 @@ __global__ __launch_bounds__(64) void k_chol_backsolve(const float* __restrict__
   const int j = nb - 1 - (int)blockIdx.x;
   const int c = threadIdx.x;
   const float* yrow = A + (size_t)npad * ld;
+  const float y = yrow[NB * j + c];
+  const float* Li = Linv + (size_t)j * NB * NB;
+  float lic[NB];
+#pragma unroll
+  for (int m = 0; m < NB; m++) lic[m] = Li[m * NB + c];
   float acc = 0.0f;
   bool ok = true;
   for (int k = nb - 1; k > j; k--) {
-    // the tile column is ready (written by the factorisation); load it before waiting
+    // the tile column is final (written by the factorisation): fetch it before waiting
     float col[NB];
 #pragma unroll
     for (int m = 0; m < NB; m++) col[m] = A[(size_t)(NB * k + m) * ld + NB * j + c];
     if (c == 0) ok = wait_flag(flags + k, epoch) && ok;
     __syncthreads();
-    __threadfence();
     xs[c] = __hip_atomic_load(x + NB * k + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < NB; m++) acc += col[m] * xs[m];
     __syncthreads();
   }
-  rs[c] = yrow[NB * j + c] - acc;
+  rs[c] = y - acc;
   __syncthreads();
-  const float* Li = Linv + (size_t)j * NB * NB;
   float s = 0.0f;
-#pragma unroll 8
-  for (int m = 0; m < NB; m++) s += Li[m * NB + c] * rs[m];
+#pragma unroll
+  for (int m = 0; m < NB; m++) s += lic[m] * rs[m];
   __hip_atomic_store(x + NB * j + c, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);  // this lane's result store has completed
   __syncthreads();
   if (c == 0) {
-    __threadfence();
-    __hip_atomic_store(flags + j, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (!ok) sc->chol_fail = 1;
+    __hip_atomic_store(flags + j, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!ok) {
+      sc->chol_fail = 1;
+      sc->err = TT_DEVERR_CHOL_SYNC;
+    }
   }
 }
 
 }  // namespace
 
-hipError_t launch_cholesky_solve(DevState& d, int epoch, hipStream_t st) {
-  const int nb = d.nb;
-  for (int k = 0; k < nb; k++) {
-    hipLaunchKernelGGL(k_chol_panel, dim3(nb - k + 1), dim3(256), 0, st, d.A, d.ld, d.npad, nb, k, d.dscale, d.Linv,
-                       d.sc);
-    const int m = nb - 1 - k;
-    const int tiles = m * (m + 1) / 2 + m;
-    if (tiles > 0)
-      hipLaunchKernelGGL(k_chol_update, dim3(tiles), dim3(256), 0, st, d.A, d.ld, d.npad, nb, k, d.dscale);
-  }
-  hipLaunchKernelGGL(k_chol_backsolve, dim3(nb), dim3(64), 0, st, d.A, d.ld, d.npad, nb, d.Linv, d.x, d.flags,
+size_t chol_flag_ints(int nb) { return (size_t)nb + (size_t)(nb + 1) * nb + 3 * (size_t)nb + 2; }
+
+hipError_t launch_cholesky_factor(DevState& d, int epoch, hipStream_t st) {
+  CholArgs P;
+  P.A = d.A;
+  P.ld = d.ld;
+  P.npad = d.npad;
+  P.nb = d.nb;
+  P.ntasks = chol_task_count(d.nb);
+  P.epoch = epoch;
+  P.dscale = d.dscale;
+  P.Linv = d.Linv;
+  P.flags = d.flags;
+  P.sc = d.sc;
+  const int cus = d.num_cus > 0 ? d.num_cus : 256;
+  const int grid = P.ntasks < 2 * cus ? P.ntasks : 2 * cus;
+  hipLaunchKernelGGL(k_chol_dataflow, dim3(grid), dim3(256), 0, st, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholesky_backsolve(DevState& d, int epoch, hipStream_t st) {
+  hipLaunchKernelGGL(k_chol_backsolve, dim3(d.nb), dim3(64), 0, st, d.A, d.ld, d.npad, d.nb, d.Linv, d.x, d.flags,
                      epoch, d.sc);
   return hipGetLastError();
 }

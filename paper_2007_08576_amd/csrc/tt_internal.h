@@ -41,8 +41,10 @@ struct LMScalars {
   int chol_fail;     // set by the factorisation when a pivot is not positive
   int accept;        // decision of the last iteration
   int it;            // iteration counter
-  int err;           // device-side error bits
+  int err;           // device-side error bits (TT_DEVERR_*), reported as TT_EDEVICE
 };
+
+#define TT_DEVERR_CHOL_SYNC 1  // a hand-over wait of the factorisation passed its deadline
 
 struct DevState {
   // sizes
@@ -99,7 +101,8 @@ struct DevState {
   float* x = nullptr;        // [npad] solution of the equilibrated system
   float* dscale = nullptr;   // [npad] symmetric diagonal equilibration d_k = 1/sqrt(damped A_kk)
   float* Linv = nullptr;     // [nb][TT_NB][TT_NB]
-  int* flags = nullptr;      // [nb] back-substitution block flags (epoch of the solve)
+  int* flags = nullptr;      // [chol_flag_ints(nb)] factorisation and back-substitution flags
+  int num_cus = 0;           // compute units of the device (persistent launch size)
   double* partial = nullptr; // reduction partials
   int npartial = 0;
   LMScalars* sc = nullptr;
@@ -134,8 +137,8 @@ struct tt_stream {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
-  double stage_ms[TT_NSTAGES] = {0, 0, 0, 0, 0, 0};
-  int64_t stage_n[TT_NSTAGES] = {0, 0, 0, 0, 0, 0};
+  double stage_ms[TT_NSTAGES] = {};
+  int64_t stage_n[TT_NSTAGES] = {};
 };
 
 // ---- launchers (each queues kernels on st and returns hipGetLastError()) --------------------
@@ -161,4 +164,9 @@ hipError_t launch_lm_damp(DevState& d, hipStream_t st);
 hipError_t launch_lm_finish(DevState& d, const tt_params& P, const Intr& K, hipStream_t st);
 hipError_t launch_deform_out(const DevState& d, float* out_xyz, float* out_dq, hipStream_t st);
 
-hipError_t launch_cholesky_solve(DevState& d, int epoch, hipStream_t st);
+// Ints of the flag area used by one Cholesky solve (tile flags, ticket counters, abort word).
+size_t chol_flag_ints(int nb);
+// Factorisation of the damped, equilibrated system (forward substitution included), then the back
+// substitution into d.x; epoch tags this solve's flags.
+hipError_t launch_cholesky_factor(DevState& d, int epoch, hipStream_t st);
+hipError_t launch_cholesky_backsolve(DevState& d, int epoch, hipStream_t st);

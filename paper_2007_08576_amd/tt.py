@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtt.so")
 
 TT_OK, TT_EINVAL, TT_ENOMEM, TT_ESTATE, TT_EDEVICE, TT_EBUSY = 0, -1, -2, -3, -4, -5
 TT_FP32 = 0
-STAGES = ("front", "rows", "arap", "data", "solve", "update")
+STAGES = ("front", "rows", "arap", "data", "solve", "update", "factor")
 
 _lib = None
 

@@ -12,7 +12,7 @@ def T():
     return tt
 
 
-@pytest.mark.parametrize("n", [1, 7, 64, 72, 128, 200, 384, 700])
+@pytest.mark.parametrize("n", [1, 7, 64, 72, 128, 200, 384, 700, 2400])
 def test_cholesky_solve_random_spd(T, n):
     rng = np.random.default_rng(n)
     B = rng.normal(size=(n, n))
