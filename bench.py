@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--frames", type=int, default=8, help="distinct synthetic frames (replayed ping-pong)")
     ap.add_argument("--cpu-lm-sample", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the run, copy this many MiB device-to-device 3 times (a plain copy of known "
+                         "size whose FETCH_SIZE / WRITE_SIZE counters calibrate the HBM traffic readings)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -182,6 +185,14 @@ def main():
         out["rms_vs_oracle_mm"] = float(np.sqrt(((vg - vo) ** 2).sum(1).mean()))
         out["rms_vs_oracle_note"] = f"frame 1 from identity, {args.cpu_lm_sample} LM iterations on both sides"
     print(json.dumps(out), flush=True)
+    if args.copy_calibration_mib > 0:
+        nf = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(nf, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {args.copy_calibration_mib} MiB read + written")
 
 
 if __name__ == "__main__":

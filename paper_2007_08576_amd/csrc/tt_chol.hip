@@ -25,29 +25,73 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 #define MFMA16(a, b, c) __builtin_amdgcn_mfma_f32_16x16x4f32((a), (b), (c), 0, 0, 0)
 
-// Broadcast of lane n of each 16-lane row to the whole row (DPP row_newbcast, a VALU operand
-// modifier: no LDS traffic). n must fold to a constant (the callers' loops are fully unrolled).
-__device__ __forceinline__ float bcast16(float v, int n) {
-  int x = __float_as_int(v);
+// Row broadcasts (DPP row_newbcast: lane n of each 16-lane row feeds the whole row; a VALU operand
+// modifier, no LDS traffic). n must fold to a constant (the callers' loops are fully unrolled).
+// Written as inline assembly so that the broadcast and the multiply-add are one v_fmac_f32_dpp; the
+// leading s_nop gives the two wait states a DPP source needs after a VALU write to it.
+__device__ __forceinline__ float bcast16(float v, int n) {  // returns v of lane n of the row
+  float d;
   switch (n) {
-    case 0: x = __builtin_amdgcn_mov_dpp(x, 0x150, 0xF, 0xF, false); break;
-    case 1: x = __builtin_amdgcn_mov_dpp(x, 0x151, 0xF, 0xF, false); break;
-    case 2: x = __builtin_amdgcn_mov_dpp(x, 0x152, 0xF, 0xF, false); break;
-    case 3: x = __builtin_amdgcn_mov_dpp(x, 0x153, 0xF, 0xF, false); break;
-    case 4: x = __builtin_amdgcn_mov_dpp(x, 0x154, 0xF, 0xF, false); break;
-    case 5: x = __builtin_amdgcn_mov_dpp(x, 0x155, 0xF, 0xF, false); break;
-    case 6: x = __builtin_amdgcn_mov_dpp(x, 0x156, 0xF, 0xF, false); break;
-    case 7: x = __builtin_amdgcn_mov_dpp(x, 0x157, 0xF, 0xF, false); break;
-    case 8: x = __builtin_amdgcn_mov_dpp(x, 0x158, 0xF, 0xF, false); break;
-    case 9: x = __builtin_amdgcn_mov_dpp(x, 0x159, 0xF, 0xF, false); break;
-    case 10: x = __builtin_amdgcn_mov_dpp(x, 0x15a, 0xF, 0xF, false); break;
-    case 11: x = __builtin_amdgcn_mov_dpp(x, 0x15b, 0xF, 0xF, false); break;
-    case 12: x = __builtin_amdgcn_mov_dpp(x, 0x15c, 0xF, 0xF, false); break;
-    case 13: x = __builtin_amdgcn_mov_dpp(x, 0x15d, 0xF, 0xF, false); break;
-    case 14: x = __builtin_amdgcn_mov_dpp(x, 0x15e, 0xF, 0xF, false); break;
-    case 15: x = __builtin_amdgcn_mov_dpp(x, 0x15f, 0xF, 0xF, false); break;
+    case 0: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:0 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 1: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:1 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 2: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:2 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 3: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:3 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 4: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:4 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 5: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:5 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 6: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:6 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 7: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:7 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 8: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:8 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 9: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:9 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 10: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:10 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 11: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:11 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 12: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:12 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 13: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:13 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 14: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:14 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 15: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:15 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
   }
-  return __int_as_float(x);
+  return d;
+}
+__device__ __forceinline__ void fmac_bcast16(float& acc, float src, float mul, int n, bool guard) {
+  // acc += (src of lane n of the row) * mul
+  if (guard) {
+    switch (n) {
+    case 0: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 1: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:1 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 2: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:2 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 3: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 4: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:4 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 5: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:5 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 6: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:6 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 7: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:7 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 8: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 9: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:9 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 10: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:10 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 11: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:11 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 12: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:12 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 13: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:13 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 14: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:14 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 15: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:15 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    }
+  } else {
+    switch (n) {
+    case 0: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 1: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:1 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 2: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:2 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 3: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 4: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:4 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 5: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:5 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 6: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:6 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 7: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:7 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 8: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 9: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:9 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 10: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:10 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 11: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:11 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 12: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:12 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 13: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:13 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 14: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:14 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 15: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:15 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    }
+  }
 }
 
 // 16 x 16 leaf on one wavefront: factors the block at (o, o) of L in place (lower, zeros above)
@@ -71,11 +115,13 @@ __device__ __forceinline__ void leaf16(float (*L)[LDS_LD], float (*Li)[LDS_LD], 
     ok = ok && (d > 0.0f);
     const float il = __builtin_amdgcn_rsqf(d);
     invd[j] = il;
-    const float lr = (r > j) ? a[j] * il : 0.0f;
+    // lane masks as integer arithmetic (all ones where r > j, resp. r == j)
+    const int gt = (j - r) >> 31, eq = ((r ^ j) - 1) >> 31;
+    const float lr = __int_as_float(__float_as_int(a[j] * il) & gt);
     const float nlr = -lr;
-    a[j] = (r > j) ? lr : ((r == j) ? d * il : 0.0f);
+    a[j] = __int_as_float(__float_as_int(lr) | (__float_as_int(d * il) & eq));
 #pragma unroll
-    for (int m = j + 1; m < 16; m++) a[m] = fmaf(bcast16(lr, m), nlr, a[m]);
+    for (int m = j + 1; m < 16; m++) fmac_bcast16(a[m], lr, nlr, m, m == j + 1);
   }
   if (writer) {
 #pragma unroll
@@ -89,7 +135,7 @@ __device__ __forceinline__ void leaf16(float (*L)[LDS_LD], float (*Li)[LDS_LD], 
     x[i] = p[i] * invd[i];
     const float nx = -x[i];
 #pragma unroll
-    for (int k = i + 1; k < 16; k++) p[k] = fmaf(bcast16(a[i], k), nx, p[k]);
+    for (int k = i + 1; k < 16; k++) fmac_bcast16(p[k], a[i], nx, k, k == i + 1);
   }
   if (writer) {
 #pragma unroll
@@ -97,92 +143,151 @@ __device__ __forceinline__ void leaf16(float (*L)[LDS_LD], float (*Li)[LDS_LD], 
   }
 }
 
-// Cholesky factor (in place, lower, zeros above) and inverse Li of the 64 x 64 block in LDS,
-// blocked by 16: per block column a leaf (above), then the rows below are solved against the
-// leaf inverse and the trailing lower triangle is updated, both as 16 x 16 x 16 products on the
-// matrix cores; finally the inverse is assembled by the 2 x 2 block recursion
-// [[A, 0], [C, D]]^{-1} = [[A^{-1}, 0], [-D^{-1} C A^{-1}, D^{-1}]] (16 -> 32 -> 64), also on the
-// matrix cores. Returns false if a pivot is not positive. All 256 threads must call it.
-__device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LDS_LD], float* T /* 32 x 32 */) {
-  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  const int li = lane % 16, lk = lane / 16;
+// 16 x 16 tile products on the matrix cores (v_mfma_f32_16x16x4f32), row-major tiles in LDS with
+// strides given as template arguments. acc element q of lane (li, lk) = (lane % 16, lane / 16) is
+// entry (4 lk + q, li).
+template <int SA, int SB>
+__device__ __forceinline__ floatx4 mm16_abt(const float* A, const float* B, floatx4 acc) {  // acc += A B^T
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 16; kk += 4) acc = MFMA16(A[li * SA + kk + lk], B[li * SB + kk + lk], acc);
+  return acc;
+}
+template <int SA, int SB>
+__device__ __forceinline__ floatx4 mm16_ab(const float* A, const float* B, floatx4 acc) {  // acc += A B
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 16; kk += 4) acc = MFMA16(A[li * SA + kk + lk], B[(kk + lk) * SB + li], acc);
+  return acc;
+}
+template <int SC>
+__device__ __forceinline__ void put16(float* C, floatx4 acc, float sign) {  // C = sign * acc
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; q++) C[(4 * lk + q) * SC + li] = sign * acc[q];
+}
+template <int SC>
+__device__ __forceinline__ void sub16(float* C, floatx4 acc) {  // C -= acc
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; q++) C[(4 * lk + q) * SC + li] -= acc[q];
+}
+
+constexpr int XS = 18;  // stride of the 16 x 16 scratch tiles
+constexpr int TS = 34;  // stride of the 32 x 32 scratch block
+constexpr int POTRF_SCRATCH_FLOATS = 8 * 16 * XS + 32 * TS;
+
+// Cholesky factor and inverse Li of the 64 x 64 lower triangle in L (LDS), blocked by 16. Writing
+// T_rc for the 16 x 16 tiles of L and X_rk = T_rk Li_kk^T for the factor's off-diagonal tiles, the
+// serial chain is leaf(k) -> X_{k+1,k} -> T_{k+1,k+1} -= X X^T -> leaf(k+1); wavefront 0 runs only
+// that chain, while wavefronts 1-3 compute the other X tiles (each keeps its own copy of the ones it
+// needs; copies of one tile are bit-identical), the trailing updates and the blocks of the inverse,
+// [[A, 0], [C, D]]^{-1} = [[A^{-1}, 0], [-D^{-1} C A^{-1}, D^{-1}]] (16 -> 32 -> 64). Six barriers.
+// L's off-diagonal tiles are left as the updated T (only Li is an output); scratch holds
+// POTRF_SCRATCH_FLOATS floats of LDS. Returns false if a pivot is not positive. All 256 threads
+// must call it.
+__device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LDS_LD], float* scratch) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  float* XB = scratch;               // X tiles: 0 = X10, 1 = X20, 2 = X30, 3 = X21, 4 = X31, 5 = X32
+  float* W01 = XB + 6 * 16 * XS;     // X10 Li00
+  float* W23 = W01 + 16 * XS;        // X32 Li22
+  float* TT = W23 + 16 * XS;         // C A^{-1}, 32 x 32
   __shared__ int bad;
-  if (tid == 0) bad = 0;
-  for (int e = tid; e < NB * NB; e += blockDim.x) Li[e / NB][e % NB] = 0.0f;
-  __syncthreads();
-#pragma unroll 1
-  for (int kb = 0; kb < 4; kb++) {
-    const int o = 16 * kb;
-    if (wave == 0) {
-      bool ok = true;
-      leaf16(L, Li, o, ok);
-      if (lane == 0 && !ok) bad = 1;
+  auto Xt = [&](int id) { return XB + id * 16 * XS; };
+  auto Lt = [&](int r, int c) { return &L[16 * r][16 * c]; };
+  auto Lit = [&](int r, int c) { return &Li[16 * r][16 * c]; };
+  auto TTt = [&](int r, int c) { return TT + 16 * r * TS + 16 * c; };
+  const floatx4 z4 = {0.f, 0.f, 0.f, 0.f};
+  // X_rk = T_rk Li_kk^T into scratch tile id
+  auto makeX = [&](int r, int k, int id) { put16<XS>(Xt(id), mm16_abt<LDS_LD, LDS_LD>(Lt(r, k), Lit(k, k), z4), 1.0f); };
+  // T_rc -= X_a X_b^T
+  auto updT = [&](int r, int c, int a, int b) { sub16<LDS_LD>(Lt(r, c), mm16_abt<XS, XS>(Xt(a), Xt(b), z4)); };
+  auto leaf = [&](int k) {
+    bool ok = true;
+    leaf16(L, Li, 16 * k, ok);
+    if (lane == 0 && !ok) bad = 1;
+  };
+  // phase 1: leaf 0; the other wavefronts clear the upper tiles of Li
+  if (wave == 0) {
+    if (lane == 0) bad = 0;
+    leaf(0);
+  } else {
+    for (int e = tid - 64; e < 6 * 256; e += 192) {
+      const int t = e >> 8, w = e & 255;
+      const int r = (t < 3) ? 0 : (t < 5 ? 1 : 2);
+      const int c = (t < 3) ? 1 + t : (t < 5 ? t - 1 : 3);
+      Li[16 * r + (w >> 4)][16 * c + (w & 15)] = 0.0f;
     }
-    __syncthreads();
-    const int nt = 3 - kb;  // 16-row tiles below the leaf
-    if (nt == 0) break;
-    // rows below: X = B D^{-T}, one 16 x 16 tile per wavefront
-    if (wave < nt) {
-      const int rb = o + 16 + 16 * wave;
-      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) acc = MFMA16(L[rb + li][o + kk + lk], Li[o + li][o + kk + lk], acc);
-#pragma unroll
-      for (int q = 0; q < 4; q++) L[rb + 4 * lk + q][o + li] = acc[q];
-    }
-    __syncthreads();
-    // trailing lower triangle -= X X^T (K = 16); diagonal tiles keep their upper part zero
-    const int ntiles = nt * (nt + 1) / 2;
-    for (int t = wave; t < ntiles; t += 4) {
-      int ti = 0;
-      while ((ti + 1) * (ti + 2) / 2 <= t) ti++;
-      const int tj = t - ti * (ti + 1) / 2;
-      const int r0 = o + 16 + 16 * ti, c0 = o + 16 + 16 * tj;
-      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) acc = MFMA16(L[r0 + li][o + kk + lk], L[c0 + li][o + kk + lk], acc);
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const int rr = r0 + 4 * lk + q, cc = c0 + li;
-        if (cc <= rr) L[rr][cc] -= acc[q];
-      }
-    }
-    __syncthreads();
-  }
-  // inverse 16 -> 32: wavefronts 0 and 1 take one 32-block each
-  if (wave < 2) {
-    const int o = 32 * wave;
-    float* Tw = T + wave * 256;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) acc = MFMA16(L[o + 16 + li][o + kk + lk], Li[o + kk + lk][o + li], acc);
-#pragma unroll
-    for (int q = 0; q < 4; q++) Tw[(4 * lk + q) * 16 + li] = acc[q];
-    __builtin_amdgcn_wave_barrier();
-    floatx4 acc2 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) acc2 = MFMA16(Li[o + 16 + li][o + 16 + kk + lk], Tw[(kk + lk) * 16 + li], acc2);
-#pragma unroll
-    for (int q = 0; q < 4; q++) Li[o + 16 + 4 * lk + q][o + li] = -acc2[q];
   }
   __syncthreads();
-  // 32 -> 64: wavefront w computes output tile (w / 2, w % 2) of T = C A^{-1}, then of -D^{-1} T
-  {
-    const int ti = wave / 2, tj = wave % 2;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < 32; kk += 4) acc = MFMA16(L[32 + 16 * ti + li][kk + lk], Li[kk + lk][16 * tj + li], acc);
-#pragma unroll
-    for (int q = 0; q < 4; q++) T[(16 * ti + 4 * lk + q) * 32 + 16 * tj + li] = acc[q];
+  // phase 2
+  if (wave == 0) {
+    makeX(1, 0, 0);
+    updT(1, 1, 0, 0);
+    leaf(1);
+  } else if (wave == 1) {
+    makeX(1, 0, 0);
+    makeX(2, 0, 1);
+    updT(2, 1, 1, 0);
+    updT(2, 2, 1, 1);
+  } else if (wave == 2) {
+    makeX(1, 0, 0);
+    makeX(2, 0, 1);
+    makeX(3, 0, 2);
+    updT(3, 1, 2, 0);
+    updT(3, 2, 2, 1);
+  } else {
+    makeX(3, 0, 2);
+    updT(3, 3, 2, 2);
   }
   __syncthreads();
-  {
-    const int ti = wave / 2, tj = wave % 2;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < 32; kk += 4) acc = MFMA16(Li[32 + 16 * ti + li][32 + kk + lk], T[(kk + lk) * 32 + 16 * tj + li], acc);
-#pragma unroll
-    for (int q = 0; q < 4; q++) Li[32 + 16 * ti + 4 * lk + q][16 * tj + li] = -acc[q];
+  // phase 3
+  if (wave == 0) {
+    makeX(2, 1, 3);
+    updT(2, 2, 3, 3);
+    leaf(2);
+  } else if (wave == 1) {
+    makeX(2, 1, 3);
+    makeX(3, 1, 4);
+    updT(3, 2, 4, 3);
+  } else if (wave == 2) {
+    makeX(3, 1, 4);
+    updT(3, 3, 4, 4);
+  } else {
+    put16<XS>(W01, mm16_ab<XS, LDS_LD>(Xt(0), Lit(0, 0), z4), 1.0f);
+    put16<LDS_LD>(Lit(1, 0), mm16_ab<LDS_LD, XS>(Lit(1, 1), W01, z4), -1.0f);
+  }
+  __syncthreads();
+  // phase 4
+  if (wave == 0) {
+    makeX(3, 2, 5);
+    updT(3, 3, 5, 5);
+    leaf(3);
+  } else if (wave == 1) {
+    put16<TS>(TTt(0, 0), mm16_ab<XS, LDS_LD>(Xt(3), Lit(1, 0), mm16_ab<XS, LDS_LD>(Xt(1), Lit(0, 0), z4)), 1.0f);
+    put16<TS>(TTt(0, 1), mm16_ab<XS, LDS_LD>(Xt(3), Lit(1, 1), z4), 1.0f);
+  } else if (wave == 2) {
+    put16<TS>(TTt(1, 0), mm16_ab<XS, LDS_LD>(Xt(4), Lit(1, 0), mm16_ab<XS, LDS_LD>(Xt(2), Lit(0, 0), z4)), 1.0f);
+    put16<TS>(TTt(1, 1), mm16_ab<XS, LDS_LD>(Xt(4), Lit(1, 1), z4), 1.0f);
+  }
+  __syncthreads();
+  // phase 5
+  if (wave == 0) {
+    put16<XS>(W23, mm16_ab<XS, LDS_LD>(Xt(5), Lit(2, 2), z4), 1.0f);
+    put16<LDS_LD>(Lit(3, 2), mm16_ab<LDS_LD, XS>(Lit(3, 3), W23, z4), -1.0f);
+  } else if (wave == 1) {
+    put16<LDS_LD>(Lit(2, 0), mm16_ab<LDS_LD, TS>(Lit(2, 2), TTt(0, 0), z4), -1.0f);
+  } else if (wave == 2) {
+    put16<LDS_LD>(Lit(2, 1), mm16_ab<LDS_LD, TS>(Lit(2, 2), TTt(0, 1), z4), -1.0f);
+  }
+  __syncthreads();
+  // phase 6
+  if (wave == 0) {
+    put16<LDS_LD>(Lit(3, 0),
+                  mm16_ab<LDS_LD, TS>(Lit(3, 3), TTt(1, 0), mm16_ab<LDS_LD, TS>(Lit(3, 2), TTt(0, 0), z4)), -1.0f);
+  } else if (wave == 1) {
+    put16<LDS_LD>(Lit(3, 1),
+                  mm16_ab<LDS_LD, TS>(Lit(3, 3), TTt(1, 1), mm16_ab<LDS_LD, TS>(Lit(3, 2), TTt(0, 1), z4)), -1.0f);
   }
   __syncthreads();
   return bad == 0;
@@ -193,14 +298,16 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
 // Left-looking tile tasks, handed out in a fixed order through an atomic ticket counter. Task
 // kinds, for block column c (tiles are 64 x 64; row block nb is the right-hand side):
 //   CRIT(j)      the critical chain: L_{j,j-1} = C_{j,j-1} Linv_{j-1}^T, C_jj -= L_{j,j-1} L_{j,j-1}^T,
-//                then factor and invert C_jj (publishes L_{j,j-1} and Linv_j)
+//                then factor and invert C_jj (publishes L_{j,j-1} and Linv_j); all CRIT steps run
+//                on one workgroup, which keeps Linv_j in LDS from one step to the next
 //   DIAGP(j)     C_jj = A_jj - sum_{k <= j-2} L_jk L_jk^T            (j >= 2; finished by CRIT(j))
 //   SUBP(j)      C_{j,j-1} = A_{j,j-1} - sum_{k <= j-2} L_jk L_{j-1,k}^T  (j >= 2; finished by CRIT(j))
 //   FULL(i, c)   L_ic = (A_ic - sum_{k < c} L_ik L_ck^T) Linv_c^T   (i >= c + 2, and the right-hand side)
 // Order: for j = 0, 1, ...: DIAGP(j), SUBP(j), CRIT(j), FULL(j+2 .. nb-1, j), FULL(nb, j). Every task
-// waits only on tasks with smaller tickets, which were claimed by running workgroups, so the waits
-// always end whatever the number of resident workgroups. Only CRIT tasks lie on the critical path:
-// the accumulations run ahead on the other workgroups.
+// waits only on tasks with smaller tickets, which were claimed by running workgroups (the chain
+// workgroup's rule is given in the kernel), so the waits always end whatever the number of
+// resident workgroups. Only CRIT steps lie on the critical path: the accumulations run ahead on
+// the other workgroups.
 //
 // Hand-over: a producer's stores complete (s_waitcnt), then one thread releases at agent scope
 // (L2 write-back) and stores the tile's flag (the solve's epoch); a consumer polls the flag with
@@ -267,23 +374,24 @@ __device__ __forceinline__ int ld_flag(const int* f) {
   return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Thread 0 waits until every non-null flag equals epoch, then acquires; the block learns the result.
+// Thread 0 waits until every non-null flag equals epoch (the flags are read together, one round
+// trip per poll), then acquires; the block learns the result.
 __device__ bool block_wait(const int* f0, const int* f1, const int* f2, int epoch, const CholSync& S,
                            uint64_t deadline, int* s_ok) {
   if (threadIdx.x == 0) {
     bool ok = true;
-    const int* fs[3] = {f0, f1, f2};
-    for (int q = 0; q < 3 && ok; q++) {
-      if (!fs[q]) continue;
-      int spins = 0;
-      while (ld_flag(fs[q]) != epoch) {
-        if ((++spins & 15) == 0 &&
-            (ld_flag(S.abort_) == epoch || __builtin_amdgcn_s_memrealtime() > deadline)) {
-          ok = false;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
+    const int* g0 = f0 ? f0 : S.abort_;
+    const int* g1 = f1 ? f1 : S.abort_;
+    const int* g2 = f2 ? f2 : S.abort_;
+    int spins = 0;
+    for (;;) {
+      const int v0 = ld_flag(g0), v1 = ld_flag(g1), v2 = ld_flag(g2);
+      if ((!f0 || v0 == epoch) && (!f1 || v1 == epoch) && (!f2 || v2 == epoch)) break;
+      if ((++spins & 15) == 0 && (ld_flag(S.abort_) == epoch || __builtin_amdgcn_s_memrealtime() > deadline)) {
+        ok = false;
+        break;
       }
+      __builtin_amdgcn_s_sleep(2);
     }
     if (!ok) __hip_atomic_store(S.abort_, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -430,93 +538,167 @@ struct CholArgs {
   LMScalars* sc;
 };
 
+// Ticket of CRIT(j): the number of tasks in the groups before j, plus DIAGP(j) and SUBP(j).
+__device__ __forceinline__ int crit_ticket(int j, int nb) {
+  int t = 0;
+  for (int q = 0; q < j; q++) t += (q >= 2 ? 2 : 0) + 1 + (nb - q - 2 > 0 ? nb - q - 2 : 0) + 1;
+  return t + (j >= 2 ? 2 : 0);
+}
+
+enum { MODE_TASK = 0, MODE_CRIT = 1, MODE_RETRY = 2 };
+
+// The chain's inputs for step j: C_{j,j-1} (tile layout) and C_jj (accumulator layout). For j <= 1
+// these are the raw, not yet equilibrated blocks of A; later they are the partial tiles.
+__device__ __forceinline__ void chain_load(const CholArgs& P, int j, float4 va[4], floatx4 cp[2][2]) {
+  const size_t rj = (size_t)NB * j;
+  acc_load(P.A, P.ld, rj, rj, P.dscale, j <= 1, cp);
+  if (j == 0) return;
+  tile_load(P.A, P.ld, rj, rj - NB, va);
+  if (j == 1) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int e = threadIdx.x + 256 * q;
+      const float sr = P.dscale[NB + (e >> 4)];
+      const int cc = 4 * (e & 15);
+      va[q].x *= sr * P.dscale[cc];
+      va[q].y *= sr * P.dscale[cc + 1];
+      va[q].z *= sr * P.dscale[cc + 2];
+      va[q].w *= sr * P.dscale[cc + 3];
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_chol_dataflow(CholArgs P) {
   __shared__ float X[NB][LDS_LD];
   __shared__ float Y[NB][LDS_LD];
-  __shared__ float T[32 * 32];
-  __shared__ int s_task, s_val;
+  __shared__ float Z[NB][LDS_LD];  // the chain's Linv_{j-1} between CRIT steps
+  static_assert(POTRF_SCRATCH_FLOATS <= NB * LDS_LD, "factorisation scratch must fit in one tile buffer");
+  __shared__ int s_task, s_val, s_mode;
   const int tid = threadIdx.x;
   const int nb = P.nb, ld = P.ld, epoch = P.epoch;
   const CholSync S = chol_sync(P.flags, nb);
   int* ctr = S.ctr;
   const uint64_t deadline = __builtin_amdgcn_s_memrealtime() + kDeadlineTicks;
+  // The workgroup that claims ticket 0 (CRIT(0)) runs the whole critical chain CRIT(0..nb-1) and
+  // keeps each Linv_j in LDS for the next step; CRIT tickets claimed by others are empty. Before
+  // CRIT(j) may wait on DIAGP(j) and SUBP(j), their tickets must have been handed out: until the
+  // counter has passed them, the chain workgroup claims the next ticket itself (compare-and-swap,
+  // so it never takes one at or beyond CRIT(j)) and runs that task, which depends only on smaller
+  // tickets. So the waits end whatever the number of resident workgroups.
+  int chain = -1;
+  int ctr_seen = 0;          // thread 0: last counter value read by the chain (the counter only grows)
+  bool have_pref = false;    // the chain's inputs for its next step are already in cva / ccp
+  float4 cva[4];             // chain prefetch: C_{j,j-1} (tile layout)
+  floatx4 ccp[2][2];         // chain prefetch: C_jj (accumulator layout)
   for (;;) {
-    __syncthreads();  // every thread is done with the shared scalars of the previous task
+    __syncthreads();  // every thread is done with the shared scalars of the previous step
     if (tid == 0) {
-      const int t = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int t = -1, mode = MODE_TASK;
+      bool chain_fast = false;
+      if (chain >= 0) {
+        const int need = crit_ticket(chain, nb);
+        if (ctr_seen < need) ctr_seen = ld_flag(ctr);
+        const int cur = ctr_seen;
+        if (cur >= need) {
+          mode = MODE_CRIT;
+          chain_fast = true;
+        } else {
+          int expect = cur;
+          mode = __hip_atomic_compare_exchange_strong(ctr, &expect, cur + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)
+                     ? MODE_TASK
+                     : MODE_RETRY;
+          t = cur;
+        }
+      } else {
+        t = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // every workgroup ends on exactly one such claim >= ntasks, so this claim is the solve's
+        // last one: rearm the counter for the next solve (queued after this launch on the stream)
+        if (t == P.ntasks + (int)gridDim.x - 1) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       s_task = t;
-      s_val = ld_flag(S.abort_) == epoch;
-      // every workgroup ends on exactly one claim >= ntasks, so this claim is the solve's last one:
-      // rearm the counter for the next solve (queued after this launch on the stream)
-      if (t == P.ntasks + (int)gridDim.x - 1) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_mode = mode;
+      // the chain's waits watch the abort word themselves; skip the extra round trip on its path
+      s_val = chain_fast ? 0 : (ld_flag(S.abort_) == epoch);
     }
     __syncthreads();
-    const int t = s_task;
+    const int t = s_task, mode = s_mode;
     const bool aborted = s_val != 0;
-    if (t >= P.ntasks) break;
+    if (mode == MODE_RETRY) continue;
+    if (mode == MODE_TASK && t >= P.ntasks) break;
     if (aborted) {
       if (tid == 0) {
         P.sc->chol_fail = 1;
         P.sc->err = TT_DEVERR_CHOL_SYNC;
       }
+      chain = -1;
       continue;
     }
-    int kind, i, c;
-    decode_task(t, nb, kind, i, c);
     floatx4 acc[2][2], cpre[2][2];
-    if (kind == TASK_CRIT) {
-      const int j = i;
+    if (mode == MODE_CRIT) {
+      const int j = chain;
       const size_t rj = (size_t)NB * j;
-      if (!block_wait(j >= 1 ? S.dinv + j - 1 : nullptr, j >= 2 ? S.pdiag + j : nullptr,
-                      j >= 2 ? S.psub + j : nullptr, epoch, S, deadline, &s_val))
-        continue;
-      if (j >= 1) {
-        float4 va[4], vb[4];
-        tile_load(P.A, ld, rj, rj - NB, va);
-        tile_load(P.Linv + (size_t)(j - 1) * NB * NB, NB, 0, 0, vb);
-        acc_load(P.A, ld, rj, rj, P.dscale, j <= 1, cpre);
-        if (j == 1) {  // raw tile: equilibrate here
-#pragma unroll
-          for (int q = 0; q < 4; q++) {
-            const int e = tid + 256 * q;
-            const float sr = P.dscale[NB + (e >> 4)];
-            const int cc = 4 * (e & 15);
-            va[q].x *= sr * P.dscale[cc];
-            va[q].y *= sr * P.dscale[cc + 1];
-            va[q].z *= sr * P.dscale[cc + 2];
-            va[q].w *= sr * P.dscale[cc + 3];
-          }
+      chain = (j + 1 < nb) ? j + 1 : -1;
+      if (!have_pref) {
+        if (j >= 2 && !block_wait(S.pdiag + j, S.psub + j, nullptr, epoch, S, deadline, &s_val)) {
+          chain = -1;
+          continue;
         }
-        tile_to_lds(X, va);
-        tile_to_lds(Y, vb);
+        chain_load(P, j, cva, ccp);
+      }
+      have_pref = false;
+      if (j >= 1) {
+        tile_to_lds(X, cva);
         __syncthreads();
         acc_zero(acc);
-        mma64_acc(X, Y, acc);  // L_{j,j-1}
+        mma64_acc(X, Z, acc);  // L_{j,j-1} = C_{j,j-1} Linv_{j-1}^T
         __syncthreads();
-        acc_store(P.A, ld, rj, rj - NB, acc);
+        acc_store(P.A, ld, rj, rj - NB, acc);  // completes while the update below runs
         acc_to_lds(X, acc, false);
-        block_publish(S.fin + (size_t)j * nb + (j - 1), epoch);
         __syncthreads();
         acc_zero(acc);
         mma64_acc(X, X, acc);
 #pragma unroll
         for (int a = 0; a < 2; a++)
 #pragma unroll
-          for (int b = 0; b < 2; b++) cpre[a][b] -= acc[a][b];
-        __syncthreads();
-      } else {
-        acc_load(P.A, ld, 0, 0, P.dscale, true, cpre);
+          for (int b = 0; b < 2; b++) ccp[a][b] -= acc[a][b];
       }
-      acc_to_lds(Y, cpre, true);
-      __syncthreads();
-      const bool ok = potrf_trtri64(Y, X, T);
+      acc_to_lds(Y, ccp, true);
+      if (j >= 1) block_publish(S.fin + (size_t)j * nb + (j - 1), epoch);  // also the barrier for Y
+      else __syncthreads();
+      const bool ok = potrf_trtri64(Y, Z, &X[0][0]);  // Z = Linv_j, kept for step j + 1
       float* Lj = P.Linv + (size_t)j * NB * NB;
       for (int e = tid; e < NB * NB / 4; e += 256) {
         const int r = e >> 4, cc = 4 * (e & 15);
-        *reinterpret_cast<float4*>(Lj + r * NB + cc) = make_float4(X[r][cc], X[r][cc + 1], X[r][cc + 2], X[r][cc + 3]);
+        *reinterpret_cast<float4*>(Lj + r * NB + cc) = make_float4(Z[r][cc], Z[r][cc + 1], Z[r][cc + 2], Z[r][cc + 3]);
+      }
+      if (tid == 0 && !ok) P.sc->chol_fail = 1;
+      // Look once for the next step's partial tiles; if they are ready, their loads overlap the
+      // completion of the Linv_j stores that the publication below waits for.
+      if (j + 1 < nb) {
+        bool ready = true;
+        if (j + 1 >= 2) {
+          if (tid == 0) {
+            const int v0 = ld_flag(S.pdiag + j + 1), v1 = ld_flag(S.psub + j + 1);
+            const bool r = (v0 == epoch) && (v1 == epoch);
+            if (r) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_val = r ? 1 : 0;
+          }
+          __syncthreads();
+          ready = s_val != 0;
+        }
+        if (ready) {
+          chain_load(P, j + 1, cva, ccp);
+          have_pref = true;
+        }
       }
       block_publish(S.dinv + j, epoch);
-      if (tid == 0 && !ok) P.sc->chol_fail = 1;
+      continue;
+    }
+    int kind, i, c;
+    decode_task(t, nb, kind, i, c);
+    if (kind == TASK_CRIT) {
+      if (i == 0) chain = 0;  // this workgroup runs the critical chain
       continue;
     }
     // DIAGP / SUBP / FULL: accumulate the finished columns k < nk into the tile
