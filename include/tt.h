@@ -127,6 +127,28 @@ int tt_track_frame(tt_stream* s, const float* depth, const float* feat_xyz, cons
 int tt_track_frame_device(tt_stream* s, const float* d_depth, const float* d_feat_xyz,
                           const uint8_t* d_feat_desc, int K2, float* d_out_vertices, float* d_out_dq);
 
+/* One frame for each of several streams, all arrays in device memory (as for
+ * tt_track_frame_device). */
+typedef struct {
+  const float* depth;       /* [height][width] of that stream's intrinsics                     */
+  const float* feat_xyz;    /* [K2][3], NaN = no depth                                          */
+  const uint8_t* feat_desc; /* [K2][32], 16-byte aligned                                        */
+  int K2;
+  float* out_vertices;      /* [M][3] float32 or NULL                                           */
+  float* out_dq;            /* [N][8] float32 or NULL                                           */
+} tt_frame_device;
+
+/* Batched form of tt_track_frame_device: the same per-frame solve (Sec. 2) for S distinct streams
+ * (templates, sizes and intrinsics may differ; lm_iters must be equal), queued as one batch on
+ * streams[0]'s HIP stream. The per-stream stages are queued stream after stream; the Cholesky
+ * factorisations and back substitutions of all S normal systems run as one launch each per LM
+ * iteration. The batch starts after all work already queued on every stream's HIP stream, and
+ * later work on those HIP streams runs after it. Each stream's result is the same as when it is
+ * tracked alone. Returns without waiting. TT_EINVAL: bad arguments or a stream listed twice;
+ * TT_EBUSY: a stream is in use by another call (no stream is then touched); TT_ESTATE: a stream
+ * has no template. */
+int tt_track_batch_device(tt_stream* const* streams, int S, const tt_frame_device* frames);
+
 /* Waits for the stream's queued work; returns TT_EDEVICE if a device-side check failed. */
 int tt_sync(tt_stream* s);
 

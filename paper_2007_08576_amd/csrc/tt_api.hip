@@ -155,85 +155,145 @@ struct StageTimer {
   tt_stream* s;
   int stage;
   hipEvent_t a = nullptr, b = nullptr;
-  StageTimer(tt_stream* s_, int stage_) : s(s_), stage(stage_) {
+  hipStream_t st;
+  StageTimer(tt_stream* s_, int stage_, hipStream_t st_) : s(s_), stage(stage_), st(st_) {
     if (!s->timing) return;
     if (ev_get(s, &a) != hipSuccess || ev_get(s, &b) != hipSuccess) {
       s->timing = false;
       return;
     }
-    (void)hipEventRecord(a, s->st);
+    (void)hipEventRecord(a, st);
   }
   ~StageTimer() {
     if (!a || !b) return;
-    (void)hipEventRecord(b, s->st);
+    (void)hipEventRecord(b, st);
     s->ev_pending.push_back({stage, {a, b}});
     if (s->ev_pending.size() > 16384) (void)timing_flush(s);
   }
 };
 
-// Queue the whole frame. depth/xyz/desc are device pointers.
-int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint8_t* desc, int K2, float* out_xyz,
-                  float* out_dq, bool dbg) {
-  DevState& d = s->d;
-  const tt_params& P = s->P;
-  Intr K = intr_of(s);
-  hipStream_t st = s->st;
-  DevState dd = d;  // launchers read the frame inputs from these fields
+// The stream's state with this frame's inputs (device pointers) in the frame fields.
+DevState frame_view(tt_stream* s, const float* depth, const float* xyz, const uint8_t* desc) {
+  DevState dd = s->d;
   dd.depth = const_cast<float*>(depth);
   dd.f2xyz = const_cast<float*>(xyz);
   dd.f2desc = reinterpret_cast<uint32_t*>(const_cast<uint8_t*>(desc));
+  return dd;
+}
+
+// Normal map, matching, pre-selection, LM set-up.
+int enqueue_front(tt_stream* s, DevState& dd, int K2, hipStream_t st) {
+  const tt_params& P = s->P;
+  Intr K = intr_of(s);
+  StageTimer tm(s, TT_STAGE_FRONT, st);
+  HIPCHK(launch_normal_map(dd, K, st));
+  if (s->d.K1 > 0) {
+    HIPCHK(launch_match(dd, K2, P.max_hamming, st));  // K2 == 0: every feature unmatched
+    HIPCHK(launch_preselect(dd, P.ransac_refs, P.ransac_iters, P.H, P.seed, s->frame, st));
+  }
+  HIPCHK(launch_lm_begin(s->d, P.lm_lambda0, st));
+  return TT_OK;
+}
+
+// One LM iteration up to the damped system: rows, assembly, damping; returns the solve's epoch.
+int enqueue_assemble(tt_stream* s, DevState& dd, int it, bool dbg, hipStream_t st, int* epoch) {
+  DevState& d = s->d;
+  const tt_params& P = s->P;
+  Intr K = intr_of(s);
   {
-    StageTimer tm(s, TT_STAGE_FRONT);
-    HIPCHK(launch_normal_map(dd, K, st));
-    if (d.K1 > 0) {
-      HIPCHK(launch_match(dd, K2, P.max_hamming, st));  // K2 == 0: every feature unmatched
-      HIPCHK(launch_preselect(dd, P.ransac_refs, P.ransac_iters, P.H, P.seed, s->frame, st));
-    }
-    HIPCHK(launch_lm_begin(d, P.lm_lambda0, st));
+    StageTimer tm(s, TT_STAGE_ROWS, st);
+    HIPCHK(launch_lm_rows(dd, P, K, it, st));
   }
-  for (int it = 0; it < P.lm_iters; it++) {
-    {
-      StageTimer tm(s, TT_STAGE_ROWS);
-      HIPCHK(launch_lm_rows(dd, P, K, it, st));
-    }
-    {
-      StageTimer tm(s, TT_STAGE_ARAP);
-      HIPCHK(launch_lm_arap(dd, P, st));
-    }
-    {
-      StageTimer tm(s, TT_STAGE_DATA);
-      HIPCHK(launch_lm_data(dd, st));
-    }
-    if (dbg && it == 0) {
-      HIPCHK(hipMemcpyAsync(d.A_dbg, d.A, sizeof(float) * (size_t)d.npad * d.ld, hipMemcpyDeviceToDevice, st));
-      HIPCHK(hipMemcpyAsync(d.g_dbg, d.g, sizeof(float) * d.npad, hipMemcpyDeviceToDevice, st));
-      HIPCHK(hipMemcpyAsync(d.corr_dbg, d.corr, sizeof(int) * d.M, hipMemcpyDeviceToDevice, st));
-      HIPCHK(hipMemcpyAsync(d.rres_dbg, d.rres, sizeof(float) * d.M, hipMemcpyDeviceToDevice, st));
-      HIPCHK(hipMemcpyAsync(d.omega_dbg, d.omega, sizeof(float) * d.M, hipMemcpyDeviceToDevice, st));
-      if (d.K1)
-        HIPCHK(hipMemcpyAsync(d.orbw_dbg, d.orbw, sizeof(float) * d.K1, hipMemcpyDeviceToDevice, st));
-    }
-    s->solve_epoch = (s->solve_epoch == 0x7FFFFFFF) ? 1 : s->solve_epoch + 1;
-    {
-      StageTimer tm(s, TT_STAGE_SOLVE);
-      HIPCHK(launch_lm_damp(dd, st));
-    }
-    {
-      StageTimer tm(s, TT_STAGE_FACTOR);
-      HIPCHK(launch_cholesky_factor(dd, s->solve_epoch, st));
-    }
-    {
-      StageTimer tm(s, TT_STAGE_SOLVE);
-      HIPCHK(launch_cholesky_backsolve(dd, s->solve_epoch, st));
-    }
-    {
-      StageTimer tm(s, TT_STAGE_UPDATE);
-      HIPCHK(launch_lm_finish(dd, P, K, st));
-    }
+  {
+    StageTimer tm(s, TT_STAGE_ARAP, st);
+    HIPCHK(launch_lm_arap(dd, P, st));
   }
-  HIPCHK(launch_deform_out(d, out_xyz, out_dq, st));
+  {
+    StageTimer tm(s, TT_STAGE_DATA, st);
+    HIPCHK(launch_lm_data(dd, st));
+  }
+  if (dbg && it == 0) {
+    HIPCHK(hipMemcpyAsync(d.A_dbg, d.A, sizeof(float) * (size_t)d.npad * d.ld, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.g_dbg, d.g, sizeof(float) * d.npad, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.corr_dbg, d.corr, sizeof(int) * d.M, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.rres_dbg, d.rres, sizeof(float) * d.M, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.omega_dbg, d.omega, sizeof(float) * d.M, hipMemcpyDeviceToDevice, st));
+    if (d.K1) HIPCHK(hipMemcpyAsync(d.orbw_dbg, d.orbw, sizeof(float) * d.K1, hipMemcpyDeviceToDevice, st));
+  }
+  s->solve_epoch = (s->solve_epoch == 0x7FFFFFFF) ? 1 : s->solve_epoch + 1;
+  *epoch = s->solve_epoch;
+  {
+    StageTimer tm(s, TT_STAGE_SOLVE, st);
+    HIPCHK(launch_lm_damp(dd, st));
+  }
+  return TT_OK;
+}
+
+// Candidate, FP64 cost, accept / reject.
+int enqueue_finish(tt_stream* s, DevState& dd, hipStream_t st) {
+  StageTimer tm(s, TT_STAGE_UPDATE, st);
+  HIPCHK(launch_lm_finish(dd, s->P, intr_of(s), st));
+  return TT_OK;
+}
+
+// Queue the whole frame. depth/xyz/desc are device pointers.
+int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint8_t* desc, int K2, float* out_xyz,
+                  float* out_dq, bool dbg) {
+  hipStream_t st = s->st;
+  DevState dd = frame_view(s, depth, xyz, desc);
+  int rc = enqueue_front(s, dd, K2, st);
+  if (rc) return rc;
+  for (int it = 0; it < s->P.lm_iters; it++) {
+    int epoch = 0;
+    rc = enqueue_assemble(s, dd, it, dbg, st, &epoch);
+    if (rc) return rc;
+    {
+      StageTimer tm(s, TT_STAGE_FACTOR, st);
+      HIPCHK(launch_cholesky_factor(dd, epoch, st));
+    }
+    {
+      StageTimer tm(s, TT_STAGE_SOLVE, st);
+      HIPCHK(launch_cholesky_backsolve(dd, epoch, st));
+    }
+    rc = enqueue_finish(s, dd, st);
+    if (rc) return rc;
+  }
+  HIPCHK(launch_deform_out(s->d, out_xyz, out_dq, st));
   s->frame += 1;
   return TT_OK;
+}
+
+// One frame of each of S streams as one batch on batch_st: the per-stream stages are queued
+// stream after stream, the factorisations and back substitutions of all S systems run as one
+// launch each per LM iteration.
+int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStream_t batch_st) {
+  std::vector<DevState> dd(S);
+  std::vector<DevState*> dp(S);
+  std::vector<int> epochs(S);
+  for (int q = 0; q < S; q++) {
+    dd[q] = frame_view(ss[q], fr[q].depth, fr[q].feat_xyz, fr[q].feat_desc);
+    dp[q] = &dd[q];
+  }
+  int rc = TT_OK;
+  for (int q = 0; q < S && !rc; q++) rc = enqueue_front(ss[q], dd[q], fr[q].K2, batch_st);
+  for (int it = 0; it < ss[0]->P.lm_iters && !rc; it++) {
+    for (int q = 0; q < S && !rc; q++) rc = enqueue_assemble(ss[q], dd[q], it, false, batch_st, &epochs[q]);
+    if (rc) break;
+    {
+      StageTimer tm(ss[0], TT_STAGE_FACTOR, batch_st);
+      HIPCHK(launch_cholesky_factor_batch(dp.data(), epochs.data(), S, batch_st));
+    }
+    {
+      StageTimer tm(ss[0], TT_STAGE_SOLVE, batch_st);
+      HIPCHK(launch_cholesky_backsolve_batch(dp.data(), epochs.data(), S, batch_st));
+    }
+    for (int q = 0; q < S && !rc; q++) rc = enqueue_finish(ss[q], dd[q], batch_st);
+  }
+  for (int q = 0; q < S && !rc; q++) {
+    HIPCHK(launch_deform_out(ss[q]->d, fr[q].out_vertices, fr[q].out_dq, batch_st));
+    ss[q]->frame += 1;
+  }
+  return rc;
 }
 
 int ensure_debug_buffers(tt_stream* s) {
@@ -694,6 +754,47 @@ int tt_track_frame_device(tt_stream* s, const float* d_depth, const float* d_fea
   if (!busy.ok) return TT_EBUSY;
   if (!s->has_template) return TT_ESTATE;
   return enqueue_frame(s, d_depth, d_feat_xyz, d_feat_desc, K2, d_out_vertices, d_out_dq, false);
+}
+
+int tt_track_batch_device(tt_stream* const* streams, int S, const tt_frame_device* frames) {
+  if (!streams || !frames || S < 1 || S > 4096) return TT_EINVAL;
+  for (int q = 0; q < S; q++) {
+    const tt_frame_device& f = frames[q];
+    if (!streams[q] || !f.depth || f.K2 < 0 || f.K2 > (1 << 23) || (f.K2 > 0 && (!f.feat_xyz || !f.feat_desc)))
+      return TT_EINVAL;
+    if (f.K2 > 0 && ((uintptr_t)f.feat_desc % 16 != 0)) return TT_EINVAL;
+    if (streams[q]->P.lm_iters != streams[0]->P.lm_iters) return TT_EINVAL;
+    for (int r = 0; r < q; r++)
+      if (streams[r] == streams[q]) return TT_EINVAL;
+  }
+  // lock every stream (all or none)
+  int locked = 0;
+  for (; locked < S; locked++)
+    if (!streams[locked]->mu.try_lock()) break;
+  int rc = TT_OK;
+  if (locked < S) rc = TT_EBUSY;
+  for (int q = 0; q < S && !rc; q++)
+    if (!streams[q]->has_template) rc = TT_ESTATE;
+  hipStream_t st = streams[0]->st;
+  // the batch runs on the first stream's HIP stream, after every stream's earlier work; each
+  // stream's later work runs after the batch
+  for (int q = 1; q < S && !rc; q++) {
+    hipEvent_t ev = nullptr;
+    if (ev_get(streams[q], &ev) != hipSuccess || hipEventRecord(ev, streams[q]->st) != hipSuccess ||
+        hipStreamWaitEvent(st, ev, 0) != hipSuccess)
+      rc = TT_EDEVICE;
+    if (ev) streams[q]->ev_pool.push_back(ev);
+  }
+  if (!rc) rc = enqueue_batch(streams, S, frames, st);
+  if (!rc && S > 1) {
+    hipEvent_t ev = nullptr;
+    if (ev_get(streams[0], &ev) != hipSuccess || hipEventRecord(ev, st) != hipSuccess) rc = TT_EDEVICE;
+    for (int q = 1; q < S && !rc; q++)
+      if (hipStreamWaitEvent(streams[q]->st, ev, 0) != hipSuccess) rc = TT_EDEVICE;
+    if (ev) streams[0]->ev_pool.push_back(ev);
+  }
+  for (int q = 0; q < locked; q++) streams[q]->mu.unlock();
+  return rc;
 }
 
 int tt_track_frame(tt_stream* s, const float* depth, const float* feat_xyz, const uint8_t* feat_desc, int K2,

@@ -32,22 +32,22 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ float bcast16(float v, int n) {  // returns v of lane n of the row
   float d;
   switch (n) {
-    case 0: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:0 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 1: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:1 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 2: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:2 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 3: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:3 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 4: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:4 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 5: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:5 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 6: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:6 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 7: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:7 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 8: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:8 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 9: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:9 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 10: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:10 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 11: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:11 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 12: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:12 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 13: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:13 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 14: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:14 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 15: asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:15 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 0: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:0 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 1: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:1 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 2: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:2 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 3: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:3 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 4: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:4 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 5: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:5 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 6: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:6 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 7: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:7 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 8: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:8 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 9: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:9 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 10: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:10 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 11: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:11 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 12: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:12 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 13: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:13 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 14: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:14 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
+    case 15: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:15 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
   }
   return d;
 }
@@ -55,41 +55,41 @@ __device__ __forceinline__ void fmac_bcast16(float& acc, float src, float mul, i
   // acc += (src of lane n of the row) * mul
   if (guard) {
     switch (n) {
-    case 0: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 1: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:1 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 2: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:2 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 3: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 4: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:4 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 5: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:5 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 6: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:6 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 7: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:7 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 8: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 9: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:9 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 10: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:10 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 11: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:11 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 12: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:12 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 13: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:13 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 14: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:14 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 15: asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:15 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 0: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 1: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:1 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 2: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:2 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 3: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 4: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:4 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 5: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:5 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 6: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:6 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 7: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:7 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 8: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 9: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:9 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 10: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:10 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 11: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:11 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 12: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:12 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 13: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:13 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 14: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:14 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 15: asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:15 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
     }
   } else {
     switch (n) {
-    case 0: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 1: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:1 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 2: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:2 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 3: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 4: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:4 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 5: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:5 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 6: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:6 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 7: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:7 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 8: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 9: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:9 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 10: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:10 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 11: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:11 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 12: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:12 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 13: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:13 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 14: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:14 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
-    case 15: asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:15 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 0: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 1: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:1 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 2: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:2 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 3: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 4: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:4 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 5: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:5 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 6: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:6 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 7: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:7 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 8: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 9: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:9 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 10: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:10 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 11: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:11 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 12: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:12 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 13: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:13 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 14: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:14 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
+    case 15: asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:15 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(src), "v"(mul)); break;
     }
   }
 }
@@ -115,11 +115,12 @@ __device__ __forceinline__ void leaf16(float (*L)[LDS_LD], float (*Li)[LDS_LD], 
     ok = ok && (d > 0.0f);
     const float il = __builtin_amdgcn_rsqf(d);
     invd[j] = il;
-    // lane masks as integer arithmetic (all ones where r > j, resp. r == j)
-    const int gt = (j - r) >> 31, eq = ((r ^ j) - 1) >> 31;
-    const float lr = __int_as_float(__float_as_int(a[j] * il) & gt);
-    const float nlr = -lr;
-    a[j] = __int_as_float(__float_as_int(lr) | (__float_as_int(d * il) & eq));
+    // No lane masks: in lanes r < j, a[j] and everything derived from it lie in the row's upper
+    // triangle, which is never broadcast (sources are lane j for the pivot and lanes m > j for the
+    // column) and never stored; lane j itself gets a[j] = d / sqrt(d), its diagonal entry.
+    const float lr = a[j] * il;
+    const float nlr = a[j] * (-il);
+    a[j] = lr;
 #pragma unroll
     for (int m = j + 1; m < 16; m++) fmac_bcast16(a[m], lr, nlr, m, m == j + 1);
   }
@@ -133,7 +134,7 @@ __device__ __forceinline__ void leaf16(float (*L)[LDS_LD], float (*Li)[LDS_LD], 
 #pragma unroll
   for (int i = 0; i < 16; i++) {
     x[i] = p[i] * invd[i];
-    const float nx = -x[i];
+    const float nx = p[i] * (-invd[i]);
 #pragma unroll
     for (int k = i + 1; k < 16; k++) fmac_bcast16(p[k], a[i], nx, k, k == i + 1);
   }
@@ -536,6 +537,7 @@ struct CholArgs {
   float* Linv;
   int* flags;
   LMScalars* sc;
+  float* x;  // solution of the back substitution
 };
 
 // Ticket of CRIT(j): the number of tasks in the groups before j, plus DIAGP(j) and SUBP(j).
@@ -568,24 +570,38 @@ __device__ __forceinline__ void chain_load(const CholArgs& P, int j, float4 va[4
   }
 }
 
-__global__ __launch_bounds__(256) void k_chol_dataflow(CholArgs P) {
+// Up to kMaxCholBatch independent systems per launch, passed by value (no upload per solve).
+constexpr int kMaxCholBatch = 32;
+struct CholBatch {
+  int nprob;
+  CholArgs p[kMaxCholBatch];
+};
+
+enum { MODE_EXIT = 3 };
+
+__global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
   __shared__ float X[NB][LDS_LD];
   __shared__ float Y[NB][LDS_LD];
   __shared__ float Z[NB][LDS_LD];  // the chain's Linv_{j-1} between CRIT steps
   static_assert(POTRF_SCRATCH_FLOATS <= NB * LDS_LD, "factorisation scratch must fit in one tile buffer");
-  __shared__ int s_task, s_val, s_mode;
+  __shared__ int s_task, s_val, s_mode, s_prob;
   const int tid = threadIdx.x;
-  const int nb = P.nb, ld = P.ld, epoch = P.epoch;
-  const CholSync S = chol_sync(P.flags, nb);
-  int* ctr = S.ctr;
   const uint64_t deadline = __builtin_amdgcn_s_memrealtime() + kDeadlineTicks;
-  // The workgroup that claims ticket 0 (CRIT(0)) runs the whole critical chain CRIT(0..nb-1) and
-  // keeps each Linv_j in LDS for the next step; CRIT tickets claimed by others are empty. Before
-  // CRIT(j) may wait on DIAGP(j) and SUBP(j), their tickets must have been handed out: until the
-  // counter has passed them, the chain workgroup claims the next ticket itself (compare-and-swap,
-  // so it never takes one at or beyond CRIT(j)) and runs that task, which depends only on smaller
-  // tickets. So the waits end whatever the number of resident workgroups.
-  int chain = -1;
+  // Each system has its own ticket counter and task order. A workgroup visits the systems in a
+  // cyclic order starting at blockIdx % nprob, claiming tasks from one until its counter runs out
+  // (one failing claim per system per workgroup, so the claim that returns ntasks + gridDim - 1
+  // is a system's last and rearms its counter for the next solve), then moves to the next.
+  //
+  // The workgroup that claims a system's ticket 0 (CRIT(0)) runs that system's whole critical
+  // chain CRIT(0..nb-1) and keeps each Linv_j in LDS for the next step; CRIT tickets claimed by
+  // others are empty. Before CRIT(j) may wait on DIAGP(j) and SUBP(j), their tickets must have
+  // been handed out: until the counter has passed them, the chain workgroup claims the system's
+  // next ticket itself (compare-and-swap, so it never takes one at or beyond CRIT(j)) and runs
+  // that task, which depends only on smaller tickets of the same system. Tasks of different systems
+  // never wait on each other, so every wait ends whatever the number of resident workgroups.
+  int cur = (int)blockIdx.x % B.nprob;  // thread 0: system being claimed from
+  int vis = 0;                          // thread 0: systems whose counter this workgroup exhausted
+  int chain = -1, chain_p = 0;
   int ctr_seen = 0;          // thread 0: last counter value read by the chain (the counter only grows)
   bool have_pref = false;    // the chain's inputs for its next step are already in cva / ccp
   float4 cva[4];             // chain prefetch: C_{j,j-1} (tile layout)
@@ -593,45 +609,60 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(CholArgs P) {
   for (;;) {
     __syncthreads();  // every thread is done with the shared scalars of the previous step
     if (tid == 0) {
-      int t = -1, mode = MODE_TASK;
+      int t = -1, mode = MODE_TASK, prob = cur;
       bool chain_fast = false;
       if (chain >= 0) {
-        const int need = crit_ticket(chain, nb);
+        prob = chain_p;
+        const CholArgs& Q = B.p[prob];
+        int* ctr = chol_sync(Q.flags, Q.nb).ctr;
+        const int need = crit_ticket(chain, Q.nb);
         if (ctr_seen < need) ctr_seen = ld_flag(ctr);
-        const int cur = ctr_seen;
-        if (cur >= need) {
+        const int c0 = ctr_seen;
+        if (c0 >= need) {
           mode = MODE_CRIT;
           chain_fast = true;
         } else {
-          int expect = cur;
-          mode = __hip_atomic_compare_exchange_strong(ctr, &expect, cur + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+          int expect = c0;
+          mode = __hip_atomic_compare_exchange_strong(ctr, &expect, c0 + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT)
                      ? MODE_TASK
                      : MODE_RETRY;
-          t = cur;
+          t = c0;
         }
+      } else if (vis >= B.nprob) {
+        mode = MODE_EXIT;
       } else {
+        const CholArgs& Q = B.p[prob];
+        int* ctr = chol_sync(Q.flags, Q.nb).ctr;
         t = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // every workgroup ends on exactly one such claim >= ntasks, so this claim is the solve's
-        // last one: rearm the counter for the next solve (queued after this launch on the stream)
-        if (t == P.ntasks + (int)gridDim.x - 1) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t >= Q.ntasks) {
+          if (t == Q.ntasks + (int)gridDim.x - 1) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          vis++;
+          cur = (cur + 1 == B.nprob) ? 0 : cur + 1;
+          mode = MODE_RETRY;
+        }
       }
       s_task = t;
       s_mode = mode;
+      s_prob = prob;
       // the chain's waits watch the abort word themselves; skip the extra round trip on its path
-      s_val = chain_fast ? 0 : (ld_flag(S.abort_) == epoch);
+      const CholArgs& Q = B.p[prob];
+      s_val = (chain_fast || mode != MODE_TASK) ? 0 : (ld_flag(chol_sync(Q.flags, Q.nb).abort_) == Q.epoch);
     }
     __syncthreads();
-    const int t = s_task, mode = s_mode;
+    const int t = s_task, mode = s_mode, prob = s_prob;
     const bool aborted = s_val != 0;
+    if (mode == MODE_EXIT) break;
     if (mode == MODE_RETRY) continue;
-    if (mode == MODE_TASK && t >= P.ntasks) break;
+    const CholArgs& P = B.p[prob];
+    const int nb = P.nb, ld = P.ld, epoch = P.epoch;
+    const CholSync S = chol_sync(P.flags, nb);
     if (aborted) {
       if (tid == 0) {
         P.sc->chol_fail = 1;
         P.sc->err = TT_DEVERR_CHOL_SYNC;
       }
-      chain = -1;
+      if (mode == MODE_CRIT) chain = -1;
       continue;
     }
     floatx4 acc[2][2], cpre[2][2];
@@ -698,7 +729,11 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(CholArgs P) {
     int kind, i, c;
     decode_task(t, nb, kind, i, c);
     if (kind == TASK_CRIT) {
-      if (i == 0) chain = 0;  // this workgroup runs the critical chain
+      if (i == 0) {  // this workgroup runs the system's critical chain
+        chain = 0;
+        chain_p = prob;
+        if (tid == 0) ctr_seen = 0;
+      }
       continue;
     }
     // DIAGP / SUBP / FULL: accumulate the finished columns k < nk into the tile
@@ -780,17 +815,30 @@ __device__ __forceinline__ bool wait_flag(const int* flag, int epoch) {
   return true;
 }
 
-// Back substitution L^T x = y (y in the right-hand-side row): one wavefront per block row.
-__global__ __launch_bounds__(64) void k_chol_backsolve(const float* __restrict__ A, int ld, int npad, int nb,
-                                                      const float* __restrict__ Linv, float* __restrict__ x,
-                                                      int* __restrict__ flags, int epoch, LMScalars* sc) {
+// Back substitution L^T x = y (y in the right-hand-side row): one wavefront per block row, for a
+// batch of systems laid out one after another over the grid (workgroups wg0[q] .. wg0[q+1]-1 serve
+// system q, block rows from the last).
+struct BackBatch {
+  int nprob;
+  int wg0[kMaxCholBatch + 1];
+  CholArgs p[kMaxCholBatch];
+};
+
+__global__ __launch_bounds__(64) void k_chol_backsolve(const BackBatch B) {
   __shared__ float xs[NB];
   __shared__ float rs[NB];
-  const int j = nb - 1 - (int)blockIdx.x;
+  int q = 0;
+  while (q + 1 < B.nprob && (int)blockIdx.x >= B.wg0[q + 1]) q++;
+  const CholArgs& P = B.p[q];
+  const int nb = P.nb, ld = P.ld, epoch = P.epoch;
+  const float* __restrict__ A = P.A;
+  float* __restrict__ x = P.x;
+  int* flags = chol_sync(P.flags, nb).bflag;
+  const int j = nb - 1 - ((int)blockIdx.x - B.wg0[q]);
   const int c = threadIdx.x;
-  const float* yrow = A + (size_t)npad * ld;
+  const float* yrow = A + (size_t)P.npad * ld;
   const float y = yrow[NB * j + c];
-  const float* Li = Linv + (size_t)j * NB * NB;
+  const float* Li = P.Linv + (size_t)j * NB * NB;
   float lic[NB];
 #pragma unroll
   for (int m = 0; m < NB; m++) lic[m] = Li[m * NB + c];
@@ -820,8 +868,8 @@ __global__ __launch_bounds__(64) void k_chol_backsolve(const float* __restrict__
   if (c == 0) {
     __hip_atomic_store(flags + j, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!ok) {
-      sc->chol_fail = 1;
-      sc->err = TT_DEVERR_CHOL_SYNC;
+      P.sc->chol_fail = 1;
+      P.sc->err = TT_DEVERR_CHOL_SYNC;
     }
   }
 }
@@ -830,7 +878,7 @@ __global__ __launch_bounds__(64) void k_chol_backsolve(const float* __restrict__
 
 size_t chol_flag_ints(int nb) { return (size_t)nb + (size_t)(nb + 1) * nb + 3 * (size_t)nb + 2; }
 
-hipError_t launch_cholesky_factor(DevState& d, int epoch, hipStream_t st) {
+static CholArgs chol_args(const DevState& d, int epoch) {
   CholArgs P;
   P.A = d.A;
   P.ld = d.ld;
@@ -842,14 +890,46 @@ hipError_t launch_cholesky_factor(DevState& d, int epoch, hipStream_t st) {
   P.Linv = d.Linv;
   P.flags = d.flags;
   P.sc = d.sc;
-  const int cus = d.num_cus > 0 ? d.num_cus : 256;
-  const int grid = P.ntasks < 2 * cus ? P.ntasks : 2 * cus;
-  hipLaunchKernelGGL(k_chol_dataflow, dim3(grid), dim3(256), 0, st, P);
+  P.x = d.x;
+  return P;
+}
+
+hipError_t launch_cholesky_factor_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st) {
+  for (int b0 = 0; b0 < S; b0 += kMaxCholBatch) {
+    CholBatch B;
+    B.nprob = (S - b0 < kMaxCholBatch) ? S - b0 : kMaxCholBatch;
+    int tasks = 0, cus = 256;
+    for (int q = 0; q < B.nprob; q++) {
+      B.p[q] = chol_args(*ds[b0 + q], epochs[b0 + q]);
+      tasks += B.p[q].ntasks;
+      if (ds[b0 + q]->num_cus > 0) cus = ds[b0 + q]->num_cus;
+    }
+    const int grid = tasks < 2 * cus ? tasks : 2 * cus;
+    hipLaunchKernelGGL(k_chol_dataflow, dim3(grid), dim3(256), 0, st, B);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cholesky_factor(DevState& d, int epoch, hipStream_t st) {
+  DevState* ds[1] = {&d};
+  return launch_cholesky_factor_batch(ds, &epoch, 1, st);
+}
+
+hipError_t launch_cholesky_backsolve_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st) {
+  for (int b0 = 0; b0 < S; b0 += kMaxCholBatch) {
+    BackBatch B;
+    B.nprob = (S - b0 < kMaxCholBatch) ? S - b0 : kMaxCholBatch;
+    B.wg0[0] = 0;
+    for (int q = 0; q < B.nprob; q++) {
+      B.p[q] = chol_args(*ds[b0 + q], epochs[b0 + q]);
+      B.wg0[q + 1] = B.wg0[q] + ds[b0 + q]->nb;
+    }
+    hipLaunchKernelGGL(k_chol_backsolve, dim3(B.wg0[B.nprob]), dim3(64), 0, st, B);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_cholesky_backsolve(DevState& d, int epoch, hipStream_t st) {
-  hipLaunchKernelGGL(k_chol_backsolve, dim3(d.nb), dim3(64), 0, st, d.A, d.ld, d.npad, d.nb, d.Linv, d.x, d.flags,
-                     epoch, d.sc);
-  return hipGetLastError();
+  DevState* ds[1] = {&d};
+  return launch_cholesky_backsolve_batch(ds, &epoch, 1, st);
 }

@@ -170,3 +170,6 @@ size_t chol_flag_ints(int nb);
 // substitution into d.x; epoch tags this solve's flags.
 hipError_t launch_cholesky_factor(DevState& d, int epoch, hipStream_t st);
 hipError_t launch_cholesky_backsolve(DevState& d, int epoch, hipStream_t st);
+// The same for S independent systems at once (one launch per 32 systems).
+hipError_t launch_cholesky_factor_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st);
+hipError_t launch_cholesky_backsolve_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st);

@@ -367,6 +367,25 @@ def make_config3(seed: int = 3, n_frames: int = 300) -> Scene:
     return make_sequence(seed=seed, M=100000, N=1500, K1=2000, n_frames=n_frames, name="config3")
 
 
+def make_config4(seed: int = 4, n_streams: int = 16, n_frames: int = 300):
+    """Serving mix (config 4): n_streams independent streams with uneven sizes. Per stream s
+    (seeded 1000 * seed + s): control points N ~ U{100..800}, depth map one of 320x240, 480x360,
+    640x480 (intrinsics scaled with the width), M = W * H / 10 template points, K ~ U{500..3000}
+    features with an outlier fraction ~ U[0.2, 0.4]; each stream is a config-2-style sequence."""
+    sizes = ((320, 240), (480, 360), (640, 480))
+    scenes = []
+    for q in range(n_streams):
+        rng = Rng(1000 * seed + q, "config4/stream")
+        N = 100 + int(rng.uniform(1, 0.0, 701.0)[0])
+        W, H = sizes[int(rng.uniform(1, 0.0, 3.0)[0])]
+        K1 = 500 + int(rng.uniform(1, 0.0, 2501.0)[0])
+        out = float(rng.uniform(1, 0.2, 0.4)[0])
+        scenes.append(make_sequence(seed=1000 * seed + q, M=W * H // 10, N=min(N, 800), K1=min(K1, 3000),
+                                    outlier_frac=out, width=W, height=H, n_frames=n_frames,
+                                    name=f"config4/{q}"))
+    return scenes
+
+
 def make_small_sequence(seed: int = 11, M: int = 2000, N: int = 48, K1: int = 300,
                         width: int = 160, height: int = 120, n_frames: int = 4,
                         max_step_mm: float = 3.0) -> Scene:

@@ -2,7 +2,7 @@
 the solve runs in the library's kernels. Raises if the library has not been built.
 
 Names follow the C ABI: default_params, create_stream, Stream.set_template, Stream.track_frame,
-Stream.track_frame_device, Stream.destroy, strerror.
+Stream.track_frame_device, track_batch_device, Stream.destroy, strerror.
 """
 import ctypes as C
 import os
@@ -48,6 +48,11 @@ class FrameDebug(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in _DEBUG_FIELDS]
 
 
+class FrameDevice(C.Structure):
+    _fields_ = [("depth", C.c_void_p), ("feat_xyz", C.c_void_p), ("feat_desc", C.c_void_p), ("K2", C.c_int),
+                ("out_vertices", C.c_void_p), ("out_dq", C.c_void_p)]
+
+
 def lib():
     """The loaded library (raises if it has not been built)."""
     global _lib
@@ -68,6 +73,7 @@ def lib():
         L.tt_set_template.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int]
         L.tt_track_frame.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp, C.POINTER(FrameDebug)]
         L.tt_track_frame_device.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
+        L.tt_track_batch_device.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(FrameDevice)]
         L.tt_sync.argtypes = [vp]
         L.tt_hip_stream.argtypes = [vp]
         L.tt_hip_stream.restype = vp
@@ -244,6 +250,17 @@ def debug_cholesky_solve(A, b):
     _check(lib().tt_debug_cholesky_solve(int(b.shape[0]), _ptr(A), _ptr(b), _ptr(x), C.byref(fail)),
            "tt_debug_cholesky_solve")
     return x, bool(fail.value)
+
+
+def track_batch_device(streams, frames):
+    """One frame per stream as one batch (tt_track_batch_device). frames: sequence of
+    (depth, feat_xyz, feat_desc, K2, out_vertices, out_dq) with torch tensors or addresses."""
+    S = len(streams)
+    hs = (C.c_void_p * S)(*[s.h.value for s in streams])
+    fr = (FrameDevice * S)()
+    for q, (depth, xyz, desc, K2, ov, oq) in enumerate(frames):
+        fr[q] = FrameDevice(_dev_ptr(depth), _dev_ptr(xyz), _dev_ptr(desc), int(K2), _dev_ptr(ov), _dev_ptr(oq))
+    _check(lib().tt_track_batch_device(hs, S, fr), "tt_track_batch_device")
 
 
 def create_stream(params, intr, hip_stream=None):
