@@ -66,6 +66,110 @@ def cpu_baseline(sc, frame, lm_sample):
                        f"({t_front * 1e3:.0f} ms + 10 x {t_iter * 1e3:.0f} ms)"), verts
 
 
+def serving_bench(args, torch, tt):
+    """Config 4 serving mix: 16 streams of uneven size, plain (one frame after another through
+    tt_track_frame_device) against batched (tt_track_batch_device over every stream with a frame
+    waiting), then a Poisson-arrival run (mean 15 Hz per stream) with continuous batching: whenever
+    the device finishes a batch, every stream whose next frame has arrived joins the next one."""
+    from paper_2007_08576_amd import synth
+    t0 = time.time()
+    scenes = synth.make_config4(seed=4, n_streams=args.serving_streams, n_frames=300)
+    dev = torch.device("cuda:0")
+    nfr = 3
+    frames = [[tuple(torch.from_numpy(a).to(dev) for a in (f.depth, f.feat_xyz, f.feat_desc))
+               for f in (sc.frame(t) for t in range(1, nfr + 1))] for sc in scenes]
+    log(f"serving mix generated in {time.time() - t0:.1f} s")
+    budget = args.serving_hbm_gib * (1 << 30)
+    streams, used = [], 0
+    for sc in scenes:
+        s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=4),
+                      tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy))
+        s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        b = s.device_bytes()
+        if used + b > budget:  # admission by device-memory budget
+            s.destroy()
+            continue
+        used += b
+        streams.append(s)
+    S = len(streams)
+    outs = [(torch.empty((sc.pts.shape[0], 3), dtype=torch.float32, device=dev),
+             torch.empty((sc.num_control_points, 8), dtype=torch.float32, device=dev)) for sc in scenes[:S]]
+    order = [0, 1, 2, 1]
+
+    def fr(q, k):
+        d = frames[q][order[k % len(order)]]
+        return (d[0], d[1], d[2], d[1].shape[0], outs[q][0], outs[q][1])
+
+    def plain_round(k):
+        for q in range(S):
+            f = fr(q, k)
+            streams[q].track_frame_device(*f)
+
+    def batch_round(k, idx=None):
+        idx = list(range(S)) if idx is None else idx
+        tt.track_batch_device([streams[q] for q in idx], [fr(q, k) for q in idx])
+
+    res = {}
+    for name, fn in (("plain", plain_round), ("batched", batch_round)):
+        fn(0)
+        torch.cuda.synchronize()
+        for s in streams:
+            s.sync()
+        t1 = time.perf_counter()
+        rounds = args.serving_rounds
+        for k in range(rounds):
+            fn(k + 1)
+        for s in streams:
+            s.sync()
+        dt = time.perf_counter() - t1
+        res[name] = S * rounds / dt
+        log(f"  {name:8s} {res[name]:8.1f} frames/s over {S} streams")
+    # Poisson arrivals, continuous batching
+    rng = np.random.default_rng(4)
+    dur = args.serving_seconds
+    arrivals = []
+    for q in range(S):
+        t, a = 0.0, []
+        while t < dur:
+            t += rng.exponential(1.0 / args.serving_hz)
+            if t < dur:
+                a.append(t)
+        arrivals.append(a)
+    nxt = [0] * S
+    lat = []
+    done = 0
+    total = sum(len(a) for a in arrivals)
+    t_start = time.perf_counter()
+    k = 0
+    while done < total:
+        now = time.perf_counter() - t_start
+        ready = [q for q in range(S) if nxt[q] < len(arrivals[q]) and arrivals[q][nxt[q]] <= now]
+        if not ready:
+            soon = min(arrivals[q][nxt[q]] for q in range(S) if nxt[q] < len(arrivals[q]))
+            time.sleep(max(0.0, soon - now))
+            continue
+        batch_round(k, ready)
+        k += 1
+        streams[ready[0]].sync()
+        t_end = time.perf_counter() - t_start
+        for q in ready:
+            lat.append(t_end - arrivals[q][nxt[q]])
+            nxt[q] += 1
+            done += 1
+    wall = time.perf_counter() - t_start
+    lat = np.array(lat) * 1e3
+    for s in streams:
+        s.destroy()
+    return {"workload": f"config4: {S} streams, N 100-800, depth 320x240..640x480, K 500-3000, 20-40% outliers, "
+                        f"10 LM iterations per frame, FP32",
+            "streams": S, "device_bytes": used,
+            "plain_frames_per_s": res["plain"], "batched_frames_per_s": res["batched"],
+            "batched_over_plain": res["batched"] / res["plain"],
+            "poisson": {"rate_hz_per_stream": args.serving_hz, "seconds": dur, "frames": int(total),
+                        "frames_per_s": total / wall, "p50_ms": float(np.percentile(lat, 50)),
+                        "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max())}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +178,12 @@ def main():
     ap.add_argument("--frames", type=int, default=8, help="distinct synthetic frames (replayed ping-pong)")
     ap.add_argument("--cpu-lm-sample", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=1, help="also run the config 4 serving mix (0 = skip)")
+    ap.add_argument("--serving-streams", type=int, default=16)
+    ap.add_argument("--serving-rounds", type=int, default=3)
+    ap.add_argument("--serving-seconds", type=float, default=6.0)
+    ap.add_argument("--serving-hz", type=float, default=15.0)
+    ap.add_argument("--serving-hbm-gib", type=float, default=200.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device 3 times (a plain copy of known "
                          "size whose FETCH_SIZE / WRITE_SIZE counters calibrate the HBM traffic readings)")
@@ -172,6 +282,9 @@ def main():
         "stage_us": {k: v["ms_per_call"] * 1e3 for k, v in stages.items()},
         "roofline": roof,
     }
+
+    if args.serving:
+        out["batched"] = serving_bench(args, torch, tt)
 
     if not args.no_cpu_baseline:
         # same frame, same reduced iteration count on the GPU: the full-size accuracy check
