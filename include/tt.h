@@ -46,7 +46,11 @@ extern "C" {
 #define TT_EDEVICE (-4) /* a HIP call failed, or a device-side bound was hit               */
 #define TT_EBUSY (-5)   /* another call is running on the same stream                       */
 
-#define TT_FP32 0 /* FP32 assembly and FP32 Cholesky (the only precision of this version) */
+/* Precision of the normal-equation solve (assembly is FP32 and the LM cost sums FP64 in all forms). */
+#define TT_FP32 0    /* FP32 Cholesky: FP32 tile products on the matrix cores, FP32 substitutions        */
+#define TT_BF16_IR 1 /* tile products with bfloat16 inputs and FP32 accumulation, then ir_iters steps of
+                        iterative refinement whose residual is formed in FP64                             */
+#define TT_FP16_IR 2 /* the same with binary16 inputs                                                    */
 
 typedef struct tt_stream tt_stream;
 
@@ -69,9 +73,10 @@ typedef struct {
   int lm_iters;            /* Levenberg-Marquardt iterations per frame: 10                   */
   int max_hamming;         /* matches farther than this are unusable; 256 keeps all          */
   double lm_lambda0;       /* initial Marquardt damping of each frame: 1e-4                  */
-  int precision;           /* TT_FP32                                                        */
+  int precision;           /* TT_FP32, TT_BF16_IR or TT_FP16_IR                               */
   uint64_t seed;           /* seed of the reference-match sampler                            */
   uint64_t hbm_budget_bytes; /* 0 = unlimited; otherwise a cap on the stream's device bytes  */
+  int ir_iters;            /* refinement steps per solve in the 16-bit forms (0..8); default 2 */
 } tt_params;
 
 /* Optional per-frame outputs of tt_track_frame; each pointer may be NULL. Sizes: K1 template
@@ -188,6 +193,11 @@ int tt_get_timing(tt_stream* s, double* ms, int64_t* count);
  * memory. *fail receives 1 if a pivot was not positive. Allocates and frees its own device
  * memory; synchronous. */
 int tt_debug_cholesky_solve(int n, const float* A, const float* b, float* x, int* fail);
+
+/* The same with a precision form (TT_FP32, TT_BF16_IR, TT_FP16_IR) and ir_iters refinement steps
+ * (ignored for TT_FP32): the diagnostic of the 16-bit solve and its refinement. */
+int tt_debug_cholesky_solve_ex(int n, const float* A, const float* b, float* x, int* fail, int precision,
+                               int ir_iters);
 
 /* Device bytes held by the stream. */
 int tt_device_bytes(tt_stream* s, uint64_t* bytes);

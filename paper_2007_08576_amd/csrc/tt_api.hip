@@ -61,7 +61,9 @@ void free_template(tt_stream* s) {
   LMScalars* sc = d.sc;
   double *lo = d.log_cost_old, *ln = d.log_cost_new, *ll = d.log_lambda;
   int* la = d.log_accept;
+  const int cus = d.num_cus, prec = d.prec, ir = d.ir_iters;
   d = DevState();
+  d.num_cus = cus; d.prec = prec; d.ir_iters = ir;
   d.HW = HW; d.K2cap = K2cap; d.depth = depth; d.nmap = nmap; d.f2xyz = f2xyz; d.f2desc = f2desc;
   d.sc = sc; d.log_cost_old = lo; d.log_cost_new = ln; d.log_lambda = ll; d.log_accept = la;
   s->has_template = false;
@@ -225,6 +227,48 @@ int enqueue_assemble(tt_stream* s, DevState& dd, int it, bool dbg, hipStream_t s
   {
     StageTimer tm(s, TT_STAGE_SOLVE, st);
     HIPCHK(launch_lm_damp(dd, st));
+    if (d.prec != TT_FP32) HIPCHK(launch_ir_prepare(dd, st));
+  }
+  return TT_OK;
+}
+
+static int next_subst(tt_stream* s) {
+  s->subst_epoch = (s->subst_epoch == 0x7FFFFFFF) ? 1 : s->subst_epoch + 1;
+  return s->subst_epoch;
+}
+
+// Factorisation, substitutions and (16-bit forms) refinement of S systems at once.
+int enqueue_solve(tt_stream* const* ss, DevState* const* dp, const int* epochs, int S, hipStream_t st) {
+  std::vector<int> be(S), fe(S);
+  {
+    StageTimer tm(ss[0], TT_STAGE_FACTOR, st);
+    HIPCHK(launch_cholesky_factor_batch(dp, epochs, S, st));
+  }
+  StageTimer tm(ss[0], TT_STAGE_SOLVE, st);
+  for (int q = 0; q < S; q++) be[q] = next_subst(ss[q]);
+  HIPCHK(launch_cholesky_backsolve_batch(dp, be.data(), S, st));
+  // refinement for the systems in a 16-bit form
+  std::vector<DevState*> ir;
+  std::vector<tt_stream*> irs;
+  int steps = 0;
+  for (int q = 0; q < S; q++)
+    if (dp[q]->prec != TT_FP32 && dp[q]->ir_iters > 0) {
+      ir.push_back(dp[q]);
+      irs.push_back(ss[q]);
+      steps = std::max(steps, dp[q]->ir_iters);
+    }
+  if (ir.empty()) return TT_OK;
+  HIPCHK(launch_ir_accum_batch(ir.data(), (int)ir.size(), 0, st));
+  for (int t = 0; t < steps; t++) {
+    std::vector<DevState*> act;
+    std::vector<int> f, b;
+    for (size_t q = 0; q < ir.size(); q++)
+      if (t < ir[q]->ir_iters) {
+        act.push_back(ir[q]);
+        f.push_back(next_subst(irs[q]));
+        b.push_back(next_subst(irs[q]));
+      }
+    HIPCHK(launch_ir_step_batch(act.data(), f.data(), b.data(), (int)act.size(), st));
   }
   return TT_OK;
 }
@@ -247,14 +291,9 @@ int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint
     int epoch = 0;
     rc = enqueue_assemble(s, dd, it, dbg, st, &epoch);
     if (rc) return rc;
-    {
-      StageTimer tm(s, TT_STAGE_FACTOR, st);
-      HIPCHK(launch_cholesky_factor(dd, epoch, st));
-    }
-    {
-      StageTimer tm(s, TT_STAGE_SOLVE, st);
-      HIPCHK(launch_cholesky_backsolve(dd, epoch, st));
-    }
+    DevState* dp[1] = {&dd};
+    rc = enqueue_solve(&s, dp, &epoch, 1, st);
+    if (rc) return rc;
     rc = enqueue_finish(s, dd, st);
     if (rc) return rc;
   }
@@ -279,14 +318,8 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
   for (int it = 0; it < ss[0]->P.lm_iters && !rc; it++) {
     for (int q = 0; q < S && !rc; q++) rc = enqueue_assemble(ss[q], dd[q], it, false, batch_st, &epochs[q]);
     if (rc) break;
-    {
-      StageTimer tm(ss[0], TT_STAGE_FACTOR, batch_st);
-      HIPCHK(launch_cholesky_factor_batch(dp.data(), epochs.data(), S, batch_st));
-    }
-    {
-      StageTimer tm(ss[0], TT_STAGE_SOLVE, batch_st);
-      HIPCHK(launch_cholesky_backsolve_batch(dp.data(), epochs.data(), S, batch_st));
-    }
+    rc = enqueue_solve(ss, dp.data(), epochs.data(), S, batch_st);
+    if (rc) break;
     for (int q = 0; q < S && !rc; q++) rc = enqueue_finish(ss[q], dd[q], batch_st);
   }
   for (int q = 0; q < S && !rc; q++) {
@@ -411,6 +444,7 @@ void tt_default_params(tt_params* p) {
   p->precision = TT_FP32;
   p->seed = 0;
   p->hbm_budget_bytes = 0;
+  p->ir_iters = 2;
 }
 
 const char* tt_strerror(int code) {
@@ -439,7 +473,8 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
   if (p->num_control_points < 1 || p->knn != 4 || p->ransac_refs < 1 || p->ransac_refs > 1024 ||
       p->ransac_iters < 1 || p->lm_iters < 0 || p->lm_iters > 1000 || !(p->H > 0) || !(p->tukey_c > 0) ||
       !(p->w_orb >= 0) || !(p->w_angle >= 0) || !(p->w_rotation >= 0) || !(p->lambda_arap >= 0) ||
-      !(p->lm_lambda0 > 0) || p->precision != TT_FP32)
+      !(p->lm_lambda0 > 0) || p->precision < TT_FP32 || p->precision > TT_FP16_IR || p->ir_iters < 0 ||
+      p->ir_iters > 8)
     return TT_EINVAL;
   if (K->width < 3 || K->height < 3 || !(K->fx > 0) || !(K->fy > 0) || !isfinite(K->cx) || !isfinite(K->cy) ||
       (int64_t)K->width * K->height > (1 << 28))
@@ -460,6 +495,8 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
   DevState& d = s->d;
   d.HW = K->width * K->height;
   d.num_cus = device_cus();
+  d.prec = p->precision;
+  d.ir_iters = (p->precision == TT_FP32) ? 0 : p->ir_iters;
   int T = p->lm_iters > 0 ? p->lm_iters : 1;
   int rc = TT_OK;
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.depth, (size_t)d.HW);
@@ -505,13 +542,22 @@ int tt_get_timing(tt_stream* s, double* ms, int64_t* count) {
 }
 
 int tt_debug_cholesky_solve(int n, const float* A, const float* b, float* x, int* fail) {
-  if (n < 1 || n > 65536 || !A || !b || !x || !fail) return TT_EINVAL;
+  return tt_debug_cholesky_solve_ex(n, A, b, x, fail, TT_FP32, 0);
+}
+
+int tt_debug_cholesky_solve_ex(int n, const float* A, const float* b, float* x, int* fail, int precision,
+                               int ir_iters) {
+  if (n < 1 || n > 65536 || !A || !b || !x || !fail || precision < TT_FP32 || precision > TT_FP16_IR ||
+      ir_iters < 0 || ir_iters > 8)
+    return TT_EINVAL;
   DevState d;
   d.num_cus = device_cus();
   d.n = n;
   d.npad = ((n + TT_NB - 1) / TT_NB) * TT_NB;
   d.nb = d.npad / TT_NB;
   d.ld = d.npad;
+  d.prec = precision;
+  d.ir_iters = (precision == TT_FP32) ? 0 : ir_iters;
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return TT_EDEVICE;
   std::vector<void*> mem;
@@ -522,9 +568,14 @@ int tt_debug_cholesky_solve(int n, const float* A, const float* b, float* x, int
   };
   int rc = TT_OK;
   const size_t rows = (size_t)d.npad + TT_NB;
-  if (!al((void**)&d.A, sizeof(float) * rows * d.ld) || !al((void**)&d.x, sizeof(float) * d.npad) ||
-      !al((void**)&d.Linv, sizeof(float) * (size_t)d.nb * TT_NB * TT_NB) || !al((void**)&d.flags, sizeof(int) * chol_flag_ints(d.nb)) ||
-      !al((void**)&d.sc, sizeof(LMScalars)) || !al((void**)&d.dscale, sizeof(float) * d.npad)) {
+  bool okm = al((void**)&d.A, sizeof(float) * rows * d.ld) && al((void**)&d.x, sizeof(float) * d.npad) &&
+             al((void**)&d.Linv, sizeof(float) * (size_t)d.nb * TT_NB * TT_NB) &&
+             al((void**)&d.flags, sizeof(int) * chol_flag_ints(d.nb)) && al((void**)&d.sc, sizeof(LMScalars)) &&
+             al((void**)&d.dscale, sizeof(float) * d.npad);
+  if (okm && precision != TT_FP32)
+    okm = al((void**)&d.A16, sizeof(uint16_t) * rows * d.ld) && al((void**)&d.A0, sizeof(float) * d.npad * d.ld) &&
+          al((void**)&d.cvec, sizeof(float) * d.npad) && al((void**)&d.xd, sizeof(double) * d.npad);
+  if (!okm) {
     rc = TT_ENOMEM;
   } else {
     std::vector<float> h(rows * d.ld, 0.0f);
@@ -535,18 +586,30 @@ int tt_debug_cholesky_solve(int n, const float* A, const float* b, float* x, int
     std::vector<float> hx(d.npad), ones(d.npad, 1.0f);  // no equilibration in this diagnostic
     LMScalars sc;
     memset(&sc, 0, sizeof(sc));
-    if (hipMemcpyAsync(d.A, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemsetAsync(d.flags, 0, sizeof(int) * chol_flag_ints(d.nb), st) != hipSuccess ||
-        hipMemcpyAsync(d.dscale, ones.data(), sizeof(float) * d.npad, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(d.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, st) != hipSuccess ||
-        launch_cholesky_factor(d, 1, st) != hipSuccess || launch_cholesky_backsolve(d, 1, st) != hipSuccess ||
-        hipMemcpyAsync(hx.data(), d.x, sizeof(float) * d.npad, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipMemcpyAsync(&sc, d.sc, sizeof(sc), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) {
+    int epoch = 1, e2 = 2;
+    DevState* dp[1] = {&d};
+    bool ok = hipMemcpyAsync(d.A, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemsetAsync(d.flags, 0, sizeof(int) * chol_flag_ints(d.nb), st) == hipSuccess &&
+              hipMemcpyAsync(d.dscale, ones.data(), sizeof(float) * d.npad, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(d.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, st) == hipSuccess;
+    if (ok && precision != TT_FP32) ok = launch_ir_prepare(d, st) == hipSuccess;
+    ok = ok && launch_cholesky_factor(d, epoch, st) == hipSuccess && launch_cholesky_backsolve(d, epoch, st) == hipSuccess;
+    if (ok && d.ir_iters > 0) {
+      ok = launch_ir_accum_batch(dp, 1, 0, st) == hipSuccess;
+      for (int t = 0; ok && t < d.ir_iters; t++, e2 += 2) {
+        int fe = e2, be = e2 + 1;
+        ok = launch_ir_step_batch(dp, &fe, &be, 1, st) == hipSuccess;
+      }
+    }
+    ok = ok && hipMemcpyAsync(hx.data(), d.x, sizeof(float) * d.npad, hipMemcpyDeviceToHost, st) == hipSuccess &&
+         hipMemcpyAsync(&sc, d.sc, sizeof(sc), hipMemcpyDeviceToHost, st) == hipSuccess &&
+         hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) {
       rc = TT_EDEVICE;
     } else {
       for (int i = 0; i < n; i++) x[i] = hx[i];
       *fail = sc.chol_fail;
+      if (sc.err) rc = TT_EDEVICE;
     }
   }
   (void)hipStreamSynchronize(st);
@@ -666,6 +729,12 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
   ALLOC(allocs_template, bytes_template, d.x, (size_t)d.npad);
   ALLOC(allocs_template, bytes_template, d.Linv, (size_t)d.nb * TT_NB * TT_NB);
   ALLOC(allocs_template, bytes_template, d.flags, chol_flag_ints(d.nb));
+  if (d.prec != TT_FP32) {
+    ALLOC(allocs_template, bytes_template, d.A16, (size_t)(d.npad + TT_NB) * d.ld);
+    ALLOC(allocs_template, bytes_template, d.A0, (size_t)d.npad * d.ld);
+    ALLOC(allocs_template, bytes_template, d.cvec, (size_t)d.npad);
+    ALLOC(allocs_template, bytes_template, d.xd, (size_t)d.npad);
+  }
   ALLOC(allocs_template, bytes_template, d.dscale, (size_t)d.npad);
   d.npartial = partial_count(M, K1, N) + 8;
   ALLOC(allocs_template, bytes_template, d.partial, (size_t)d.npartial);

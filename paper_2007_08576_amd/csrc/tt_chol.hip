@@ -324,6 +324,7 @@ struct CholSync {
   int* dinv;    // [nb] Linv_j published
   int* ctr;     // [1] ticket counter (0 between solves)
   int* abort_;  // [1] epoch of an aborted solve
+  int* fflag;   // [nb] forward substitution (refinement steps)
 };
 
 __host__ __device__ inline CholSync chol_sync(int* base, int nb) {
@@ -335,6 +336,7 @@ __host__ __device__ inline CholSync chol_sync(int* base, int nb) {
   S.dinv = S.psub + nb;
   S.ctr = S.dinv + nb;
   S.abort_ = S.ctr + 1;
+  S.fflag = S.abort_ + 1;
   return S;
 }
 
@@ -530,6 +532,79 @@ __device__ __forceinline__ void acc_zero(floatx4 v[2][2]) {
     for (int b = 0; b < 2; b++) v[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 }
 
+// ---- 16-bit tile products (precision forms) --------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+constexpr int LD16 = NB + 8;  // 16-bit LDS tiles: rows of 144 bytes (16-byte aligned)
+
+// FP32 -> bfloat16 bits, round to nearest even (finite inputs) / FP32 -> binary16 bits.
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ uint16_t to_f16(float f) {
+  const _Float16 h = (_Float16)f;
+  return __builtin_bit_cast(uint16_t, h);
+}
+
+// 16-bit copy of a tile held in the accumulator layout.
+__device__ __forceinline__ void acc_store16(uint16_t* __restrict__ A16, int ld, size_t r0, size_t c0,
+                                            const floatx4 v[2][2], int prec) {
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const float f = v[a][b][r];
+        A16[(r0 + acc_row(a, r)) * ld + c0 + acc_col(b)] = (prec == TT_BF16_IR) ? to_bf16(f) : to_f16(f);
+      }
+}
+
+// 64 x 64 16-bit tile at (r0, c0) into registers (two 16-byte pieces per thread) and into LDS.
+__device__ __forceinline__ void tile_load16(const uint16_t* __restrict__ M, int ld, size_t r0, size_t c0, uint4 v[2]) {
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    const int e = threadIdx.x + 256 * q;  // 512 pieces of 8 elements: row e / 8, columns 8 (e % 8)
+    v[q] = *reinterpret_cast<const uint4*>(M + (r0 + (e >> 3)) * ld + c0 + 8 * (e & 7));
+  }
+}
+__device__ __forceinline__ void tile16_to_lds(uint16_t* X, const uint4 v[2]) {
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    const int e = threadIdx.x + 256 * q;
+    *reinterpret_cast<uint4*>(X + (e >> 3) * LD16 + 8 * (e & 7)) = v[q];
+  }
+}
+
+// acc += X Y^T for 64 x 64 16-bit tiles in LDS (v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulation),
+// same quadrant layout as mma64_acc. Lane (li, lk) supplies the 8 consecutive reduction indices
+// 32 s + 8 lk .. + 7 of step s for both operands, so the two 32-step halves cover all 64.
+__device__ __forceinline__ void mma64_acc16(const uint16_t* X, const uint16_t* Y, floatx4 acc[2][2], int prec) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int qr = 32 * (w / 2), qc = 32 * (w % 2);
+  const int li = lane % 16, k8 = 8 * (lane / 16);
+#pragma unroll
+  for (int s = 0; s < 2; s++) {
+    uint4 av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; a++) av[a] = *reinterpret_cast<const uint4*>(X + (qr + 16 * a + li) * LD16 + 32 * s + k8);
+#pragma unroll
+    for (int b = 0; b < 2; b++) bv[b] = *reinterpret_cast<const uint4*>(Y + (qc + 16 * b + li) * LD16 + 32 * s + k8);
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int b = 0; b < 2; b++) {
+        if (prec == TT_BF16_IR)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[a]),
+                                                               __builtin_bit_cast(bf16x8, bv[b]), acc[a][b], 0, 0, 0);
+        else
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, av[a]),
+                                                              __builtin_bit_cast(halfx8, bv[b]), acc[a][b], 0, 0, 0);
+      }
+  }
+}
+
 struct CholArgs {
   float* A;
   int ld, npad, nb, ntasks, epoch;
@@ -537,7 +612,12 @@ struct CholArgs {
   float* Linv;
   int* flags;
   LMScalars* sc;
-  float* x;  // solution of the back substitution
+  float* x;          // solution of the back substitution
+  int prec;          // TT_FP32, TT_BF16_IR or TT_FP16_IR: input type of the tile products
+  uint16_t* A16;     // 16-bit copies of the finished L tiles (same layout as A), or null
+  const float* A0;   // refinement: the damped matrix before factorisation (lower triangle), or null
+  const float* c;    // refinement: the equilibrated right-hand side
+  double* xd;        // refinement: the solution accumulated in FP64
 };
 
 // Ticket of CRIT(j): the number of tasks in the groups before j, plus DIAGP(j) and SUBP(j).
@@ -685,6 +765,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         mma64_acc(X, Z, acc);  // L_{j,j-1} = C_{j,j-1} Linv_{j-1}^T
         __syncthreads();
         acc_store(P.A, ld, rj, rj - NB, acc);  // completes while the update below runs
+        if (P.prec != TT_FP32) acc_store16(P.A16, ld, rj, rj - NB, acc, P.prec);
         acc_to_lds(X, acc, false);
         __syncthreads();
         acc_zero(acc);
@@ -746,7 +827,37 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
     const int* fi = S.fin + (size_t)i * nb;
     const int* fc = S.fin + (size_t)c * nb;
     bool ok = true;
-    if (nk > 0) {
+    if (nk > 0 && P.prec != TT_FP32) {
+      // 16-bit operand tiles (half the bytes), one step ahead in registers
+      uint16_t* X16 = reinterpret_cast<uint16_t*>(&X[0][0]);
+      uint16_t* Y16 = reinterpret_cast<uint16_t*>(&Y[0][0]);
+      int kr = block_ready_prefix(fi, fc, 0, nk, epoch, S, deadline, &s_val);
+      ok = kr > 0;
+      uint4 va[2], vb[2];
+      if (ok) {
+        tile_load16(P.A16, ld, ri, 0, va);
+        if (!same) tile_load16(P.A16, ld, rc, 0, vb);
+      }
+      for (int k = 0; ok && k < nk; k++) {
+        __syncthreads();
+        tile16_to_lds(X16, va);
+        if (!same) tile16_to_lds(Y16, vb);
+        __syncthreads();
+        if (k + 1 < nk) {
+          if (k + 1 >= kr) {
+            const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, deadline, &s_val);
+            if (more == 0) {
+              ok = false;
+              break;
+            }
+            kr = k + 1 + more;
+          }
+          tile_load16(P.A16, ld, ri, (size_t)NB * (k + 1), va);
+          if (!same) tile_load16(P.A16, ld, rc, (size_t)NB * (k + 1), vb);
+        }
+        mma64_acc16(X16, same ? X16 : Y16, acc, P.prec);
+      }
+    } else if (nk > 0) {
       int kr = block_ready_prefix(fi, fc, 0, nk, epoch, S, deadline, &s_val);
       ok = kr > 0;
       float4 va[4], vb[4];
@@ -796,6 +907,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
     acc_zero(acc);
     mma64_acc(X, Y, acc);
     acc_store(P.A, ld, ri, rc, acc);
+    if (P.prec != TT_FP32) acc_store16(P.A16, ld, ri, rc, acc, P.prec);
     block_publish(S.fin + (size_t)i * nb + c, epoch);
   }
 }
@@ -874,9 +986,107 @@ __global__ __launch_bounds__(64) void k_chol_backsolve(const BackBatch B) {
   }
 }
 
+// Forward substitution y = L^{-1} r for the refinement steps (the first right-hand side rides
+// along the factorisation): r is in the right-hand-side row and is overwritten by y. One wavefront
+// per block row, in increasing order; block row j waits for y_k of every k < j (flag per block).
+__global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
+  __shared__ float ys[NB];
+  __shared__ float rs[NB];
+  int q = 0;
+  while (q + 1 < B.nprob && (int)blockIdx.x >= B.wg0[q + 1]) q++;
+  const CholArgs& P = B.p[q];
+  const int ld = P.ld, epoch = P.epoch;
+  float* row = P.A + (size_t)P.npad * ld;
+  int* flags = chol_sync(P.flags, P.nb).fflag;
+  const int j = (int)blockIdx.x - B.wg0[q];
+  const int c = threadIdx.x;
+  const float rj = row[NB * j + c];
+  const float* Li = P.Linv + (size_t)j * NB * NB + (size_t)c * NB;  // row c of Linv_jj
+  float acc = 0.0f;
+  bool ok = true;
+  for (int k = 0; k < j; k++) {
+    // row c of L_jk is final (written by the factorisation): fetch it before waiting
+    const float4* Lr = reinterpret_cast<const float4*>(P.A + (size_t)(NB * j + c) * ld + NB * k);
+    float4 lr[NB / 4];
+#pragma unroll
+    for (int m = 0; m < NB / 4; m++) lr[m] = Lr[m];
+    if (c == 0) ok = wait_flag(flags + k, epoch) && ok;
+    __syncthreads();
+    ys[c] = __hip_atomic_load(row + NB * k + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NB / 4; m++)
+      acc += lr[m].x * ys[4 * m] + lr[m].y * ys[4 * m + 1] + lr[m].z * ys[4 * m + 2] + lr[m].w * ys[4 * m + 3];
+    __syncthreads();
+  }
+  rs[c] = rj - acc;
+  __syncthreads();
+  float y = 0.0f;
+#pragma unroll
+  for (int m = 0; m < NB; m++) y += Li[m] * rs[m];
+  __hip_atomic_store(row + NB * j + c, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);  // this lane's result store has completed
+  __syncthreads();
+  if (c == 0) {
+    __hip_atomic_store(flags + j, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!ok) {
+      P.sc->chol_fail = 1;
+      P.sc->err = TT_DEVERR_CHOL_SYNC;
+    }
+  }
+}
+
+// Refinement residual of the equilibrated system, r = c - D A0 D xd, formed in FP64 from the FP32
+// damped matrix A0 (lower triangle) and the FP64 solution; written (rounded to FP32) into the
+// right-hand-side row. One workgroup per block of 64 rows; thread (r, g) sums columns 16 g .. 16 g + 15
+// of every column block.
+__global__ __launch_bounds__(256) void k_ir_resid(const BackBatch B) {
+  __shared__ double part[4][NB];
+  int q = 0;
+  while (q + 1 < B.nprob && (int)blockIdx.x >= B.wg0[q + 1]) q++;
+  const CholArgs& P = B.p[q];
+  const int ld = P.ld, nb = P.nb;
+  const int ib = (int)blockIdx.x - B.wg0[q];
+  const int r = threadIdx.x % NB, g = threadIdx.x / NB;
+  const size_t gi = (size_t)NB * ib + r;
+  double acc = 0.0;
+  for (int jb = 0; jb < nb; jb++) {
+#pragma unroll 4
+    for (int cc = 0; cc < 16; cc++) {
+      const int col = 16 * g + cc;
+      const size_t gj = (size_t)NB * jb + col;
+      const bool lower = (jb < ib) || (jb == ib && col <= r);
+      const float a = lower ? P.A0[gi * ld + gj] : P.A0[gj * ld + gi];
+      acc += (double)a * ((double)P.dscale[gj] * P.xd[gj]);
+    }
+  }
+  part[g][r] = acc;
+  __syncthreads();
+  if (g == 0) {
+    const double sr = part[0][r] + part[1][r] + part[2][r] + part[3][r];
+    const double res = (double)P.c[gi] - (double)P.dscale[gi] * sr;
+    P.A[(size_t)P.npad * ld + gi] = (float)res;
+  }
+}
+
+// xd = x (mode 0), or xd += x and x = xd rounded (mode 1). One wavefront per block of 64 entries.
+__global__ __launch_bounds__(64) void k_ir_accum(const BackBatch B, int mode) {
+  int q = 0;
+  while (q + 1 < B.nprob && (int)blockIdx.x >= B.wg0[q + 1]) q++;
+  const CholArgs& P = B.p[q];
+  const size_t i = (size_t)NB * ((int)blockIdx.x - B.wg0[q]) + threadIdx.x;
+  if (mode == 0) {
+    P.xd[i] = (double)P.x[i];
+  } else {
+    const double v = P.xd[i] + (double)P.x[i];
+    P.xd[i] = v;
+    P.x[i] = (float)v;
+  }
+}
+
 }  // namespace
 
-size_t chol_flag_ints(int nb) { return (size_t)nb + (size_t)(nb + 1) * nb + 3 * (size_t)nb + 2; }
+size_t chol_flag_ints(int nb) { return (size_t)nb + (size_t)(nb + 1) * nb + 4 * (size_t)nb + 2; }
 
 static CholArgs chol_args(const DevState& d, int epoch) {
   CholArgs P;
@@ -891,6 +1101,11 @@ static CholArgs chol_args(const DevState& d, int epoch) {
   P.flags = d.flags;
   P.sc = d.sc;
   P.x = d.x;
+  P.prec = d.prec;
+  P.A16 = d.A16;
+  P.A0 = d.A0;
+  P.c = d.cvec;
+  P.xd = d.xd;
   return P;
 }
 
@@ -915,21 +1130,56 @@ hipError_t launch_cholesky_factor(DevState& d, int epoch, hipStream_t st) {
   return launch_cholesky_factor_batch(ds, &epoch, 1, st);
 }
 
-hipError_t launch_cholesky_backsolve_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st) {
+// One launch per (up to) 32 systems of a per-block-row kernel (grid: 64-row blocks of every system).
+template <typename F>
+static hipError_t launch_rows_batch(DevState* const* ds, const int* epochs, int S, F launch) {
   for (int b0 = 0; b0 < S; b0 += kMaxCholBatch) {
     BackBatch B;
     B.nprob = (S - b0 < kMaxCholBatch) ? S - b0 : kMaxCholBatch;
     B.wg0[0] = 0;
     for (int q = 0; q < B.nprob; q++) {
-      B.p[q] = chol_args(*ds[b0 + q], epochs[b0 + q]);
+      B.p[q] = chol_args(*ds[b0 + q], epochs ? epochs[b0 + q] : 0);
       B.wg0[q + 1] = B.wg0[q] + ds[b0 + q]->nb;
     }
-    hipLaunchKernelGGL(k_chol_backsolve, dim3(B.wg0[B.nprob]), dim3(64), 0, st, B);
+    launch(B);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_cholesky_backsolve_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st) {
+  return launch_rows_batch(ds, epochs, S, [&](const BackBatch& B) {
+    hipLaunchKernelGGL(k_chol_backsolve, dim3(B.wg0[B.nprob]), dim3(64), 0, st, B);
+  });
 }
 
 hipError_t launch_cholesky_backsolve(DevState& d, int epoch, hipStream_t st) {
   DevState* ds[1] = {&d};
   return launch_cholesky_backsolve_batch(ds, &epoch, 1, st);
+}
+
+hipError_t launch_ir_prepare(DevState& d, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(d.A0, d.A, sizeof(float) * (size_t)d.npad * d.ld, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(d.cvec, d.A + (size_t)d.npad * d.ld, sizeof(float) * d.npad, hipMemcpyDeviceToDevice, st);
+}
+
+hipError_t launch_ir_step_batch(DevState* const* ds, const int* fwd_epochs, const int* back_epochs, int S,
+                                hipStream_t st) {
+  hipError_t e = launch_rows_batch(ds, nullptr, S, [&](const BackBatch& B) {
+    hipLaunchKernelGGL(k_ir_resid, dim3(B.wg0[B.nprob]), dim3(256), 0, st, B);
+  });
+  if (e != hipSuccess) return e;
+  e = launch_rows_batch(ds, fwd_epochs, S, [&](const BackBatch& B) {
+    hipLaunchKernelGGL(k_chol_fwdsolve, dim3(B.wg0[B.nprob]), dim3(64), 0, st, B);
+  });
+  if (e != hipSuccess) return e;
+  e = launch_cholesky_backsolve_batch(ds, back_epochs, S, st);
+  if (e != hipSuccess) return e;
+  return launch_ir_accum_batch(ds, S, 1, st);
+}
+
+hipError_t launch_ir_accum_batch(DevState* const* ds, int S, int mode, hipStream_t st) {
+  return launch_rows_batch(ds, nullptr, S, [&](const BackBatch& B) {
+    hipLaunchKernelGGL(k_ir_accum, dim3(B.wg0[B.nprob]), dim3(64), 0, st, B, mode);
+  });
 }

@@ -103,6 +103,12 @@ struct DevState {
   float* Linv = nullptr;     // [nb][TT_NB][TT_NB]
   int* flags = nullptr;      // [chol_flag_ints(nb)] factorisation and back-substitution flags
   int num_cus = 0;           // compute units of the device (persistent launch size)
+  int prec = TT_FP32;        // precision form of the solve
+  int ir_iters = 0;          // refinement steps per solve (16-bit forms)
+  uint16_t* A16 = nullptr;   // 16-bit copies of the finished L tiles [(npad + 64) * ld]
+  float* A0 = nullptr;       // damped matrix before factorisation [npad * ld] (refinement)
+  float* cvec = nullptr;     // equilibrated right-hand side [npad] (refinement)
+  double* xd = nullptr;      // FP64 solution of the refinement [npad]
   double* partial = nullptr; // reduction partials
   int npartial = 0;
   LMScalars* sc = nullptr;
@@ -126,7 +132,8 @@ struct tt_stream {
   bool own_stream = false;
   bool has_template = false;
   int64_t frame = 0;
-  int solve_epoch = 0;  // increments per Cholesky solve; flags of the back substitution match it
+  int solve_epoch = 0;  // increments per factorisation; its tile flags match it
+  int subst_epoch = 0;  // increments per forward / back substitution; their block flags match it
   std::mutex mu;
   DevState d;
   std::vector<void*> allocs_template;  // freed on re-template / destroy
@@ -173,3 +180,10 @@ hipError_t launch_cholesky_backsolve(DevState& d, int epoch, hipStream_t st);
 // The same for S independent systems at once (one launch per 32 systems).
 hipError_t launch_cholesky_factor_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st);
 hipError_t launch_cholesky_backsolve_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st);
+// Refinement (16-bit forms): keep the damped matrix and right-hand side before the factorisation;
+// xd = x (mode 0) or xd += x, x = xd (mode 1); one step = FP64 residual, forward and back
+// substitution, accumulation.
+hipError_t launch_ir_prepare(DevState& d, hipStream_t st);
+hipError_t launch_ir_accum_batch(DevState* const* ds, int S, int mode, hipStream_t st);
+hipError_t launch_ir_step_batch(DevState* const* ds, const int* fwd_epochs, const int* back_epochs, int S,
+                                hipStream_t st);

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtt.so")
 
 TT_OK, TT_EINVAL, TT_ENOMEM, TT_ESTATE, TT_EDEVICE, TT_EBUSY = 0, -1, -2, -3, -4, -5
-TT_FP32 = 0
+TT_FP32, TT_BF16_IR, TT_FP16_IR = 0, 1, 2
 STAGES = ("front", "rows", "arap", "data", "solve", "update", "factor")
 
 _lib = None
@@ -36,7 +36,7 @@ class Params(C.Structure):
                 ("tukey_c", C.c_double), ("H", C.c_double), ("ransac_refs", C.c_int),
                 ("ransac_iters", C.c_int), ("lm_iters", C.c_int), ("max_hamming", C.c_int),
                 ("lm_lambda0", C.c_double), ("precision", C.c_int), ("seed", C.c_uint64),
-                ("hbm_budget_bytes", C.c_uint64)]
+                ("hbm_budget_bytes", C.c_uint64), ("ir_iters", C.c_int)]
 
 
 _DEBUG_FIELDS = ("match_idx", "match_dist", "wstar", "preselected", "hyp_k0", "hyp_W", "hyp_nin",
@@ -83,6 +83,7 @@ def lib():
         L.tt_device_bytes.argtypes = [vp, C.POINTER(C.c_uint64)]
         L.tt_set_timing.argtypes = [vp, C.c_int]
         L.tt_debug_cholesky_solve.argtypes = [C.c_int, vp, vp, vp, C.POINTER(C.c_int)]
+        L.tt_debug_cholesky_solve_ex.argtypes = [C.c_int, vp, vp, vp, C.POINTER(C.c_int), C.c_int, C.c_int]
         L.tt_get_timing.argtypes = [vp, vp, vp]
         L.tt_destroy.argtypes = [vp]
         L.tt_strerror.argtypes = [C.c_int]
@@ -241,14 +242,15 @@ class Stream:
         return int(b.value)
 
 
-def debug_cholesky_solve(A, b):
-    """Solve A x = b with the library's FP32 Cholesky kernels; returns (x, failed)."""
+def debug_cholesky_solve(A, b, precision=TT_FP32, ir_iters=2):
+    """Solve A x = b with the library's Cholesky kernels (FP32, or a 16-bit form with refinement);
+    returns (x, failed)."""
     A = _c(A, np.float32)
     b = _c(b, np.float32)
     x = np.zeros(b.shape[0], np.float32)
     fail = C.c_int(0)
-    _check(lib().tt_debug_cholesky_solve(int(b.shape[0]), _ptr(A), _ptr(b), _ptr(x), C.byref(fail)),
-           "tt_debug_cholesky_solve")
+    _check(lib().tt_debug_cholesky_solve_ex(int(b.shape[0]), _ptr(A), _ptr(b), _ptr(x), C.byref(fail),
+                                            int(precision), int(ir_iters)), "tt_debug_cholesky_solve_ex")
     return x, bool(fail.value)
 
 

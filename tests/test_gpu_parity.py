@@ -297,3 +297,21 @@ def test_config2_full_size(O, T):
     print(f"config 2: |dA|/|A| {ea:.2e}, |dg|/|g| {eg:.2e}, vertex rms {_rms(vo, vg):.2e} mm", flush=True)
     assert ea < NE_TOL and eg < NE_TOL
     assert _rms(vo, vg) <= RMS_TOL_MM
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_precision_forms_vertices(O, T, prec):
+    """The 16-bit solve forms track config 1 within the 0.01 mm RMS bar of the FP64 oracle."""
+    p = T.TT_BF16_IR if prec == "bf16" else T.TT_FP16_IR
+    sc = synth.make_config1(1)
+    fr = sc.frame(1)
+    so = O.Stream(_params(O, num_control_points=sc.num_control_points, seed=1), _intr(O, sc.intr))
+    sg = T.Stream(_params(T, num_control_points=sc.num_control_points, seed=1, precision=p, ir_iters=2),
+                  _intr(T, sc.intr))
+    so.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    sg.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    vo, _, _ = so.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc)
+    vg, _, _ = sg.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc)
+    rms = _rms(vg, vo)
+    print(f"{prec}: config 1 vertex rms vs FP64 oracle {rms:.2e} mm", flush=True)
+    assert rms <= RMS_TOL_MM
