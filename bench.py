@@ -66,11 +66,30 @@ def cpu_baseline(sc, frame, lm_sample):
                        f"({t_front * 1e3:.0f} ms + 10 x {t_iter * 1e3:.0f} ms)"), verts
 
 
+def _streams_for(tt, scenes, precision, budget):
+    """Library streams for the scenes (templates set), admitted while the device bytes fit budget."""
+    streams, used = [], 0
+    for sc in scenes:
+        s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=4, precision=precision),
+                      tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy))
+        s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        b = s.device_bytes()
+        if used + b > budget:  # admission by device-memory budget
+            s.destroy()
+            continue
+        used += b
+        streams.append(s)
+    return streams, used
+
+
 def serving_bench(args, torch, tt):
-    """Config 4 serving mix: 16 streams of uneven size, plain (one frame after another through
-    tt_track_frame_device) against batched (tt_track_batch_device over every stream with a frame
-    waiting), then a Poisson-arrival run (mean 15 Hz per stream) with continuous batching: whenever
-    the device finishes a batch, every stream whose next frame has arrived joins the next one."""
+    """Config 4 serving mix: 16 streams of uneven size. Plain per-stream path (each stream on its own
+    HIP stream through tt_track_frame_device, FP32) against the batched path (tt_track_batch_device
+    over every stream with a frame waiting) in FP32 and in the mixed form (bfloat16 tile products +
+    FP64-residual refinement); the mixed form's vertices are compared with the plain FP32 ones on the
+    first frame. Then a Poisson-arrival run (mean 15 Hz per stream) of the batched mixed path with
+    continuous batching: whenever the device finishes a batch, every stream whose next frame has
+    arrived joins the next one; latency is completion minus arrival."""
     from paper_2007_08576_amd import synth
     t0 = time.time()
     scenes = synth.make_config4(seed=4, n_streams=args.serving_streams, n_frames=300)
@@ -80,51 +99,62 @@ def serving_bench(args, torch, tt):
                for f in (sc.frame(t) for t in range(1, nfr + 1))] for sc in scenes]
     log(f"serving mix generated in {time.time() - t0:.1f} s")
     budget = args.serving_hbm_gib * (1 << 30)
-    streams, used = [], 0
-    for sc in scenes:
-        s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=4),
-                      tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy))
-        s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
-        b = s.device_bytes()
-        if used + b > budget:  # admission by device-memory budget
-            s.destroy()
-            continue
-        used += b
-        streams.append(s)
-    S = len(streams)
-    outs = [(torch.empty((sc.pts.shape[0], 3), dtype=torch.float32, device=dev),
-             torch.empty((sc.num_control_points, 8), dtype=torch.float32, device=dev)) for sc in scenes[:S]]
     order = [0, 1, 2, 1]
-
-    def fr(q, k):
-        d = frames[q][order[k % len(order)]]
-        return (d[0], d[1], d[2], d[1].shape[0], outs[q][0], outs[q][1])
-
-    def plain_round(k):
-        for q in range(S):
-            f = fr(q, k)
-            streams[q].track_frame_device(*f)
-
-    def batch_round(k, idx=None):
-        idx = list(range(S)) if idx is None else idx
-        tt.track_batch_device([streams[q] for q in idx], [fr(q, k) for q in idx])
-
+    mixed = tt.TT_BF16_IR
     res = {}
-    for name, fn in (("plain", plain_round), ("batched", batch_round)):
-        fn(0)
-        torch.cuda.synchronize()
+    first = {}
+    used_bytes = {}
+    S = None
+    for name, prec, batched in (("plain", tt.TT_FP32, False), ("batched_fp32", tt.TT_FP32, True),
+                                ("batched_mixed", mixed, True)):
+        streams, used = _streams_for(tt, scenes, prec, budget)
+        S = len(streams)
+        used_bytes[name] = used
+        outs = [(torch.empty((sc.pts.shape[0], 3), dtype=torch.float32, device=dev),
+                 torch.empty((sc.num_control_points, 8), dtype=torch.float32, device=dev)) for sc in scenes[:S]]
+
+        def fr(q, k):
+            d = frames[q][order[k % len(order)]]
+            return (d[0], d[1], d[2], d[1].shape[0], outs[q][0], outs[q][1])
+
+        def one_round(k, idx=None):
+            idx = list(range(S)) if idx is None else idx
+            if batched:
+                tt.track_batch_device([streams[q] for q in idx], [fr(q, k) for q in idx])
+            else:
+                for q in idx:
+                    streams[q].track_frame_device(*fr(q, k))
+
+        one_round(0)
         for s in streams:
             s.sync()
+        first[name] = [o[0].cpu().numpy().copy() for o in outs]
         t1 = time.perf_counter()
         rounds = args.serving_rounds
         for k in range(rounds):
-            fn(k + 1)
+            one_round(k + 1)
         for s in streams:
             s.sync()
-        dt = time.perf_counter() - t1
-        res[name] = S * rounds / dt
-        log(f"  {name:8s} {res[name]:8.1f} frames/s over {S} streams")
-    # Poisson arrivals, continuous batching
+        res[name] = S * rounds / (time.perf_counter() - t1)
+        log(f"  {name:14s} {res[name]:8.1f} frames/s over {S} streams")
+        if name == "batched_mixed":
+            poisson = _poisson_run(args, streams, one_round, S)
+        for s in streams:
+            s.destroy()
+    rms_mixed = max(float(np.sqrt(((a.astype(np.float64) - b) ** 2).sum(1).mean()))
+                    for a, b in zip(first["batched_mixed"], first["plain"]))
+    return {"workload": f"config4: {S} streams, N 100-800, depth 320x240..640x480, K 500-3000, 20-40% outliers, "
+                        f"10 LM iterations per frame",
+            "streams": S, "device_bytes_fp32": used_bytes["plain"], "device_bytes_mixed": used_bytes["batched_mixed"],
+            "plain_fp32_frames_per_s": res["plain"], "batched_fp32_frames_per_s": res["batched_fp32"],
+            "batched_mixed_frames_per_s": res["batched_mixed"],
+            "batched_mixed_over_plain": res["batched_mixed"] / res["plain"],
+            "mixed_form": "bf16 tile products, FP32 accumulation, 2 FP64-residual refinement steps",
+            "mixed_vs_plain_fp32_max_stream_rms_mm": rms_mixed,
+            "poisson_batched_mixed": poisson}
+
+
+def _poisson_run(args, streams, one_round, S):
     rng = np.random.default_rng(4)
     dur = args.serving_seconds
     arrivals = []
@@ -148,7 +178,7 @@ def serving_bench(args, torch, tt):
             soon = min(arrivals[q][nxt[q]] for q in range(S) if nxt[q] < len(arrivals[q]))
             time.sleep(max(0.0, soon - now))
             continue
-        batch_round(k, ready)
+        one_round(k, ready)
         k += 1
         streams[ready[0]].sync()
         t_end = time.perf_counter() - t_start
@@ -158,19 +188,129 @@ def serving_bench(args, torch, tt):
             done += 1
     wall = time.perf_counter() - t_start
     lat = np.array(lat) * 1e3
-    for s in streams:
+    log(f"  poisson {total / wall:.1f} frames/s, p50 {np.percentile(lat, 50):.1f} ms, p99 {np.percentile(lat, 99):.1f} ms")
+    return {"rate_hz_per_stream": args.serving_hz, "seconds": dur, "frames": int(total), "frames_per_s": total / wall,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max())}
+
+
+def precision_study(args, torch, tt, sc2, dframes2, vo_oracle):
+    """Each solve form on config 2 (frames/s; vertices of frame 1 after 3 LM iterations from the
+    identity against the FP64 oracle's when it ran) and on config 3 (1,500 control points, 9,000
+    unknowns: frames/s, factorisation time, vertices of frame 1 against the FP32 form's)."""
+    from paper_2007_08576_amd import synth
+    dev = torch.device("cuda:0")
+    forms = (("fp32", tt.TT_FP32), ("bf16_ir", tt.TT_BF16_IR), ("fp16_ir", tt.TT_FP16_IR))
+    out = {"config2": {}, "config3": {}}
+
+    def run(sc, dfr, prec, steps, lm_iters=10):
+        s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=2, precision=prec,
+                                        lm_iters=lm_iters),
+                      tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy))
+        s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        ov = torch.empty((sc.pts.shape[0], 3), dtype=torch.float32, device=dev)
+        oq = torch.empty((sc.num_control_points, 8), dtype=torch.float32, device=dev)
+        s.track_frame_device(dfr[0][0], dfr[0][1], dfr[0][2], dfr[0][1].shape[0], ov, oq)
+        s.sync()
+        first = ov.cpu().numpy().astype(np.float64)
+        fps = None
+        if steps:
+            s.get_timing()
+            s.set_timing(True)
+            t0 = time.perf_counter()
+            for k in range(steps):
+                d = dfr[(k + 1) % len(dfr)]
+                s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], ov, oq)
+            s.sync()
+            fps = steps / (time.perf_counter() - t0)
+            ms, n = s.get_timing()
+            fac = float(ms[tt.STAGES.index("factor")] / max(n[tt.STAGES.index("factor")], 1)) * 1e3
+            sol = float(ms[tt.STAGES.index("solve")] / max(n[tt.STAGES.index("factor")], 1)) * 1e3
         s.destroy()
-    return {"workload": f"config4: {S} streams, N 100-800, depth 320x240..640x480, K 500-3000, 20-40% outliers, "
-                        f"10 LM iterations per frame, FP32",
-            "streams": S, "device_bytes": used,
-            "plain_frames_per_s": res["plain"], "batched_frames_per_s": res["batched"],
-            "batched_over_plain": res["batched"] / res["plain"],
-            "poisson": {"rate_hz_per_stream": args.serving_hz, "seconds": dur, "frames": int(total),
-                        "frames_per_s": total / wall, "p50_ms": float(np.percentile(lat, 50)),
-                        "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max())}}
+        return fps, first, (fac, sol) if steps else (None, None)
+
+    for name, prec in forms:
+        fps, _, (fac, sol) = run(sc2, dframes2, prec, args.precision_steps)
+        entry = {"frames_per_s": fps, "factor_us": fac, "damp_substitutions_refinement_us": sol}
+        if vo_oracle is not None:
+            _, v3, _ = run(sc2, dframes2, prec, 0, lm_iters=args.cpu_lm_sample)
+            entry["rms_vs_fp64_oracle_mm"] = float(np.sqrt(((v3 - vo_oracle) ** 2).sum(1).mean()))
+        out["config2"][name] = entry
+        log(f"  config2 {name:8s} {fps:7.1f} frames/s, factor {fac:7.1f} us, solve+refine {sol:7.1f} us"
+            + (f", rms vs oracle {entry['rms_vs_fp64_oracle_mm']:.2e} mm" if "rms_vs_fp64_oracle_mm" in entry else ""))
+    if args.precision_config3:
+        t0 = time.time()
+        sc3 = synth.make_config3(seed=3, n_frames=300)
+        dfr3 = [tuple(torch.from_numpy(a).to(dev) for a in (f.depth, f.feat_xyz, f.feat_desc))
+                for f in (sc3.frame(t) for t in (1, 2))]
+        log(f"config 3 generated in {time.time() - t0:.1f} s")
+        ref = None
+        for name, prec in forms:
+            fps, v1, (fac, sol) = run(sc3, dfr3, prec, 2)
+            if ref is None:
+                ref = v1
+            entry = {"frames_per_s": fps, "factor_us": fac, "damp_substitutions_refinement_us": sol,
+                     "rms_vs_fp32_form_mm": float(np.sqrt(((v1 - ref) ** 2).sum(1).mean()))}
+            out["config3"][name] = entry
+            log(f"  config3 {name:8s} {fps:7.2f} frames/s, factor {fac:8.1f} us, solve+refine {sol:7.1f} us, "
+                f"rms vs fp32 {entry['rms_vs_fp32_form_mm']:.2e} mm")
+    return out
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_chol_dataflow_config2_traffic.json")
+CHOL_SRC = os.path.join(ROOT, "paper_2007_08576_amd", "csrc", "tt_chol.hip")
+
+
+def _src_hash():
+    import hashlib
+    with open(CHOL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def pmc_summary(fetch_csv, write_csv, copy_mib, cmd):
+    """HBM bytes per k_chol_dataflow launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE; KiB per dispatch), each scaled by what the same counter reads for the plain copy of
+    copy_mib MiB that bench.py --copy-calibration-mib runs (largest copy dispatch)."""
+    import csv
+    import re
+
+    def per_kernel(path):
+        agg = {}
+        for r in csv.DictReader(open(path)):
+            k = re.sub(r"\(anonymous namespace\)::", "", r["Kernel_Name"]).split("(")[0]
+            agg.setdefault(k, []).append(float(r["Counter_Value"]))
+        return agg
+
+    f, w = per_kernel(fetch_csv), per_kernel(write_csv)
+    true_kib = copy_mib * 1024.0
+    fcopy = max(f["__amd_rocclr_copyBuffer"])
+    wcopy = max(w["__amd_rocclr_copyBuffer"])
+    ff, wf = true_kib / fcopy, true_kib / wcopy
+    fk = float(np.mean(f["k_chol_dataflow"])) * ff * 1024.0
+    wk = float(np.mean(w["k_chol_dataflow"])) * wf * 1024.0
+    rec = {"kernel": "k_chol_dataflow", "workload": "config2 plain FP32 (n = 2400)", "source_sha256": _src_hash(),
+           "fetch_bytes_per_launch": fk, "write_bytes_per_launch": wk, "traffic_bytes_per_launch": fk + wk,
+           "calibration": {"copy_mib": copy_mib, "fetch_size_kib_read_for_copy": fcopy,
+                           "write_size_kib_read_for_copy": wcopy, "fetch_factor": ff, "write_factor": wf},
+           "launches": len(f["k_chol_dataflow"]), "commands": cmd}
+    with open(TRAFFIC_FILE, "w") as fo:
+        json.dump(rec, fo, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def measured_traffic():
+    """Bytes per launch from the committed counter summary, or None once the kernel has changed."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == _src_hash() else None
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--pmc-summary":
+        pmc_summary(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
@@ -184,6 +324,9 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=6.0)
     ap.add_argument("--serving-hz", type=float, default=15.0)
     ap.add_argument("--serving-hbm-gib", type=float, default=200.0)
+    ap.add_argument("--precision", type=int, default=1, help="also run the solve-form study (0 = skip)")
+    ap.add_argument("--precision-steps", type=int, default=10)
+    ap.add_argument("--precision-config3", type=int, default=1)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device 3 times (a plain copy of known "
                          "size whose FETCH_SIZE / WRITE_SIZE counters calibrate the HBM traffic readings)")
@@ -253,7 +396,7 @@ def main():
     flops = n ** 3 / 3.0 + float(n) * n  # Cholesky of the n x n system + the forward substitution
     achieved = flops / (fac_ms * 1e-3) / 1e12
     roof = dict(kernel="k_chol_dataflow", bound="mfma", achieved=achieved, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                frac=achieved / FP32_PEAK_TFLOPS, traffic=None,
+                frac=achieved / FP32_PEAK_TFLOPS, traffic=measured_traffic(),
                 algorithmic=f"n^3/3 + n^2 = {flops:.4e} FLOP per launch (one factorisation, n = {n}), "
                             "dense FP32 matrix-core peak",
                 avg_duration_us=fac_ms * 1e3)
@@ -286,6 +429,7 @@ def main():
     if args.serving:
         out["batched"] = serving_bench(args, torch, tt)
 
+    vo_oracle = None
     if not args.no_cpu_baseline:
         # same frame, same reduced iteration count on the GPU: the full-size accuracy check
         s2 = tt.Stream(tt.default_params(num_control_points=N, seed=2, lm_iters=args.cpu_lm_sample), intr)
@@ -297,6 +441,9 @@ def main():
         out["cpu_baseline"] = cb
         out["rms_vs_oracle_mm"] = float(np.sqrt(((vg - vo) ** 2).sum(1).mean()))
         out["rms_vs_oracle_note"] = f"frame 1 from identity, {args.cpu_lm_sample} LM iterations on both sides"
+        vo_oracle = vo
+    if args.precision:
+        out["precision_forms"] = precision_study(args, torch, tt, sc, dframes, vo_oracle)
     print(json.dumps(out), flush=True)
     if args.copy_calibration_mib > 0:
         nf = args.copy_calibration_mib * (1 << 20) // 4
