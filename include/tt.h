@@ -144,11 +144,12 @@ typedef struct {
 } tt_frame_device;
 
 /* Batched form of tt_track_frame_device: the same per-frame solve (Sec. 2) for S distinct streams
- * (templates, sizes and intrinsics may differ; lm_iters must be equal), queued as one batch on
- * streams[0]'s HIP stream. The per-stream stages are queued stream after stream; the Cholesky
- * factorisations and back substitutions of all S normal systems run as one launch each per LM
- * iteration. The batch starts after all work already queued on every stream's HIP stream, and
- * later work on those HIP streams runs after it. Each stream's result is the same as when it is
+ * (templates, sizes and intrinsics may differ; lm_iters must be equal). The per-stream stages are
+ * queued on each stream's own HIP stream; the Cholesky factorisations, substitutions and
+ * refinement of all S normal systems run on streams[0]'s HIP stream as one launch each per LM
+ * iteration, ordered against the per-stream work by events. The batch starts after all work
+ * already queued on every stream's HIP stream, and later work on those HIP streams runs after it
+ * (tt_sync on a stream waits for its frame). Each stream's result is the same as when it is
  * tracked alone. Returns without waiting. TT_EINVAL: bad arguments or a stream listed twice;
  * TT_EBUSY: a stream is in use by another call (no stream is then touched); TT_ESTATE: a stream
  * has no template. */

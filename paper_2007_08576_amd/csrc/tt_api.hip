@@ -302,30 +302,57 @@ int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint
   return TT_OK;
 }
 
-// One frame of each of S streams as one batch on batch_st: the per-stream stages are queued
-// stream after stream, the factorisations and back substitutions of all S systems run as one
-// launch each per LM iteration.
+// One frame of each of S streams as one batch. The per-stream stages run on each stream's own HIP
+// stream (so that the small kernels of different streams overlap on the hardware queues); the
+// factorisations, substitutions and refinement of all S systems run on batch_st (= the first
+// stream's) as one launch each per LM iteration, joined with and forked to the per-stream queues by
+// events.
 int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStream_t batch_st) {
   std::vector<DevState> dd(S);
   std::vector<DevState*> dp(S);
   std::vector<int> epochs(S);
+  std::vector<hipStream_t> qs(S);
   for (int q = 0; q < S; q++) {
     dd[q] = frame_view(ss[q], fr[q].depth, fr[q].feat_xyz, fr[q].feat_desc);
     dp[q] = &dd[q];
+    qs[q] = (q == 0) ? batch_st : ss[q]->st;
   }
-  int rc = TT_OK;
-  for (int q = 0; q < S && !rc; q++) rc = enqueue_front(ss[q], dd[q], fr[q].K2, batch_st);
+  // batch_st -> every per-stream queue
+  auto fork = [&]() -> int {
+    hipEvent_t ev = nullptr;
+    if (ev_get(ss[0], &ev) != hipSuccess) return TT_EDEVICE;
+    int rc = hipEventRecord(ev, batch_st) == hipSuccess ? TT_OK : TT_EDEVICE;
+    for (int q = 1; q < S && !rc; q++)
+      if (qs[q] != batch_st && hipStreamWaitEvent(qs[q], ev, 0) != hipSuccess) rc = TT_EDEVICE;
+    ss[0]->ev_pool.push_back(ev);
+    return rc;
+  };
+  // every per-stream queue -> batch_st
+  auto join = [&]() -> int {
+    for (int q = 1; q < S; q++) {
+      if (qs[q] == batch_st) continue;
+      hipEvent_t ev = nullptr;
+      if (ev_get(ss[q], &ev) != hipSuccess) return TT_EDEVICE;
+      const bool ok = hipEventRecord(ev, qs[q]) == hipSuccess && hipStreamWaitEvent(batch_st, ev, 0) == hipSuccess;
+      ss[q]->ev_pool.push_back(ev);
+      if (!ok) return TT_EDEVICE;
+    }
+    return TT_OK;
+  };
+  int rc = fork();
+  for (int q = 0; q < S && !rc; q++) rc = enqueue_front(ss[q], dd[q], fr[q].K2, qs[q]);
   for (int it = 0; it < ss[0]->P.lm_iters && !rc; it++) {
-    for (int q = 0; q < S && !rc; q++) rc = enqueue_assemble(ss[q], dd[q], it, false, batch_st, &epochs[q]);
-    if (rc) break;
-    rc = enqueue_solve(ss, dp.data(), epochs.data(), S, batch_st);
-    if (rc) break;
-    for (int q = 0; q < S && !rc; q++) rc = enqueue_finish(ss[q], dd[q], batch_st);
+    for (int q = 0; q < S && !rc; q++) rc = enqueue_assemble(ss[q], dd[q], it, false, qs[q], &epochs[q]);
+    if (!rc) rc = join();
+    if (!rc) rc = enqueue_solve(ss, dp.data(), epochs.data(), S, batch_st);
+    if (!rc) rc = fork();
+    for (int q = 0; q < S && !rc; q++) rc = enqueue_finish(ss[q], dd[q], qs[q]);
   }
   for (int q = 0; q < S && !rc; q++) {
-    HIPCHK(launch_deform_out(ss[q]->d, fr[q].out_vertices, fr[q].out_dq, batch_st));
+    HIPCHK(launch_deform_out(ss[q]->d, fr[q].out_vertices, fr[q].out_dq, qs[q]));
     ss[q]->frame += 1;
   }
+  if (!rc) rc = join();
   return rc;
 }
 

@@ -94,8 +94,8 @@ __device__ __forceinline__ void fmac_bcast16(float& acc, float src, float mul, i
   }
 }
 
-// 16 x 16 leaf on one wavefront: factors the block at (o, o) of L in place (lower, zeros above)
-// and writes its inverse to Li at (o, o). Lane r (mod 16) keeps row r in registers; pivots and
+// 16 x 16 leaf on one wavefront: factors the block at (o, o) of L (in registers) and writes the
+// inverse of the factor to Li at (o, o); L itself is only read (callers need only the inverse). Lane r (mod 16) keeps row r in registers; pivots and
 // column entries move between lanes by row broadcasts. 1/sqrt(pivot) comes from one v_rsq. The
 // inverse is built column-oriented (lane r holds column r): x_i = p_i / L_ii, then
 // p_k -= L_ki x_i for k > i.
@@ -104,9 +104,10 @@ __device__ __forceinline__ void leaf16(float (*L)[LDS_LD], float (*Li)[LDS_LD], 
   const bool writer = lane < 16;
   float a[16];
 #pragma unroll
-  for (int c = 0; c < 16; c++) {
-    const float v = L[o + r][o + c];
-    a[c] = (c <= r) ? v : 0.0f;
+  for (int c = 0; c < 16; c += 2) {
+    const float2 v = *reinterpret_cast<const float2*>(&L[o + r][o + c]);
+    a[c] = (c <= r) ? v.x : 0.0f;
+    a[c + 1] = (c + 1 <= r) ? v.y : 0.0f;
   }
   float invd[16];
 #pragma unroll
@@ -123,10 +124,6 @@ __device__ __forceinline__ void leaf16(float (*L)[LDS_LD], float (*Li)[LDS_LD], 
     a[j] = lr;
 #pragma unroll
     for (int m = j + 1; m < 16; m++) fmac_bcast16(a[m], lr, nlr, m, m == j + 1);
-  }
-  if (writer) {
-#pragma unroll
-    for (int c = 0; c < 16; c++) L[o + r][o + c] = (c <= r) ? a[c] : 0.0f;
   }
   float p[16], x[16];
 #pragma unroll
@@ -660,9 +657,9 @@ struct CholBatch {
 enum { MODE_EXIT = 3 };
 
 __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
-  __shared__ float X[NB][LDS_LD];
-  __shared__ float Y[NB][LDS_LD];
-  __shared__ float Z[NB][LDS_LD];  // the chain's Linv_{j-1} between CRIT steps
+  __shared__ __attribute__((aligned(16))) float X[NB][LDS_LD];
+  __shared__ __attribute__((aligned(16))) float Y[NB][LDS_LD];
+  __shared__ __attribute__((aligned(16))) float Z[NB][LDS_LD];  // the chain's Linv_{j-1} between CRIT steps
   static_assert(POTRF_SCRATCH_FLOATS <= NB * LDS_LD, "factorisation scratch must fit in one tile buffer");
   __shared__ int s_task, s_val, s_mode, s_prob;
   const int tid = threadIdx.x;
