@@ -12,8 +12,9 @@
 //   data-term blocks  blk_ab, blk_ptr, blk_ent: static block-CSR of node pairs (a >= b) that
 //                     share a template point or feature, with the contributing rows
 //   per frame         depth f32 [H*W]; nmap float4 [H*W] = (n, z) of the target surface
-//   per iteration     jac f32 [24][M], wres f32 [M] (weighted ICP rows); jacF f32 [72][K1],
-//                     wresF f32 [3][K1] (weighted feature rows)
+//   per iteration     jac f32 [M][24], wres f32 [M] (weighted ICP rows); jacF f32 [K1][72],
+//                     wresF f32 [3][K1] (weighted feature rows); the Jacobian rows are per point so
+//                     that the block assembly reads each point's 2 x 6 entries as contiguous pairs
 //   normal matrix     A f32 [(npad + 64) x npad] row-major, lower triangle; rows npad..npad+63
 //                     hold the right-hand side row(s) so that the forward substitution runs
 //                     inside the blocked factorisation; Linv f32 [nb][64][64] inverse diagonal
@@ -91,10 +92,10 @@ struct DevState {
   int* corr = nullptr;
   float* rres = nullptr;
   float* omega = nullptr;
-  float* jac = nullptr;      // [24][M]
+  float* jac = nullptr;      // [M][24]
   float* wres = nullptr;     // [M]
   float* orbw = nullptr;     // [K1]
-  float* jacF = nullptr;     // [72][K1]
+  float* jacF = nullptr;     // [K1][72]
   float* wresF = nullptr;    // [3][K1]
   float* A = nullptr;        // [(npad + TT_NB) * ld]
   float* g = nullptr;        // [npad]

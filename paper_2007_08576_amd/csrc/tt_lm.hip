@@ -31,7 +31,6 @@
 
 namespace {
 
-constexpr int kWave = 64;
 constexpr int kRowThreads = 256;
 
 struct Parts {
@@ -218,7 +217,8 @@ __global__ __launch_bounds__(kRowThreads) void k_data_rows(RowArgs a, int it) {
         }
       }
 #pragma unroll
-      for (int c = 0; c < 24; c++) a.jac[(size_t)c * a.M + j] = J[c];
+      for (int c = 0; c < 24; c += 4)
+        *reinterpret_cast<float4*>(a.jac + (size_t)j * 24 + c) = make_float4(J[c], J[c + 1], J[c + 2], J[c + 3]);
       s0 = (double)om;
       s1 = (double)om * (double)r * (double)r;
     }
@@ -280,7 +280,8 @@ __global__ __launch_bounds__(kRowThreads) void k_data_rows(RowArgs a, int it) {
 #pragma unroll
       for (int c = 0; c < 3; c++) a.wresF[(size_t)c * a.K1 + k] = sw * e[c];
 #pragma unroll
-      for (int c = 0; c < 72; c++) a.jacF[(size_t)c * a.K1 + k] = J[c];
+      for (int c = 0; c < 72; c += 4)
+        *reinterpret_cast<float4*>(a.jacF + (size_t)k * 72 + c) = make_float4(J[c], J[c + 1], J[c + 2], J[c + 3]);
       s0 = (double)w;
       s1 = (double)a.w_orb * (double)w * ((double)e[0] * e[0] + (double)e[1] * e[1] + (double)e[2] * e[2]);
     }
@@ -397,7 +398,8 @@ constexpr int kArapThreads = 256;
 constexpr int kArapAcc = 36 + 6;
 
 __global__ __launch_bounds__(kArapThreads) void k_arap_assemble(ArapArgs a) {
-  __shared__ float red[kArapAcc][kArapThreads];
+  __shared__ float red[kArapAcc][kArapThreads + 1];
+  __shared__ float wsum[kArapThreads / 64][kArapAcc];
   __shared__ double shd[kArapThreads];
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
@@ -504,28 +506,40 @@ __global__ __launch_bounds__(kArapThreads) void k_arap_assemble(ArapArgs a) {
       }
     }
   }
-  // reduce the diagonal block, gradient and cost over the workgroup (fixed tree)
+  // reduce the diagonal block, gradient and cost over the workgroup in a fixed order: within each
+  // wavefront, lane t < 42 sums entry t of the wavefront's 64 lanes; then the four wavefront sums
 #pragma unroll
   for (int t = 0; t < 36; t++) red[t][tid] = D[t];
 #pragma unroll
   for (int t = 0; t < 6; t++) red[36 + t][tid] = gi[t];
   shd[tid] = cost;
   __syncthreads();
-  for (int s = kArapThreads / 2; s > 0; s >>= 1) {
-    if (tid < s) {
+  const int lane = tid & 63, wv = tid >> 6;
+  if (lane < kArapAcc) {
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
-      for (int t = 0; t < kArapAcc; t++) red[t][tid] += red[t][tid + s];
-      shd[tid] += shd[tid + s];
+    for (int l = 0; l < 64; l += 4) {
+      s0 += red[lane][64 * wv + l];
+      s1 += red[lane][64 * wv + l + 1];
+      s2 += red[lane][64 * wv + l + 2];
+      s3 += red[lane][64 * wv + l + 3];
     }
-    __syncthreads();
+    wsum[wv][lane] = (s0 + s1) + (s2 + s3);
   }
-  if (tid < 36) {
-    int r = tid / 6, c = tid % 6;
-    a.A[(size_t)(6 * i + r) * a.ld + 6 * i + c] = red[tid][0];
-  } else if (tid < 42) {
-    a.g[6 * i + tid - 36] = red[tid][0];
+  __syncthreads();
+  if (tid < kArapAcc) {
+    const float v = (wsum[0][tid] + wsum[1][tid]) + (wsum[2][tid] + wsum[3][tid]);
+    if (tid < 36) {
+      const int r = tid / 6, c = tid % 6;
+      a.A[(size_t)(6 * i + r) * a.ld + 6 * i + c] = v;
+    } else {
+      a.g[6 * i + tid - 36] = v;
+    }
+  } else if (tid == 64) {
+    double c = 0.0;
+    for (int l = 0; l < kArapThreads; l++) c += shd[l];
+    a.part[a.P.arap + i] = c;
   }
-  if (tid == 0) a.part[a.P.arap + i] = shd[0];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -545,6 +559,7 @@ __global__ __launch_bounds__(kDataThreads) void k_data_assemble(const int2* __re
                                                                 const float* __restrict__ wresF, int K1,
                                                                 float* __restrict__ A, float* __restrict__ g, int ld) {
   __shared__ float fin[42];
+  __shared__ float red[42][kDataThreads + 1];
   const int blk = blockIdx.x;
   const int2 ab = blk_ab[blk];
   const int lane = threadIdx.x;
@@ -560,10 +575,13 @@ __global__ __launch_bounds__(kDataThreads) void k_data_assemble(const int2* __re
     int idx = (int)(en >> 5);
     if (kind == 0) {
       float Ja[6], Jb[6];
+      const float2* ra = reinterpret_cast<const float2*>(jac + (size_t)idx * 24 + 6 * sa);
+      const float2* rb = reinterpret_cast<const float2*>(jac + (size_t)idx * 24 + 6 * sb);
 #pragma unroll
-      for (int c = 0; c < 6; c++) {
-        Ja[c] = jac[(size_t)(6 * sa + c) * M + idx];
-        Jb[c] = jac[(size_t)(6 * sb + c) * M + idx];
+      for (int c = 0; c < 3; c++) {
+        const float2 u = ra[c], v = rb[c];
+        Ja[2 * c] = u.x; Ja[2 * c + 1] = u.y;
+        Jb[2 * c] = v.x; Jb[2 * c + 1] = v.y;
       }
 #pragma unroll
       for (int r = 0; r < 6; r++)
@@ -578,10 +596,13 @@ __global__ __launch_bounds__(kDataThreads) void k_data_assemble(const int2* __re
 #pragma unroll
       for (int q = 0; q < 3; q++) {
         float Ja[6], Jb[6];
+        const float2* ra = reinterpret_cast<const float2*>(jacF + (size_t)idx * 72 + q * 24 + 6 * sa);
+        const float2* rb = reinterpret_cast<const float2*>(jacF + (size_t)idx * 72 + q * 24 + 6 * sb);
 #pragma unroll
-        for (int c = 0; c < 6; c++) {
-          Ja[c] = jacF[(size_t)(q * 24 + 6 * sa + c) * K1 + idx];
-          Jb[c] = jacF[(size_t)(q * 24 + 6 * sb + c) * K1 + idx];
+        for (int c = 0; c < 3; c++) {
+          const float2 u = ra[c], v = rb[c];
+          Ja[2 * c] = u.x; Ja[2 * c + 1] = u.y;
+          Jb[2 * c] = v.x; Jb[2 * c + 1] = v.y;
         }
 #pragma unroll
         for (int r = 0; r < 6; r++)
@@ -595,20 +616,22 @@ __global__ __launch_bounds__(kDataThreads) void k_data_assemble(const int2* __re
       }
     }
   }
-  // wavefront butterfly reduction (fixed pattern, deterministic)
+  // reduction over the wavefront in a fixed order: lane t < 42 sums entry t of all lanes
 #pragma unroll
-  for (int t = 0; t < 36; t++)
+  for (int t = 0; t < 36; t++) red[t][lane] = S[t];
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) S[t] += __shfl_xor(S[t], off, kWave);
+  for (int t = 0; t < 6; t++) red[36 + t][lane] = G[t];
+  __syncthreads();
+  if (lane < 42) {
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
-  for (int t = 0; t < 6; t++)
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) G[t] += __shfl_xor(G[t], off, kWave);
-  if (lane == 0) {
-#pragma unroll
-    for (int t = 0; t < 36; t++) fin[t] = S[t];
-#pragma unroll
-    for (int t = 0; t < 6; t++) fin[36 + t] = G[t];
+    for (int l = 0; l < kDataThreads; l += 4) {
+      s0 += red[lane][l];
+      s1 += red[lane][l + 1];
+      s2 += red[lane][l + 2];
+      s3 += red[lane][l + 3];
+    }
+    fin[lane] = (s0 + s1) + (s2 + s3);
   }
   __syncthreads();
   if (lane < 36) {
