@@ -598,6 +598,7 @@ int tt_debug_cholesky_solve_ex(int n, const float* A, const float* b, float* x, 
   bool okm = al((void**)&d.A, sizeof(float) * rows * d.ld) && al((void**)&d.x, sizeof(float) * d.npad) &&
              al((void**)&d.Linv, sizeof(float) * (size_t)d.nb * TT_NB * TT_NB) &&
              al((void**)&d.flags, sizeof(int) * chol_flag_ints(d.nb)) && al((void**)&d.sc, sizeof(LMScalars)) &&
+             al((void**)&d.tw, sizeof(uint64_t) * d.npad) &&
              al((void**)&d.dscale, sizeof(float) * d.npad);
   if (okm && precision != TT_FP32)
     okm = al((void**)&d.A16, sizeof(uint16_t) * rows * d.ld) && al((void**)&d.A0, sizeof(float) * d.npad * d.ld) &&
@@ -617,6 +618,7 @@ int tt_debug_cholesky_solve_ex(int n, const float* A, const float* b, float* x, 
     DevState* dp[1] = {&d};
     bool ok = hipMemcpyAsync(d.A, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
               hipMemsetAsync(d.flags, 0, sizeof(int) * chol_flag_ints(d.nb), st) == hipSuccess &&
+              hipMemsetAsync(d.tw, 0, sizeof(uint64_t) * d.npad, st) == hipSuccess &&
               hipMemcpyAsync(d.dscale, ones.data(), sizeof(float) * d.npad, hipMemcpyHostToDevice, st) == hipSuccess &&
               hipMemcpyAsync(d.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, st) == hipSuccess;
     if (ok && precision != TT_FP32) ok = launch_ir_prepare(d, st) == hipSuccess;
@@ -756,6 +758,7 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
   ALLOC(allocs_template, bytes_template, d.x, (size_t)d.npad);
   ALLOC(allocs_template, bytes_template, d.Linv, (size_t)d.nb * TT_NB * TT_NB);
   ALLOC(allocs_template, bytes_template, d.flags, chol_flag_ints(d.nb));
+  ALLOC(allocs_template, bytes_template, d.tw, (size_t)d.npad);
   if (d.prec != TT_FP32) {
     ALLOC(allocs_template, bytes_template, d.A16, (size_t)(d.npad + TT_NB) * d.ld);
     ALLOC(allocs_template, bytes_template, d.A0, (size_t)d.npad * d.ld);
@@ -834,6 +837,7 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
       HIPCHK(hipMemcpyAsync(d.A + (size_t)k * d.ld + k, one.data(), sizeof(float), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemsetAsync(d.x, 0, sizeof(float) * d.npad, st));
     HIPCHK(hipMemsetAsync(d.flags, 0, sizeof(int) * chol_flag_ints(d.nb), st));
+    HIPCHK(hipMemsetAsync(d.tw, 0, sizeof(uint64_t) * d.npad, st));
     s->solve_epoch = 0;
     HIPCHK(hipStreamSynchronize(st));
   }

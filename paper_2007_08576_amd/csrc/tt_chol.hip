@@ -314,14 +314,14 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
 enum { TASK_CRIT = 0, TASK_DIAGP = 1, TASK_SUBP = 2, TASK_FULL = 3 };
 
 struct CholSync {
-  int* bflag;   // [nb] back substitution
+  int* bflag;   // [nb] (unused: the substitutions exchange tagged entries, see wait_tagged)
   int* fin;     // [(nb + 1) * nb] final L tile (i, c) at fin[i * nb + c]
   int* pdiag;   // [nb] partial diagonal tile of DIAGP(j)
   int* psub;    // [nb] partial sub-diagonal tile of SUBP(j)
   int* dinv;    // [nb] Linv_j published
   int* ctr;     // [1] ticket counter (0 between solves)
   int* abort_;  // [1] epoch of an aborted solve
-  int* fflag;   // [nb] forward substitution (refinement steps)
+  int* fflag;   // [nb] (unused, as bflag)
 };
 
 __host__ __device__ inline CholSync chol_sync(int* base, int nb) {
@@ -615,6 +615,7 @@ struct CholArgs {
   const float* A0;   // refinement: the damped matrix before factorisation (lower triangle), or null
   const float* c;    // refinement: the equilibrated right-hand side
   double* xd;        // refinement: the solution accumulated in FP64
+  uint64_t* tw;      // [npad] tagged solution entries exchanged inside a substitution
 };
 
 // Ticket of CRIT(j): the number of tasks in the groups before j, plus DIAGP(j) and SUBP(j).
@@ -911,22 +912,30 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
 
 constexpr long long kSpinLimit = 1ll << 22;
 
-// Hand-over between workgroups of the back substitution: results and flags are written and read
-// with agent-scope atomics (coherent across the whole device, not held in one XCD's L2); a
-// producer waits for its result stores to complete before raising the flag, and a consumer reads
-// the results only after it has seen the flag.
-__device__ __forceinline__ bool wait_flag(const int* flag, int epoch) {
+// Hand-over between the workgroups of a substitution: each solution entry travels as one 64-bit
+// word (epoch << 32 | float bits) written and read with agent-scope atomics, so a consumer lane
+// polls the entry it needs and gets the value with the same read that tells it the value is there
+// (one memory round trip per block step, no separate flag). A bounded spin marks the solve failed.
+__device__ __forceinline__ float wait_tagged(const uint64_t* w, int epoch, bool& ok) {
   long long spins = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-    if (++spins > kSpinLimit) return false;
+  uint64_t v;
+  while (((v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != (uint32_t)epoch) {
+    if (++spins > kSpinLimit) {
+      ok = false;
+      break;
+    }
     __builtin_amdgcn_s_sleep(1);
   }
-  return true;
+  return __uint_as_float((uint32_t)v);
+}
+__device__ __forceinline__ void put_tagged(uint64_t* w, float x, int epoch) {
+  __hip_atomic_store(w, ((uint64_t)(uint32_t)epoch << 32) | __float_as_uint(x), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Back substitution L^T x = y (y in the right-hand-side row): one wavefront per block row, for a
 // batch of systems laid out one after another over the grid (workgroups wg0[q] .. wg0[q+1]-1 serve
-// system q, block rows from the last).
+// system q, block rows from the last). Block row j folds in x_k of every later block as it arrives.
 struct BackBatch {
   int nprob;
   int wg0[kMaxCholBatch + 1];
@@ -941,8 +950,6 @@ __global__ __launch_bounds__(64) void k_chol_backsolve(const BackBatch B) {
   const CholArgs& P = B.p[q];
   const int nb = P.nb, ld = P.ld, epoch = P.epoch;
   const float* __restrict__ A = P.A;
-  float* __restrict__ x = P.x;
-  int* flags = chol_sync(P.flags, nb).bflag;
   const int j = nb - 1 - ((int)blockIdx.x - B.wg0[q]);
   const int c = threadIdx.x;
   const float* yrow = A + (size_t)P.npad * ld;
@@ -958,9 +965,7 @@ __global__ __launch_bounds__(64) void k_chol_backsolve(const BackBatch B) {
     float col[NB];
 #pragma unroll
     for (int m = 0; m < NB; m++) col[m] = A[(size_t)(NB * k + m) * ld + NB * j + c];
-    if (c == 0) ok = wait_flag(flags + k, epoch) && ok;
-    __syncthreads();
-    xs[c] = __hip_atomic_load(x + NB * k + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    xs[c] = wait_tagged(P.tw + NB * k + c, epoch, ok);
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < NB; m++) acc += col[m] * xs[m];
@@ -971,21 +976,17 @@ __global__ __launch_bounds__(64) void k_chol_backsolve(const BackBatch B) {
   float s = 0.0f;
 #pragma unroll
   for (int m = 0; m < NB; m++) s += lic[m] * rs[m];
-  __hip_atomic_store(x + NB * j + c, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __builtin_amdgcn_s_waitcnt(0);  // this lane's result store has completed
-  __syncthreads();
-  if (c == 0) {
-    __hip_atomic_store(flags + j, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (!ok) {
-      P.sc->chol_fail = 1;
-      P.sc->err = TT_DEVERR_CHOL_SYNC;
-    }
+  P.x[NB * j + c] = s;
+  put_tagged(P.tw + NB * j + c, s, epoch);
+  if (!ok) {
+    P.sc->chol_fail = 1;
+    P.sc->err = TT_DEVERR_CHOL_SYNC;
   }
 }
 
 // Forward substitution y = L^{-1} r for the refinement steps (the first right-hand side rides
 // along the factorisation): r is in the right-hand-side row and is overwritten by y. One wavefront
-// per block row, in increasing order; block row j waits for y_k of every k < j (flag per block).
+// per block row, in increasing order; block row j folds in y_k of every k < j as it arrives.
 __global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
   __shared__ float ys[NB];
   __shared__ float rs[NB];
@@ -994,7 +995,6 @@ __global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
   const CholArgs& P = B.p[q];
   const int ld = P.ld, epoch = P.epoch;
   float* row = P.A + (size_t)P.npad * ld;
-  int* flags = chol_sync(P.flags, P.nb).fflag;
   const int j = (int)blockIdx.x - B.wg0[q];
   const int c = threadIdx.x;
   const float rj = row[NB * j + c];
@@ -1007,9 +1007,7 @@ __global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
     float4 lr[NB / 4];
 #pragma unroll
     for (int m = 0; m < NB / 4; m++) lr[m] = Lr[m];
-    if (c == 0) ok = wait_flag(flags + k, epoch) && ok;
-    __syncthreads();
-    ys[c] = __hip_atomic_load(row + NB * k + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ys[c] = wait_tagged(P.tw + NB * k + c, epoch, ok);
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < NB / 4; m++)
@@ -1021,15 +1019,11 @@ __global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
   float y = 0.0f;
 #pragma unroll
   for (int m = 0; m < NB; m++) y += Li[m] * rs[m];
-  __hip_atomic_store(row + NB * j + c, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __builtin_amdgcn_s_waitcnt(0);  // this lane's result store has completed
-  __syncthreads();
-  if (c == 0) {
-    __hip_atomic_store(flags + j, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (!ok) {
-      P.sc->chol_fail = 1;
-      P.sc->err = TT_DEVERR_CHOL_SYNC;
-    }
+  row[NB * j + c] = y;  // read by the back substitution, a later launch
+  put_tagged(P.tw + NB * j + c, y, epoch);
+  if (!ok) {
+    P.sc->chol_fail = 1;
+    P.sc->err = TT_DEVERR_CHOL_SYNC;
   }
 }
 
@@ -1103,6 +1097,7 @@ static CholArgs chol_args(const DevState& d, int epoch) {
   P.A0 = d.A0;
   P.c = d.cvec;
   P.xd = d.xd;
+  P.tw = d.tw;
   return P;
 }
 

@@ -110,6 +110,7 @@ struct DevState {
   float* A0 = nullptr;       // damped matrix before factorisation [npad * ld] (refinement)
   float* cvec = nullptr;     // equilibrated right-hand side [npad] (refinement)
   double* xd = nullptr;      // FP64 solution of the refinement [npad]
+  uint64_t* tw = nullptr;    // [npad] tagged entries (epoch << 32 | float) of a running substitution
   double* partial = nullptr; // reduction partials
   int npartial = 0;
   LMScalars* sc = nullptr;
