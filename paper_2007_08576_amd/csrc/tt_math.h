@@ -209,7 +209,7 @@ TT_HD void jacobi_sym(double* A, double* V) {
       dg += A[p * n + p] * A[p * n + p];
       for (int q = p + 1; q < n; q++) off += A[p * n + q] * A[p * n + q];
     }
-    if (off <= 1e-36 * dg || off == 0.0) break;
+    if (off <= 1e-32 * dg || off == 0.0) break;  // off-diagonal norm at the FP64 rounding level
     for (int p = 0; p < n - 1; p++) {
       for (int q = p + 1; q < n; q++) {
         double apq = A[p * n + q];
@@ -239,22 +239,11 @@ TT_HD void jacobi_sym(double* A, double* V) {
 
 // Rotation R (row-major) maximising sum_k w_k b_k . (R a_k), given C[i][j] = sum_k w_k b_i a_j
 // (b = target, a = source), by Horn's quaternion method: the unit quaternion is the eigenvector
-// of the largest eigenvalue of the 4 x 4 symmetric matrix built from C. Returns 1 when the
-// two largest singular values of C fail sigma_2 >= 1e-9 sigma_1 (rotation not fixed).
+// of the largest eigenvalue of the 4 x 4 symmetric matrix N built from C. N's eigenvalues are
+// +-s1 +- s2 +- s3 (s_i the singular values of C, signs with the parity of det C), so with them
+// sorted decreasingly s1 = (l1 + l2) / 2 and s2 = (l1 + l3) / 2. Returns 1 when s2 >= 1e-9 s1
+// fails (rotation not fixed), with R = I.
 TT_HD int rotation_fit_horn(const double* C, double* R) {
-  // degeneracy test on the singular values of C (eigenvalues of C^T C)
-  double CtC[9], Vs[9];
-  for (int i = 0; i < 3; i++)
-    for (int j = 0; j < 3; j++)
-      CtC[i * 3 + j] = C[0 * 3 + i] * C[0 * 3 + j] + C[1 * 3 + i] * C[1 * 3 + j] + C[2 * 3 + i] * C[2 * 3 + j];
-  jacobi_sym<3>(CtC, Vs);
-  double e0 = CtC[0], e1 = CtC[4], e2 = CtC[8], t;
-  if (e1 > e0) { t = e0; e0 = e1; e1 = t; }
-  if (e2 > e0) { t = e0; e0 = e2; e2 = t; }
-  if (e2 > e1) { t = e1; e1 = e2; e2 = t; }
-  double s1 = sqrt(e0 > 0.0 ? e0 : 0.0), s2 = sqrt(e1 > 0.0 ? e1 : 0.0);
-  for (int i = 0; i < 9; i++) R[i] = (i % 4 == 0) ? 1.0 : 0.0;
-  if (!(s1 > 0.0) || s2 < 1e-9 * s1) return 1;
   // S_xy = sum a_x b_y = C[y][x]
   double Sxx = C[0], Syx = C[1], Szx = C[2];
   double Sxy = C[3], Syy = C[4], Szy = C[5];
@@ -265,9 +254,20 @@ TT_HD int rotation_fit_horn(const double* C, double* R) {
                   Sxy - Syx,       Szx + Sxz,        Syz + Szy,        -Sxx - Syy + Szz};
   double V[16];
   jacobi_sym<4>(N, V);
+  double l[4] = {N[0], N[5], N[10], N[15]};
   int best = 0;
   for (int i = 1; i < 4; i++)
-    if (N[i * 5] > N[best * 5]) best = i;
+    if (l[i] > l[best]) best = i;
+  // sort the eigenvalues decreasingly (4 elements)
+  for (int i = 1; i < 4; i++)
+    for (int k = i; k > 0 && l[k] > l[k - 1]; k--) {
+      double t = l[k];
+      l[k] = l[k - 1];
+      l[k - 1] = t;
+    }
+  const double s1 = 0.5 * (l[0] + l[1]), s2 = 0.5 * (l[0] + l[2]);
+  for (int i = 0; i < 9; i++) R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  if (!(s1 > 0.0) || s2 < 1e-9 * s1) return 1;
   double w = V[0 * 4 + best], x = V[1 * 4 + best], y = V[2 * 4 + best], z = V[3 * 4 + best];
   double nn = 1.0 / sqrt(w * w + x * x + y * y + z * z);
   w *= nn; x *= nn; y *= nn; z *= nn;
