@@ -184,7 +184,13 @@ constexpr int POTRF_SCRATCH_FLOATS = 8 * 16 * XS + 32 * TS;
 // L's off-diagonal tiles are left as the updated T (only Li is an output); scratch holds
 // POTRF_SCRATCH_FLOATS floats of LDS. Returns false if a pivot is not positive. All 256 threads
 // must call it.
-__device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LDS_LD], float* scratch) {
+// Optionally (U non-null) the block is first updated, L -= U U^T with U the 64 x 64 tile in LDS:
+// wavefront 0 updates only tile (0, 0) before leaf 0 and the others update the remaining nine lower
+// tiles meanwhile. When pub is non-null, every wavefront's earlier global stores are completed
+// before the end of that first phase and thread 64 then raises *pub = epoch (release).
+__device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LDS_LD], float* scratch,
+                                              const float (*U)[LDS_LD] = nullptr, int* pub = nullptr,
+                                              int pub_epoch = 0) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   float* XB = scratch;               // X tiles: 0 = X10, 1 = X20, 2 = X30, 3 = X21, 4 = X31, 5 = X32
   float* W01 = XB + 6 * 16 * XS;     // X10 Li00
@@ -205,11 +211,35 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
     leaf16(L, Li, 16 * k, ok);
     if (lane == 0 && !ok) bad = 1;
   };
-  // phase 1: leaf 0; the other wavefronts clear the upper tiles of Li
+  // T_rc -= U_r U_c^T over the 64-wide reduction (the block update folded into phase 1)
+  auto updU = [&](int r, int c) {
+    floatx4 acc = z4;
+#pragma unroll
+    for (int k0 = 0; k0 < NB; k0 += 16) acc = mm16_abt<LDS_LD, LDS_LD>(&U[16 * r][k0], &U[16 * c][k0], acc);
+    sub16<LDS_LD>(Lt(r, c), acc);
+  };
+  // phase 1: (update tile (0, 0)) leaf 0; the other wavefronts update the other tiles and clear
+  // the upper tiles of Li
   if (wave == 0) {
     if (lane == 0) bad = 0;
+    if (U) updU(0, 0);
     leaf(0);
   } else {
+    if (U) {
+      if (wave == 1) {
+        updU(1, 0);
+        updU(1, 1);
+        updU(2, 0);
+      } else if (wave == 2) {
+        updU(2, 1);
+        updU(2, 2);
+        updU(3, 0);
+      } else {
+        updU(3, 1);
+        updU(3, 2);
+        updU(3, 3);
+      }
+    }
     for (int e = tid - 64; e < 6 * 256; e += 192) {
       const int t = e >> 8, w = e & 255;
       const int r = (t < 3) ? 0 : (t < 5 ? 1 : 2);
@@ -217,7 +247,9 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
       Li[16 * r + (w >> 4)][16 * c + (w & 15)] = 0.0f;
     }
   }
+  if (pub) __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  if (pub && tid == 64) __hip_atomic_store(pub, pub_epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   // phase 2
   if (wave == 0) {
     makeX(1, 0, 0);
@@ -756,27 +788,37 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         chain_load(P, j, cva, ccp);
       }
       have_pref = false;
-      if (j >= 1) {
-        tile_to_lds(X, cva);
-        __syncthreads();
-        acc_zero(acc);
-        mma64_acc(X, Z, acc);  // L_{j,j-1} = C_{j,j-1} Linv_{j-1}^T
-        __syncthreads();
-        acc_store(P.A, ld, rj, rj - NB, acc);  // completes while the update below runs
-        if (P.prec != TT_FP32) acc_store16(P.A16, ld, rj, rj - NB, acc, P.prec);
-        acc_to_lds(X, acc, false);
-        __syncthreads();
-        acc_zero(acc);
-        mma64_acc(X, X, acc);
-#pragma unroll
-        for (int a = 0; a < 2; a++)
-#pragma unroll
-          for (int b = 0; b < 2; b++) ccp[a][b] -= acc[a][b];
-      }
       acc_to_lds(Y, ccp, true);
-      if (j >= 1) block_publish(S.fin + (size_t)j * nb + (j - 1), epoch);  // also the barrier for Y
-      else __syncthreads();
-      const bool ok = potrf_trtri64(Y, Z, &X[0][0]);  // Z = Linv_j, kept for step j + 1
+      if (j >= 1) tile_to_lds(X, cva);
+      __syncthreads();
+      if (j >= 1) {
+        // L_{j,j-1} = C_{j,j-1} Linv_{j-1}^T: wavefront g computes rows 16 g .. 16 g + 15 (four
+        // 16 x 16 tiles), then overwrites those rows of X and stores them
+        const int g = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+        floatx4 t4[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+          floatx4 a4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int k0 = 0; k0 < NB; k0 += 16) a4 = mm16_abt<LDS_LD, LDS_LD>(&X[16 * g][k0], &Z[16 * c][k0], a4);
+          t4[c] = a4;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            const int row = 16 * g + 4 * lk + q, col = 16 * c + li;
+            const float v = t4[c][q];
+            X[row][col] = v;
+            P.A[(rj + row) * ld + rj - NB + col] = v;
+            if (P.prec != TT_FP32) P.A16[(rj + row) * ld + rj - NB + col] = (P.prec == TT_BF16_IR) ? to_bf16(v) : to_f16(v);
+          }
+        __syncthreads();
+      }
+      // Z = Linv_j, kept for step j + 1; for j >= 1 the update C_jj -= L_{j,j-1} L_{j,j-1}^T is folded
+      // into the factorisation's first phase, which also publishes L_{j,j-1}
+      const bool ok = (j >= 1) ? potrf_trtri64(Y, Z, &X[0][0], X, S.fin + (size_t)j * nb + (j - 1), epoch)
+                               : potrf_trtri64(Y, Z, &X[0][0]);
       float* Lj = P.Linv + (size_t)j * NB * NB;
       for (int e = tid; e < NB * NB / 4; e += 256) {
         const int r = e >> 4, cc = 4 * (e & 15);
