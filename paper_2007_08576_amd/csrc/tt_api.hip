@@ -129,13 +129,25 @@ int ensure_k2(tt_stream* s, int K2) {
 }
 
 // ---- stage timers
+// Timing events: no system-scope fence when recorded (they only measure; reading them waits for the
+// stream first), which keeps the recording from stalling the kernels that follow.
 hipError_t ev_get(tt_stream* s, hipEvent_t* e) {
   if (!s->ev_pool.empty()) {
     *e = s->ev_pool.back();
     s->ev_pool.pop_back();
     return hipSuccess;
   }
-  return hipEventCreate(e);
+  return hipEventCreateWithFlags(e, hipEventDisableSystemFence);
+}
+
+// Ordering events between HIP streams (no timing, default fences).
+hipError_t ev_sync_get(tt_stream* s, hipEvent_t* e) {
+  if (!s->ev_sync_pool.empty()) {
+    *e = s->ev_sync_pool.back();
+    s->ev_sync_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreateWithFlags(e, hipEventDisableTiming);
 }
 
 int timing_flush(tt_stream* s) {
@@ -320,11 +332,11 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
   // batch_st -> every per-stream queue
   auto fork = [&]() -> int {
     hipEvent_t ev = nullptr;
-    if (ev_get(ss[0], &ev) != hipSuccess) return TT_EDEVICE;
+    if (ev_sync_get(ss[0], &ev) != hipSuccess) return TT_EDEVICE;
     int rc = hipEventRecord(ev, batch_st) == hipSuccess ? TT_OK : TT_EDEVICE;
     for (int q = 1; q < S && !rc; q++)
       if (qs[q] != batch_st && hipStreamWaitEvent(qs[q], ev, 0) != hipSuccess) rc = TT_EDEVICE;
-    ss[0]->ev_pool.push_back(ev);
+    ss[0]->ev_sync_pool.push_back(ev);
     return rc;
   };
   // every per-stream queue -> batch_st
@@ -332,9 +344,9 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
     for (int q = 1; q < S; q++) {
       if (qs[q] == batch_st) continue;
       hipEvent_t ev = nullptr;
-      if (ev_get(ss[q], &ev) != hipSuccess) return TT_EDEVICE;
+      if (ev_sync_get(ss[q], &ev) != hipSuccess) return TT_EDEVICE;
       const bool ok = hipEventRecord(ev, qs[q]) == hipSuccess && hipStreamWaitEvent(batch_st, ev, 0) == hipSuccess;
-      ss[q]->ev_pool.push_back(ev);
+      ss[q]->ev_sync_pool.push_back(ev);
       if (!ok) return TT_EDEVICE;
     }
     return TT_OK;
@@ -654,6 +666,8 @@ int tt_destroy(tt_stream* s) {
     (void)timing_flush(s);
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     s->ev_pool.clear();
+    for (hipEvent_t e : s->ev_sync_pool) (void)hipEventDestroy(e);
+    s->ev_sync_pool.clear();
     free_template(s);
     free_list(s->allocs_k2, s->bytes_k2);
     free_list(s->allocs_frame, s->bytes_frame);
@@ -880,18 +894,18 @@ int tt_track_batch_device(tt_stream* const* streams, int S, const tt_frame_devic
   // stream's later work runs after the batch
   for (int q = 1; q < S && !rc; q++) {
     hipEvent_t ev = nullptr;
-    if (ev_get(streams[q], &ev) != hipSuccess || hipEventRecord(ev, streams[q]->st) != hipSuccess ||
+    if (ev_sync_get(streams[q], &ev) != hipSuccess || hipEventRecord(ev, streams[q]->st) != hipSuccess ||
         hipStreamWaitEvent(st, ev, 0) != hipSuccess)
       rc = TT_EDEVICE;
-    if (ev) streams[q]->ev_pool.push_back(ev);
+    if (ev) streams[q]->ev_sync_pool.push_back(ev);
   }
   if (!rc) rc = enqueue_batch(streams, S, frames, st);
   if (!rc && S > 1) {
     hipEvent_t ev = nullptr;
-    if (ev_get(streams[0], &ev) != hipSuccess || hipEventRecord(ev, st) != hipSuccess) rc = TT_EDEVICE;
+    if (ev_sync_get(streams[0], &ev) != hipSuccess || hipEventRecord(ev, st) != hipSuccess) rc = TT_EDEVICE;
     for (int q = 1; q < S && !rc; q++)
       if (hipStreamWaitEvent(streams[q]->st, ev, 0) != hipSuccess) rc = TT_EDEVICE;
-    if (ev) streams[0]->ev_pool.push_back(ev);
+    if (ev) streams[0]->ev_sync_pool.push_back(ev);
   }
   for (int q = 0; q < locked; q++) streams[q]->mu.unlock();
   return rc;

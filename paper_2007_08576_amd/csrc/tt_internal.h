@@ -144,7 +144,8 @@ struct tt_stream {
   uint64_t bytes_template = 0, bytes_frame = 0, bytes_k2 = 0;
   // stage timers
   bool timing = false;
-  std::vector<hipEvent_t> ev_pool;
+  std::vector<hipEvent_t> ev_pool;       // timing events
+  std::vector<hipEvent_t> ev_sync_pool;  // ordering events between HIP streams (batched path)
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   double stage_ms[TT_NSTAGES] = {};
   int64_t stage_n[TT_NSTAGES] = {};
