@@ -217,7 +217,7 @@ def precision_study(args, torch, tt, sc2, dframes2, vo_oracle):
         fps = None
         if steps:
             s.get_timing()
-            s.set_timing(True)
+            s.set_timing(True, stages=("factor", "solve"))
             t0 = time.perf_counter()
             for k in range(steps):
                 d = dfr[(k + 1) % len(dfr)]
@@ -366,7 +366,9 @@ def main():
     s.sync()
     torch.cuda.synchronize()
     s.get_timing()  # reset
-    s.set_timing(True)
+    # only the dominant kernel's launch is bracketed in the timed region (for the roofline); the
+    # per-stage breakdown comes from a separate pass below
+    s.set_timing(True, stages=("factor",))
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -383,9 +385,17 @@ def main():
     fps = args.steps / wall
     lat = np.array([ev0[k].elapsed_time(ev1[k]) for k in range(args.steps)])
     stage_ms, stage_n = s.get_timing()
+    fac_ms = float(stage_ms[tt.STAGES.index("factor")] / max(stage_n[tt.STAGES.index("factor")], 1))
+    log(f"{fps:.1f} frames/s, p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
+    # stage breakdown: a few more frames with every stage bracketed by events (outside the timed region)
+    s.set_timing(True)
+    for k in range(min(args.steps, 10)):
+        step(args.warmup + args.steps + k)
+    s.sync()
+    s.set_timing(False)
+    stage_ms, stage_n = s.get_timing()
     stages = {name: dict(ms_per_call=float(stage_ms[i] / max(stage_n[i], 1)), calls=int(stage_n[i]))
               for i, name in enumerate(tt.STAGES)}
-    log(f"{fps:.1f} frames/s, p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
     for name, v in stages.items():
         log(f"  {name:7s} {v['ms_per_call'] * 1e3:9.1f} us x {v['calls']}")
 
@@ -393,7 +403,6 @@ def main():
     # timer brackets exactly that launch on the library's HIP stream)
     n = 6 * N
     pairs = N * (N - 1) // 2
-    fac_ms = stages["factor"]["ms_per_call"]
     flops = n ** 3 / 3.0 + float(n) * n  # Cholesky of the n x n system + the forward substitution
     achieved = flops / (fac_ms * 1e-3) / 1e12
     roof = dict(kernel="k_chol_dataflow", bound="mfma", achieved=achieved, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",

@@ -180,8 +180,13 @@ int tt_set_state(tt_stream* s, const double* dq, int64_t frame);
 #define TT_STAGE_FACTOR 6 /* blocked Cholesky factorisation with the forward substitution */
 #define TT_NSTAGES 7
 
-/* Enables (1) or disables (0) the stage timers. */
-int tt_set_timing(tt_stream* s, int enable);
+#define TT_TIMING_ALL ((1 << TT_NSTAGES) - 1)
+
+/* Selects the stages whose GPU time is measured: bit i of stages (0 <= stages <= TT_TIMING_ALL)
+ * times stage i, 0 turns the timers off. Each timed stage records two HIP events on the stream
+ * per call, so time only what is needed where the throughput itself is measured.
+ * TT_EINVAL for a bit outside the stages. */
+int tt_set_timing(tt_stream* s, int stages);
 
 /* Waits for the stream, then returns the GPU milliseconds accumulated per stage since the last
  * call (ms [TT_NSTAGES]) and how many times each stage ran (count [TT_NSTAGES]); either may be

@@ -171,9 +171,9 @@ struct StageTimer {
   hipEvent_t a = nullptr, b = nullptr;
   hipStream_t st;
   StageTimer(tt_stream* s_, int stage_, hipStream_t st_) : s(s_), stage(stage_), st(st_) {
-    if (!s->timing) return;
+    if (!((s->timing >> stage) & 1u)) return;
     if (ev_get(s, &a) != hipSuccess || ev_get(s, &b) != hipSuccess) {
-      s->timing = false;
+      s->timing = 0;
       return;
     }
     (void)hipEventRecord(a, st);
@@ -557,11 +557,11 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
   return TT_OK;
 }
 
-int tt_set_timing(tt_stream* s, int enable) {
-  if (!s) return TT_EINVAL;
+int tt_set_timing(tt_stream* s, int stages) {
+  if (!s || stages < 0 || stages > TT_TIMING_ALL) return TT_EINVAL;
   Busy busy(s);
   if (!busy.ok) return TT_EBUSY;
-  s->timing = enable != 0;
+  s->timing = (unsigned)stages;
   return TT_OK;
 }
 

@@ -94,44 +94,76 @@ __device__ __forceinline__ void fmac_bcast16(float& acc, float src, float mul, i
   }
 }
 
-// 16 x 16 leaf on one wavefront: factors the block at (o, o) of L (in registers) and writes the
-// inverse of the factor to Li at (o, o); L itself is only read (callers need only the inverse). Lane r (mod 16) keeps row r in registers; pivots and
-// column entries move between lanes by row broadcasts. 1/sqrt(pivot) comes from one v_rsq. The
-// inverse is built column-oriented (lane r holds column r): x_i = p_i / L_ii, then
-// p_k -= L_ki x_i for k > i.
-__device__ __forceinline__ void leaf16(float (*L)[LDS_LD], float (*Li)[LDS_LD], int o, bool& ok) {
+// (src of lane n of the row) * m and -(src of lane n of the row) * m as one v_mul_f32_dpp each; the
+// leading s_nop covers a VALU write of src just before. mul_bcast16_fenced adds a trailing s_nop so
+// that its result may be the broadcast source of whichever instruction the compiler puts next.
+#define TT_BC16_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+__device__ __forceinline__ float mul_bcast16(float src, float m, int n) {
+  float d;
+  switch (n) {
+#define TT_C(k) case k: asm("s_nop 1\n\tv_mul_f32_dpp %0, %1, %2 row_newbcast:" #k " row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(src), "v"(m)); break;
+    TT_BC16_CASES(TT_C)
+#undef TT_C
+  }
+  return d;
+}
+__device__ __forceinline__ float mul_bcast16_fenced(float src, float m, int n) {
+  float d;
+  switch (n) {
+#define TT_C(k) case k: asm("s_nop 1\n\tv_mul_f32_dpp %0, %1, %2 row_newbcast:" #k " row_mask:0xf bank_mask:0xf\n\ts_nop 1" : "=v"(d) : "v"(src), "v"(m)); break;
+    TT_BC16_CASES(TT_C)
+#undef TT_C
+  }
+  return d;
+}
+__device__ __forceinline__ float nmul_bcast16(float src, float m, int n) {
+  float d;
+  switch (n) {
+#define TT_C(k) case k: asm("s_nop 1\n\tv_mul_f32_dpp %0, -%1, %2 row_newbcast:" #k " row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(src), "v"(m)); break;
+    TT_BC16_CASES(TT_C)
+#undef TT_C
+  }
+  return d;
+}
+
+// 16 x 16 leaf on one wavefront: factors the block at (o, o) of L (read from LDS into registers)
+// and writes the inverse of the factor to Li at (o, o); L itself is left as it was. Lane r (mod 16)
+// keeps row r in registers; pivots and column entries move between lanes by row broadcasts, so
+// each 16-lane row of the wave runs the same factorisation. Step j: every lane takes 1/sqrt of its
+// own entry j (only lane j's, the pivot's, is used), and the broadcast of that value from lane j
+// scales the column in the same instruction. The inverse is built column-oriented (lane r holds
+// column r): x_i = p_i / L_ii, then p_k -= L_ki x_i for k > i.
+// No lane masks: in lanes r < j, entry j and everything derived from it lie in the row's upper
+// triangle, which is never broadcast (sources are lane j for the pivot and lanes m > j for the
+// column) and never stored. A pivot that is not positive leaves a non-finite or non-positive
+// diagonal entry of the inverse (1/sqrt of it), which the caller checks.
+__device__ __forceinline__ void leaf16(float (*L)[LDS_LD], float (*Li)[LDS_LD], int o) {
   const int lane = threadIdx.x & 63, r = lane & 15;
   const bool writer = lane < 16;
   float a[16];
 #pragma unroll
   for (int c = 0; c < 16; c += 2) {
     const float2 v = *reinterpret_cast<const float2*>(&L[o + r][o + c]);
-    a[c] = (c <= r) ? v.x : 0.0f;
-    a[c + 1] = (c + 1 <= r) ? v.y : 0.0f;
+    a[c] = v.x;
+    a[c + 1] = v.y;
   }
-  float invd[16];
+  float il[16];
 #pragma unroll
   for (int j = 0; j < 16; j++) {
-    const float d = bcast16(a[j], j);
-    ok = ok && (d > 0.0f);
-    const float il = __builtin_amdgcn_rsqf(d);
-    invd[j] = il;
-    // No lane masks: in lanes r < j, a[j] and everything derived from it lie in the row's upper
-    // triangle, which is never broadcast (sources are lane j for the pivot and lanes m > j for the
-    // column) and never stored; lane j itself gets a[j] = d / sqrt(d), its diagonal entry.
-    const float lr = a[j] * il;
-    const float nlr = a[j] * (-il);
+    il[j] = __builtin_amdgcn_rsqf(a[j]);
+    const float lr = mul_bcast16_fenced(il[j], a[j], j);  // the broadcast source of the updates below
+    const float nlr = nmul_bcast16(il[j], a[j], j);
     a[j] = lr;
 #pragma unroll
-    for (int m = j + 1; m < 16; m++) fmac_bcast16(a[m], lr, nlr, m, m == j + 1);
+    for (int m = j + 1; m < 16; m++) fmac_bcast16(a[m], lr, nlr, m, false);
   }
   float p[16], x[16];
 #pragma unroll
   for (int i = 0; i < 16; i++) p[i] = (i == r) ? 1.0f : 0.0f;
 #pragma unroll
   for (int i = 0; i < 16; i++) {
-    x[i] = p[i] * invd[i];
-    const float nx = p[i] * (-invd[i]);
+    x[i] = mul_bcast16(il[i], p[i], i);
+    const float nx = nmul_bcast16(il[i], p[i], i);
 #pragma unroll
     for (int k = i + 1; k < 16; k++) fmac_bcast16(p[k], a[i], nx, k, k == i + 1);
   }
@@ -172,45 +204,42 @@ __device__ __forceinline__ void sub16(float* C, floatx4 acc) {  // C -= acc
 }
 
 constexpr int XS = 18;  // stride of the 16 x 16 scratch tiles
-constexpr int TS = 34;  // stride of the 32 x 32 scratch block
-constexpr int POTRF_SCRATCH_FLOATS = 8 * 16 * XS + 32 * TS;
+constexpr int POTRF_SCRATCH_FLOATS = 12 * 16 * XS;
 
 // Cholesky factor and inverse Li of the 64 x 64 lower triangle in L (LDS), blocked by 16. Writing
 // T_rc for the 16 x 16 tiles of L and X_rk = T_rk Li_kk^T for the factor's off-diagonal tiles, the
 // serial chain is leaf(k) -> X_{k+1,k} -> T_{k+1,k+1} -= X X^T -> leaf(k+1); wavefront 0 runs only
 // that chain, while wavefronts 1-3 compute the other X tiles (each keeps its own copy of the ones it
-// needs; copies of one tile are bit-identical), the trailing updates and the blocks of the inverse,
-// [[A, 0], [C, D]]^{-1} = [[A^{-1}, 0], [-D^{-1} C A^{-1}, D^{-1}]] (16 -> 32 -> 64). Six barriers.
+// needs; copies of one tile are bit-identical), the trailing updates and the blocks of the inverse.
+// From L Li = I, the block below the diagonal is Li_rc = -Li_rr S_rc with
+// S_rc = sum_{c <= m < r} X_rm Li_mc; every S_rc is complete when leaf 3 ends, so only the three
+// products Li_3c = -Li_33 S_3c follow the chain. Five barriers.
 // L's off-diagonal tiles are left as the updated T (only Li is an output); scratch holds
-// POTRF_SCRATCH_FLOATS floats of LDS. Returns false if a pivot is not positive. All 256 threads
-// must call it.
+// POTRF_SCRATCH_FLOATS floats of LDS. Returns false if a pivot is not positive (a diagonal entry
+// of Li that is not positive and finite). All 256 threads must call it.
 // Optionally (U non-null) the block is first updated, L -= U U^T with U the 64 x 64 tile in LDS:
 // wavefront 0 updates only tile (0, 0) before leaf 0 and the others update the remaining nine lower
 // tiles meanwhile. When pub is non-null, every wavefront's earlier global stores are completed
-// before the end of that first phase and thread 64 then raises *pub = epoch (release).
+// before the end of that first phase and thread 64 then raises *pub = epoch (release). Scratch is
+// first written after that phase, so U may share its memory.
 __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LDS_LD], float* scratch,
                                               const float (*U)[LDS_LD] = nullptr, int* pub = nullptr,
                                               int pub_epoch = 0) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  float* XB = scratch;               // X tiles: 0 = X10, 1 = X20, 2 = X30, 3 = X21, 4 = X31, 5 = X32
-  float* W01 = XB + 6 * 16 * XS;     // X10 Li00
-  float* W23 = W01 + 16 * XS;        // X32 Li22
-  float* TT = W23 + 16 * XS;         // C A^{-1}, 32 x 32
-  __shared__ int bad;
-  auto Xt = [&](int id) { return XB + id * 16 * XS; };
+  // scratch tiles: 0 = X10, 1 = X20, 2 = X30, 3 = X21, 4 = X31, 5 = X32, then the sums S_rc
+  enum { S10 = 6, S20, S21, S30, S31, S32 };
+  auto Xt = [&](int id) { return scratch + id * 16 * XS; };
   auto Lt = [&](int r, int c) { return &L[16 * r][16 * c]; };
   auto Lit = [&](int r, int c) { return &Li[16 * r][16 * c]; };
-  auto TTt = [&](int r, int c) { return TT + 16 * r * TS + 16 * c; };
   const floatx4 z4 = {0.f, 0.f, 0.f, 0.f};
   // X_rk = T_rk Li_kk^T into scratch tile id
   auto makeX = [&](int r, int k, int id) { put16<XS>(Xt(id), mm16_abt<LDS_LD, LDS_LD>(Lt(r, k), Lit(k, k), z4), 1.0f); };
   // T_rc -= X_a X_b^T
   auto updT = [&](int r, int c, int a, int b) { sub16<LDS_LD>(Lt(r, c), mm16_abt<XS, XS>(Xt(a), Xt(b), z4)); };
-  auto leaf = [&](int k) {
-    bool ok = true;
-    leaf16(L, Li, 16 * k, ok);
-    if (lane == 0 && !ok) bad = 1;
-  };
+  // acc += X_a Li_mc
+  auto xli = [&](int a, int m, int c, floatx4 acc) { return mm16_ab<XS, LDS_LD>(Xt(a), Lit(m, c), acc); };
+  // Li_rc = -Li_rr S
+  auto finish = [&](int r, int c, int sid) { put16<LDS_LD>(Lit(r, c), mm16_ab<LDS_LD, XS>(Lit(r, r), Xt(sid), z4), -1.0f); };
   // T_rc -= U_r U_c^T over the 64-wide reduction (the block update folded into phase 1)
   auto updU = [&](int r, int c) {
     floatx4 acc = z4;
@@ -218,12 +247,12 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
     for (int k0 = 0; k0 < NB; k0 += 16) acc = mm16_abt<LDS_LD, LDS_LD>(&U[16 * r][k0], &U[16 * c][k0], acc);
     sub16<LDS_LD>(Lt(r, c), acc);
   };
+  floatx4 s3 = z4;  // S_31 (wavefront 1) or S_30 (wavefront 2), carried from phase 3 to phase 4
   // phase 1: (update tile (0, 0)) leaf 0; the other wavefronts update the other tiles and clear
   // the upper tiles of Li
   if (wave == 0) {
-    if (lane == 0) bad = 0;
     if (U) updU(0, 0);
-    leaf(0);
+    leaf16(L, Li, 0);
   } else {
     if (U) {
       if (wave == 1) {
@@ -250,11 +279,11 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
   if (pub) __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (pub && tid == 64) __hip_atomic_store(pub, pub_epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  // phase 2
+  // phase 2: leaf 1; X_r0, trailing updates
   if (wave == 0) {
     makeX(1, 0, 0);
     updT(1, 1, 0, 0);
-    leaf(1);
+    leaf16(L, Li, 16);
   } else if (wave == 1) {
     makeX(1, 0, 0);
     makeX(2, 0, 1);
@@ -271,56 +300,57 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
     updT(3, 3, 2, 2);
   }
   __syncthreads();
-  // phase 3
+  // phase 3: leaf 2; X_r1, trailing updates; Li_10; S_21 and the first terms of S_31, S_30
   if (wave == 0) {
     makeX(2, 1, 3);
     updT(2, 2, 3, 3);
-    leaf(2);
+    leaf16(L, Li, 32);
   } else if (wave == 1) {
     makeX(2, 1, 3);
     makeX(3, 1, 4);
     updT(3, 2, 4, 3);
+    put16<XS>(Xt(S21), xli(3, 1, 1, z4), 1.0f);
+    s3 = xli(4, 1, 1, z4);
   } else if (wave == 2) {
     makeX(3, 1, 4);
     updT(3, 3, 4, 4);
+    s3 = xli(2, 0, 0, z4);
   } else {
-    put16<XS>(W01, mm16_ab<XS, LDS_LD>(Xt(0), Lit(0, 0), z4), 1.0f);
-    put16<LDS_LD>(Lit(1, 0), mm16_ab<LDS_LD, XS>(Lit(1, 1), W01, z4), -1.0f);
+    put16<XS>(Xt(S10), xli(0, 0, 0, z4), 1.0f);
+    finish(1, 0, S10);
   }
   __syncthreads();
-  // phase 4
+  // phase 4: leaf 3; X_32; Li_21, Li_20; S_32 and the rest of S_31, S_30
   if (wave == 0) {
     makeX(3, 2, 5);
     updT(3, 3, 5, 5);
-    leaf(3);
+    leaf16(L, Li, 48);
   } else if (wave == 1) {
-    put16<TS>(TTt(0, 0), mm16_ab<XS, LDS_LD>(Xt(3), Lit(1, 0), mm16_ab<XS, LDS_LD>(Xt(1), Lit(0, 0), z4)), 1.0f);
-    put16<TS>(TTt(0, 1), mm16_ab<XS, LDS_LD>(Xt(3), Lit(1, 1), z4), 1.0f);
+    makeX(3, 2, 5);
+    finish(2, 1, S21);
+    put16<XS>(Xt(S31), xli(5, 2, 1, s3), 1.0f);
   } else if (wave == 2) {
-    put16<TS>(TTt(1, 0), mm16_ab<XS, LDS_LD>(Xt(4), Lit(1, 0), mm16_ab<XS, LDS_LD>(Xt(2), Lit(0, 0), z4)), 1.0f);
-    put16<TS>(TTt(1, 1), mm16_ab<XS, LDS_LD>(Xt(4), Lit(1, 1), z4), 1.0f);
+    put16<XS>(Xt(S20), xli(3, 1, 0, xli(1, 0, 0, z4)), 1.0f);
+    finish(2, 0, S20);
+    makeX(3, 2, 5);
+    put16<XS>(Xt(S30), xli(5, 2, 0, xli(4, 1, 0, s3)), 1.0f);
+  } else {
+    makeX(3, 2, 5);
+    put16<XS>(Xt(S32), xli(5, 2, 2, z4), 1.0f);
   }
   __syncthreads();
-  // phase 5
-  if (wave == 0) {
-    put16<XS>(W23, mm16_ab<XS, LDS_LD>(Xt(5), Lit(2, 2), z4), 1.0f);
-    put16<LDS_LD>(Lit(3, 2), mm16_ab<LDS_LD, XS>(Lit(3, 3), W23, z4), -1.0f);
-  } else if (wave == 1) {
-    put16<LDS_LD>(Lit(2, 0), mm16_ab<LDS_LD, TS>(Lit(2, 2), TTt(0, 0), z4), -1.0f);
+  // phase 5: Li_3c = -Li_33 S_3c
+  if (wave == 1) {
+    finish(3, 1, S31);
   } else if (wave == 2) {
-    put16<LDS_LD>(Lit(2, 1), mm16_ab<LDS_LD, TS>(Lit(2, 2), TTt(0, 1), z4), -1.0f);
+    finish(3, 0, S30);
+  } else if (wave == 3) {
+    finish(3, 2, S32);
   }
   __syncthreads();
-  // phase 6
-  if (wave == 0) {
-    put16<LDS_LD>(Lit(3, 0),
-                  mm16_ab<LDS_LD, TS>(Lit(3, 3), TTt(1, 0), mm16_ab<LDS_LD, TS>(Lit(3, 2), TTt(0, 0), z4)), -1.0f);
-  } else if (wave == 1) {
-    put16<LDS_LD>(Lit(3, 1),
-                  mm16_ab<LDS_LD, TS>(Lit(3, 3), TTt(1, 1), mm16_ab<LDS_LD, TS>(Lit(3, 2), TTt(0, 1), z4)), -1.0f);
-  }
-  __syncthreads();
-  return bad == 0;
+  // every wavefront checks all 64 diagonal entries of the inverse (1 / the pivots' square roots)
+  const float dv = Li[lane][lane];
+  return __all((dv > 0.0f) && (dv < __builtin_huge_valf()));
 }
 
 // ---- dataflow factorisation: one persistent launch per solve ---------------------------------

@@ -143,7 +143,7 @@ struct tt_stream {
   std::vector<void*> allocs_k2;        // grows with K2
   uint64_t bytes_template = 0, bytes_frame = 0, bytes_k2 = 0;
   // stage timers
-  bool timing = false;
+  unsigned timing = 0;  // bit i set: stage i is timed
   std::vector<hipEvent_t> ev_pool;       // timing events
   std::vector<hipEvent_t> ev_sync_pool;  // ordering events between HIP streams (batched path)
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;

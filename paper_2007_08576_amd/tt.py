@@ -226,8 +226,14 @@ class Stream:
         dq = None if dq is None else _c(dq, np.float64).reshape(self.N, 8)
         _check(lib().tt_set_state(self.h, _ptr(dq), int(frame)), "tt_set_state")
 
-    def set_timing(self, enable=True):
-        _check(lib().tt_set_timing(self.h, 1 if enable else 0), "tt_set_timing")
+    def set_timing(self, enable=True, stages=None):
+        """Stage timers on (every stage, or only the names in `stages`) or off."""
+        mask = 0
+        if enable:
+            names = STAGES if stages is None else stages
+            for name in names:
+                mask |= 1 << STAGES.index(name)
+        _check(lib().tt_set_timing(self.h, mask), "tt_set_timing")
 
     def get_timing(self):
         """(ms per stage, count per stage) accumulated since the last call; stage order as STAGES."""

@@ -1,5 +1,6 @@
 """Batched tracking (tt_track_batch_device): each stream's result in a batch equals its result when
-tracked alone, and the batch entry point rejects bad arguments (GPU).
+tracked alone, and the batch entry point rejects bad arguments; the stage timers count exactly the
+selected stages (GPU).
 
 The per-stream stages run the same kernels on the same data, and every tile sum of the batched
 factorisation is accumulated in a fixed order whichever workgroup computes it, so the comparison
@@ -101,3 +102,30 @@ def test_batch_rejects_bad_arguments(env):
     assert s.get_state()[1] == 1
     s.destroy()
     t2.destroy()
+
+
+def test_stage_timer_selection(env):
+    tt, torch = env
+    dev = torch.device("cuda:0")
+    sc = _scenes()[2]
+    s = _stream(tt, sc)
+    d = _dev_frame(torch, sc.frame(1), dev)
+    with pytest.raises(tt.TTError) as e:
+        tt._check(tt.lib().tt_set_timing(s.h, 1 << len(tt.STAGES)), "tt_set_timing")
+    assert e.value.code == tt.TT_EINVAL
+    s.set_timing(True, stages=("factor",))
+    s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], None, None)
+    ms, n = s.get_timing()
+    lm = s.params.lm_iters
+    fi = tt.STAGES.index("factor")
+    assert n[fi] == lm and ms[fi] > 0
+    assert all(n[i] == 0 for i in range(len(tt.STAGES)) if i != fi)
+    s.set_timing(True)
+    s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], None, None)
+    ms, n = s.get_timing()
+    assert n[tt.STAGES.index("front")] == 1 and all(n[i] >= lm for i in range(1, len(tt.STAGES)))
+    s.set_timing(False)
+    s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], None, None)
+    ms, n = s.get_timing()
+    assert not n.any()
+    s.destroy()
