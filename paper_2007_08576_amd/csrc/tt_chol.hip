@@ -222,9 +222,33 @@ constexpr int POTRF_SCRATCH_FLOATS = 12 * 16 * XS;
 // tiles meanwhile. When pub is non-null, every wavefront's earlier global stores are completed
 // before the end of that first phase and thread 64 then raises *pub = epoch (release). Scratch is
 // first written after that phase, so U may share its memory.
+// A look ahead that one idle thread runs during the factorisation's fourth phase: it reads the
+// ticket counter into *s_ctr and whether both flags f0, f1 (if non-null) equal epoch into *s_ready,
+// acquiring when they do; the results are in LDS for the whole block once the call returns.
+struct ChainPoll {
+  const int* f0;
+  const int* f1;
+  const int* ctr;
+  int epoch;
+  int* s_ready;
+  int* s_ctr;
+};
+__device__ __forceinline__ void chain_poll(const ChainPoll& q) {
+  const int c = __hip_atomic_load(q.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  bool r = true;
+  if (q.f0) {
+    const int v0 = __hip_atomic_load(q.f0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int v1 = __hip_atomic_load(q.f1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    r = (v0 == q.epoch) && (v1 == q.epoch);
+    if (r) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  *q.s_ctr = c;
+  *q.s_ready = r ? 1 : 0;
+}
+
 __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LDS_LD], float* scratch,
                                               const float (*U)[LDS_LD] = nullptr, int* pub = nullptr,
-                                              int pub_epoch = 0) {
+                                              int pub_epoch = 0, const ChainPoll* poll = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // scratch tiles: 0 = X10, 1 = X20, 2 = X30, 3 = X21, 4 = X31, 5 = X32, then the sums S_rc
   enum { S10 = 6, S20, S21, S30, S31, S32 };
@@ -337,6 +361,7 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
   } else {
     makeX(3, 2, 5);
     put16<XS>(Xt(S32), xli(5, 2, 2, z4), 1.0f);
+    if (poll && lane == 0) chain_poll(*poll);
   }
   __syncthreads();
   // phase 5: Li_3c = -Li_33 S_3c
@@ -399,35 +424,53 @@ __host__ __device__ inline CholSync chol_sync(int* base, int nb) {
   return S;
 }
 
-__host__ __device__ inline int chol_task_count(int nb) {
-  int t = 0;
-  for (int j = 0; j < nb; j++) t += (j >= 2 ? 2 : 0) + 1 + (nb - j - 2 > 0 ? nb - j - 2 : 0) + 1;
+// Task groups: group j holds DIAGP(j), SUBP(j) (from j = 2), CRIT(j), FULL(j + 2 .. nb - 1, j) and
+// FULL(nb, j), in that ticket order; it has
+//   g(j) = (j >= 2 ? 2 : 0) + 1 + max(nb - j - 2, 0) + 1
+// tasks. group_start(j) = g(0) + ... + g(j - 1) in closed form: g(0) = 2 + max(nb - 2, 0),
+// g(1) = 2 + max(nb - 3, 0), g(q) = nb + 2 - q for 2 <= q <= nb - 2 and g(nb - 1) = 4 (nb >= 3).
+__host__ __device__ inline int group_size(int j, int nb) {
+  return (j >= 2 ? 2 : 0) + 1 + (nb - j - 2 > 0 ? nb - j - 2 : 0) + 1;
+}
+__host__ __device__ inline int group_start(int j, int nb) {
+  if (j <= 0) return 0;
+  const int g0 = 2 + (nb - 2 > 0 ? nb - 2 : 0);
+  if (j == 1) return g0;
+  const int g1 = 2 + (nb - 3 > 0 ? nb - 3 : 0);
+  const int m = (j < nb - 1) ? j : nb - 1;  // groups 2 .. m - 1 have nb + 2 - q tasks
+  int t = g0 + g1;
+  if (m > 2) t += (m - 2) * (nb + 2) - ((m - 1) * m / 2 - 1);
+  if (j >= nb && nb - 1 >= 2) t += 4;  // the last group
   return t;
 }
 
+__host__ __device__ inline int chol_task_count(int nb) { return group_start(nb, nb); }
+
 __device__ __forceinline__ void decode_task(int t, int nb, int& kind, int& i, int& c) {
-  int t0 = 0;
-  for (int j = 0; j < nb; j++) {
-    const int nfull = (nb - j - 2 > 0 ? nb - j - 2 : 0) + 1;
-    const int gsz = (j >= 2 ? 2 : 0) + 1 + nfull;
-    if (t < t0 + gsz) {
-      int r = t - t0;
-      if (j >= 2) {
-        if (r == 0) { kind = TASK_DIAGP; i = j; c = j; return; }
-        if (r == 1) { kind = TASK_SUBP; i = j; c = j - 1; return; }
-        r -= 2;
-      }
-      if (r == 0) { kind = TASK_CRIT; i = j; c = j; return; }
-      r -= 1;
-      kind = TASK_FULL;
-      i = (r < nfull - 1) ? j + 2 + r : nb;
-      c = j;
-      return;
-    }
-    t0 += gsz;
+  if (t < 0 || t >= group_start(nb, nb)) {
+    kind = -1;
+    i = c = 0;
+    return;
   }
-  kind = -1;
-  i = c = 0;
+  int lo = 0, hi = nb - 1;  // the group j with group_start(j) <= t < group_start(j + 1)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (group_start(mid, nb) <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const int j = lo;
+  const int nfull = (nb - j - 2 > 0 ? nb - j - 2 : 0) + 1;
+  int r = t - group_start(j, nb);
+  if (j >= 2) {
+    if (r == 0) { kind = TASK_DIAGP; i = j; c = j; return; }
+    if (r == 1) { kind = TASK_SUBP; i = j; c = j - 1; return; }
+    r -= 2;
+  }
+  if (r == 0) { kind = TASK_CRIT; i = j; c = j; return; }
+  r -= 1;
+  kind = TASK_FULL;
+  i = (r < nfull - 1) ? j + 2 + r : nb;
+  c = j;
 }
 
 constexpr uint64_t kDeadlineTicks = 25000000ull;  // 0.25 s of the 100 MHz constant clock
@@ -681,11 +724,7 @@ struct CholArgs {
 };
 
 // Ticket of CRIT(j): the number of tasks in the groups before j, plus DIAGP(j) and SUBP(j).
-__device__ __forceinline__ int crit_ticket(int j, int nb) {
-  int t = 0;
-  for (int q = 0; q < j; q++) t += (q >= 2 ? 2 : 0) + 1 + (nb - q - 2 > 0 ? nb - q - 2 : 0) + 1;
-  return t + (j >= 2 ? 2 : 0);
-}
+__device__ __forceinline__ int crit_ticket(int j, int nb) { return group_start(j, nb) + (j >= 2 ? 2 : 0); }
 
 enum { MODE_TASK = 0, MODE_CRIT = 1, MODE_RETRY = 2 };
 
@@ -724,7 +763,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
   __shared__ __attribute__((aligned(16))) float Y[NB][LDS_LD];
   __shared__ __attribute__((aligned(16))) float Z[NB][LDS_LD];  // the chain's Linv_{j-1} between CRIT steps
   static_assert(POTRF_SCRATCH_FLOATS <= NB * LDS_LD, "factorisation scratch must fit in one tile buffer");
-  __shared__ int s_task, s_val, s_mode, s_prob;
+  __shared__ int s_task, s_val, s_mode, s_prob, s_ctr;
   const int tid = threadIdx.x;
   const uint64_t deadline = __builtin_amdgcn_s_memrealtime() + kDeadlineTicks;
   // Each system has its own ticket counter and task order. A workgroup visits the systems in a
@@ -756,6 +795,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         const CholArgs& Q = B.p[prob];
         int* ctr = chol_sync(Q.flags, Q.nb).ctr;
         const int need = crit_ticket(chain, Q.nb);
+        if (ctr_seen < need) ctr_seen = max(ctr_seen, s_ctr);  // the look ahead's reading
         if (ctr_seen < need) ctr_seen = ld_flag(ctr);
         const int c0 = ctr_seen;
         if (c0 >= need) {
@@ -823,14 +863,15 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
       __syncthreads();
       if (j >= 1) {
         // L_{j,j-1} = C_{j,j-1} Linv_{j-1}^T: wavefront g computes rows 16 g .. 16 g + 15 (four
-        // 16 x 16 tiles), then overwrites those rows of X and stores them
+        // 16 x 16 tiles), then overwrites those rows of X and stores them. Linv is lower
+        // triangular, so column block c only sums over the blocks k0 <= 16 c.
         const int g = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
         floatx4 t4[4];
 #pragma unroll
         for (int c = 0; c < 4; c++) {
           floatx4 a4 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int k0 = 0; k0 < NB; k0 += 16) a4 = mm16_abt<LDS_LD, LDS_LD>(&X[16 * g][k0], &Z[16 * c][k0], a4);
+          for (int k0 = 0; k0 <= 16 * c; k0 += 16) a4 = mm16_abt<LDS_LD, LDS_LD>(&X[16 * g][k0], &Z[16 * c][k0], a4);
           t4[c] = a4;
         }
 #pragma unroll
@@ -847,19 +888,29 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
       }
       // Z = Linv_j, kept for step j + 1; for j >= 1 the update C_jj -= L_{j,j-1} L_{j,j-1}^T is folded
       // into the factorisation's first phase, which also publishes L_{j,j-1}
-      const bool ok = (j >= 1) ? potrf_trtri64(Y, Z, &X[0][0], X, S.fin + (size_t)j * nb + (j - 1), epoch)
-                               : potrf_trtri64(Y, Z, &X[0][0]);
+      // the look ahead: the next step's partial tiles (from step 2 on) and the ticket counter
+      ChainPoll poll;
+      poll.f0 = (j + 1 >= 2 && j + 1 < nb) ? S.pdiag + j + 1 : nullptr;
+      poll.f1 = (j + 1 >= 2 && j + 1 < nb) ? S.psub + j + 1 : nullptr;
+      poll.ctr = S.ctr;
+      poll.epoch = epoch;
+      poll.s_ready = &s_val;
+      poll.s_ctr = &s_ctr;
+      const bool ok = (j >= 1) ? potrf_trtri64(Y, Z, &X[0][0], X, S.fin + (size_t)j * nb + (j - 1), epoch, &poll)
+                               : potrf_trtri64(Y, Z, &X[0][0], nullptr, nullptr, 0, &poll);
       float* Lj = P.Linv + (size_t)j * NB * NB;
       for (int e = tid; e < NB * NB / 4; e += 256) {
         const int r = e >> 4, cc = 4 * (e & 15);
         *reinterpret_cast<float4*>(Lj + r * NB + cc) = make_float4(Z[r][cc], Z[r][cc + 1], Z[r][cc + 2], Z[r][cc + 3]);
       }
       if (tid == 0 && !ok) P.sc->chol_fail = 1;
-      // Look once for the next step's partial tiles; if they are ready, their loads overlap the
-      // completion of the Linv_j stores that the publication below waits for.
+      // If the look ahead did not find the next step's partial tiles ready, look once more; if they
+      // are, their loads overlap the completion of the Linv_j stores that the publication below
+      // waits for.
       if (j + 1 < nb) {
-        bool ready = true;
-        if (j + 1 >= 2) {
+        bool ready = s_val != 0;
+        if (!ready) {
+          __syncthreads();  // every thread has read s_val
           if (tid == 0) {
             const int v0 = ld_flag(S.pdiag + j + 1), v1 = ld_flag(S.psub + j + 1);
             const bool r = (v0 == epoch) && (v1 == epoch);
@@ -883,7 +934,10 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
       if (i == 0) {  // this workgroup runs the system's critical chain
         chain = 0;
         chain_p = prob;
-        if (tid == 0) ctr_seen = 0;
+        if (tid == 0) {
+          ctr_seen = 0;
+          s_ctr = 0;
+        }
       }
       continue;
     }
