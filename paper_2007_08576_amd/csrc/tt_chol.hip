@@ -758,6 +758,19 @@ struct CholBatch {
 
 enum { MODE_EXIT = 3 };
 
+// What thread 0 needs of a system to claim its tasks, kept in registers (reading the kernel
+// arguments with a per-thread index costs a memory round trip).
+struct SysRef {
+  int* ctr;
+  const int* abort_;
+  int ntasks, epoch, nb;
+};
+__device__ __forceinline__ SysRef sys_ref(const CholBatch& B, int q) {
+  const CholArgs& Q = B.p[q];
+  const CholSync S = chol_sync(Q.flags, Q.nb);
+  return SysRef{S.ctr, S.abort_, Q.ntasks, Q.epoch, Q.nb};
+}
+
 __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
   __shared__ __attribute__((aligned(16))) float X[NB][LDS_LD];
   __shared__ __attribute__((aligned(16))) float Y[NB][LDS_LD];
@@ -780,6 +793,8 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
   // never wait on each other, so every wait ends whatever the number of resident workgroups.
   int cur = (int)blockIdx.x % B.nprob;  // thread 0: system being claimed from
   int vis = 0;                          // thread 0: systems whose counter this workgroup exhausted
+  SysRef qc = {}, qh = {};              // thread 0: the chain's system and system cur
+  if (tid == 0) qh = sys_ref(B, cur);
   int chain = -1, chain_p = 0;
   int ctr_seen = 0;          // thread 0: last counter value read by the chain (the counter only grows)
   bool have_pref = false;    // the chain's inputs for its next step are already in cva / ccp
@@ -791,10 +806,11 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
       int t = -1, mode = MODE_TASK, prob = cur;
       bool chain_fast = false;
       if (chain >= 0) {
+        // the chain's system fields are kept in registers: reading them from the kernel
+        // arguments here, in code only thread 0 runs, would cost a memory round trip per step
         prob = chain_p;
-        const CholArgs& Q = B.p[prob];
-        int* ctr = chol_sync(Q.flags, Q.nb).ctr;
-        const int need = crit_ticket(chain, Q.nb);
+        int* ctr = qc.ctr;
+        const int need = crit_ticket(chain, qc.nb);
         if (ctr_seen < need) ctr_seen = max(ctr_seen, s_ctr);  // the look ahead's reading
         if (ctr_seen < need) ctr_seen = ld_flag(ctr);
         const int c0 = ctr_seen;
@@ -812,22 +828,23 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
       } else if (vis >= B.nprob) {
         mode = MODE_EXIT;
       } else {
-        const CholArgs& Q = B.p[prob];
-        int* ctr = chol_sync(Q.flags, Q.nb).ctr;
-        t = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (t >= Q.ntasks) {
-          if (t == Q.ntasks + (int)gridDim.x - 1) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the abort word is read in the same round trip as the claim
+        const int ab = ld_flag(qh.abort_);
+        t = __hip_atomic_fetch_add(qh.ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t >= qh.ntasks) {
+          if (t == qh.ntasks + (int)gridDim.x - 1) __hip_atomic_store(qh.ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           vis++;
           cur = (cur + 1 == B.nprob) ? 0 : cur + 1;
+          if (vis < B.nprob) qh = sys_ref(B, cur);
           mode = MODE_RETRY;
         }
+        s_val = (mode == MODE_TASK) && (ab == qh.epoch);
       }
       s_task = t;
       s_mode = mode;
       s_prob = prob;
-      // the chain's waits watch the abort word themselves; skip the extra round trip on its path
-      const CholArgs& Q = B.p[prob];
-      s_val = (chain_fast || mode != MODE_TASK) ? 0 : (ld_flag(chol_sync(Q.flags, Q.nb).abort_) == Q.epoch);
+      // the chain's waits watch the abort word themselves; a task the chain claims checks it here
+      if (chain >= 0) s_val = (chain_fast || mode != MODE_TASK) ? 0 : (ld_flag(qc.abort_) == qc.epoch);
     }
     __syncthreads();
     const int t = s_task, mode = s_mode, prob = s_prob;
@@ -935,6 +952,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         chain = 0;
         chain_p = prob;
         if (tid == 0) {
+          qc = sys_ref(B, prob);
           ctr_seen = 0;
           s_ctr = 0;
         }
