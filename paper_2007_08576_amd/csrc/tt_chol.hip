@@ -812,18 +812,25 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         int* ctr = qc.ctr;
         const int need = crit_ticket(chain, qc.nb);
         if (ctr_seen < need) ctr_seen = max(ctr_seen, s_ctr);  // the look ahead's reading
-        if (ctr_seen < need) ctr_seen = ld_flag(ctr);
-        const int c0 = ctr_seen;
-        if (c0 >= need) {
+        if (ctr_seen >= need) {
           mode = MODE_CRIT;
           chain_fast = true;
         } else {
-          int expect = c0;
-          mode = __hip_atomic_compare_exchange_strong(ctr, &expect, c0 + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT)
-                     ? MODE_TASK
-                     : MODE_RETRY;
-          t = c0;
+          // Only this path waits for memory, and the wait stays inside it (the previous step's
+          // flag store may still be in flight, and a wait here would wait for it too).
+          const int c0 = ld_flag(ctr);
+          ctr_seen = c0;
+          if (c0 >= need) {
+            mode = MODE_CRIT;
+            chain_fast = true;
+          } else {
+            int expect = c0;
+            mode = __hip_atomic_compare_exchange_strong(ctr, &expect, c0 + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)
+                       ? MODE_TASK
+                       : MODE_RETRY;
+            t = c0;
+          }
         }
       } else if (vis >= B.nprob) {
         mode = MODE_EXIT;
