@@ -219,8 +219,9 @@ constexpr int POTRF_SCRATCH_FLOATS = 12 * 16 * XS;
 // of Li that is not positive and finite). All 256 threads must call it.
 // Optionally (U non-null) the block is first updated, L -= U U^T with U the 64 x 64 tile in LDS:
 // wavefront 0 updates only tile (0, 0) before leaf 0 and the others update the remaining nine lower
-// tiles meanwhile. When pub is non-null, every wavefront's earlier global stores are completed
-// before the end of that first phase and thread 64 then raises *pub = epoch (release). Scratch is
+// tiles meanwhile. When pub is non-null, each wavefront completes its earlier global stores as soon
+// as its part of that first phase is done, and the last of the four raises *pub = epoch (release,
+// counted in the LDS word *pub_cnt, which must be 0 on entry and is 0 again on return). Scratch is
 // first written after that phase, so U may share its memory.
 // A look ahead that one idle thread runs during the factorisation's fourth phase: it reads the
 // ticket counter into *s_ctr and whether both flags f0, f1 (if non-null) equal epoch into *s_ready,
@@ -246,9 +247,24 @@ __device__ __forceinline__ void chain_poll(const ChainPoll& q) {
   *q.s_ready = r ? 1 : 0;
 }
 
+// One wavefront's share of a block-wide publication: its stores complete, then it counts itself in
+// *cnt (LDS); the fourth to arrive resets the count and raises *flag = epoch (release at agent
+// scope, which writes back the L2 that holds every wavefront's completed stores).
+__device__ __forceinline__ void wave_publish(int* cnt, int* flag, int epoch) {
+  __builtin_amdgcn_s_waitcnt(0);
+  if ((threadIdx.x & 63) == 0) {
+    const int prev = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (prev == 3) {
+      __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LDS_LD], float* scratch,
                                               const float (*U)[LDS_LD] = nullptr, int* pub = nullptr,
-                                              int pub_epoch = 0, const ChainPoll* poll = nullptr) {
+                                              int pub_epoch = 0, const ChainPoll* poll = nullptr,
+                                              int* pub_cnt = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // scratch tiles: 0 = X10, 1 = X20, 2 = X30, 3 = X21, 4 = X31, 5 = X32, then the sums S_rc
   enum { S10 = 6, S20, S21, S30, S31, S32 };
@@ -276,6 +292,7 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
   // the upper tiles of Li
   if (wave == 0) {
     if (U) updU(0, 0);
+    if (pub) wave_publish(pub_cnt, pub, pub_epoch);
     leaf16(L, Li, 0);
   } else {
     if (U) {
@@ -293,6 +310,7 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
         updU(3, 3);
       }
     }
+    if (pub) wave_publish(pub_cnt, pub, pub_epoch);
     for (int e = tid - 64; e < 6 * 256; e += 192) {
       const int t = e >> 8, w = e & 255;
       const int r = (t < 3) ? 0 : (t < 5 ? 1 : 2);
@@ -300,9 +318,7 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
       Li[16 * r + (w >> 4)][16 * c + (w & 15)] = 0.0f;
     }
   }
-  if (pub) __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (pub && tid == 64) __hip_atomic_store(pub, pub_epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   // phase 2: leaf 1; X_r0, trailing updates
   if (wave == 0) {
     makeX(1, 0, 0);
@@ -776,9 +792,10 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
   __shared__ __attribute__((aligned(16))) float Y[NB][LDS_LD];
   __shared__ __attribute__((aligned(16))) float Z[NB][LDS_LD];  // the chain's Linv_{j-1} between CRIT steps
   static_assert(POTRF_SCRATCH_FLOATS <= NB * LDS_LD, "factorisation scratch must fit in one tile buffer");
-  __shared__ int s_task, s_val, s_mode, s_prob, s_ctr;
+  __shared__ int s_task, s_val, s_mode, s_prob, s_ctr, s_pubcnt;
   const int tid = threadIdx.x;
   const uint64_t deadline = __builtin_amdgcn_s_memrealtime() + kDeadlineTicks;
+  if (tid == 0) s_pubcnt = 0;
   // Each system has its own ticket counter and task order. A workgroup visits the systems in a
   // cyclic order starting at blockIdx % nprob, claiming tasks from one until its counter runs out
   // (one failing claim per system per workgroup, so the claim that returns ntasks + gridDim - 1
@@ -920,7 +937,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
       poll.epoch = epoch;
       poll.s_ready = &s_val;
       poll.s_ctr = &s_ctr;
-      const bool ok = (j >= 1) ? potrf_trtri64(Y, Z, &X[0][0], X, S.fin + (size_t)j * nb + (j - 1), epoch, &poll)
+      const bool ok = (j >= 1) ? potrf_trtri64(Y, Z, &X[0][0], X, S.fin + (size_t)j * nb + (j - 1), epoch, &poll, &s_pubcnt)
                                : potrf_trtri64(Y, Z, &X[0][0], nullptr, nullptr, 0, &poll);
       float* Lj = P.Linv + (size_t)j * NB * NB;
       for (int e = tid; e < NB * NB / 4; e += 256) {
