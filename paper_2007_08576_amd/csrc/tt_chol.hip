@@ -176,18 +176,38 @@ __device__ __forceinline__ void leaf16(float (*L)[LDS_LD], float (*Li)[LDS_LD], 
 // 16 x 16 tile products on the matrix cores (v_mfma_f32_16x16x4f32), row-major tiles in LDS with
 // strides given as template arguments. acc element q of lane (li, lk) = (lane % 16, lane / 16) is
 // entry (4 lk + q, li).
+// The operand loads of a product are all issued before its first MFMA (a scheduling barrier keeps
+// the compiler from pairing each load with its MFMA, which costs one LDS round trip per MFMA when
+// registers are scarce). nk = number of 16-wide reduction blocks (a compile-time value after
+// unrolling at every call site).
 template <int SA, int SB>
-__device__ __forceinline__ floatx4 mm16_abt(const float* A, const float* B, floatx4 acc) {  // acc += A B^T
+__device__ __forceinline__ floatx4 mm16_abt(const float* A, const float* B, floatx4 acc, int nk = 1) {  // acc += A B^T
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  float a[16], b[16];
 #pragma unroll
-  for (int kk = 0; kk < 16; kk += 4) acc = MFMA16(A[li * SA + kk + lk], B[li * SB + kk + lk], acc);
+  for (int t = 0; t < 16; t++)
+    if (t < 4 * nk) {
+      a[t] = A[li * SA + 4 * t + lk];
+      b[t] = B[li * SB + 4 * t + lk];
+    }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int t = 0; t < 16; t++)
+    if (t < 4 * nk) acc = MFMA16(a[t], b[t], acc);
   return acc;
 }
 template <int SA, int SB>
 __device__ __forceinline__ floatx4 mm16_ab(const float* A, const float* B, floatx4 acc) {  // acc += A B
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  float a[4], b[4];
 #pragma unroll
-  for (int kk = 0; kk < 16; kk += 4) acc = MFMA16(A[li * SA + kk + lk], B[(kk + lk) * SB + li], acc);
+  for (int t = 0; t < 4; t++) {
+    a[t] = A[li * SA + 4 * t + lk];
+    b[t] = B[(4 * t + lk) * SB + li];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int t = 0; t < 4; t++) acc = MFMA16(a[t], b[t], acc);
   return acc;
 }
 template <int SC>
@@ -282,10 +302,7 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
   auto finish = [&](int r, int c, int sid) { put16<LDS_LD>(Lit(r, c), mm16_ab<LDS_LD, XS>(Lit(r, r), Xt(sid), z4), -1.0f); };
   // T_rc -= U_r U_c^T over the 64-wide reduction (the block update folded into phase 1)
   auto updU = [&](int r, int c) {
-    floatx4 acc = z4;
-#pragma unroll
-    for (int k0 = 0; k0 < NB; k0 += 16) acc = mm16_abt<LDS_LD, LDS_LD>(&U[16 * r][k0], &U[16 * c][k0], acc);
-    sub16<LDS_LD>(Lt(r, c), acc);
+    sub16<LDS_LD>(Lt(r, c), mm16_abt<LDS_LD, LDS_LD>(&U[16 * r][0], &U[16 * c][0], z4, NB / 16));
   };
   floatx4 s3 = z4;  // S_31 (wavefront 1) or S_30 (wavefront 2), carried from phase 3 to phase 4
   // phase 1: (update tile (0, 0)) leaf 0; the other wavefronts update the other tiles and clear
@@ -910,10 +927,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         floatx4 t4[4];
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-          floatx4 a4 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int k0 = 0; k0 <= 16 * c; k0 += 16) a4 = mm16_abt<LDS_LD, LDS_LD>(&X[16 * g][k0], &Z[16 * c][k0], a4);
-          t4[c] = a4;
+          t4[c] = mm16_abt<LDS_LD, LDS_LD>(&X[16 * g][0], &Z[16 * c][0], floatx4{0.f, 0.f, 0.f, 0.f}, c + 1);
         }
 #pragma unroll
         for (int c = 0; c < 4; c++)
