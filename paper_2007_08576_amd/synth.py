@@ -10,7 +10,11 @@ The paper evaluates on stereo laparoscope videos, the Hamlyn phantom and an EM-t
   points, 400 control points, 2,000 features (30 % outliers), a sequence of frames deformed by
   six oscillating Gaussian bumps whose largest per-frame motion is 15 mm, feature positions
   lifted from the rendered depth;
-* config 3 -- config 2 with 1,500 control points and 100,000 template points.
+* config 3 -- config 2 with 1,500 control points and 100,000 template points;
+* config 4 -- 16 streams of uneven size (see make_config4);
+* config 5 -- 64 stressed streams (see make_config5): in a fifth of the frames 60 % of the matches
+  are outliers, 30 % of the depth pixels are occluded by smoke-like blobs, and the camera jumps
+  10 deg / 20 mm.
 
 This module holds only the workload recipe (surfaces, warps, a z-buffered mesh rasteriser and
 descriptor noise); none of the tracking method's arithmetic. Every draw comes from a
@@ -195,6 +199,7 @@ class Frame:
     feat_desc: np.ndarray   # (K2, 32) uint8
     gt_vertices: np.ndarray  # (M, 3) float64 ground-truth positions of the template points
     inlier_of: np.ndarray   # (K2,) template feature index of an inlier, -1 for an outlier
+    stressed: bool = False   # a stressed frame (config 5)
 
 
 @dataclasses.dataclass
@@ -290,10 +295,49 @@ def make_config1(seed: int = 1) -> Scene:
                  frame_fn)
 
 
+@dataclasses.dataclass
+class Stress:
+    """Stressed frames (config 5): each frame is stressed with probability prob (a draw keyed by the
+    frame); a stressed frame has outlier_frac of its matches outliers, exactly invalid_frac of its
+    pixels invalid (the largest values of a sum of n_blobs Gaussian blobs with radii U[20, 80] px,
+    ties to the lower pixel index), and is seen from the stream's second camera pose: the scene
+    rotated by angle_deg about a random axis through the template centroid and moved by shift_mm."""
+    prob: float = 0.2
+    outlier_frac: float = 0.6
+    invalid_frac: float = 0.3
+    n_blobs: int = 8
+    angle_deg: float = 10.0
+    shift_mm: float = 20.0
+
+
+def stressed_frame(seed: int, name: str, t: int, prob: float) -> bool:
+    """Whether frame t of the sequence (seed, name) is stressed (one draw keyed by the frame)."""
+    return bool(Rng(seed, f"{name}/stress/{t}").uniform(1)[0] < prob)
+
+
+def blob_mask(rng: Rng, width: int, height: int, frac: float, n_blobs: int) -> np.ndarray:
+    """(H, W) bool: exactly round(frac * W * H) pixels, those with the largest sum of random
+    Gaussian blobs (centres uniform in the image, radii U[20, 80] px at 640 wide)."""
+    cu = rng.uniform(n_blobs, 0.0, width)
+    cv = rng.uniform(n_blobs, 0.0, height)
+    rad = rng.uniform(n_blobs, 20.0, 80.0) * (width / 640.0)
+    amp = rng.uniform(n_blobs, 0.5, 1.0)
+    u = np.arange(width, dtype=np.float64)[None, :, None]
+    v = np.arange(height, dtype=np.float64)[:, None, None]
+    f = (amp * np.exp(-((u - cu) ** 2 + (v - cv) ** 2) / (2 * rad ** 2))).sum(-1).ravel()
+    n = int(round(frac * width * height))
+    order = np.lexsort((np.arange(f.size), -f))  # largest first, ties to the lower index
+    m = np.zeros(f.size, bool)
+    m[order[:n]] = True
+    return m.reshape(height, width)
+
+
 def make_sequence(seed: int = 2, M: int = 30000, N: int = 400, K1: int = 2000,
                   outlier_frac: float = 0.30, width: int = 640, height: int = 480,
-                  n_frames: int = 300, max_step_mm: float = 15.0, name: str = "config2") -> Scene:
-    """Gaussian-dent surface and an oscillating six-bump deformation sequence (config 2/3)."""
+                  n_frames: int = 300, max_step_mm: float = 15.0, name: str = "config2",
+                  stress: Stress | None = None) -> Scene:
+    """Gaussian-dent surface and an oscillating six-bump deformation sequence (config 2/3); with
+    stress, some frames are stressed as described by Stress (config 5)."""
     K = intrinsics_for(width, height)
     W, H = width, height
     rng = Rng(seed, f"{name}/surface")
@@ -345,15 +389,30 @@ def make_sequence(seed: int = 2, M: int = 30000, N: int = 400, K1: int = 2000,
         return x + (disp_coeff(x) * (amp * osc(t))[None, :]) @ dirs
 
     n_out = int(round(outlier_frac * K1))
+    if stress is not None:
+        rc = Rng(seed, f"{name}/camera")
+        cam_R = rotation_matrix(rc.unit_vectors(1)[0], math.radians(stress.angle_deg))
+        cam_t = stress.shift_mm * rc.unit_vectors(1)[0]
+        centroid = pts.astype(np.float64).mean(0)
 
     def frame_fn(t):
-        Pt = G(P0.reshape(-1, 3), t).reshape(H, W, 3)
+        hard = stress is not None and stressed_frame(seed, name, t, stress.prob)
+
+        def Gc(x):  # the deformed scene in this frame's camera coordinates
+            y = G(x, t)
+            return (y - centroid) @ cam_R.T + centroid + cam_t if hard else y
+
+        Pt = Gc(P0.reshape(-1, 3)).reshape(H, W, 3)
         depth = render_depth(Pt, K)
+        if hard:
+            occ = blob_mask(Rng(seed, f"{name}/occlusion/{t}"), W, H, stress.invalid_frac, stress.n_blobs)
+            depth = np.where(occ, np.float32(0.0), depth).astype(np.float32)
         tP = backproject_grid(depth, K)
         valid = depth > 0
-        gt_f = G(feat_xyz.astype(np.float64), t)
-        fx, fd, inl = _features(seed, name, t, feat_xyz, feat_desc, gt_f, tP, valid, n_out, False, K)
-        return Frame(depth, fx, fd, G(pts.astype(np.float64), t), inl)
+        gt_f = Gc(feat_xyz.astype(np.float64))
+        n_o = int(round(stress.outlier_frac * K1)) if hard else n_out
+        fx, fd, inl = _features(seed, name, t, feat_xyz, feat_desc, gt_f, tP, valid, n_o, False, K)
+        return Frame(depth, fx, fd, Gc(pts.astype(np.float64)), inl, hard)
 
     return Scene(name, K, N, pts.astype(np.float32), feat_xyz.astype(np.float32), feat_desc,
                  n_frames, frame_fn)
@@ -384,6 +443,41 @@ def make_config4(seed: int = 4, n_streams: int = 16, n_frames: int = 300):
                                     outlier_frac=out, width=W, height=H, n_frames=n_frames,
                                     name=f"config4/{q}"))
     return scenes
+
+
+def config5_stream(seed: int, q: int, n_frames: int = 300) -> Scene:
+    """Stream q of config 5 (seeded 1000 * seed + q): 640 x 480, N ~ U{200..1500} control points,
+    M = W * H / 10 template points, 2,000 features with 30 % outliers, stressed frames as Stress()."""
+    rng = Rng(1000 * seed + q, "config5/stream")
+    N = 200 + int(rng.uniform(1, 0.0, 1301.0)[0])
+    return make_sequence(seed=1000 * seed + q, M=640 * 480 // 10, N=min(N, 1500), K1=2000,
+                         outlier_frac=0.3, width=640, height=480, n_frames=n_frames,
+                         name=f"config5/{q}", stress=Stress())
+
+
+@dataclasses.dataclass
+class StreamSpec:
+    """What a stream needs of a Scene, without its frame generator (picklable)."""
+    num_control_points: int
+    intr: Intrinsics
+    pts: np.ndarray
+    feat_xyz: np.ndarray
+    feat_desc: np.ndarray
+
+
+def config5_arrays(seed: int, q: int, n_frames: int):
+    """Config 5 stream q as plain arrays: (StreamSpec, [(depth, feat_xyz, feat_desc)] for frames
+    1 .. n_frames, number of stressed frames among them). For generating streams in worker
+    processes."""
+    sc = config5_stream(seed, q, n_frames=300)
+    frs = [sc.frame(t) for t in range(1, n_frames + 1)]
+    spec = StreamSpec(sc.num_control_points, sc.intr, sc.pts, sc.feat_xyz, sc.feat_desc)
+    return spec, [(f.depth, f.feat_xyz, f.feat_desc) for f in frs], sum(f.stressed for f in frs)
+
+
+def make_config5(seed: int = 5, n_streams: int = 64, n_frames: int = 300):
+    """Stress serving (config 5): n_streams streams from config5_stream."""
+    return [config5_stream(seed, q, n_frames) for q in range(n_streams)]
 
 
 def make_small_sequence(seed: int = 11, M: int = 2000, N: int = 48, K1: int = 300,

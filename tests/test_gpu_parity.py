@@ -196,6 +196,31 @@ def test_sequence_teacher_forced(O, T):
         assert _rms(vo, vg) <= RMS_TOL_MM
 
 
+def test_stressed_frames_teacher_forced(O, T):
+    """Config 5's stressed frames (60 % outlier matches, 30 % of the pixels occluded, the camera
+    10 deg / 20 mm away) on a reduced stream: the frame before a stressed one, the stressed one and
+    the one after, each from the oracle's state."""
+    st = synth.Stress()
+    sc = synth.make_sequence(seed=77, M=2000, N=48, K1=300, width=160, height=120, n_frames=40,
+                             max_step_mm=3.0, name="s5", stress=st)
+    t1 = next(t for t in range(2, 40) if synth.stressed_frame(77, "s5", t, st.prob)
+              and not synth.stressed_frame(77, "s5", t + 1, st.prob))
+    so, sg = _pair(O, T, sc, seed=7)
+    for t in (t1 - 1, t1, t1 + 1):
+        fr = sc.frame(t)
+        dq, f = so.get_state()
+        sg.set_state(dq, f)
+        vo, qo, do = so.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+        vg, qg, dg = sg.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+        print(f"frame {t} stressed={fr.stressed}: rms {_rms(vo, vg):.2e} mm, "
+              f"truth rms gpu {_rms(vg, fr.gt_vertices):.3f}", flush=True)
+        assert np.array_equal(do["match_idx"], dg["match_idx"])
+        amb = _near_threshold(do["wstar"], 0.5)
+        assert np.array_equal(do["preselected"][~amb], dg["preselected"][~amb])
+        assert np.array_equal(do["hyp_k0"], dg["hyp_k0"])
+        assert _rms(vo, vg) <= RMS_TOL_MM
+
+
 # ------------------------------------------------------------------------------------------------
 # degenerate inputs
 

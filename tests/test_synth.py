@@ -67,3 +67,47 @@ def test_rng_uniform_range_and_choice():
     assert u.min() >= 0 and u.max() < 1 and abs(u.mean() - 0.5) < 0.02
     c = synth.Rng(5, "y").choice(100, 30)
     assert len(set(c.tolist())) == 30
+
+
+def test_blob_mask_is_exact_and_seeded():
+    m = synth.blob_mask(synth.Rng(3, "t"), 160, 120, 0.3, 8)
+    assert m.shape == (120, 160) and m.sum() == round(0.3 * 160 * 120)
+    assert np.array_equal(m, synth.blob_mask(synth.Rng(3, "t"), 160, 120, 0.3, 8))
+    assert not np.array_equal(m, synth.blob_mask(synth.Rng(4, "t"), 160, 120, 0.3, 8))
+
+
+def test_stressed_frames_config5_recipe():
+    """A fifth of the frames are stressed; a stressed frame has 60 % outliers, at least 30 % of its
+    pixels invalid, and sees the scene from the second camera pose (10 deg about an axis through
+    the template centroid, then 20 mm)."""
+    n = 2000
+    frac = np.mean([synth.stressed_frame(9, "x", t, 0.2) for t in range(1, n + 1)])
+    assert abs(frac - 0.2) < 4 * np.sqrt(0.2 * 0.8 / n)
+    st = synth.Stress()
+    sc = synth.make_sequence(seed=77, M=2000, N=48, K1=300, width=160, height=120, n_frames=40,
+                             max_step_mm=3.0, name="s5", stress=st)
+    t = next(t for t in range(2, 41) if synth.stressed_frame(77, "s5", t, st.prob))
+    fr = sc.frame(t)
+    assert fr.stressed
+    assert (fr.inlier_of < 0).sum() == round(0.6 * 300)
+    assert (fr.depth == 0).mean() >= 0.3
+    # the same frame without stress differs by the camera's rigid motion only
+    plain = synth.make_sequence(seed=77, M=2000, N=48, K1=300, width=160, height=120, n_frames=40,
+                                max_step_mm=3.0, name="s5").frame(t)
+    assert not plain.stressed and (plain.inlier_of < 0).sum() == round(0.3 * 300)
+    P, Q = plain.gt_vertices, fr.gt_vertices
+    Pc, Qc = P - P.mean(0), Q - Q.mean(0)
+    U, _, Vt = np.linalg.svd(Qc.T @ Pc)
+    R = U @ np.diag([1, 1, np.linalg.det(U @ Vt)]) @ Vt
+    assert np.allclose(Pc @ R.T, Qc, atol=1e-9)
+    ang = np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1)))
+    assert abs(ang - st.angle_deg) < 1e-6
+    c = sc.pts.astype(np.float64).mean(0)
+    shift = (Q - ((P - c) @ R.T + c)).mean(0)
+    assert abs(np.linalg.norm(shift) - st.shift_mm) < 1e-6
+
+
+def test_config5_stream_sizes():
+    sc = synth.config5_stream(5, 0, n_frames=3)
+    assert 200 <= sc.num_control_points <= 1500 and sc.pts.shape[0] == 640 * 480 // 10
+    assert sc.intr.width == 640 and sc.feat_xyz.shape[0] == 2000
