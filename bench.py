@@ -85,7 +85,7 @@ def _streams_for(tt, scenes, precision, budget):
 
 
 def _serving_compare(args, torch, tt, scenes, frames_np, order, hz_list, seconds):
-    """Plain per-stream path (each stream on its own HIP stream through tt_track_frame_device, FP32)
+    """Plain per-stream path (each stream on its own HIP stream through tt_track_frame_device_ev, FP32)
     against the batched path (tt_track_batch_device over every stream with a frame waiting) in FP32
     and in the mixed form (bfloat16 tile products + FP64-residual refinement): frames/s at
     saturation, and the mixed form's vertices against the plain FP32 ones on the first frame. Then
@@ -95,6 +95,8 @@ def _serving_compare(args, torch, tt, scenes, frames_np, order, hz_list, seconds
     frames_np[q] holds stream q's frames (depth, feat_xyz, feat_desc), replayed in `order`."""
     dev = torch.device("cuda:0")
     frames = [[tuple(torch.from_numpy(a).to(dev) for a in f) for f in fl] for fl in frames_np]
+    inputs_ready = torch.cuda.Event()  # the replayed inputs are resident from here on
+    inputs_ready.record()
     budget = args.serving_hbm_gib * (1 << 30)
     res, first, used_bytes, poisson = {}, {}, {}, []
     S = None
@@ -108,7 +110,7 @@ def _serving_compare(args, torch, tt, scenes, frames_np, order, hz_list, seconds
 
         def fr(q, k):
             d = frames[idx[q]][order[k % len(order)]]
-            return (d[0], d[1], d[2], d[1].shape[0], outs[q][0], outs[q][1])
+            return (d[0], d[1], d[2], d[1].shape[0], outs[q][0], outs[q][1], inputs_ready)
 
         def one_round(k, sel=None):
             sel = list(range(S)) if sel is None else sel
@@ -403,9 +405,14 @@ def main():
     ov = torch.empty((M, 3), dtype=torch.float32, device=dev)
     oq = torch.empty((N, 8), dtype=torch.float32, device=dev)
 
+    # the inputs are resident before the timed region: one event marks them ready, so that each
+    # frame's matching and pre-selection may overlap the previous frame's solve
+    inputs_ready = torch.cuda.Event()
+    inputs_ready.record()
+
     def step(k):
         d = dframes[order[k % len(order)]]
-        s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], ov, oq)
+        s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], ov, oq, inputs_ready=inputs_ready)
 
     for k in range(args.warmup):
         step(k)
@@ -476,6 +483,9 @@ def main():
                    "mode": "plain", "frames_replayed": len(frames)},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
+        "latency_note": "p50/p99: events on the library's stream before and after each frame's call, i.e. the "
+                        "frame's LM solve; its matching and pre-selection (front stage) run on a second HIP "
+                        "stream overlapping the previous frame and are in stage_us['front']",
         "gn_iters_per_s": fps * params.lm_iters,
         "arap_pairs_per_s": fps * params.lm_iters * pairs,
         "stage_us": {k: v["ms_per_call"] * 1e3 for k, v in stages.items()},

@@ -132,6 +132,16 @@ int tt_track_frame(tt_stream* s, const float* depth, const float* feat_xyz, cons
 int tt_track_frame_device(tt_stream* s, const float* d_depth, const float* d_feat_xyz,
                           const uint8_t* d_feat_desc, int K2, float* d_out_vertices, float* d_out_dq);
 
+/* As tt_track_frame_device, except that the frame's inputs count as ready once the HIP event
+ * inputs_ready (a hipEvent_t the caller recorded after writing them; NULL: as
+ * tt_track_frame_device) has completed, not after all work queued earlier on the stream's HIP
+ * stream. The frame's normal map, matching and pre-selection then run on a second HIP stream of
+ * the library's while the stream's previous frame is still being solved; its LM iterations start
+ * after that frame's, as always. */
+int tt_track_frame_device_ev(tt_stream* s, const float* d_depth, const float* d_feat_xyz,
+                             const uint8_t* d_feat_desc, int K2, float* d_out_vertices, float* d_out_dq,
+                             const void* inputs_ready);
+
 /* One frame for each of several streams, all arrays in device memory (as for
  * tt_track_frame_device). */
 typedef struct {
@@ -141,6 +151,8 @@ typedef struct {
   int K2;
   float* out_vertices;      /* [M][3] float32 or NULL                                           */
   float* out_dq;            /* [N][8] float32 or NULL                                           */
+  const void* inputs_ready; /* hipEvent_t after which the inputs are written (as
+                               tt_track_frame_device_ev), or NULL                                */
 } tt_frame_device;
 
 /* Batched form of tt_track_frame_device: the same per-frame solve (Sec. 2) for S distinct streams

@@ -51,11 +51,12 @@ void free_list(std::vector<void*>& list, uint64_t& bytes) {
 
 void free_template(tt_stream* s) {
   if (s->st) (void)hipStreamSynchronize(s->st);
+  if (s->st_front) (void)hipStreamSynchronize(s->st_front);
   free_list(s->allocs_template, s->bytes_template);
   DevState& d = s->d;
   int HW = d.HW, K2cap = d.K2cap;
   float* depth = d.depth;
-  float4* nmap = d.nmap;
+  float4* nmap = d.nmap_b;
   float* f2xyz = d.f2xyz;
   uint32_t* f2desc = d.f2desc;
   LMScalars* sc = d.sc;
@@ -64,7 +65,7 @@ void free_template(tt_stream* s) {
   const int cus = d.num_cus, prec = d.prec, ir = d.ir_iters;
   d = DevState();
   d.num_cus = cus; d.prec = prec; d.ir_iters = ir;
-  d.HW = HW; d.K2cap = K2cap; d.depth = depth; d.nmap = nmap; d.f2xyz = f2xyz; d.f2desc = f2desc;
+  d.HW = HW; d.K2cap = K2cap; d.depth = depth; d.nmap_b = nmap; d.nmap = nmap; d.f2xyz = f2xyz; d.f2desc = f2desc;
   d.sc = sc; d.log_cost_old = lo; d.log_cost_new = ln; d.log_lambda = ll; d.log_accept = la;
   s->has_template = false;
 }
@@ -196,16 +197,59 @@ DevState frame_view(tt_stream* s, const float* depth, const float* xyz, const ui
 }
 
 // Normal map, matching, pre-selection, LM set-up.
-int enqueue_front(tt_stream* s, DevState& dd, int K2, hipStream_t st) {
+// The side stream and the per-set events of the front stage, created on first use.
+int ensure_front_stream(tt_stream* s) {
+  if (s->st_front) return TT_OK;
+  HIPCHK(hipStreamCreateWithFlags(&s->st_front, hipStreamNonBlocking));
+  for (int f = 0; f < 2; f++) {
+    HIPCHK(hipEventCreateWithFlags(&s->ev_front_done[f], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&s->ev_lm_done[f], hipEventDisableTiming));
+    HIPCHK(hipEventRecord(s->ev_lm_done[f], s->st));  // both sets free
+  }
+  return TT_OK;
+}
+
+// Normal map, matching and pre-selection of this frame on the stream's side HIP stream, into the
+// front-output set of this frame's parity (once the frame before last has finished reading it);
+// then the LM set-up on st, after them. They start once the inputs are ready: after the event
+// inputs_ready when the caller gives one (so that they overlap the previous frame's LM
+// iterations), else after all work queued on st so far.
+int enqueue_front(tt_stream* s, DevState& dd, int K2, hipStream_t st, const void* inputs_ready) {
   const tt_params& P = s->P;
   Intr K = intr_of(s);
-  StageTimer tm(s, TT_STAGE_FRONT, st);
-  HIPCHK(launch_normal_map(dd, K, st));
-  if (s->d.K1 > 0) {
-    HIPCHK(launch_match(dd, K2, P.max_hamming, st));  // K2 == 0: every feature unmatched
-    HIPCHK(launch_preselect(dd, P.ransac_refs, P.ransac_iters, P.H, P.seed, s->frame, st));
+  int rc = ensure_front_stream(s);
+  if (rc) return rc;
+  const int f = (int)(s->frame & 1);
+  select_front_set(s->d, f);
+  select_front_set(dd, f);
+  hipStream_t sf = s->st_front;
+  if (inputs_ready) {
+    HIPCHK(hipStreamWaitEvent(sf, static_cast<hipEvent_t>(const_cast<void*>(inputs_ready)), 0));
+  } else {
+    hipEvent_t ev = nullptr;
+    HIPCHK(ev_sync_get(s, &ev));
+    const bool ok = hipEventRecord(ev, st) == hipSuccess && hipStreamWaitEvent(sf, ev, 0) == hipSuccess;
+    s->ev_sync_pool.push_back(ev);
+    if (!ok) return TT_EDEVICE;
   }
+  HIPCHK(hipStreamWaitEvent(sf, s->ev_lm_done[f], 0));
+  {
+    StageTimer tm(s, TT_STAGE_FRONT, sf);
+    HIPCHK(launch_normal_map(dd, K, sf));
+    if (s->d.K1 > 0) {
+      HIPCHK(launch_match(dd, K2, P.max_hamming, sf));  // K2 == 0: every feature unmatched
+      HIPCHK(launch_preselect(dd, P.ransac_refs, P.ransac_iters, P.H, P.seed, s->frame, sf));
+    }
+  }
+  HIPCHK(hipEventRecord(s->ev_front_done[f], sf));
+  HIPCHK(hipStreamWaitEvent(st, s->ev_front_done[f], 0));
   HIPCHK(launch_lm_begin(s->d, P.lm_lambda0, st));
+  return TT_OK;
+}
+
+// The frame's LM iterations are queued: its front-output set is free once they have run.
+int enqueue_lm_done(tt_stream* s, hipStream_t st) {
+  HIPCHK(hipEventRecord(s->ev_lm_done[s->frame & 1], st));
   return TT_OK;
 }
 
@@ -294,10 +338,10 @@ int enqueue_finish(tt_stream* s, DevState& dd, hipStream_t st) {
 
 // Queue the whole frame. depth/xyz/desc are device pointers.
 int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint8_t* desc, int K2, float* out_xyz,
-                  float* out_dq, bool dbg) {
+                  float* out_dq, bool dbg, const void* inputs_ready = nullptr) {
   hipStream_t st = s->st;
   DevState dd = frame_view(s, depth, xyz, desc);
-  int rc = enqueue_front(s, dd, K2, st);
+  int rc = enqueue_front(s, dd, K2, st, inputs_ready);
   if (rc) return rc;
   for (int it = 0; it < s->P.lm_iters; it++) {
     int epoch = 0;
@@ -310,6 +354,8 @@ int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint
     if (rc) return rc;
   }
   HIPCHK(launch_deform_out(s->d, out_xyz, out_dq, st));
+  rc = enqueue_lm_done(s, st);
+  if (rc) return rc;
   s->frame += 1;
   return TT_OK;
 }
@@ -352,7 +398,7 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
     return TT_OK;
   };
   int rc = fork();
-  for (int q = 0; q < S && !rc; q++) rc = enqueue_front(ss[q], dd[q], fr[q].K2, qs[q]);
+  for (int q = 0; q < S && !rc; q++) rc = enqueue_front(ss[q], dd[q], fr[q].K2, qs[q], fr[q].inputs_ready);
   for (int it = 0; it < ss[0]->P.lm_iters && !rc; it++) {
     for (int q = 0; q < S && !rc; q++) rc = enqueue_assemble(ss[q], dd[q], it, false, qs[q], &epochs[q]);
     if (!rc) rc = join();
@@ -362,6 +408,8 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
   }
   for (int q = 0; q < S && !rc; q++) {
     HIPCHK(launch_deform_out(ss[q]->d, fr[q].out_vertices, fr[q].out_dq, qs[q]));
+    rc = enqueue_lm_done(ss[q], qs[q]);
+    if (rc) break;
     ss[q]->frame += 1;
   }
   if (!rc) rc = join();
@@ -539,7 +587,8 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
   int T = p->lm_iters > 0 ? p->lm_iters : 1;
   int rc = TT_OK;
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.depth, (size_t)d.HW);
-  rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.nmap, (size_t)d.HW);
+  rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.nmap_b, 2 * (size_t)d.HW);
+  if (!rc) d.nmap = d.nmap_b;
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.sc, 1);
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_cost_old, (size_t)T);
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_cost_new, (size_t)T);
@@ -668,9 +717,16 @@ int tt_destroy(tt_stream* s) {
     s->ev_pool.clear();
     for (hipEvent_t e : s->ev_sync_pool) (void)hipEventDestroy(e);
     s->ev_sync_pool.clear();
+    if (s->st_front) (void)hipStreamSynchronize(s->st_front);
     free_template(s);
     free_list(s->allocs_k2, s->bytes_k2);
     free_list(s->allocs_frame, s->bytes_frame);
+    for (int f = 0; f < 2; f++) {
+      if (s->ev_front_done[f]) (void)hipEventDestroy(s->ev_front_done[f]);
+      if (s->ev_lm_done[f]) (void)hipEventDestroy(s->ev_lm_done[f]);
+    }
+    if (s->st_front) (void)hipStreamDestroy(s->st_front);
+    s->st_front = nullptr;
     if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);
     s->st = nullptr;
   }
@@ -750,15 +806,17 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
   ALLOC(allocs_template, bytes_template, d.ndispc, (size_t)N);
   ALLOC(allocs_template, bytes_template, d.midx, K1a);
   ALLOC(allocs_template, bytes_template, d.mdist, K1a);
-  ALLOC(allocs_template, bytes_template, d.o2, K1a);
+  ALLOC(allocs_template, bytes_template, d.o2_b, 2 * K1a);
   ALLOC(allocs_template, bytes_template, d.ulist, K1a);
   ALLOC(allocs_template, bytes_template, d.refs, (size_t)R);
   ALLOC(allocs_template, bytes_template, d.hyp_w, (size_t)R * K1a);
   ALLOC(allocs_template, bytes_template, d.hyp_W, (size_t)R);
   ALLOC(allocs_template, bytes_template, d.hyp_nin, (size_t)R);
   ALLOC(allocs_template, bytes_template, d.hyp_state, (size_t)R);
-  ALLOC(allocs_template, bytes_template, d.wstar, K1a);
-  ALLOC(allocs_template, bytes_template, d.presel, K1a);
+  ALLOC(allocs_template, bytes_template, d.wstar_b, 2 * K1a);
+  ALLOC(allocs_template, bytes_template, d.presel_b, 2 * K1a);
+  d.K1a = K1a;
+  select_front_set(d, 0);
   ALLOC(allocs_template, bytes_template, d.corr, (size_t)M);
   ALLOC(allocs_template, bytes_template, d.rres, (size_t)M);
   ALLOC(allocs_template, bytes_template, d.omega, (size_t)M);
@@ -860,14 +918,19 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
   return TT_OK;
 }
 
-int tt_track_frame_device(tt_stream* s, const float* d_depth, const float* d_feat_xyz, const uint8_t* d_feat_desc,
-                          int K2, float* d_out_vertices, float* d_out_dq) {
+int tt_track_frame_device_ev(tt_stream* s, const float* d_depth, const float* d_feat_xyz, const uint8_t* d_feat_desc,
+                             int K2, float* d_out_vertices, float* d_out_dq, const void* inputs_ready) {
   if (!s || !d_depth || K2 < 0 || K2 > (1 << 23) || (K2 > 0 && (!d_feat_xyz || !d_feat_desc))) return TT_EINVAL;
   if (K2 > 0 && ((uintptr_t)d_feat_desc % 16 != 0)) return TT_EINVAL;
   Busy busy(s);
   if (!busy.ok) return TT_EBUSY;
   if (!s->has_template) return TT_ESTATE;
-  return enqueue_frame(s, d_depth, d_feat_xyz, d_feat_desc, K2, d_out_vertices, d_out_dq, false);
+  return enqueue_frame(s, d_depth, d_feat_xyz, d_feat_desc, K2, d_out_vertices, d_out_dq, false, inputs_ready);
+}
+
+int tt_track_frame_device(tt_stream* s, const float* d_depth, const float* d_feat_xyz, const uint8_t* d_feat_desc,
+                          int K2, float* d_out_vertices, float* d_out_dq) {
+  return tt_track_frame_device_ev(s, d_depth, d_feat_xyz, d_feat_desc, K2, d_out_vertices, d_out_dq, nullptr);
 }
 
 int tt_track_batch_device(tt_stream* const* streams, int S, const tt_frame_device* frames) {

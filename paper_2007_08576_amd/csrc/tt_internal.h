@@ -73,7 +73,15 @@ struct DevState {
   float4 *ndisp = nullptr, *ndispc = nullptr;  // p_i^t - p_i^0
   // frame inputs (staging)
   float* depth = nullptr;
-  float4* nmap = nullptr;
+  float4* nmap = nullptr;    // the current frame's set of the double-buffered front outputs
+  // Front outputs the LM iterations read (nmap, o2, wstar, presel) come in two sets, so that the
+  // next frame's front stage can fill one while the current frame's iterations read the other;
+  // set f starts at base + f * count.
+  float4* nmap_b = nullptr;
+  float4* o2_b = nullptr;
+  double* wstar_b = nullptr;
+  uint8_t* presel_b = nullptr;
+  size_t K1a = 0;
   float* f2xyz = nullptr;    // [K2cap][3]
   uint32_t* f2desc = nullptr;  // [8][K2cap]
   // matching + pre-selection
@@ -149,7 +157,22 @@ struct tt_stream {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   double stage_ms[TT_NSTAGES] = {};
   int64_t stage_n[TT_NSTAGES] = {};
+  // the front stage (normal map, matching, pre-selection) of a frame runs on its own HIP stream,
+  // overlapping the previous frame's LM iterations; per buffer set f: front done / LM done
+  hipStream_t st_front = nullptr;
+  hipEvent_t ev_front_done[2] = {nullptr, nullptr};
+  hipEvent_t ev_lm_done[2] = {nullptr, nullptr};
 };
+
+// Points d's front outputs at buffer set f (0 or 1).
+inline void select_front_set(DevState& d, int f) {
+  d.nmap = d.nmap_b + (size_t)f * d.HW;
+  if (d.o2_b) {
+    d.o2 = d.o2_b + (size_t)f * d.K1a;
+    d.wstar = d.wstar_b + (size_t)f * d.K1a;
+    d.presel = d.presel_b + (size_t)f * d.K1a;
+  }
+}
 
 // ---- launchers (each queues kernels on st and returns hipGetLastError()) --------------------
 struct Intr {

@@ -50,7 +50,7 @@ class FrameDebug(C.Structure):
 
 class FrameDevice(C.Structure):
     _fields_ = [("depth", C.c_void_p), ("feat_xyz", C.c_void_p), ("feat_desc", C.c_void_p), ("K2", C.c_int),
-                ("out_vertices", C.c_void_p), ("out_dq", C.c_void_p)]
+                ("out_vertices", C.c_void_p), ("out_dq", C.c_void_p), ("inputs_ready", C.c_void_p)]
 
 
 def lib():
@@ -73,6 +73,7 @@ def lib():
         L.tt_set_template.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int]
         L.tt_track_frame.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp, C.POINTER(FrameDebug)]
         L.tt_track_frame_device.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
+        L.tt_track_frame_device_ev.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp, vp]
         L.tt_track_batch_device.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(FrameDevice)]
         L.tt_sync.argtypes = [vp]
         L.tt_hip_stream.argtypes = [vp]
@@ -191,11 +192,20 @@ class Stream:
             out["lambda"] = out.pop("lambda_")
         return verts, dq, out
 
-    def track_frame_device(self, depth, feat_xyz, feat_desc, K2, out_vertices=None, out_dq=None):
-        """Device-memory frame (torch tensors or raw addresses); queued, not waited for."""
-        _check(lib().tt_track_frame_device(self.h, _dev_ptr(depth), _dev_ptr(feat_xyz), _dev_ptr(feat_desc),
-                                           int(K2), _dev_ptr(out_vertices), _dev_ptr(out_dq)),
-               "tt_track_frame_device")
+    def track_frame_device(self, depth, feat_xyz, feat_desc, K2, out_vertices=None, out_dq=None,
+                           inputs_ready=None):
+        """Device-memory frame (torch tensors or raw addresses); queued, not waited for. inputs_ready:
+        a torch.cuda.Event recorded after the inputs were written (tt_track_frame_device_ev), which
+        lets the frame's matching and pre-selection overlap the previous frame's solve."""
+        if inputs_ready is None:
+            _check(lib().tt_track_frame_device(self.h, _dev_ptr(depth), _dev_ptr(feat_xyz), _dev_ptr(feat_desc),
+                                               int(K2), _dev_ptr(out_vertices), _dev_ptr(out_dq)),
+                   "tt_track_frame_device")
+        else:
+            _check(lib().tt_track_frame_device_ev(self.h, _dev_ptr(depth), _dev_ptr(feat_xyz), _dev_ptr(feat_desc),
+                                                  int(K2), _dev_ptr(out_vertices), _dev_ptr(out_dq),
+                                                  _event_ptr(inputs_ready)),
+                   "tt_track_frame_device_ev")
 
     def sync(self):
         _check(lib().tt_sync(self.h), "tt_sync")
@@ -260,14 +270,26 @@ def debug_cholesky_solve(A, b, precision=TT_FP32, ir_iters=2):
     return x, bool(fail.value)
 
 
+def _event_ptr(ev):
+    """hipEvent_t of a torch.cuda.Event (or a raw handle)."""
+    if ev is None:
+        return None
+    h = getattr(ev, "cuda_event", ev)
+    return C.c_void_p(int(h))
+
+
 def track_batch_device(streams, frames):
     """One frame per stream as one batch (tt_track_batch_device). frames: sequence of
-    (depth, feat_xyz, feat_desc, K2, out_vertices, out_dq) with torch tensors or addresses."""
+    (depth, feat_xyz, feat_desc, K2, out_vertices, out_dq[, inputs_ready]) with torch tensors or
+    addresses; inputs_ready as for Stream.track_frame_device."""
     S = len(streams)
     hs = (C.c_void_p * S)(*[s.h.value for s in streams])
     fr = (FrameDevice * S)()
-    for q, (depth, xyz, desc, K2, ov, oq) in enumerate(frames):
-        fr[q] = FrameDevice(_dev_ptr(depth), _dev_ptr(xyz), _dev_ptr(desc), int(K2), _dev_ptr(ov), _dev_ptr(oq))
+    for q, f in enumerate(frames):
+        depth, xyz, desc, K2, ov, oq = f[:6]
+        ev = _event_ptr(f[6]) if len(f) > 6 else None
+        fr[q] = FrameDevice(_dev_ptr(depth), _dev_ptr(xyz), _dev_ptr(desc), int(K2), _dev_ptr(ov), _dev_ptr(oq),
+                            ev.value if ev is not None else None)
     _check(lib().tt_track_batch_device(hs, S, fr), "tt_track_batch_device")
 
 

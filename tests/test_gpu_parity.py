@@ -168,6 +168,39 @@ def test_device_path_matches_host_path(c1, T):
     assert np.array_equal(oq.cpu().numpy().astype(np.float64), c1["qg"])
 
 
+def test_overlapped_front_stage_matches_serial(T):
+    """Frames queued back to back with an input-ready event (each frame's matching and
+    pre-selection may run during the previous frame's solve, into the other of two buffer sets)
+    give bit for bit the vertices and warps of frames tracked one at a time."""
+    import torch
+    sc = synth.make_small_sequence(seed=12, M=2000, N=40, K1=250, width=160, height=120, n_frames=5)
+    frs = [sc.frame(t) for t in range(1, 6)]
+    dev = torch.device("cuda:0")
+    res = {}
+    for mode in ("serial", "overlapped"):
+        sg = T.Stream(_params(T, num_control_points=sc.num_control_points, seed=3), _intr(T, sc.intr))
+        sg.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        ins = [tuple(torch.from_numpy(a).to(dev) for a in (f.depth, f.feat_xyz, f.feat_desc)) for f in frs]
+        ready = torch.cuda.Event()
+        ready.record()
+        outs = [(torch.zeros((sc.pts.shape[0], 3), dtype=torch.float32, device=dev),
+                 torch.zeros((sc.num_control_points, 8), dtype=torch.float32, device=dev)) for _ in frs]
+        torch.cuda.synchronize()
+        for (d, x, f), (ov, oq) in zip(ins, outs):
+            if mode == "serial":
+                sg.track_frame_device(d, x, f, x.shape[0], ov, oq)
+                sg.sync()
+            else:
+                sg.track_frame_device(d, x, f, x.shape[0], ov, oq, inputs_ready=ready)
+        sg.sync()
+        res[mode] = [(ov.cpu().numpy().copy(), oq.cpu().numpy().copy()) for ov, oq in outs]
+        sg.destroy()
+    for t in range(len(frs)):
+        assert np.isfinite(res["serial"][t][0]).all()
+        assert np.array_equal(res["serial"][t][0], res["overlapped"][t][0]), f"frame {t + 1}: vertices differ"
+        assert np.array_equal(res["serial"][t][1], res["overlapped"][t][1]), f"frame {t + 1}: warps differ"
+
+
 # ------------------------------------------------------------------------------------------------
 # a reduced sequence (several Cholesky blocks and a ragged last block), warm-started frames with
 # the GPU teacher-forced to the oracle's state before each frame
@@ -295,7 +328,9 @@ def test_api_errors(T):
     with pytest.raises(T.TTError) as e:
         sg.set_template(dup, sc.feat_xyz, sc.feat_desc)
     assert e.value.code == T.TT_EINVAL
-    small = T.Stream(_params(T, num_control_points=64, hbm_budget_bytes=400 << 10), _intr(T, sc.intr))
+    # a budget that holds the frame-size buffers (depth and two normal-map sets, ~0.45 MB at
+    # 128 x 96) but not the template's (the 448 x 384 normal matrix alone is 0.69 MB)
+    small = T.Stream(_params(T, num_control_points=64, hbm_budget_bytes=600 << 10), _intr(T, sc.intr))
     with pytest.raises(T.TTError) as e:
         small.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
     assert e.value.code == T.TT_ENOMEM
