@@ -35,7 +35,10 @@ class Params(C.Structure):
                 ("w_angle", C.c_double), ("w_rotation", C.c_double), ("lambda_arap", C.c_double),
                 ("tukey_c", C.c_double), ("H", C.c_double), ("ransac_refs", C.c_int),
                 ("ransac_iters", C.c_int), ("lm_iters", C.c_int), ("max_hamming", C.c_int),
-                ("lm_lambda0", C.c_double), ("seed", C.c_uint64)]
+                ("lm_lambda0", C.c_double), ("seed", C.c_uint64), ("solver", C.c_int)]
+
+
+SOLVE_DENSE, SOLVE_NODE = 0, 1
 
 
 _P = C.c_void_p
@@ -45,7 +48,7 @@ class FrameDebug(C.Structure):
     _fields_ = [(n, _P) for n in (
         "match_idx", "match_dist", "wstar", "preselected", "hyp_k0", "hyp_W", "hyp_nin",
         "hyp_kept", "corr0", "r0", "omega0", "orbw0", "A0", "g0", "w_arap", "cost_old",
-        "cost_new", "lambda_", "accepted")]
+        "cost_new", "lambda_", "accepted", "delta0")]
 
 
 def _declare(L):
@@ -193,7 +196,7 @@ class Stream:
                        hyp_kept=np.zeros(R, np.uint8), corr0=np.zeros(M, np.int32), r0=np.zeros(M),
                        omega0=np.zeros(M), orbw0=np.zeros(K1), A0=np.zeros((n, n)), g0=np.zeros(n),
                        w_arap=np.zeros(1), cost_old=np.zeros(T), cost_new=np.zeros(T),
-                       lambda_=np.zeros(T), accepted=np.zeros(T, np.uint8))
+                       lambda_=np.zeros(T), accepted=np.zeros(T, np.uint8), delta0=np.full(n, np.nan))
             dbg = FrameDebug(**{k: _ptr(v) for k, v in out.items()})
         rc = lib().tto_track_frame(self.h, _ptr(depth), _ptr(feat_xyz), _ptr(feat_desc), K2,
                                    _ptr(verts), _ptr(dq), C.byref(dbg) if dbg is not None else None)

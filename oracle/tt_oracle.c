@@ -288,6 +288,7 @@ void tto_default_params(tto_params* p) {
   p->max_hamming = 256;
   p->lm_lambda0 = 1e-4;
   p->seed = 0;
+  p->solver = TTO_SOLVE_DENSE;
 }
 
 static void free_frame(tto_stream* s) {
@@ -313,7 +314,7 @@ int tto_create_stream(const tto_params* p, const tto_intrinsics* K, tto_stream**
   if (p->num_control_points < 1 || p->knn < 1 || p->knn > 8 || p->ransac_refs < 1 ||
       p->ransac_iters < 1 || p->lm_iters < 0 || !(p->H > 0) || !(p->tukey_c > 0) ||
       !(p->w_orb >= 0) || !(p->w_angle >= 0) || !(p->w_rotation >= 0) || !(p->lambda_arap >= 0) ||
-      !(p->lm_lambda0 > 0))
+      !(p->lm_lambda0 > 0) || (p->solver != TTO_SOLVE_DENSE && p->solver != TTO_SOLVE_NODE))
     return TTO_EINVAL;
   if (K->width < 3 || K->height < 3 || !(K->fx > 0) || !(K->fy > 0) || !isfinite(K->cx) ||
       !isfinite(K->cy))
@@ -1268,6 +1269,20 @@ void tto_cholesky_solve(const double* L, int n, const double* b, double* x) {
 /* ------------------------------------------------------------------------------------------ */
 /* Levenberg-Marquardt over the node warps (Sec. 2)                                            */
 
+/* Per-node step (Sec. 2, each W_i updated on its own): node i solves B_i delta_i = rhs_i with
+ * B_i the 6 x 6 diagonal block of the damped normal matrix. Returns 0, or 1 if a block is not
+ * positive definite. */
+static int node_steps(const double* A, int n, const double* rhs, double* delta) {
+  double B[36], Lb[36];
+  for (int i = 0; i < n / 6; i++) {
+    for (int r = 0; r < 6; r++)
+      for (int c = 0; c < 6; c++) B[6 * r + c] = A[(size_t)(6 * i + r) * n + 6 * i + c];
+    if (tto_cholesky(B, 6, Lb) != 0) return 1;
+    tto_cholesky_solve(Lb, 6, rhs + 6 * i, delta + 6 * i);
+  }
+  return 0;
+}
+
 static double sumsq(const double* r, int n) {
   double e = 0.0;
   for (int i = 0; i < n; i++) e += r[i] * r[i];
@@ -1334,9 +1349,16 @@ int tto_track_frame(tto_stream* s, const float* depth_mm, const float* feat_xyz,
     for (int i = 0; i < n; i++) A[(size_t)i * n + i] = A[(size_t)i * n + i] * (1.0 + lambda) + 1e-12 * dmax;
     double e_new = NAN;
     int accept = 0;
-    if (tto_cholesky(A, n, L) == 0) {
-      for (int i = 0; i < n; i++) rhs[i] = -g[i];
-      tto_cholesky_solve(L, n, rhs, delta);
+    for (int i = 0; i < n; i++) rhs[i] = -g[i];
+    int fail;
+    if (s->P.solver == TTO_SOLVE_NODE) {
+      fail = node_steps(A, n, rhs, delta);
+    } else {
+      fail = tto_cholesky(A, n, L) != 0;
+      if (!fail) tto_cholesky_solve(L, n, rhs, delta);
+    }
+    if (!fail) {
+      if (t == 0 && dbg && dbg->delta0) memcpy(dbg->delta0, delta, sizeof(double) * n);
       tto_apply_increment(s, s->dq, delta, cand);
       residual_rows(s, cand, &a, r, NULL);
       e_new = sumsq(r, rows);

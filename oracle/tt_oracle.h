@@ -33,6 +33,13 @@ extern "C" {
 
 enum { TTO_OK = 0, TTO_EINVAL = -1, TTO_ENOMEM = -2, TTO_ESTATE = -3 };
 
+/* How the damped normal equations of an LM step are solved (tto_params.solver).
+ * TTO_SOLVE_DENSE: one coupled 6N x 6N system, textbook Cholesky.
+ * TTO_SOLVE_NODE: the literal reading of Sec. 2, where each node warp W_i is updated on its own:
+ * only the 6 x 6 diagonal block of node i (and its part of J^T r) enters node i's step, each
+ * block is factored by Cholesky, and the step is accepted or rejected as a whole. */
+enum { TTO_SOLVE_DENSE = 0, TTO_SOLVE_NODE = 1 };
+
 typedef struct {
   int width, height;      /* depth map size in pixels */
   double fx, fy, cx, cy;  /* pinhole: u = fx x / z + cx, v = fy y / z + cy (pixel centres at integers) */
@@ -53,6 +60,7 @@ typedef struct {
   int max_hamming;        /* matches with a larger distance are unusable; 256 keeps all */
   double lm_lambda0;      /* initial Marquardt damping per frame: 1e-4 */
   uint64_t seed;          /* seed of the reference-match sampler */
+  int solver;             /* TTO_SOLVE_DENSE or TTO_SOLVE_NODE */
 } tto_params;
 
 typedef struct tto_stream tto_stream;
@@ -79,6 +87,7 @@ typedef struct {
   double* cost_new;       /* [T] cost at the candidate (NaN if the factorisation failed) */
   double* lambda;         /* [T] damping used in the step */
   uint8_t* accepted;      /* [T] 1 if the candidate was accepted */
+  double* delta0;         /* [n] iteration-0 step (left unwritten if the factorisation failed) */
 } tto_frame_debug;
 
 void tto_default_params(tto_params* p);

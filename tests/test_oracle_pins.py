@@ -747,3 +747,100 @@ def test_dynamic_arap_weight_bookkeeping(O):
     _, _, d = s.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
     want = 1.5 * (d["omega0"].sum() + 10.0 * d["orbw0"].sum()) / s.template_info()["s_arap"]
     assert abs(d["w_arap"] - want) < 1e-12 * want
+
+
+# ------------------------------------------------------------------------------------------------
+# per-node solve (the literal reading of Sec. 2: each node warp is updated on its own)
+
+def test_node_solver_step_is_each_nodes_damped_least_squares(O):
+    """Rebuild the iteration-0 step of the per-node solver from a central-difference Jacobian,
+    node by node: numpy's least squares on [J_i; sqrt(lambda diag(J_i^T J_i) + eps)] against
+    [-r; 0], with eps = 1e-12 max diag(J^T J). The oracle's step comes from its analytic blocks
+    and its own Cholesky; a wrong block index, a transposed block or a dropped damping term
+    shows up as a step far outside the finite-difference error."""
+    sc = _small_scene(N=6)
+    fr = sc.frame(1)
+    p = O.default_params(num_control_points=6, seed=3, lm_iters=1, solver=O.SOLVE_NODE)
+    s = O.Stream(p, _intr(O, sc.intr))
+    s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    _, _, dbg = s.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+    ref = O.Stream(p, _intr(O, sc.intr))
+    ref.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    ref.frame_begin(fr.depth, fr.feat_xyz, fr.feat_desc)
+    ident = np.tile(np.r_[1.0, 0, 0, 0, 0, 0, 0, 0], (6, 1))
+    r, _, wa = ref.residuals(ident, jacobian=True)
+    assert wa == dbg["w_arap"]
+    n = 36
+    Jfd = np.zeros((len(r), n))
+    h = 1e-6
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = h
+        rp, _ = ref.residuals(ref.apply_increment(ident, e), dq_assoc=ident, w_arap=wa)
+        rm, _ = ref.residuals(ref.apply_increment(ident, -e), dq_assoc=ident, w_arap=wa)
+        Jfd[:, c] = (rp - rm) / (2 * h)
+    lam = dbg["lambda"][0]
+    eps = 1e-12 * (Jfd ** 2).sum(0).max()
+    want = np.zeros(n)
+    for i in range(6):
+        Ji = Jfd[:, 6 * i:6 * i + 6]
+        damp = np.sqrt(lam * (Ji ** 2).sum(0) + eps)
+        aug = np.vstack([Ji, np.diag(damp)])
+        want[6 * i:6 * i + 6] = np.linalg.lstsq(aug, np.r_[-r, np.zeros(6)], rcond=None)[0]
+    got = dbg["delta0"]
+    assert np.linalg.norm(got - want) < 1e-5 * np.linalg.norm(want)
+    # the candidate's cost is that of the rebuilt step
+    rc, _ = ref.residuals(ref.apply_increment(ident, want), dq_assoc=ident, w_arap=wa)
+    assert abs(dbg["cost_new"][0] - (rc ** 2).sum()) < 1e-6 * dbg["cost_new"][0]
+    # and the coupled solve takes a different step on the same system
+    pd = O.default_params(num_control_points=6, seed=3, lm_iters=1)
+    sd = O.Stream(pd, _intr(O, sc.intr))
+    sd.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    _, _, dd = sd.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+    assert np.linalg.norm(dd["delta0"] - got) > 1e-2 * np.linalg.norm(got)
+
+
+def test_node_solver_equals_dense_solver_for_one_node(O):
+    """With a single control point the only diagonal block is the whole normal matrix, so the
+    per-node and the coupled solver take the same steps bit for bit."""
+    sc = _small_scene(N=1)
+    fr = sc.frame(1)
+    out = []
+    for solver in (O.SOLVE_DENSE, O.SOLVE_NODE):
+        s = O.Stream(O.default_params(num_control_points=1, seed=3, solver=solver), _intr(O, sc.intr))
+        s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        out.append(s.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2]["cost_new"], out[1][2]["cost_new"])
+
+
+def test_node_solver_fixed_point_and_descent(O):
+    """Features only with exact o2 = G(o1) for a rigid G. Started at G itself, every residual is
+    0 up to FP64 rounding, so the per-node steps vanish and G is returned to 1e-9 mm. Started at
+    the identity, each accepted step lowers the cost and the warp moves toward G (each node sees
+    only its own block, so after 10 steps it is not yet there, unlike the coupled solve)."""
+    pts, feats, R, t = scenes.lattice_scene()
+    o2 = feats @ R.T + t
+    K = synth.Intrinsics(16, 16, 20.0, 20.0, 8.0, 8.0)
+    rng = np.random.default_rng(23)
+    desc = rng.integers(0, 256, (25, 32), dtype=np.uint8)
+    p = O.default_params(num_control_points=12, lm_iters=10, solver=O.SOLVE_NODE)
+    want = pts @ R.T + t
+    s = O.Stream(p, _intr(O, K))
+    s.set_template(pts.astype(np.float32), feats.astype(np.float32), desc)
+    half = 0.5 * math.atan2(40.0, 399.0)
+    G = O.dq_from_rt(np.r_[math.cos(half), 0.0, 0.0, math.sin(half)], t)
+    s.set_state(np.tile(G, (12, 1)), 0)
+    v, _, _ = s.track_frame(np.zeros((16, 16), np.float32), o2.astype(np.float32), desc)
+    assert np.abs(v - want).max() < 1e-9
+    s.set_state(np.tile(np.r_[1.0, 0, 0, 0, 0, 0, 0, 0], (12, 1)), 0)
+    v, dq, dbg = s.track_frame(np.zeros((16, 16), np.float32), o2.astype(np.float32), desc, debug=True)
+    acc = dbg["accepted"].astype(bool)
+    assert acc.sum() >= 2
+    assert np.all(dbg["cost_new"][acc] < dbg["cost_old"][acc])
+    assert np.sqrt(((v - want) ** 2).sum(1).mean()) < 0.75 * np.sqrt(((pts - want) ** 2).sum(1).mean())
+
+
+def test_node_solver_rejected_by_bad_params(O):
+    with pytest.raises(O.OracleError):
+        O.Stream(O.default_params(num_control_points=4, solver=2), O.intrinsics(16, 16, 20.0, 20.0, 8.0, 8.0))
