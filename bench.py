@@ -301,6 +301,45 @@ def precision_study(args, torch, tt, sc2, dframes2, vo_oracle):
     return out
 
 
+def solver_study(args, torch, tt, sc, frames, dframes):
+    """The per-node solve (each control point's damped 6x6 diagonal block on its own, the literal
+    reading of Sec. 2) against the coupled dense solve on config 2: frames/s of each, and how far
+    each gets in the frame's 10 LM iterations: frames 1..F tracked in sequence from the identity
+    (warm-started), vertex RMS against the generator's ground truth and the cost left after the
+    last iteration."""
+    dev = torch.device("cuda:0")
+    out = {}
+    intr = tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy)
+    for name, solver in (("dense", tt.TT_SOLVE_DENSE), ("node", tt.TT_SOLVE_NODE)):
+        s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=2, solver=solver), intr)
+        s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        rms, cost = [], []
+        for fr in frames:
+            v, _, d = s.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+            rms.append(float(np.sqrt(((v - fr.gt_vertices) ** 2).sum(1).mean())))
+            cost.append(float(d["cost_new"][-1] if d["accepted"][-1] else d["cost_old"][-1]))
+        ov = torch.empty((sc.pts.shape[0], 3), dtype=torch.float32, device=dev)
+        oq = torch.empty((sc.num_control_points, 8), dtype=torch.float32, device=dev)
+        for k in range(2):
+            d = dframes[k % len(dframes)]
+            s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], ov, oq)
+        s.sync()
+        t0 = time.perf_counter()
+        for k in range(args.solver_steps):
+            d = dframes[k % len(dframes)]
+            s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], ov, oq)
+        s.sync()
+        fps = args.solver_steps / (time.perf_counter() - t0)
+        s.destroy()
+        out[name] = {"frames_per_s": fps, "truth_rms_mm_per_frame": rms, "final_cost_per_frame": cost,
+                     "mean_truth_rms_mm": float(np.mean(rms))}
+        log(f"  solver {name:5s} {fps:7.1f} frames/s, truth rms over {len(frames)} frames {np.mean(rms):.3f} mm "
+            f"(last {rms[-1]:.3f}), final cost of frame 1 {cost[0]:.4g}")
+    out["note"] = ("frames 1..F of config 2 tracked in sequence from the identity, 10 LM iterations each; "
+                   "frames/s without the input-ready event (front stage not overlapped)")
+    return out
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_chol_dataflow_config2_traffic.json")
 CHOL_SRC = os.path.join(ROOT, "paper_2007_08576_amd", "csrc", "tt_chol.hip")
 
@@ -374,6 +413,9 @@ def main():
     ap.add_argument("--stress-workers", type=int, default=16, help="processes generating the stress streams")
     ap.add_argument("--stress-hz", type=float, default=15.0)
     ap.add_argument("--precision", type=int, default=1, help="also run the solve-form study (0 = skip)")
+    ap.add_argument("--solver", type=int, default=1,
+                    help="also compare the per-node solve with the coupled dense solve (0 = skip)")
+    ap.add_argument("--solver-steps", type=int, default=30)
     ap.add_argument("--precision-steps", type=int, default=10)
     ap.add_argument("--precision-config3", type=int, default=1)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -512,6 +554,8 @@ def main():
         vo_oracle = vo
     if args.precision:
         out["precision_forms"] = precision_study(args, torch, tt, sc, dframes, vo_oracle)
+    if args.solver:
+        out["solver_forms"] = solver_study(args, torch, tt, sc, frames, dframes)
     print(json.dumps(out), flush=True)
     if args.copy_calibration_mib > 0:
         nf = args.copy_calibration_mib * (1 << 20) // 4

@@ -52,6 +52,17 @@ extern "C" {
                         iterative refinement whose residual is formed in FP64                             */
 #define TT_FP16_IR 2 /* the same with binary16 inputs                                                    */
 
+/* How the damped normal equations of an LM step are solved (tt_params.solver).
+ * TT_SOLVE_DENSE: one coupled 6N x 6N system (all ARAP and shared-point couplings), dense
+ *   Cholesky; the default.
+ * TT_SOLVE_NODE: the literal reading of Sec. 2, where every control point's warp W_i is updated
+ *   on its own: only node i's 6 x 6 diagonal block of the damped normal matrix and its part of
+ *   J^T r enter node i's step; one Cholesky per node (FP64 on the device), no coupled system.
+ *   Only the diagonal blocks are assembled. The LM damping, cost and accept / reject rule are
+ *   the same, applied to the step of all nodes together. Ignores precision. */
+#define TT_SOLVE_DENSE 0
+#define TT_SOLVE_NODE 1
+
 typedef struct tt_stream tt_stream;
 
 typedef struct {
@@ -77,6 +88,7 @@ typedef struct {
   uint64_t seed;           /* seed of the reference-match sampler                            */
   uint64_t hbm_budget_bytes; /* 0 = unlimited; otherwise a cap on the stream's device bytes  */
   int ir_iters;            /* refinement steps per solve in the 16-bit forms (0..8); default 2 */
+  int solver;              /* TT_SOLVE_DENSE (default) or TT_SOLVE_NODE                        */
 } tt_params;
 
 /* Optional per-frame outputs of tt_track_frame; each pointer may be NULL. Sizes: K1 template
@@ -101,6 +113,7 @@ typedef struct {
   double* cost_new;     /* [T] cost at the candidate (NaN if the factorisation failed) */
   double* lambda;       /* [T] damping used */
   uint8_t* accepted;    /* [T] 1 if the candidate was accepted */
+  double* delta0;       /* [n] iteration-0 step, node-centred (omega_i, tau_i) per node; unwritten if the factorisation failed */
 } tt_frame_debug;
 
 /* Fills every field with the paper's constants and this library's defaults. */

@@ -62,9 +62,9 @@ void free_template(tt_stream* s) {
   LMScalars* sc = d.sc;
   double *lo = d.log_cost_old, *ln = d.log_cost_new, *ll = d.log_lambda;
   int* la = d.log_accept;
-  const int cus = d.num_cus, prec = d.prec, ir = d.ir_iters;
+  const int cus = d.num_cus, prec = d.prec, ir = d.ir_iters, solver = d.solver;
   d = DevState();
-  d.num_cus = cus; d.prec = prec; d.ir_iters = ir;
+  d.num_cus = cus; d.prec = prec; d.ir_iters = ir; d.solver = solver;
   d.HW = HW; d.K2cap = K2cap; d.depth = depth; d.nmap_b = nmap; d.nmap = nmap; d.f2xyz = f2xyz; d.f2desc = f2desc;
   d.sc = sc; d.log_cost_old = lo; d.log_cost_new = ln; d.log_lambda = ll; d.log_accept = la;
   s->has_template = false;
@@ -329,6 +329,21 @@ int enqueue_solve(tt_stream* const* ss, DevState* const* dp, const int* epochs, 
   return TT_OK;
 }
 
+// Per-node solve (one 6x6 system per control point) in place of the coupled factorisation.
+int enqueue_node_solve(tt_stream* s, DevState& dd, hipStream_t st) {
+  StageTimer tm(s, TT_STAGE_FACTOR, st);
+  HIPCHK(launch_node_solve(dd, st));
+  return TT_OK;
+}
+
+// Iteration-0 step for the debug taps: the solution of the equilibrated system and its scaling.
+int enqueue_step_debug(tt_stream* s, hipStream_t st) {
+  DevState& d = s->d;
+  HIPCHK(hipMemcpyAsync(d.x_dbg, d.x, sizeof(float) * d.npad, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(d.x_dbg + d.npad, d.dscale, sizeof(float) * d.npad, hipMemcpyDeviceToDevice, st));
+  return TT_OK;
+}
+
 // Candidate, FP64 cost, accept / reject.
 int enqueue_finish(tt_stream* s, DevState& dd, hipStream_t st) {
   StageTimer tm(s, TT_STAGE_UPDATE, st);
@@ -348,7 +363,9 @@ int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint
     rc = enqueue_assemble(s, dd, it, dbg, st, &epoch);
     if (rc) return rc;
     DevState* dp[1] = {&dd};
-    rc = enqueue_solve(&s, dp, &epoch, 1, st);
+    rc = (s->P.solver == TT_SOLVE_NODE) ? enqueue_node_solve(s, dd, st) : enqueue_solve(&s, dp, &epoch, 1, st);
+    if (rc) return rc;
+    if (dbg && it == 0) rc = enqueue_step_debug(s, st);
     if (rc) return rc;
     rc = enqueue_finish(s, dd, st);
     if (rc) return rc;
@@ -364,7 +381,7 @@ int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint
 // stream (so that the small kernels of different streams overlap on the hardware queues); the
 // factorisations, substitutions and refinement of all S systems run on batch_st (= the first
 // stream's) as one launch each per LM iteration, joined with and forked to the per-stream queues by
-// events.
+// events. Streams with the per-node solver take their 6x6 solves on their own queue instead.
 int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStream_t batch_st) {
   std::vector<DevState> dd(S);
   std::vector<DevState*> dp(S);
@@ -399,10 +416,27 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
   };
   int rc = fork();
   for (int q = 0; q < S && !rc; q++) rc = enqueue_front(ss[q], dd[q], fr[q].K2, qs[q], fr[q].inputs_ready);
+  // the streams whose systems go to the batched factorisation
+  std::vector<tt_stream*> cs;
+  std::vector<DevState*> cp;
+  std::vector<int> ce;
+  for (int q = 0; q < S; q++)
+    if (ss[q]->P.solver != TT_SOLVE_NODE) {
+      cs.push_back(ss[q]);
+      cp.push_back(dp[q]);
+    }
+  ce.resize(cs.size());
   for (int it = 0; it < ss[0]->P.lm_iters && !rc; it++) {
-    for (int q = 0; q < S && !rc; q++) rc = enqueue_assemble(ss[q], dd[q], it, false, qs[q], &epochs[q]);
+    for (int q = 0, c = 0; q < S && !rc; q++) {
+      rc = enqueue_assemble(ss[q], dd[q], it, false, qs[q], &epochs[q]);
+      if (rc) break;
+      if (ss[q]->P.solver == TT_SOLVE_NODE)
+        rc = enqueue_node_solve(ss[q], dd[q], qs[q]);
+      else
+        ce[c++] = epochs[q];
+    }
     if (!rc) rc = join();
-    if (!rc) rc = enqueue_solve(ss, dp.data(), epochs.data(), S, batch_st);
+    if (!rc && !cs.empty()) rc = enqueue_solve(cs.data(), cp.data(), ce.data(), (int)cs.size(), batch_st);
     if (!rc) rc = fork();
     for (int q = 0; q < S && !rc; q++) rc = enqueue_finish(ss[q], dd[q], qs[q]);
   }
@@ -425,6 +459,7 @@ int ensure_debug_buffers(tt_stream* s) {
   ALLOC(allocs_template, bytes_template, d.rres_dbg, (size_t)d.M);
   ALLOC(allocs_template, bytes_template, d.omega_dbg, (size_t)d.M);
   ALLOC(allocs_template, bytes_template, d.orbw_dbg, (size_t)(d.K1 ? d.K1 : 1));
+  ALLOC(allocs_template, bytes_template, d.x_dbg, 2 * (size_t)d.npad);
   return TT_OK;
 }
 
@@ -457,7 +492,8 @@ int copy_debug(tt_stream* s, tt_frame_debug* dbg) {
     if (dbg->hyp_nin) for (int h = 0; h < R; h++) dbg->hyp_nin[h] = 0;
   }
   if (d2h(dbg->corr0, d.corr_dbg, M, st)) return TT_EDEVICE;
-  std::vector<float> rr(M), om(M), ow(K1 ? K1 : 1), gg(d.npad);
+  std::vector<float> rr(M), om(M), ow(K1 ? K1 : 1), gg(d.npad), xs(2 * (size_t)d.npad);
+  if (d2h(xs.data(), d.x_dbg, xs.size(), st)) return TT_EDEVICE;
   if (d2h(rr.data(), d.rres_dbg, M, st)) return TT_EDEVICE;
   if (d2h(om.data(), d.omega_dbg, M, st)) return TT_EDEVICE;
   if (K1 && d2h(ow.data(), d.orbw_dbg, K1, st)) return TT_EDEVICE;
@@ -489,14 +525,18 @@ int copy_debug(tt_stream* s, tt_frame_debug* dbg) {
     if (dbg->orbw0) dbg->orbw0[k] = ow[k];
   if (dbg->g0)
     for (int i = 0; i < n; i++) dbg->g0[i] = gg[i];
+  // the per-node solve assembles only the diagonal 6x6 blocks; the coupling blocks read as 0
+  const bool diag_only = d.solver == TT_SOLVE_NODE;
   if (dbg->A0)
     for (int i = 0; i < n; i++)
       for (int j = 0; j <= i; j++) {
-        double v = fbuf[(size_t)i * d.ld + j];
+        double v = (diag_only && i / 6 != j / 6) ? 0.0 : fbuf[(size_t)i * d.ld + j];
         dbg->A0[(size_t)i * n + j] = v;
         dbg->A0[(size_t)j * n + i] = v;
       }
   if (dbg->w_arap) *dbg->w_arap = sc.w_arap;
+  if (dbg->delta0 && T > 0 && !std::isnan(ln[0]))
+    for (int i = 0; i < n; i++) dbg->delta0[i] = (double)xs[i] * (double)xs[(size_t)d.npad + i];
   for (int t = 0; t < T; t++) {
     if (dbg->cost_old) dbg->cost_old[t] = lo[t];
     if (dbg->cost_new) dbg->cost_new[t] = ln[t];
@@ -532,6 +572,7 @@ void tt_default_params(tt_params* p) {
   p->seed = 0;
   p->hbm_budget_bytes = 0;
   p->ir_iters = 2;
+  p->solver = TT_SOLVE_DENSE;
 }
 
 const char* tt_strerror(int code) {
@@ -561,7 +602,7 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
       p->ransac_iters < 1 || p->lm_iters < 0 || p->lm_iters > 1000 || !(p->H > 0) || !(p->tukey_c > 0) ||
       !(p->w_orb >= 0) || !(p->w_angle >= 0) || !(p->w_rotation >= 0) || !(p->lambda_arap >= 0) ||
       !(p->lm_lambda0 > 0) || p->precision < TT_FP32 || p->precision > TT_FP16_IR || p->ir_iters < 0 ||
-      p->ir_iters > 8)
+      p->ir_iters > 8 || (p->solver != TT_SOLVE_DENSE && p->solver != TT_SOLVE_NODE))
     return TT_EINVAL;
   if (K->width < 3 || K->height < 3 || !(K->fx > 0) || !(K->fy > 0) || !isfinite(K->cx) || !isfinite(K->cy) ||
       (int64_t)K->width * K->height > (1 << 28))
@@ -582,8 +623,9 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
   DevState& d = s->d;
   d.HW = K->width * K->height;
   d.num_cus = device_cus();
-  d.prec = p->precision;
-  d.ir_iters = (p->precision == TT_FP32) ? 0 : p->ir_iters;
+  d.solver = p->solver;
+  d.prec = (p->solver == TT_SOLVE_NODE) ? TT_FP32 : p->precision;
+  d.ir_iters = (d.prec == TT_FP32) ? 0 : p->ir_iters;
   int T = p->lm_iters > 0 ? p->lm_iters : 1;
   int rc = TT_OK;
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.depth, (size_t)d.HW);

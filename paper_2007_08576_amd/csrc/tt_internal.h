@@ -114,6 +114,7 @@ struct DevState {
   int num_cus = 0;           // compute units of the device (persistent launch size)
   int prec = TT_FP32;        // precision form of the solve
   int ir_iters = 0;          // refinement steps per solve (16-bit forms)
+  int solver = TT_SOLVE_DENSE; // coupled dense solve or one 6 x 6 solve per node
   uint16_t* A16 = nullptr;   // 16-bit copies of the finished L tiles [(npad + 64) * ld]
   float* A0 = nullptr;       // damped matrix before factorisation [npad * ld] (refinement)
   float* cvec = nullptr;     // equilibrated right-hand side [npad] (refinement)
@@ -133,6 +134,7 @@ struct DevState {
   float* rres_dbg = nullptr;
   float* omega_dbg = nullptr;
   float* orbw_dbg = nullptr;
+  float* x_dbg = nullptr;     // iteration-0 solution and equilibration [2 npad]
 };
 
 struct tt_stream {
@@ -194,6 +196,7 @@ hipError_t launch_lm_rows(DevState& d, const tt_params& P, const Intr& K, int it
 hipError_t launch_lm_arap(DevState& d, const tt_params& P, hipStream_t st);
 hipError_t launch_lm_data(DevState& d, hipStream_t st);
 hipError_t launch_lm_damp(DevState& d, hipStream_t st);
+hipError_t launch_node_solve(DevState& d, hipStream_t st);
 hipError_t launch_lm_finish(DevState& d, const tt_params& P, const Intr& K, hipStream_t st);
 hipError_t launch_deform_out(const DevState& d, float* out_xyz, float* out_dq, hipStream_t st);
 

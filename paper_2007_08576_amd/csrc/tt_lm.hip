@@ -13,7 +13,9 @@
 //   k_data_assemble    adds the ICP and feature rows into the node-pair blocks through the
 //                      static block-CSR (deterministic, no atomics)
 //   k_damp             Marquardt damping A + lambda diag(A) + eps I and the right-hand side
-//   (Cholesky + solves: tt_chol.hip)
+//   (Cholesky + solves: tt_chol.hip), or, for the per-node solve,
+//   k_node_solve       one 6x6 FP64 Cholesky per node on its diagonal block (only the diagonal
+//                      blocks are assembled then)
 //   k_update           candidate warps W' = Delta(delta_i) W_i (node-centred increments)
 //   k_cost_data/arap   FP64 cost of the candidate with correspondences and weights frozen
 //   k_accept           accept if the cost drops (lambda / 10), else reject (lambda * 10)
@@ -397,6 +399,9 @@ struct ArapArgs {
 constexpr int kArapThreads = 256;
 constexpr int kArapAcc = 36 + 6;
 
+// kOff: also write the off-diagonal blocks (the coupled solve); the per-node solve reads only the
+// diagonal blocks and g.
+template <bool kOff>
 __global__ __launch_bounds__(kArapThreads) void k_arap_assemble(ArapArgs a) {
   __shared__ float red[kArapAcc][kArapThreads + 1];
   __shared__ float wsum[kArapThreads / 64][kArapAcc];
@@ -495,7 +500,7 @@ __global__ __launch_bounds__(kArapThreads) void k_arap_assemble(ArapArgs a) {
           B[(3 + r) * 6 + 3 + c] = -2.0f * W2 * (bb[r] * bb[c] + wg * Pb2[r * 3 + c]);
         }
     }
-    if (j < i) {
+    if (kOff && j < i) {
       float* dst = a.A + (size_t)(6 * i) * a.ld + 6 * j;
 #pragma unroll
       for (int r = 0; r < 6; r++) {
@@ -557,11 +562,13 @@ __global__ __launch_bounds__(kDataThreads) void k_data_assemble(const int2* __re
                                                                 const float* __restrict__ wres, int M,
                                                                 const float* __restrict__ jacF,
                                                                 const float* __restrict__ wresF, int K1,
-                                                                float* __restrict__ A, float* __restrict__ g, int ld) {
+                                                                float* __restrict__ A, float* __restrict__ g, int ld,
+                                                                int diag_only) {
   __shared__ float fin[42];
   __shared__ float red[42][kDataThreads + 1];
   const int blk = blockIdx.x;
   const int2 ab = blk_ab[blk];
+  if (diag_only && ab.x != ab.y) return;  // whole workgroup: the per-node solve reads no coupling block
   const int lane = threadIdx.x;
   float S[36], G[6];
 #pragma unroll
@@ -684,6 +691,54 @@ __global__ __launch_bounds__(1024) void k_damp(float* __restrict__ A, const floa
     sc->eps = (double)eps;
     sc->chol_fail = 0;
   }
+}
+
+// Per-node step (Sec. 2, each warp W_i updated on its own): node i solves its 6 x 6 diagonal block
+// of the damped, equilibrated matrix D A D against its part of the equilibrated right-hand side, by
+// Cholesky in FP64 (the block is read from the FP32 lower triangle). One thread per node. A block
+// that is not positive definite raises chol_fail, which rejects the step.
+__global__ __launch_bounds__(64) void k_node_solve(const float* __restrict__ A, int ld, int npad,
+                                                   const float* __restrict__ dscale, int N, float* __restrict__ x,
+                                                   LMScalars* sc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int o = 6 * i;
+  double ds[6], L[6][6], y[6];
+#pragma unroll
+  for (int r = 0; r < 6; r++) ds[r] = (double)dscale[o + r];
+  bool ok = true;
+#pragma unroll
+  for (int r = 0; r < 6; r++) {
+#pragma unroll
+    for (int c = 0; c <= r; c++) {
+      double v = (double)A[(size_t)(o + r) * ld + o + c] * ds[r] * ds[c];
+#pragma unroll
+      for (int k = 0; k < c; k++) v -= L[r][k] * L[c][k];
+      if (c == r) {
+        ok = ok && (v > 0.0);
+        L[r][r] = sqrt(ok ? v : 1.0);
+      } else {
+        L[r][c] = v / L[c][c];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 6; r++) {
+    double v = (double)A[(size_t)npad * ld + o + r];
+#pragma unroll
+    for (int k = 0; k < r; k++) v -= L[r][k] * y[k];
+    y[r] = v / L[r][r];
+  }
+#pragma unroll
+  for (int r = 5; r >= 0; r--) {
+    double v = y[r];
+#pragma unroll
+    for (int k = r + 1; k < 6; k++) v -= L[k][r] * y[k];
+    y[r] = v / L[r][r];
+  }
+#pragma unroll
+  for (int r = 0; r < 6; r++) x[o + r] = ok ? (float)y[r] : 0.0f;
+  if (!ok) sc->chol_fail = 1;
 }
 
 // Candidate warps from the solution D y of (A + damping) x = -g (y solves the equilibrated system).
@@ -902,20 +957,29 @@ hipError_t launch_lm_rows(DevState& d, const tt_params& P, const Intr& K, int it
 
 hipError_t launch_lm_arap(DevState& d, const tt_params& P, hipStream_t st) {
   ArapArgs aa = arap_args(d, P);
-  hipLaunchKernelGGL(k_arap_assemble, dim3(d.N), dim3(kArapThreads), 0, st, aa);
+  if (d.solver == TT_SOLVE_NODE)
+    hipLaunchKernelGGL(k_arap_assemble<false>, dim3(d.N), dim3(kArapThreads), 0, st, aa);
+  else
+    hipLaunchKernelGGL(k_arap_assemble<true>, dim3(d.N), dim3(kArapThreads), 0, st, aa);
   return hipGetLastError();
 }
 
 hipError_t launch_lm_data(DevState& d, hipStream_t st) {
   if (d.nblk > 0)
     hipLaunchKernelGGL(k_data_assemble, dim3(d.nblk), dim3(kDataThreads), 0, st, d.blk_ab, d.blk_ptr, d.blk_ent,
-                       d.jac, d.wres, d.M, d.jacF, d.wresF, d.K1, d.A, d.g, d.ld);
+                       d.jac, d.wres, d.M, d.jacF, d.wresF, d.K1, d.A, d.g, d.ld, (int)(d.solver == TT_SOLVE_NODE));
   return hipGetLastError();
 }
 
 hipError_t launch_lm_damp(DevState& d, hipStream_t st) {
   Parts p = parts_of(d.M, d.K1, d.N);
   hipLaunchKernelGGL(k_damp, dim3(1), dim3(1024), 0, st, d.A, d.g, d.n, d.npad, d.ld, d.dscale, d.partial, p,
+                     d.sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_solve(DevState& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_node_solve, dim3((d.N + 63) / 64), dim3(64), 0, st, d.A, d.ld, d.npad, d.dscale, d.N, d.x,
                      d.sc);
   return hipGetLastError();
 }

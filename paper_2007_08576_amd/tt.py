@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtt.so")
 
 TT_OK, TT_EINVAL, TT_ENOMEM, TT_ESTATE, TT_EDEVICE, TT_EBUSY = 0, -1, -2, -3, -4, -5
 TT_FP32, TT_BF16_IR, TT_FP16_IR = 0, 1, 2
+TT_SOLVE_DENSE, TT_SOLVE_NODE = 0, 1
 STAGES = ("front", "rows", "arap", "data", "solve", "update", "factor")
 
 _lib = None
@@ -36,12 +37,13 @@ class Params(C.Structure):
                 ("tukey_c", C.c_double), ("H", C.c_double), ("ransac_refs", C.c_int),
                 ("ransac_iters", C.c_int), ("lm_iters", C.c_int), ("max_hamming", C.c_int),
                 ("lm_lambda0", C.c_double), ("precision", C.c_int), ("seed", C.c_uint64),
-                ("hbm_budget_bytes", C.c_uint64), ("ir_iters", C.c_int)]
+                ("hbm_budget_bytes", C.c_uint64), ("ir_iters", C.c_int),
+                ("solver", C.c_int)]
 
 
 _DEBUG_FIELDS = ("match_idx", "match_dist", "wstar", "preselected", "hyp_k0", "hyp_W", "hyp_nin",
                  "hyp_kept", "corr0", "r0", "omega0", "orbw0", "A0", "g0", "w_arap", "cost_old",
-                 "cost_new", "lambda_", "accepted")
+                 "cost_new", "lambda_", "accepted", "delta0")
 
 
 class FrameDebug(C.Structure):
@@ -182,7 +184,7 @@ class Stream:
                        hyp_kept=np.zeros(R, np.uint8), corr0=np.zeros(M, np.int32), r0=np.zeros(M),
                        omega0=np.zeros(M), orbw0=np.zeros(K1), A0=np.zeros((n, n)), g0=np.zeros(n),
                        w_arap=np.zeros(1), cost_old=np.zeros(T), cost_new=np.zeros(T),
-                       lambda_=np.zeros(T), accepted=np.zeros(T, np.uint8))
+                       lambda_=np.zeros(T), accepted=np.zeros(T, np.uint8), delta0=np.full(n, np.nan))
             dbg = FrameDebug(**{k: _ptr(v) for k, v in out.items()})
         rc = lib().tt_track_frame(self.h, _ptr(depth), _ptr(feat_xyz), _ptr(feat_desc), feat_xyz.shape[0],
                                   _ptr(verts), _ptr(dq), C.byref(dbg) if dbg is not None else None)

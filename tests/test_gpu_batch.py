@@ -32,8 +32,9 @@ def _scenes():
                                 max_step_mm=3.0, name="batchC")]
 
 
-def _stream(tt, sc, precision=0):
-    s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=5, precision=precision),
+def _stream(tt, sc, precision=0, solver=0):
+    s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=5, precision=precision,
+                                    solver=solver),
                   tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy))
     s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
     return s
@@ -47,12 +48,17 @@ def _dev_frame(torch, fr, dev):
 def test_batch_equals_alone(env):
     tt, torch = env
     dev = torch.device("cuda:0")
+    # a fourth stream tracks the first scene with the per-node solve (its 6x6 solves run on its own
+    # queue, outside the batched factorisation)
     scenes = _scenes()
+    scenes.append(scenes[0])
     frames = [[_dev_frame(torch, sc.frame(t), dev) for t in (1, 2)] for sc in scenes]
     outs = {}
     for mode in ("alone", "batch"):
         # the second stream solves in the bfloat16 form with refinement
-        streams = [_stream(tt, sc, precision=(tt.TT_BF16_IR if q == 1 else 0)) for q, sc in enumerate(scenes)]
+        streams = [_stream(tt, sc, precision=(tt.TT_BF16_IR if q == 1 else 0),
+                           solver=(tt.TT_SOLVE_NODE if q == 3 else tt.TT_SOLVE_DENSE))
+                   for q, sc in enumerate(scenes)]
         ov = [torch.zeros((sc.pts.shape[0], 3), dtype=torch.float32, device=dev) for sc in scenes]
         oq = [torch.zeros((sc.num_control_points, 8), dtype=torch.float32, device=dev) for sc in scenes]
         res = []
@@ -80,6 +86,8 @@ def test_batch_equals_alone(env):
             assert np.array_equal(qa, qb), f"frame {t + 1}, stream {q}: warps differ in the batch"
     for q in range(len(scenes)):
         assert outs["alone"][1][q][1] == outs["batch"][1][q][1] == 2  # frame counters
+    # the per-node stream really took other steps than the dense one on the same scene
+    assert not np.array_equal(outs["batch"][0][1][0][1], outs["batch"][0][1][3][1])
 
 
 def test_batch_rejects_bad_arguments(env):
