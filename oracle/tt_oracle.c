@@ -33,6 +33,7 @@ struct tto_stream {
   uint8_t* desc1;          /* [K1*32] */
   int32_t* knn_feat;       /* [K1*kk] */
   double* alpha_feat;      /* [K1*kk] */
+  uint8_t* adj;            /* [N*N] ARAP graph when P.arap_knn > 0 (1 = pair kept), else NULL */
   double* dq;              /* [N*8] current warps W_i^t */
   int64_t frame;
   /* per-frame state, set by tto_frame_begin */
@@ -289,6 +290,7 @@ void tto_default_params(tto_params* p) {
   p->lm_lambda0 = 1e-4;
   p->seed = 0;
   p->solver = TTO_SOLVE_DENSE;
+  p->arap_knn = 0;
 }
 
 static void free_frame(tto_stream* s) {
@@ -301,9 +303,9 @@ static void free_frame(tto_stream* s) {
 
 static void free_template(tto_stream* s) {
   free(s->pts); free(s->node_idx); free(s->c0); free(s->knn_pts); free(s->alpha_pts);
-  free(s->f1); free(s->desc1); free(s->knn_feat); free(s->alpha_feat); free(s->dq);
+  free(s->f1); free(s->desc1); free(s->knn_feat); free(s->alpha_feat); free(s->dq); free(s->adj);
   s->pts = NULL; s->node_idx = NULL; s->c0 = NULL; s->knn_pts = NULL; s->alpha_pts = NULL;
-  s->f1 = NULL; s->desc1 = NULL; s->knn_feat = NULL; s->alpha_feat = NULL; s->dq = NULL;
+  s->f1 = NULL; s->desc1 = NULL; s->knn_feat = NULL; s->alpha_feat = NULL; s->dq = NULL; s->adj = NULL;
   s->has_template = 0;
   free_frame(s);
 }
@@ -314,7 +316,8 @@ int tto_create_stream(const tto_params* p, const tto_intrinsics* K, tto_stream**
   if (p->num_control_points < 1 || p->knn < 1 || p->knn > 8 || p->ransac_refs < 1 ||
       p->ransac_iters < 1 || p->lm_iters < 0 || !(p->H > 0) || !(p->tukey_c > 0) ||
       !(p->w_orb >= 0) || !(p->w_angle >= 0) || !(p->w_rotation >= 0) || !(p->lambda_arap >= 0) ||
-      !(p->lm_lambda0 > 0) || (p->solver != TTO_SOLVE_DENSE && p->solver != TTO_SOLVE_NODE))
+      !(p->lm_lambda0 > 0) || (p->solver != TTO_SOLVE_DENSE && p->solver != TTO_SOLVE_NODE) ||
+      p->arap_knn < 0 || p->arap_knn > 32)
     return TTO_EINVAL;
   if (K->width < 3 || K->height < 3 || !(K->fx > 0) || !(K->fy > 0) || !isfinite(K->cx) ||
       !isfinite(K->cy))
@@ -379,7 +382,8 @@ static void knn_blend(const double* c0, int N, double sbar, const double* x, int
 
 static double arap_pair_weight(const tto_stream* s, int a, int b) {
   /* w_{i1,i2}: larger for control points that are closer at time 0 (Sec. 2.2); Gaussian of
-   * the rest distance with sigma = 2 sbar. */
+   * the rest distance with sigma = 2 sbar. With a sparse ARAP graph, 0 off the graph. */
+  if (s->adj && !s->adj[(size_t)a * s->N + b]) return 0.0;
   double sa = 2.0 * s->sbar;
   return exp(-dist2(s->c0 + 3 * a, s->c0 + 3 * b) / (2.0 * sa * sa));
 }
@@ -461,6 +465,34 @@ int tto_set_template(tto_stream* s, const float* pts_xyz, int M, const float* fe
     knn_blend(s->c0, N, s->sbar, s->pts + 3 * j, kk, s->knn_pts + kk * j, s->alpha_pts + kk * j);
   for (int k = 0; k < K1; k++)
     knn_blend(s->c0, N, s->sbar, s->f1 + 3 * k, kk, s->knn_feat + kk * k, s->alpha_feat + kk * k);
+  /* Sparse ARAP graph (the alternative to the dense connection of Sec. 2.2): node a keeps its
+   * arap_knn nearest other nodes (squared rest distance, ties to the lower index), and a pair is
+   * kept if either node keeps the other. */
+  if (s->P.arap_knn > 0) {
+    s->adj = (uint8_t*)calloc((size_t)N * N, 1);
+    if (!s->adj) {
+      free_template(s);
+      return TTO_ENOMEM;
+    }
+    for (int a = 0; a < N; a++) {
+      for (int r = 0; r < s->P.arap_knn && r < N - 1; r++) {
+        int best = -1;
+        double bd = INFINITY;
+        for (int b = 0; b < N; b++) {
+          if (b == a || s->adj[(size_t)a * N + b] == 2) continue;
+          double d = dist2(s->c0 + 3 * a, s->c0 + 3 * b);
+          if (d < bd) { bd = d; best = b; }
+        }
+        s->adj[(size_t)a * N + best] = 2; /* chosen by a */
+      }
+    }
+    for (int a = 0; a < N; a++)
+      for (int b = 0; b < N; b++)
+        if (s->adj[(size_t)a * N + b] == 2 || s->adj[(size_t)b * N + a] == 2) {
+          s->adj[(size_t)a * N + b] |= 1;
+          s->adj[(size_t)b * N + a] |= 1;
+        }
+  }
   /* sum of ARAP weights over all ordered pairs (used to scale the dynamic ARAP weight) */
   double sa = 0.0;
   for (int a = 0; a < N; a++)

@@ -61,6 +61,8 @@ typedef struct {
   double lm_lambda0;      /* initial Marquardt damping per frame: 1e-4 */
   uint64_t seed;          /* seed of the reference-match sampler */
   int solver;             /* TTO_SOLVE_DENSE or TTO_SOLVE_NODE */
+  int arap_knn;           /* 0: ARAP over all pairs of control points (Sec. 2.2, dense); k > 0:
+                             only pairs where one node is among the other's k nearest (0..32) */
 } tto_params;
 
 typedef struct tto_stream tto_stream;

@@ -844,3 +844,90 @@ def test_node_solver_fixed_point_and_descent(O):
 def test_node_solver_rejected_by_bad_params(O):
     with pytest.raises(O.OracleError):
         O.Stream(O.default_params(num_control_points=4, solver=2), O.intrinsics(16, 16, 20.0, 20.0, 8.0, 8.0))
+
+
+# ------------------------------------------------------------------------------------------------
+# sparse ARAP graph (the alternative to the dense connection of Sec. 2.2)
+
+def _graph(C, k):
+    """Brute-force k-nearest-node graph: node a keeps its k nearest others (stable order, so ties
+    go to the lower index); a pair is kept if either node keeps the other."""
+    N = len(C)
+    D2 = ((C[:, None, :] - C[None, :, :]) ** 2).sum(-1)
+    adj = np.zeros((N, N), bool)
+    for a in range(N):
+        d = D2[a].copy()
+        d[a] = np.inf
+        adj[a, np.argsort(d, kind="stable")[:k]] = True
+    return adj | adj.T, D2
+
+
+def test_sparse_arap_weight_sum_brute_force(O):
+    sc = _small_scene(N=10)
+    for k in (1, 3):
+        s = O.Stream(O.default_params(num_control_points=10, arap_knn=k), _intr(O, sc.intr))
+        s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        info = s.template_info()
+        C = sc.pts.astype(np.float64)[info["node_idx"]]
+        adj, D2 = _graph(C, k)
+        sa = 2.0 * info["sbar"]
+        want = np.exp(-D2 / (2 * sa * sa))[adj].sum()
+        assert abs(info["s_arap"] - want) <= 1e-12 * want
+        assert adj.sum() < 90  # a proper subset of the 90 ordered pairs
+
+
+def test_sparse_arap_with_every_neighbour_is_dense(O):
+    sc = _small_scene(N=6)
+    fr = sc.frame(1)
+    out = []
+    for k in (0, 5):
+        s = O.Stream(O.default_params(num_control_points=6, seed=3, arap_knn=k), _intr(O, sc.intr))
+        s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        out.append(s.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_sparse_arap_normal_equations(O):
+    """With a 2-nearest-node graph: J^T J against a central-difference Jacobian, and every 6x6
+    block of a node pair that is off the graph and shares no blend set is exactly zero (in the
+    dense connection the same blocks are not)."""
+    sc = _small_scene(N=8)
+    fr = sc.frame(1)
+    rng = np.random.default_rng(33)
+    dq = scenes.random_dq(rng, 8, 3.0, 1.0)
+    res = {}
+    for k in (0, 2):
+        s = O.Stream(O.default_params(num_control_points=8, seed=3, arap_knn=k), _intr(O, sc.intr))
+        s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        s.frame_begin(fr.depth, fr.feat_xyz, fr.feat_desc)
+        r, J, wa = s.residuals(dq, jacobian=True)
+        A, g = s.normal_equations(dq, w_arap=wa)
+        res[k] = (s, A, wa)
+        if k == 2:
+            n = 48
+            Jfd = np.zeros_like(J)
+            h = 1e-6
+            for c in range(n):
+                e = np.zeros(n)
+                e[c] = h
+                rp, _ = s.residuals(s.apply_increment(dq, e), dq_assoc=dq, w_arap=wa)
+                rm, _ = s.residuals(s.apply_increment(dq, -e), dq_assoc=dq, w_arap=wa)
+                Jfd[:, c] = (rp - rm) / (2 * h)
+            assert np.linalg.norm(A - Jfd.T @ Jfd) < 1e-6 * np.linalg.norm(A)
+    s2, A2, _ = res[2]
+    info = s2.template_info()
+    C = sc.pts.astype(np.float64)[info["node_idx"]]
+    adj, _ = _graph(C, 2)
+    share = np.zeros((8, 8), bool)
+    for sets in (info["knn_pts"], info["knn_feat"]):
+        for row in sets:
+            for a in row:
+                share[a, row] = True
+    quiet = ~adj & ~share & ~np.eye(8, dtype=bool)
+    assert quiet.any()
+    A0 = res[0][1]
+    for a, b in zip(*np.nonzero(quiet)):
+        assert not A2[6 * a:6 * a + 6, 6 * b:6 * b + 6].any()
+        assert np.abs(A0[6 * a:6 * a + 6, 6 * b:6 * b + 6]).max() > 0
+    for a, b in zip(*np.nonzero(adj & ~share)):
+        assert np.abs(A2[6 * a:6 * a + 6, 6 * b:6 * b + 6]).max() > 0
