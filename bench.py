@@ -303,15 +303,18 @@ def precision_study(args, torch, tt, sc2, dframes2, vo_oracle):
 
 def solver_study(args, torch, tt, sc, frames, dframes):
     """The per-node solve (each control point's damped 6x6 diagonal block on its own, the literal
-    reading of Sec. 2) against the coupled dense solve on config 2: frames/s of each, and how far
-    each gets in the frame's 10 LM iterations: frames 1..F tracked in sequence from the identity
-    (warm-started), vertex RMS against the generator's ground truth and the cost left after the
-    last iteration."""
+    reading of Sec. 2) and the sparse ARAP graph (8 nearest control points instead of Sec. 2.2's
+    dense connection) against the coupled dense solve with dense ARAP on config 2: frames/s of
+    each, and how far each gets in the frame's 10 LM iterations: frames 1..F tracked in sequence
+    from the identity (warm-started), vertex RMS against the generator's ground truth and the cost
+    left after the last iteration (the sparse graph's cost has fewer ARAP terms)."""
     dev = torch.device("cuda:0")
     out = {}
     intr = tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy)
-    for name, solver in (("dense", tt.TT_SOLVE_DENSE), ("node", tt.TT_SOLVE_NODE)):
-        s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=2, solver=solver), intr)
+    for name, solver, knn in (("dense", tt.TT_SOLVE_DENSE, 0), ("node", tt.TT_SOLVE_NODE, 0),
+                              ("dense_arap_knn8", tt.TT_SOLVE_DENSE, 8)):
+        s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=2, solver=solver,
+                                        arap_knn=knn), intr)
         s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
         rms, cost = [], []
         for fr in frames:
@@ -333,7 +336,7 @@ def solver_study(args, torch, tt, sc, frames, dframes):
         s.destroy()
         out[name] = {"frames_per_s": fps, "truth_rms_mm_per_frame": rms, "final_cost_per_frame": cost,
                      "mean_truth_rms_mm": float(np.mean(rms))}
-        log(f"  solver {name:5s} {fps:7.1f} frames/s, truth rms over {len(frames)} frames {np.mean(rms):.3f} mm "
+        log(f"  solver {name:15s} {fps:7.1f} frames/s, truth rms over {len(frames)} frames {np.mean(rms):.3f} mm "
             f"(last {rms[-1]:.3f}), final cost of frame 1 {cost[0]:.4g}")
     out["note"] = ("frames 1..F of config 2 tracked in sequence from the identity, 10 LM iterations each; "
                    "frames/s without the input-ready event (front stage not overlapped)")

@@ -89,6 +89,9 @@ typedef struct {
   uint64_t hbm_budget_bytes; /* 0 = unlimited; otherwise a cap on the stream's device bytes  */
   int ir_iters;            /* refinement steps per solve in the 16-bit forms (0..8); default 2 */
   int solver;              /* TT_SOLVE_DENSE (default) or TT_SOLVE_NODE                        */
+  int arap_knn;            /* 0 (default): ARAP over every pair of control points, the dense
+                              connection of Sec. 2.2; k in 1..32: only pairs where one node is
+                              among the other's k nearest at time 0 (ties to the lower index) */
 } tt_params;
 
 /* Optional per-frame outputs of tt_track_frame; each pointer may be NULL. Sizes: K1 template

@@ -573,6 +573,7 @@ void tt_default_params(tt_params* p) {
   p->hbm_budget_bytes = 0;
   p->ir_iters = 2;
   p->solver = TT_SOLVE_DENSE;
+  p->arap_knn = 0;
 }
 
 const char* tt_strerror(int code) {
@@ -602,7 +603,8 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
       p->ransac_iters < 1 || p->lm_iters < 0 || p->lm_iters > 1000 || !(p->H > 0) || !(p->tukey_c > 0) ||
       !(p->w_orb >= 0) || !(p->w_angle >= 0) || !(p->w_rotation >= 0) || !(p->lambda_arap >= 0) ||
       !(p->lm_lambda0 > 0) || p->precision < TT_FP32 || p->precision > TT_FP16_IR || p->ir_iters < 0 ||
-      p->ir_iters > 8 || (p->solver != TT_SOLVE_DENSE && p->solver != TT_SOLVE_NODE))
+      p->ir_iters > 8 || (p->solver != TT_SOLVE_DENSE && p->solver != TT_SOLVE_NODE) ||
+      p->arap_knn < 0 || p->arap_knn > 32)
     return TT_EINVAL;
   if (K->width < 3 || K->height < 3 || !(K->fx > 0) || !(K->fy > 0) || !isfinite(K->cx) || !isfinite(K->cy) ||
       (int64_t)K->width * K->height > (1 << 28))
@@ -915,6 +917,12 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
       free_template(s);
       return TT_EINVAL;
     }
+  }
+  if (s->P.arap_knn > 0 && N > 1) {
+    d.adj_words = (N + 31) / 32;
+    ALLOC(allocs_template, bytes_template, d.adj, (size_t)N * d.adj_words);
+    HIPCHK(hipMemsetAsync(d.adj, 0, sizeof(uint32_t) * (size_t)N * d.adj_words, st));
+    HIPCHK(launch_node_graph(d, s->P.arap_knn, st));
   }
   double sbar = 1.0, sarap = 0.0;
   HIPCHK(launch_template_tables(d, st, &sbar, &sarap));

@@ -1,6 +1,7 @@
 // tt_frame.hip -- template set-up and per-frame front kernels for gfx950:
 //   * control points by farthest-point sampling, blend neighbours and Gaussian weights
-//     (Sec. 2: sparse control points whose warps the template interpolates);
+//     (Sec. 2: sparse control points whose warps the template interpolates); the optional
+//     k-nearest-node ARAP graph (the sparse alternative to Sec. 2.2's dense connection);
 //   * target normal map from the depth map (Sec. 2: point-to-plane ICP along the normal);
 //   * Hamming matching of template ORB descriptors against the frame (Sec. 2.1);
 //   * 1-point RANSAC + reweighting inlier pre-selection in FP64 (Sec. 2.1, Eqs. (2)-(4)).
@@ -125,18 +126,51 @@ __global__ void k_node_nn(const float4* __restrict__ c0, int N, double* __restri
   out[i] = sqrt(best);
 }
 
-// sum over ordered pairs of the ARAP pair weights exp(-d^2 / (2 (2 sbar)^2)), per row
-__global__ void k_arap_rowsum(const float4* __restrict__ c0, int N, double sbar, double* __restrict__ out) {
+// sum over ordered pairs of the ARAP pair weights exp(-d^2 / (2 (2 sbar)^2)), per row; with a
+// sparse graph (adj != nullptr) only over the pairs in it
+__global__ void k_arap_rowsum(const float4* __restrict__ c0, int N, double sbar, const uint32_t* __restrict__ adj,
+                              int words, double* __restrict__ out) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   float4 a = c0[i];
   double sa = 2.0 * sbar, acc = 0.0;
   for (int k = 0; k < N; k++) {
     if (k == i) continue;
+    if (adj && !((adj[(size_t)i * words + (k >> 5)] >> (k & 31)) & 1u)) continue;
     float4 b = c0[k];
     acc += exp(-d2_f64(a.x, a.y, a.z, b.x, b.y, b.z) / (2.0 * sa * sa));
   }
   out[i] = acc;
+}
+
+// Sparse ARAP graph: node a keeps its k nearest other nodes (FP64 squared rest distance, ties to
+// the lower index), found as k successive minima of (distance, index) above the last one taken;
+// both directions of each kept pair are set, so the graph is symmetric. adj starts zeroed.
+__global__ void k_node_graph(const float4* __restrict__ c0, int N, int k, uint32_t* __restrict__ adj, int words) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= N) return;
+  const float4 ca = c0[a];
+  double last_d = -1.0;
+  int last_b = -1;
+  for (int r = 0; r < k && r < N - 1; r++) {
+    double bd = DBL_MAX;
+    int bb = -1;
+    for (int b = 0; b < N; b++) {
+      if (b == a) continue;
+      const float4 cb = c0[b];
+      const double d = d2_f64(ca.x, ca.y, ca.z, cb.x, cb.y, cb.z);
+      const bool after = d > last_d || (d == last_d && b > last_b);
+      if (after && (d < bd || (d == bd && b < bb))) {
+        bd = d;
+        bb = b;
+      }
+    }
+    if (bb < 0) break;
+    atomicOr(&adj[(size_t)a * words + (bb >> 5)], 1u << (bb & 31));
+    atomicOr(&adj[(size_t)bb * words + (a >> 5)], 1u << (a & 31));
+    last_d = bd;
+    last_b = bb;
+  }
 }
 
 // deterministic single-workgroup sum of n doubles
@@ -507,7 +541,8 @@ hipError_t launch_template_tables(DevState& d, hipStream_t st, double* sbar_out,
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return e;
   double sbar = s / N;
-  hipLaunchKernelGGL(k_arap_rowsum, dim3((N + 255) / 256), dim3(256), 0, st, d.c0, N, sbar, tmp);
+  hipLaunchKernelGGL(k_arap_rowsum, dim3((N + 255) / 256), dim3(256), 0, st, d.c0, N, sbar, d.adj, d.adj_words,
+                     tmp);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, st, tmp, N, dsum);
   double sa = 0.0;
   e = hipMemcpyAsync(&sa, dsum, sizeof(double), hipMemcpyDeviceToHost, st);
@@ -516,6 +551,12 @@ hipError_t launch_template_tables(DevState& d, hipStream_t st, double* sbar_out,
   if (e != hipSuccess) return e;
   *sbar_out = sbar;
   *sarap_out = sa;
+  return hipGetLastError();
+}
+
+hipError_t launch_node_graph(DevState& d, int k, hipStream_t st) {
+  if (d.N > 1)
+    hipLaunchKernelGGL(k_node_graph, dim3((d.N + 255) / 256), dim3(256), 0, st, d.c0, d.N, k, d.adj, d.adj_words);
   return hipGetLastError();
 }
 

@@ -67,6 +67,8 @@ struct DevState {
   int* blk_ptr = nullptr;
   uint32_t* blk_ent = nullptr;
   double sbar = 0.0, s_arap = 0.0;
+  uint32_t* adj = nullptr;   // [N][adj_words] sparse ARAP graph bit rows (nullptr: every pair)
+  int adj_words = 0;
   // warps
   float *W = nullptr, *Wc = nullptr;
   float4 *pos = nullptr, *posc = nullptr;    // p_i^t
@@ -184,6 +186,7 @@ struct Intr {
 
 hipError_t launch_fps(const DevState& d, int M, int N, int* err_flag, hipStream_t st);
 hipError_t launch_template_tables(DevState& d, hipStream_t st, double* sbar_out, double* sarap_out);
+hipError_t launch_node_graph(DevState& d, int k, hipStream_t st);
 hipError_t launch_knn(const DevState& d, double sbar, hipStream_t st);
 
 hipError_t launch_normal_map(const DevState& d, const Intr& K, hipStream_t st);

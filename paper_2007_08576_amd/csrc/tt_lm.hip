@@ -394,7 +394,14 @@ struct ArapArgs {
   float* g;
   double* part;
   Parts P;
+  const uint32_t* adj;  // sparse ARAP graph bit rows, nullptr: every pair
+  int adj_words;
 };
+
+// pair (i, j) is off the sparse ARAP graph: its weight is 0
+__device__ __forceinline__ bool off_graph(const ArapArgs& a, int i, int j) {
+  return a.adj && !((a.adj[(size_t)i * a.adj_words + (j >> 5)] >> (j & 31)) & 1u);
+}
 
 constexpr int kArapThreads = 256;
 constexpr int kArapAcc = 36 + 6;
@@ -427,6 +434,7 @@ __global__ __launch_bounds__(kArapThreads) void k_arap_assemble(ArapArgs a) {
     load_dq(a.W, j, qj);
     const float4 cj = a.c0[j], pj = a.ndisp[j];
     PairGeom pg = pair_geom(ci, cj, pi, pj, qi, qj, w_arap, a.inv8s2);
+    if (off_graph(a, i, j)) pg.W2 = 0.0f;
     const float W2 = pg.W2, wg = a.wg, wr = a.wr;
     if (j > i) cost += pair_cost(pg, qi, qj, wg, wr);
     float Gj[12];
@@ -829,6 +837,7 @@ __global__ __launch_bounds__(kArapThreads) void k_cost_arap(ArapArgs a, const fl
     float qj[8];
     load_dq(Wc, j, qj);
     PairGeom pg = pair_geom(ci, a.c0[j], pi, ndispc[j], qi, qj, w_arap, a.inv8s2);
+    if (off_graph(a, i, j)) pg.W2 = 0.0f;
     cost += pair_cost(pg, qi, qj, a.wg, a.wr);
   }
   double t = block_sum_d<kArapThreads>(cost, sh);
@@ -928,6 +937,8 @@ ArapArgs arap_args(DevState& d, const tt_params& P) {
   a.inv8s2 = (float)(1.0 / (2.0 * sa * sa));
   a.sc = d.sc; a.A = d.A; a.g = d.g; a.part = d.partial;
   a.P = parts_of(d.M, d.K1, d.N);
+  a.adj = d.adj;
+  a.adj_words = d.adj_words;
   return a;
 }
 
