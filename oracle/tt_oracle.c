@@ -291,6 +291,7 @@ void tto_default_params(tto_params* p) {
   p->seed = 0;
   p->solver = TTO_SOLVE_DENSE;
   p->arap_knn = 0;
+  p->assoc_zbuffer = 0;
 }
 
 static void free_frame(tto_stream* s) {
@@ -317,7 +318,7 @@ int tto_create_stream(const tto_params* p, const tto_intrinsics* K, tto_stream**
       p->ransac_iters < 1 || p->lm_iters < 0 || !(p->H > 0) || !(p->tukey_c > 0) ||
       !(p->w_orb >= 0) || !(p->w_angle >= 0) || !(p->w_rotation >= 0) || !(p->lambda_arap >= 0) ||
       !(p->lm_lambda0 > 0) || (p->solver != TTO_SOLVE_DENSE && p->solver != TTO_SOLVE_NODE) ||
-      p->arap_knn < 0 || p->arap_knn > 32)
+      p->arap_knn < 0 || p->arap_knn > 32 || (p->assoc_zbuffer != 0 && p->assoc_zbuffer != 1))
     return TTO_EINVAL;
   if (K->width < 3 || K->height < 3 || !(K->fx > 0) || !(K->fy > 0) || !isfinite(K->cx) ||
       !isfinite(K->cy))
@@ -863,6 +864,8 @@ typedef struct {
   double* r_icp;   /* [M] point-to-plane residual at the association state */
   double* orbw;    /* [K1] feature weight */
   double w_arap;
+  int32_t* zwin;   /* [H*W] z-buffer: the point nearest the camera at each pixel, -1 (z-buffer mode) */
+  float* zmin;     /* [H*W] its z */
 } assoc_t;
 
 static int assoc_alloc(const tto_stream* s, assoc_t* a) {
@@ -872,9 +875,30 @@ static int assoc_alloc(const tto_stream* s, assoc_t* a) {
   a->r_icp = (double*)malloc(sizeof(double) * M);
   a->orbw = (double*)malloc(sizeof(double) * K1a);
   a->w_arap = 0.0;
+  a->zwin = NULL;
+  a->zmin = NULL;
+  if (s->P.assoc_zbuffer) {
+    size_t HW = (size_t)s->K.width * s->K.height;
+    a->zwin = (int32_t*)malloc(sizeof(int32_t) * HW);
+    a->zmin = (float*)malloc(sizeof(float) * HW);
+    if (!a->zwin || !a->zmin) return -1;
+  }
   return (a->corr && a->omega && a->r_icp && a->orbw) ? 0 : -1;
 }
-static void assoc_free(assoc_t* a) { free(a->corr); free(a->omega); free(a->r_icp); free(a->orbw); }
+static void assoc_free(assoc_t* a) {
+  free(a->corr); free(a->omega); free(a->r_icp); free(a->orbw); free(a->zwin); free(a->zmin);
+}
+
+/* Nearest pixel of a camera-frame point, u = floor(fx x / z + cx + 1/2) (same for v), or -1 if
+ * z <= 0 or the pixel is outside the image. */
+static int nearest_pixel(const tto_intrinsics* K, const double* v) {
+  if (!(v[2] > 0.0)) return -1;
+  double uf = K->fx * v[0] / v[2] + K->cx;
+  double vf = K->fy * v[1] / v[2] + K->cy;
+  double ur = floor(uf + 0.5), vr = floor(vf + 0.5);
+  if (!(ur >= 0.0 && ur < (double)K->width && vr >= 0.0 && vr < (double)K->height)) return -1;
+  return (int)vr * K->width + (int)ur;
+}
 
 /* current node positions p_i^t = W_i^t(p_i^0) */
 static void node_positions(const tto_stream* s, const double* dq, double* pos) {
@@ -892,18 +916,29 @@ static void associate(const tto_stream* s, const double* dq, assoc_t* a, int set
   const tto_intrinsics* K = &s->K;
   int kk = s->kk;
   double sumw = 0.0;
+  if (a->zwin) {
+    /* z-buffer ("rasterization", Sec. 2): a pixel belongs to the template point nearest the
+     * camera among those that project to it */
+    size_t HW = (size_t)K->width * K->height;
+    for (size_t p = 0; p < HW; p++) { a->zwin[p] = -1; a->zmin[p] = INFINITY; }
+    for (int j = 0; j < s->M; j++) {
+      double v[3];
+      tto_dqb(dq, s->knn_pts + kk * j, s->alpha_pts + kk * j, kk, s->pts + 3 * j, v);
+      int pix = nearest_pixel(K, v);
+      if (pix < 0) continue;
+      float z = (float)v[2];
+      if (z < a->zmin[pix]) { a->zmin[pix] = z; a->zwin[pix] = j; } /* equal z: lower j kept */
+    }
+  }
   for (int j = 0; j < s->M; j++) {
     double v[3];
     tto_dqb(dq, s->knn_pts + kk * j, s->alpha_pts + kk * j, kk, s->pts + 3 * j, v);
     a->corr[j] = -1;
     a->omega[j] = 0.0;
     a->r_icp[j] = 0.0;
-    if (!(v[2] > 0.0)) continue;
-    double uf = K->fx * v[0] / v[2] + K->cx;
-    double vf = K->fy * v[1] / v[2] + K->cy;
-    double ur = floor(uf + 0.5), vr = floor(vf + 0.5);
-    if (!(ur >= 0.0 && ur < (double)K->width && vr >= 0.0 && vr < (double)K->height)) continue;
-    int pix = (int)vr * K->width + (int)ur;
+    int pix = nearest_pixel(K, v);
+    if (pix < 0) continue;
+    if (a->zwin && a->zwin[pix] != j) continue; /* hidden behind another template point */
     if (!s->nvalid[pix]) continue;
     const double* n = s->normals + 3 * pix;
     const double* q = s->qpts + 3 * pix;

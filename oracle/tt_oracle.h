@@ -63,6 +63,9 @@ typedef struct {
   int solver;             /* TTO_SOLVE_DENSE or TTO_SOLVE_NODE */
   int arap_knn;           /* 0: ARAP over all pairs of control points (Sec. 2.2, dense); k > 0:
                              only pairs where one node is among the other's k nearest (0..32) */
+  int assoc_zbuffer;      /* 0: every deformed template point takes its nearest pixel; 1: of the
+                             points that project to one pixel only the nearest to the camera
+                             (smallest z as float32, ties to the lower index) takes it */
 } tto_params;
 
 typedef struct tto_stream tto_stream;

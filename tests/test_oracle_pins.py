@@ -931,3 +931,55 @@ def test_sparse_arap_normal_equations(O):
         assert np.abs(A0[6 * a:6 * a + 6, 6 * b:6 * b + 6]).max() > 0
     for a, b in zip(*np.nonzero(adj & ~share)):
         assert np.abs(A2[6 * a:6 * a + 6, 6 * b:6 * b + 6]).max() > 0
+
+
+# ------------------------------------------------------------------------------------------------
+# z-buffered association (the "rasterization" of Sec. 2 read with visibility)
+
+def two_layer_scene():
+    """A plane's interior pixel centres (front) and the same points at twice the distance (back,
+    on the same camera rays, so on the same pixels), back layer first in index order, plus an
+    exact copy of front point 0 at the end (an equal-z tie that the lower index wins)."""
+    K, depth, P = scenes.dyadic_plane()
+    front = P[2:-2, 2:-2].reshape(-1, 3)
+    back = 2.0 * front
+    pts = np.vstack([back, front, front[:1]]).astype(np.float32)
+    return K, depth, pts, len(back), len(front)
+
+
+def test_zbuffer_keeps_only_the_nearest_point_per_pixel(O):
+    K, depth, pts, nb, nf = two_layer_scene()
+    rng = np.random.default_rng(34)
+    desc = rng.integers(0, 256, (4, 32), dtype=np.uint8)
+    fi = np.arange(nb, nb + 4)
+    corr = {}
+    for zb in (0, 1):
+        s = O.Stream(O.default_params(num_control_points=8, lm_iters=1, assoc_zbuffer=zb), _intr(O, K))
+        s.set_template(pts, pts[fi], desc)
+        _, _, d = s.track_frame(depth, pts[fi], desc, debug=True)
+        corr[zb] = d["corr0"]
+    pix_front = corr[0][nb:nb + nf]
+    assert (pix_front >= 0).all()
+    # without the z-buffer the back layer takes the same pixels as the front layer
+    assert np.array_equal(corr[0][:nb], pix_front)
+    assert corr[0][-1] == pix_front[0]
+    # with it the back layer and the later copy are hidden; the front layer keeps its pixels
+    assert (corr[1][:nb] == -1).all()
+    assert np.array_equal(corr[1][nb:nb + nf], pix_front)
+    assert corr[1][-1] == -1
+
+
+def test_zbuffer_without_collisions_changes_nothing(O):
+    """At the identity every config 1 template point has a pixel of its own, so the first
+    iteration is the same with and without the z-buffer."""
+    sc = synth.make_config1(1)
+    fr = sc.frame(1)
+    out = []
+    for zb in (0, 1):
+        s = O.Stream(O.default_params(num_control_points=64, seed=1, lm_iters=1, assoc_zbuffer=zb),
+                     _intr(O, sc.intr))
+        s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        out.append(s.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][2]["corr0"], out[1][2]["corr0"])
+    assert len(np.unique(out[0][2]["corr0"][out[0][2]["corr0"] >= 0])) == (out[0][2]["corr0"] >= 0).sum()
