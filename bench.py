@@ -307,14 +307,16 @@ def solver_study(args, torch, tt, sc, frames, dframes):
     dense connection) against the coupled dense solve with dense ARAP on config 2: frames/s of
     each, and how far each gets in the frame's 10 LM iterations: frames 1..F tracked in sequence
     from the identity (warm-started), vertex RMS against the generator's ground truth and the cost
-    left after the last iteration (the sparse graph's cost has fewer ARAP terms)."""
+    left after the last iteration (the sparse graph's cost has fewer ARAP terms); and the
+    z-buffered association (nearest template point per pixel) with the dense solve."""
     dev = torch.device("cuda:0")
     out = {}
     intr = tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy)
-    for name, solver, knn in (("dense", tt.TT_SOLVE_DENSE, 0), ("node", tt.TT_SOLVE_NODE, 0),
-                              ("dense_arap_knn8", tt.TT_SOLVE_DENSE, 8)):
+    for name, solver, knn, zb in (("dense", tt.TT_SOLVE_DENSE, 0, 0), ("node", tt.TT_SOLVE_NODE, 0, 0),
+                                  ("dense_arap_knn8", tt.TT_SOLVE_DENSE, 8, 0),
+                                  ("dense_zbuffer", tt.TT_SOLVE_DENSE, 0, 1)):
         s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=2, solver=solver,
-                                        arap_knn=knn), intr)
+                                        arap_knn=knn, assoc_zbuffer=zb), intr)
         s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
         rms, cost = [], []
         for fr in frames:

@@ -92,6 +92,11 @@ typedef struct {
   int arap_knn;            /* 0 (default): ARAP over every pair of control points, the dense
                               connection of Sec. 2.2; k in 1..32: only pairs where one node is
                               among the other's k nearest at time 0 (ties to the lower index) */
+  int assoc_zbuffer;       /* 0 (default): every deformed template point takes its nearest pixel
+                              (Sec. 2's projective association); 1: z-buffered, of the points
+                              that project to one pixel only the nearest to the camera (smallest
+                              z as float32, ties to the lower index) takes it, the others have no
+                              ICP row in that iteration */
 } tt_params;
 
 /* Optional per-frame outputs of tt_track_frame; each pointer may be NULL. Sizes: K1 template

@@ -574,6 +574,7 @@ void tt_default_params(tt_params* p) {
   p->ir_iters = 2;
   p->solver = TT_SOLVE_DENSE;
   p->arap_knn = 0;
+  p->assoc_zbuffer = 0;
 }
 
 const char* tt_strerror(int code) {
@@ -604,7 +605,7 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
       !(p->w_orb >= 0) || !(p->w_angle >= 0) || !(p->w_rotation >= 0) || !(p->lambda_arap >= 0) ||
       !(p->lm_lambda0 > 0) || p->precision < TT_FP32 || p->precision > TT_FP16_IR || p->ir_iters < 0 ||
       p->ir_iters > 8 || (p->solver != TT_SOLVE_DENSE && p->solver != TT_SOLVE_NODE) ||
-      p->arap_knn < 0 || p->arap_knn > 32)
+      p->arap_knn < 0 || p->arap_knn > 32 || (p->assoc_zbuffer != 0 && p->assoc_zbuffer != 1))
     return TT_EINVAL;
   if (K->width < 3 || K->height < 3 || !(K->fx > 0) || !(K->fy > 0) || !isfinite(K->cx) || !isfinite(K->cy) ||
       (int64_t)K->width * K->height > (1 << 28))
@@ -865,6 +866,10 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
   ALLOC(allocs_template, bytes_template, d.rres, (size_t)M);
   ALLOC(allocs_template, bytes_template, d.omega, (size_t)M);
   ALLOC(allocs_template, bytes_template, d.jac, (size_t)24 * M);
+  if (s->P.assoc_zbuffer) {
+    ALLOC(allocs_template, bytes_template, d.zbuf, (size_t)d.HW);
+    ALLOC(allocs_template, bytes_template, d.zpix, (size_t)M);
+  }
   ALLOC(allocs_template, bytes_template, d.wres, (size_t)M);
   ALLOC(allocs_template, bytes_template, d.orbw, K1a);
   ALLOC(allocs_template, bytes_template, d.jacF, 72 * K1a);

@@ -69,6 +69,8 @@ struct DevState {
   double sbar = 0.0, s_arap = 0.0;
   uint32_t* adj = nullptr;   // [N][adj_words] sparse ARAP graph bit rows (nullptr: every pair)
   int adj_words = 0;
+  unsigned long long* zbuf = nullptr; // [HW] z-buffer keys (z bits << 32 | point), z-buffered association
+  int* zpix = nullptr;       // [M] pixel of each deformed template point in the z-buffer pass
   // warps
   float *W = nullptr, *Wc = nullptr;
   float4 *pos = nullptr, *posc = nullptr;    // p_i^t

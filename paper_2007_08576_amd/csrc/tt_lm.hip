@@ -1,6 +1,7 @@
 // tt_lm.hip -- one Levenberg-Marquardt iteration of Eq. (1) on the device (Sec. 2):
 //
 //   k_node_prep        node positions p_i^t = W_i(p_i^0)
+//   k_zfill, k_zbuffer (z-buffered association only) the nearest point per pixel
 //   k_data_rows        per template point: dual-quaternion blend, nearest-pixel re-projection
 //                      (FP64 index math), point-to-plane residual along the target normal, Tukey
 //                      weight and the weighted 1x24 Jacobian row; per template feature: the
@@ -128,6 +129,9 @@ struct RowArgs {
   int Wd, Hd;
   double fx, fy, cx, cy;
   float tukey_c, w_orb, H;
+  // z-buffered association (nullptr: every point takes its nearest pixel)
+  unsigned long long* zbuf;
+  int* zpix;
   // outputs
   int* corr;
   float *rres, *omega, *jac, *wres;
@@ -160,6 +164,38 @@ __device__ __forceinline__ float plane_residual(f3 p, f3 d, int pix, float4 nm, 
   return dot(mk3(nm.x, nm.y, nm.z), d + pq);
 }
 
+// z-buffer pass of the association: every deformed template point that projects into the
+// image claims its pixel with the key (float bits of z << 32 | point index); the smallest key
+// wins (z > 0, so the float bits order like the values). The pixel is kept for the row pass.
+__global__ void k_zfill(unsigned long long* __restrict__ zbuf, int HW) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < HW) zbuf[p] = ~0ull;
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_zbuffer(RowArgs a) {
+  int j = blockIdx.x * kRowThreads + threadIdx.x;
+  if (j >= a.M) return;
+  int4 nb = a.knn[j];
+  float4 al = a.alpha[j];
+  float q0[8], q1[8], q2[8], q3[8];
+  load_dq(a.W, nb.x, q0);
+  load_dq(a.W, nb.y, q1);
+  load_dq(a.W, nb.z, q2);
+  load_dq(a.W, nb.w, q3);
+  const float alv[4] = {al.x, al.y, al.z, al.w};
+  float b[8], sg[4];
+  dq_blend4(q0, q1, q2, q3, alv, b, sg);
+  f3 p = mk3(a.px[j], a.py[j], a.pz[j]);
+  f3 dp = dq_disp(b, p);
+  int pix = project_pixel(p, dp, a);
+  a.zpix[j] = pix;
+  if (pix >= 0) {
+    const float z = (float)((double)p.z + (double)dp.z);
+    const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | (unsigned)j;
+    atomicMin(&a.zbuf[pix], key);
+  }
+}
+
 __global__ __launch_bounds__(kRowThreads) void k_data_rows(RowArgs a, int it) {
   __shared__ double sh[kRowThreads];
   const int tid = threadIdx.x;
@@ -180,7 +216,13 @@ __global__ __launch_bounds__(kRowThreads) void k_data_rows(RowArgs a, int it) {
       dq_blend4(q0, q1, q2, q3, alv, b, sg);
       f3 p = mk3(a.px[j], a.py[j], a.pz[j]);
       f3 dp = dq_disp(b, p);
-      int pix = project_pixel(p, dp, a);
+      int pix;
+      if (a.zbuf) {
+        pix = a.zpix[j];  // the pixel of the z-buffer pass; kept only by the point nearest the camera
+        if (pix >= 0 && (unsigned)(a.zbuf[pix] & 0xffffffffull) != (unsigned)j) pix = -1;
+      } else {
+        pix = project_pixel(p, dp, a);
+      }
       float r = 0.0f, om = 0.0f;
       f3 n = mk3(0.f, 0.f, 0.f);
       if (pix >= 0) {
@@ -926,6 +968,8 @@ RowArgs row_args(DevState& d, const tt_params& P, const Intr& K) {
   a.orbw = d.orbw; a.jacF = d.jacF; a.wresF = d.wresF;
   a.part = d.partial;
   a.P = parts_of(d.M, d.K1, d.N);
+  a.zbuf = d.zbuf;
+  a.zpix = d.zpix;
   return a;
 }
 
@@ -959,6 +1003,10 @@ hipError_t launch_lm_begin(DevState& d, double lambda0, hipStream_t st) {
 // data blocks.
 hipError_t launch_lm_rows(DevState& d, const tt_params& P, const Intr& K, int it, hipStream_t st) {
   RowArgs ra = row_args(d, P, K);
+  if (d.zbuf) {
+    hipLaunchKernelGGL(k_zfill, dim3((d.HW + 255) / 256), dim3(256), 0, st, d.zbuf, d.HW);
+    hipLaunchKernelGGL(k_zbuffer, dim3((d.M + kRowThreads - 1) / kRowThreads), dim3(kRowThreads), 0, st, ra);
+  }
   hipLaunchKernelGGL(k_data_rows, dim3(ra.P.nbp + ra.P.nbf), dim3(kRowThreads), 0, st, ra, it);
   if (it == 0)
     hipLaunchKernelGGL(k_lm_scalars, dim3(1), dim3(256), 0, st, d.partial, ra.P, P.lambda_arap, P.w_orb, d.s_arap,

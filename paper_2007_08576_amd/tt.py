@@ -38,7 +38,8 @@ class Params(C.Structure):
                 ("ransac_iters", C.c_int), ("lm_iters", C.c_int), ("max_hamming", C.c_int),
                 ("lm_lambda0", C.c_double), ("precision", C.c_int), ("seed", C.c_uint64),
                 ("hbm_budget_bytes", C.c_uint64), ("ir_iters", C.c_int),
-                ("solver", C.c_int), ("arap_knn", C.c_int)]
+                ("solver", C.c_int), ("arap_knn", C.c_int),
+                ("assoc_zbuffer", C.c_int)]
 
 
 _DEBUG_FIELDS = ("match_idx", "match_dist", "wstar", "preselected", "hyp_k0", "hyp_W", "hyp_nin",

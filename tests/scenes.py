@@ -70,3 +70,15 @@ def lattice_scene(n_side=17, spacing=50.0, z=401.0, f_half=2):
     R = np.array([[399.0, -40.0, 0.0], [40.0, 399.0, 0.0], [0.0, 0.0, 401.0]]) / 401.0
     t = np.array([3.0, -2.0, 1.0])
     return pts, feats, R, t
+
+
+def two_layer_scene():
+    """A plane's interior pixel centres (front) and the same points at twice the distance (back,
+    on the same camera rays, so on the same pixels), back layer first in index order, plus an
+    exact copy of front point 0 at the end (an equal-z tie that the lower index wins).
+    Returns (intrinsics, depth, template points float32, back count, front count)."""
+    K, depth, P = dyadic_plane()
+    front = P[2:-2, 2:-2].reshape(-1, 3)
+    back = 2.0 * front
+    pts = np.vstack([back, front, front[:1]]).astype(np.float32)
+    return K, depth, pts, len(back), len(front)

@@ -936,19 +936,8 @@ def test_sparse_arap_normal_equations(O):
 # ------------------------------------------------------------------------------------------------
 # z-buffered association (the "rasterization" of Sec. 2 read with visibility)
 
-def two_layer_scene():
-    """A plane's interior pixel centres (front) and the same points at twice the distance (back,
-    on the same camera rays, so on the same pixels), back layer first in index order, plus an
-    exact copy of front point 0 at the end (an equal-z tie that the lower index wins)."""
-    K, depth, P = scenes.dyadic_plane()
-    front = P[2:-2, 2:-2].reshape(-1, 3)
-    back = 2.0 * front
-    pts = np.vstack([back, front, front[:1]]).astype(np.float32)
-    return K, depth, pts, len(back), len(front)
-
-
 def test_zbuffer_keeps_only_the_nearest_point_per_pixel(O):
-    K, depth, pts, nb, nf = two_layer_scene()
+    K, depth, pts, nb, nf = scenes.two_layer_scene()
     rng = np.random.default_rng(34)
     desc = rng.integers(0, 256, (4, 32), dtype=np.uint8)
     fi = np.arange(nb, nb + 4)
