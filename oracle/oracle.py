@@ -45,6 +45,13 @@ SOLVE_DENSE, SOLVE_NODE = 0, 1
 _P = C.c_void_p
 
 
+class OrbParams(C.Structure):
+    _fields_ = [("fast_threshold", C.c_int), ("nms_radius", C.c_int), ("max_features", C.c_int)]
+
+
+ORB_BORDER = 18
+
+
 class FrameDebug(C.Structure):
     _fields_ = [(n, _P) for n in (
         "match_idx", "match_dist", "wstar", "preselected", "hyp_k0", "hyp_W", "hyp_nin",
@@ -86,6 +93,11 @@ def _declare(L):
     L.tto_cholesky.argtypes = [vp, C.c_int, vp]
     L.tto_cholesky_solve.argtypes = [vp, C.c_int, vp, vp]
     L.tto_cholesky_solve.restype = None
+    L.tto_orb_default_params.argtypes = [C.POINTER(OrbParams)]
+    L.tto_orb_default_params.restype = None
+    L.tto_fast_response.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
+    L.tto_orb_detect.argtypes = [vp, C.c_int, C.c_int, vp, C.POINTER(Intrinsics), vp, C.POINTER(OrbParams),
+                                 vp, vp, vp, vp, vp]
 
 
 def _ptr(a):
@@ -329,3 +341,37 @@ def cholesky_solve(L, b):
     x = np.zeros_like(b)
     lib().tto_cholesky_solve(_ptr(L), L.shape[0], _ptr(b), _ptr(x))
     return x
+
+
+def orb_params(**kw):
+    p = OrbParams()
+    lib().tto_orb_default_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def fast_response(img, u, v, t):
+    img = _c(img, np.uint8)
+    return lib().tto_fast_response(_ptr(img), img.shape[1], int(u), int(v), int(t))
+
+
+def orb_detect(img, pattern, depth=None, intr=None, **kw):
+    """Uniform ORB keypoints of an 8-bit image: dict(kp [n,2] int32 (u, v), xyz [n,3] float32,
+    desc [n,32] uint8, angle_bin [n] int32, total = corners kept before the cap)."""
+    img = _c(img, np.uint8)
+    H, W = img.shape
+    p = orb_params(**kw)
+    mx = p.max_features
+    kp = np.zeros((max(mx, 1), 2), np.int32)
+    xyz = np.zeros((max(mx, 1), 3), np.float32)
+    desc = np.zeros((max(mx, 1), 32), np.uint8)
+    ang = np.zeros(max(mx, 1), np.int32)
+    cnt = np.zeros(2, np.int32)
+    d = _c(depth, np.float32) if depth is not None else None
+    _check(lib().tto_orb_detect(_ptr(img), W, H, _ptr(d) if d is not None else None,
+                                C.byref(intr) if intr is not None else None, _ptr(_c(pattern, np.int8)),
+                                C.byref(p), _ptr(kp), _ptr(xyz), _ptr(desc), _ptr(ang), _ptr(cnt)), "orb_detect")
+    n = int(cnt[0])
+    return dict(kp=kp[:n].copy(), xyz=xyz[:n].copy(), desc=desc[:n].copy(), angle_bin=ang[:n].copy(),
+                total=int(cnt[1]))

@@ -1455,3 +1455,135 @@ int tto_track_frame(tto_stream* s, const float* depth_mm, const float* feat_xyz,
   assoc_free(&a);
   return TTO_OK;
 }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Uniform ORB features (Sec. 2.1)                                                             */
+
+/* radius-3 circle, clockwise from straight up: (column, row) offsets */
+static const double ORB_PI = 3.14159265358979323846;
+
+static const int FAST_CIRCLE[16][2] = {{0, -3}, {1, -3}, {2, -2}, {3, -1}, {3, 0}, {3, 1}, {2, 2}, {1, 3},
+                                       {0, 3}, {-1, 3}, {-2, 2}, {-3, 1}, {-3, 0}, {-3, -1}, {-2, -2}, {-1, -3}};
+
+void tto_orb_default_params(tto_orb_params* p) {
+  p->fast_threshold = 20;
+  p->nms_radius = 1;
+  p->max_features = 4096;
+}
+
+int tto_fast_response(const uint8_t* img, int W, int u, int v, int t) {
+  int c = img[(size_t)v * W + u];
+  int cls[16], sb = 0, sd = 0;
+  for (int k = 0; k < 16; k++) {
+    int x = img[(size_t)(v + FAST_CIRCLE[k][1]) * W + u + FAST_CIRCLE[k][0]];
+    if (x > c + t) { cls[k] = 1; sb += x - c - t; }
+    else if (x < c - t) { cls[k] = -1; sd += c - x - t; }
+    else cls[k] = 0;
+  }
+  /* longest cyclic run of one class: walk twice around the circle */
+  int best = 0;
+  for (int want = -1; want <= 1; want += 2) {
+    int run = 0;
+    for (int k = 0; k < 32; k++) {
+      run = (cls[k % 16] == want) ? run + 1 : 0;
+      if (run > best) best = run;
+    }
+  }
+  if (best < 9) return 0;
+  return sb > sd ? sb : sd;
+}
+
+int tto_orb_detect(const uint8_t* img, int W, int H, const float* depth, const tto_intrinsics* K,
+                   const int8_t* pattern, const tto_orb_params* p, int32_t* kp, float* xyz,
+                   uint8_t* desc, int32_t* angle_bin, int32_t* count) {
+  if (!img || !pattern || !p || !count || W < 1 || H < 1 || p->fast_threshold < 0 || p->nms_radius < 0 ||
+      p->max_features < 0 || (depth && !K) || (p->max_features > 0 && (!kp || !desc)))
+    return TTO_EINVAL;
+  const int B = TTO_ORB_BORDER;
+  size_t HW = (size_t)W * H;
+  int32_t* R = (int32_t*)calloc(HW, sizeof(int32_t));
+  int32_t* S = (int32_t*)calloc(HW, sizeof(int32_t));
+  int (*rot)[256][4] = (int (*)[256][4])malloc(sizeof(int) * 30 * 256 * 4);
+  if (!R || !S || !rot) { free(R); free(S); free(rot); return TTO_ENOMEM; }
+  /* corner responses inside the detection region */
+  for (int v = B; v < H - B; v++)
+    for (int u = B; u < W - B; u++) R[(size_t)v * W + u] = tto_fast_response(img, W, u, v, p->fast_threshold);
+  /* 5 x 5 box sums */
+  for (int v = 2; v < H - 2; v++)
+    for (int u = 2; u < W - 2; u++) {
+      int acc = 0;
+      for (int dy = -2; dy <= 2; dy++)
+        for (int dx = -2; dx <= 2; dx++) acc += img[(size_t)(v + dy) * W + u + dx];
+      S[(size_t)v * W + u] = acc;
+    }
+  /* the pattern rotated to each of the 30 orientation bins */
+  for (int b = 0; b < 30; b++) {
+    double th = 2.0 * ORB_PI * b / 30.0, cs = cos(th), sn = sin(th);
+    for (int k = 0; k < 256; k++)
+      for (int h = 0; h < 2; h++) {
+        double x = pattern[4 * k + 2 * h], y = pattern[4 * k + 2 * h + 1];
+        rot[b][k][2 * h] = (int)lround(x * cs - y * sn);
+        rot[b][k][2 * h + 1] = (int)lround(x * sn + y * cs);
+      }
+  }
+  int n = 0, total = 0;
+  const int r = p->nms_radius;
+  for (int v = B; v < H - B; v++)
+    for (int u = B; u < W - B; u++) {
+      size_t i = (size_t)v * W + u;
+      int Ri = R[i];
+      if (Ri <= 0) continue;
+      /* kept iff no other corner in the window has a larger response (ties: lower index wins) */
+      int keep = 1;
+      for (int dy = -r; dy <= r && keep; dy++)
+        for (int dx = -r; dx <= r; dx++) {
+          int uu = u + dx, vv = v + dy;
+          if ((dx == 0 && dy == 0) || uu < 0 || uu >= W || vv < 0 || vv >= H) continue;
+          size_t q = (size_t)vv * W + uu;
+          if (R[q] > Ri || (R[q] == Ri && q < i)) { keep = 0; break; }
+        }
+      if (!keep) continue;
+      total++;
+      if (n >= p->max_features) continue;
+      kp[2 * n] = u;
+      kp[2 * n + 1] = v;
+      /* orientation: intensity centroid over the disc of radius 15 */
+      long m10 = 0, m01 = 0;
+      for (int dy = -15; dy <= 15; dy++)
+        for (int dx = -15; dx <= 15; dx++) {
+          if (dx * dx + dy * dy > 225) continue;
+          int I = img[(size_t)(v + dy) * W + u + dx];
+          m10 += (long)dx * I;
+          m01 += (long)dy * I;
+        }
+      double th = atan2((double)m01, (double)m10);
+      int bin = (int)floor(th * 30.0 / (2.0 * ORB_PI) + 0.5);
+      bin = ((bin % 30) + 30) % 30;
+      if (angle_bin) angle_bin[n] = bin;
+      uint8_t* d = desc + 32 * (size_t)n;
+      memset(d, 0, 32);
+      for (int k = 0; k < 256; k++) {
+        const int* q = rot[bin][k];
+        int sa = S[(size_t)(v + q[1]) * W + u + q[0]];
+        int sb = S[(size_t)(v + q[3]) * W + u + q[2]];
+        if (sa < sb) d[k >> 3] |= (uint8_t)(1u << (k & 7));
+      }
+      if (xyz) {
+        float z = depth ? depth[i] : NAN;
+        if (depth && isfinite(z) && z > 0.0f) {
+          xyz[3 * n] = (float)(((double)u - K->cx) / K->fx * (double)z);
+          xyz[3 * n + 1] = (float)(((double)v - K->cy) / K->fy * (double)z);
+          xyz[3 * n + 2] = z;
+        } else {
+          xyz[3 * n] = xyz[3 * n + 1] = xyz[3 * n + 2] = NAN;
+        }
+      }
+      n++;
+    }
+  count[0] = n;
+  count[1] = total;
+  free(R);
+  free(S);
+  free(rot);
+  return TTO_OK;
+}

@@ -181,6 +181,42 @@ int tto_cholesky(const double* A, int n, double* L);
 /* Solve L L^T x = b with the factor from tto_cholesky. */
 void tto_cholesky_solve(const double* L, int n, const double* b, double* x);
 
+/* ---- Uniform ORB features (Sec. 2.1): FAST corners on the GPU's reading, kept where no
+ * neighbouring pixel has a larger corner response, with oriented binary descriptors. ---- */
+
+/* Pixels closer than this to the image border are never keypoints (FAST circle 3, orientation
+ * disc 15, rotated pattern + 5x5 box 16). */
+#define TTO_ORB_BORDER 18
+
+typedef struct {
+  int fast_threshold; /* t: circle pixels brighter than I_p + t or darker than I_p - t (20)   */
+  int nms_radius;     /* r: a corner is kept iff its response beats every other corner's in the
+                         (2r+1)^2 window around it, ties to the lower pixel index (1)           */
+  int max_features;   /* at most this many keypoints, the first in raster order (4096)        */
+} tto_orb_params;
+
+void tto_orb_default_params(tto_orb_params* p);
+
+/* FAST-9 corner response of pixel (u, v) of an 8-bit image (row-major, W x H): with the 16
+ * pixels of the radius-3 circle, the pixel is a corner iff 9 or more contiguous ones (cyclic)
+ * are all brighter than I_p + t or all darker than I_p - t; its response is then
+ * max(sum over brighter of (I - I_p - t), sum over darker of (I_p - I - t)), else 0. (u, v)
+ * must be at least 3 pixels from the border. */
+int tto_fast_response(const uint8_t* img, int W, int u, int v, int t);
+
+/* Keypoints, 3D points and descriptors of an 8-bit image.
+ *   kp [max][2] (u, v), raster order; xyz [max][3]: the back-projected depth at the keypoint
+ *   (NaN if depth is NULL or the pixel's depth is invalid); desc [max][32]: bit k (byte k/8,
+ *   bit k%8 from the least significant) = 1 iff S(p + a_k) < S(p + b_k), with S the 5x5 box
+ *   sum of the image and (a_k, b_k) = pattern row k = (x1, y1, x2, y2) rotated to the
+ *   keypoint's orientation bin; angle_bin [max] in 0..29: the intensity-centroid angle
+ *   atan2(m01, m10) over the disc of radius 15, in 12-degree bins rounded to nearest.
+ *   count[0] = keypoints written, count[1] = corners kept before the max_features cap.
+ * K may be NULL when depth is NULL. Returns 0 or TTO_EINVAL / TTO_ENOMEM. */
+int tto_orb_detect(const uint8_t* img, int W, int H, const float* depth, const tto_intrinsics* K,
+                   const int8_t* pattern, const tto_orb_params* p, int32_t* kp, float* xyz,
+                   uint8_t* desc, int32_t* angle_bin, int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

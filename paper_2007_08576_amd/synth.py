@@ -112,10 +112,12 @@ def backproject_grid(depth: np.ndarray, K: Intrinsics) -> np.ndarray:
     return np.stack([(u - K.cx) / K.fx * z, (v - K.cy) / K.fy * z, z], -1)
 
 
-def render_depth(P: np.ndarray, K: Intrinsics) -> np.ndarray:
+def render_depth(P: np.ndarray, K: Intrinsics, attr: np.ndarray | None = None):
     """Z-buffered depth of the grid mesh with vertices P (H, W, 3): two triangles per 2 x 2
     quad, perspective-correct depth (1/z interpolated in screen space) at pixel centres.
-    Uncovered pixels get depth 0 (invalid)."""
+    Uncovered pixels get depth 0 (invalid). With attr (H, W, C) per vertex, also returns the
+    attribute of the visible surface at every pixel centre (perspective-correct, NaN where
+    uncovered)."""
     H, W = P.shape[:2]
     X = P.reshape(-1, 3)
     z = X[:, 2]
@@ -148,6 +150,8 @@ def render_depth(P: np.ndarray, K: Intrinsics) -> np.ndarray:
     total = int(cnt.sum())
     zbuf = np.full(H * W, np.inf)
     if total == 0:
+        if attr is not None:
+            return np.zeros((H, W), np.float32), np.full((H, W, attr.shape[-1]), np.nan)
         return np.zeros((H, W), np.float32)
     rep = np.repeat(tri_i, cnt)
     start = np.repeat(np.cumsum(cnt) - cnt, cnt)
@@ -169,7 +173,70 @@ def render_depth(P: np.ndarray, K: Intrinsics) -> np.ndarray:
     zz = 1.0 / invz[inside]
     np.minimum.at(zbuf, pix, zz)
     out = np.where(np.isfinite(zbuf), zbuf, 0.0).astype(np.float32)
-    return out.reshape(H, W)
+    if attr is None:
+        return out.reshape(H, W)
+    # attribute of the nearest candidate of each pixel
+    A = attr.reshape(-1, attr.shape[-1]).astype(np.float64)
+    ti = tri[rep][inside]
+    w = np.stack([l0[inside] / tz[rep, 0][inside], l1[inside] / tz[rep, 1][inside],
+                  l2[inside] / tz[rep, 2][inside]], 1)
+    order = np.lexsort((zz, pix))
+    first = order[np.r_[True, pix[order][1:] != pix[order][:-1]]]
+    vals = (w[first, :, None] * A[ti[first]]).sum(1) * zz[first, None]
+    img = np.full((H * W, A.shape[1]), np.nan)
+    img[pix[first]] = vals
+    return out.reshape(H, W), img.reshape(H, W, -1)
+
+
+def surface_texture(seed: int, name: str, width: int, height: int):
+    """A fixed random texture painted on the template surface, as a function of the template
+    image coordinates (u0, v0): value noise (lattice values blended with smoothstep weights) at
+    periods of 16, 8 and 4 pixels. Returns f(u0, v0) -> intensity in [0, 255] (float)."""
+    rng = Rng(seed, f"{name}/texture")
+    octaves = []
+    for period, amp in ((16.0, 0.5), (8.0, 0.3), (4.0, 0.2)):
+        gw, gh = int(width / period) + 3, int(height / period) + 3
+        octaves.append((period, amp, rng.uniform(gw * gh).reshape(gh, gw)))
+
+    def f(u0, v0):
+        u0, v0 = np.asarray(u0, np.float64), np.asarray(v0, np.float64)
+        bad = ~(np.isfinite(u0) & np.isfinite(v0))
+        u0, v0 = np.where(bad, 0.0, u0), np.where(bad, 0.0, v0)
+        acc = np.zeros(np.shape(u0))
+        for period, amp, g in octaves:
+            x = np.clip(u0 / period, 0, g.shape[1] - 2.000001)
+            y = np.clip(v0 / period, 0, g.shape[0] - 2.000001)
+            ix, iy = np.floor(x).astype(np.int64), np.floor(y).astype(np.int64)
+            fx, fy = x - ix, y - iy
+            fx, fy = fx * fx * (3 - 2 * fx), fy * fy * (3 - 2 * fy)  # smoothstep: no creases
+            val = (g[iy, ix] * (1 - fx) * (1 - fy) + g[iy, ix + 1] * fx * (1 - fy)
+                   + g[iy + 1, ix] * (1 - fx) * fy + g[iy + 1, ix + 1] * fx * fy)
+            acc = acc + amp * val
+        return np.where(bad, np.nan, 255.0 * acc)
+
+    return f
+
+
+def to_image(intensity: np.ndarray) -> np.ndarray:
+    """8-bit grey image from intensities (NaN, i.e. background, is black)."""
+    x = np.where(np.isfinite(intensity), intensity, 0.0)
+    return np.clip(np.floor(x + 0.5), 0, 255).astype(np.uint8)
+
+
+def orb_pattern(seed: int = 0) -> np.ndarray:
+    """256 point pairs (x1, y1, x2, y2) for binary descriptors: i.i.d. Gaussian offsets with
+    sigma = 31 / 5 px (a 31-pixel patch), rounded, redrawn until inside the disc of radius 13.
+    Returns (256, 4) int8."""
+    rng = Rng(seed, "orb/pattern")
+    out = np.zeros((256, 4), np.int8)
+    for k in range(256):
+        for h in range(2):
+            while True:
+                x, y = np.floor(rng.normal(2) * (31.0 / 5.0) + 0.5)
+                if x * x + y * y <= 169:
+                    break
+            out[k, 2 * h], out[k, 2 * h + 1] = int(x), int(y)
+    return out
 
 
 def flip_bits(desc: np.ndarray, rng: Rng, nbits: int = 8) -> np.ndarray:
@@ -213,12 +280,22 @@ class Scene:
     n_frames: int
     _frame_fn: object = None
     _grid: np.ndarray = None
+    _image_fn: object = None
 
     def frame(self, t: int) -> Frame:
         """Target frame t (1 <= t <= n_frames)."""
         if not 1 <= t <= self.n_frames:
             raise IndexError(t)
         return self._frame_fn(t)
+
+    def image(self, t: int):
+        """(depth, 8-bit grey image) of frame t of the textured surface, t = 0 the template's
+        own frame (sequence scenes only)."""
+        if self._image_fn is None:
+            raise ValueError("scene has no texture")
+        if not 0 <= t <= self.n_frames:
+            raise IndexError(t)
+        return self._image_fn(t)
 
 
 def _features(rng_tag_seed, name, t, tmpl_xyz, tmpl_desc, gt_xyz, target_P, target_valid,
@@ -414,8 +491,25 @@ def make_sequence(seed: int = 2, M: int = 30000, N: int = 400, K1: int = 2000,
         fx, fd, inl = _features(seed, name, t, feat_xyz, feat_desc, gt_f, tP, valid, n_o, False, K)
         return Frame(depth, fx, fd, Gc(pts.astype(np.float64)), inl, hard)
 
+    tex = surface_texture(seed, name, W, H)
+    uv0 = np.stack(np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64)), -1)
+
+    def image_fn(t):
+        # the textured surface seen in frame t (t = 0: the template, undeformed)
+        if t == 0:
+            return depth0, to_image(tex(uv0[..., 0], uv0[..., 1]))
+        hard = stress is not None and stressed_frame(seed, name, t, stress.prob)
+        y = G(P0.reshape(-1, 3), t)
+        if hard:
+            y = (y - centroid) @ cam_R.T + centroid + cam_t
+        depth, a = render_depth(y.reshape(H, W, 3), K, uv0)
+        if hard:
+            occ = blob_mask(Rng(seed, f"{name}/occlusion/{t}"), W, H, stress.invalid_frac, stress.n_blobs)
+            depth = np.where(occ, np.float32(0.0), depth).astype(np.float32)
+        return depth, to_image(tex(a[..., 0], a[..., 1]))
+
     return Scene(name, K, N, pts.astype(np.float32), feat_xyz.astype(np.float32), feat_desc,
-                 n_frames, frame_fn)
+                 n_frames, frame_fn, _image_fn=image_fn)
 
 
 def make_config2(seed: int = 2, n_frames: int = 300) -> Scene:

@@ -972,3 +972,145 @@ def test_zbuffer_without_collisions_changes_nothing(O):
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][2]["corr0"], out[1][2]["corr0"])
     assert len(np.unique(out[0][2]["corr0"][out[0][2]["corr0"] >= 0])) == (out[0][2]["corr0"] >= 0).sum()
+
+
+# ------------------------------------------------------------------------------------------------
+# uniform ORB features (Sec. 2.1): FAST corners, neighbour suppression, oriented binary descriptors
+
+_CIRCLE = [(0, -3), (1, -3), (2, -2), (3, -1), (3, 0), (3, 1), (2, 2), (1, 3),
+           (0, 3), (-1, 3), (-2, 2), (-3, 1), (-3, 0), (-3, -1), (-2, -2), (-1, -3)]
+
+
+def _ring_patch(values, centre=100, bg=100):
+    """9 x 9 patch with the given 16 circle values around the centre pixel (4, 4)."""
+    img = np.full((9, 9), bg, np.uint8)
+    img[4, 4] = centre
+    for (dx, dy), x in zip(_CIRCLE, values):
+        img[4 + dy, 4 + dx] = x
+    return img
+
+
+def test_fast_segment_test_cases(O):
+    t = 20
+    # all 16 darker: a corner whose response sums the 16 margins
+    assert O.fast_response(_ring_patch([50] * 16), 4, 4, t) == 16 * (100 - 50 - t)
+    assert O.fast_response(_ring_patch([100] * 16), 4, 4, t) == 0
+    # 9 contiguous brighter: corner; 8: not
+    nine = [200] * 9 + [100] * 7
+    assert O.fast_response(_ring_patch(nine), 4, 4, t) == 9 * (200 - 100 - t)
+    assert O.fast_response(_ring_patch([200] * 8 + [100] * 8), 4, 4, t) == 0
+    # a run of 9 that wraps past the start of the circle
+    wrap = [200] * 5 + [100] * 7 + [200] * 4
+    assert O.fast_response(_ring_patch(wrap), 4, 4, t) == 9 * 80
+    # exactly at the threshold does not count
+    assert O.fast_response(_ring_patch([120] * 16), 4, 4, t) == 0
+    assert O.fast_response(_ring_patch([121] * 16), 4, 4, t) == 16
+    # 9 brighter split 5 + 4 by a darker pixel is no run of 9; the response is only taken by a corner
+    split = [200] * 5 + [50] + [200] * 4 + [100] * 6
+    assert O.fast_response(_ring_patch(split), 4, 4, t) == 0
+    # both classes present: the larger sum is the response
+    mixed = [200] * 9 + [50] * 7
+    assert O.fast_response(_ring_patch(mixed), 4, 4, t) == max(9 * 80, 7 * 30)
+
+
+def _dots(W, H, dots, bg=40):
+    img = np.full((H, W), bg, np.uint8)
+    for u, v, val in dots:
+        img[v, u] = val
+    return img
+
+
+def test_orb_suppression_keeps_the_larger_response_then_the_lower_index(O):
+    pat = synth.orb_pattern(0)
+    # two isolated dots: both corners, neither suppresses the other (6 px apart)
+    r = O.orb_detect(_dots(64, 64, [(30, 30, 200), (36, 30, 200)]), pat)
+    assert r["kp"].tolist() == [[30, 30], [36, 30]]
+    # adjacent dots: the brighter one (larger response) wins
+    r = O.orb_detect(_dots(64, 64, [(30, 30, 200), (31, 30, 250)]), pat)
+    assert r["kp"].tolist() == [[31, 30]]
+    # adjacent equal dots: the lower pixel index wins; with radius 0 both stay
+    r = O.orb_detect(_dots(64, 64, [(30, 30, 200), (31, 31, 200)]), pat)
+    assert r["kp"].tolist() == [[30, 30]]
+    r = O.orb_detect(_dots(64, 64, [(30, 30, 200), (31, 31, 200)]), pat, nms_radius=0)
+    assert r["kp"].tolist() == [[30, 30], [31, 31]]
+    # nothing closer than 18 px to the border (64 - 18 = 46 is outside, 45 inside)
+    r = O.orb_detect(_dots(64, 64, [(17, 30, 200), (45, 30, 200), (30, 46, 200)]), pat)
+    assert r["kp"].tolist() == [[45, 30]]
+    # the cap keeps the first corners in raster order and counts them all
+    r = O.orb_detect(_dots(64, 64, [(20, 20, 200), (40, 20, 200), (20, 40, 200)]), pat, max_features=2)
+    assert r["kp"].tolist() == [[20, 20], [40, 20]] and r["total"] == 3
+
+
+def test_orb_orientation_bins_of_intensity_ramps(O):
+    """A bright dot on a linear intensity ramp rising along angle phi: the intensity centroid
+    points along phi, so the orientation bin is phi / 12 deg."""
+    pat = synth.orb_pattern(0)
+    u = np.arange(64)[None, :] - 32.0
+    v = np.arange(64)[:, None] - 32.0
+    for b in (0, 4, 9, 17, 26):
+        phi = math.radians(12.0 * b)
+        img = np.clip(np.floor(100 + 2.5 * (u * math.cos(phi) + v * math.sin(phi)) + 0.5), 0, 255).astype(np.uint8)
+        img[32, 32] = 255
+        r = O.orb_detect(img, pat, fast_threshold=40)
+        k = [i for i, (x, y) in enumerate(r["kp"].tolist()) if (x, y) == (32, 32)]
+        assert k, b
+        assert r["angle_bin"][k[0]] == b
+
+
+def test_orb_descriptor_is_invariant_to_a_half_turn(O):
+    """Rotating the image by 180 deg maps pixel (u, v) to (W-1-u, H-1-v), negates both moments
+    (orientation + 15 bins) and rotates the sampling pattern with it: the keypoints map onto each
+    other and the descriptors agree (up to the rare pattern point whose rotated offset rounds the
+    other way)."""
+    sc = synth.make_small_sequence(seed=12, M=500, N=8, K1=40, width=160, height=120, n_frames=1,
+                                   max_step_mm=2.0)
+    _, img = sc.image(0)
+    pat = synth.orb_pattern(0)
+    a = O.orb_detect(img, pat)
+    b = O.orb_detect(img[::-1, ::-1].copy(), pat)
+    assert len(a["kp"]) > 50
+    H, W = img.shape
+    mb = {(W - 1 - x, H - 1 - y): i for i, (x, y) in enumerate(b["kp"].tolist())}
+    common = 0
+    diff_bits = []
+    for i, (x, y) in enumerate(a["kp"].tolist()):
+        j = mb.get((x, y))
+        if j is None:
+            continue
+        common += 1
+        assert (a["angle_bin"][i] + 15) % 30 == b["angle_bin"][j]
+        diff_bits.append(int(np.unpackbits(a["desc"][i] ^ b["desc"][j]).sum()))
+    assert common >= 0.95 * len(a["kp"])
+    assert np.mean(diff_bits) < 2.0 and max(diff_bits) <= 16
+
+
+def test_orb_matches_follow_the_surface(O):
+    """Template features from the textured template image and frame features from frame 1,
+    matched by nearest Hamming distance: most matches land within 2 px of where the surface
+    point under the template feature moved to (the template point nearest the keypoint, moved
+    by the frame's ground-truth warp and projected)."""
+    sc = synth.make_small_sequence(seed=12, M=12000, N=8, K1=40, width=160, height=120, n_frames=1,
+                                   max_step_mm=2.0)
+    d0, i0 = sc.image(0)
+    d1, i1 = sc.image(1)
+    pat = synth.orb_pattern(0)
+    K = _intr(O, sc.intr)
+    a = O.orb_detect(i0, pat, d0, K)
+    b = O.orb_detect(i1, pat, d1, K)
+    idx, dist = O.hamming_match(a["desc"], b["desc"])
+    fr = sc.frame(1)
+    proj = lambda X: np.stack([sc.intr.fx * X[:, 0] / X[:, 2] + sc.intr.cx,
+                               sc.intr.fy * X[:, 1] / X[:, 2] + sc.intr.cy], 1)
+    puv = proj(sc.pts.astype(np.float64))
+    gt_uv = proj(fr.gt_vertices)
+    good = seen = 0
+    for i in range(len(a["kp"])):
+        j = np.argmin(((puv - a["kp"][i]) ** 2).sum(1))
+        if ((puv[j] - a["kp"][i]) ** 2).sum() > 1.0:
+            continue
+        seen += 1
+        moved = gt_uv[j] + (a["kp"][i] - puv[j])
+        if idx[i] >= 0 and ((b["kp"][idx[i]] - moved) ** 2).sum() <= 4.0:
+            good += 1
+    assert seen >= 0.8 * len(a["kp"])
+    assert good >= 0.5 * seen, (good, seen)

@@ -111,3 +111,25 @@ def test_config5_stream_sizes():
     sc = synth.config5_stream(5, 0, n_frames=3)
     assert 200 <= sc.num_control_points <= 1500 and sc.pts.shape[0] == 640 * 480 // 10
     assert sc.intr.width == 640 and sc.feat_xyz.shape[0] == 2000
+
+
+def test_textured_images_follow_the_depth_and_are_reproducible():
+    sc = synth.make_small_sequence(seed=12, M=500, N=8, K1=40, width=160, height=120, n_frames=2,
+                                   max_step_mm=2.0)
+    d0, i0 = sc.image(0)
+    d1, i1 = sc.image(1)
+    assert i0.dtype == np.uint8 and i0.shape == (120, 160)
+    assert np.array_equal(d1, sc.frame(1).depth)  # the same raster as the frame's depth
+    assert np.array_equal(i1, sc.image(1)[1])
+    assert i0.std() > 10 and not np.array_equal(i0, i1)
+    # background (no surface) is black
+    assert (i1[d1 == 0] == 0).all()
+
+
+def test_orb_pattern_recipe():
+    p = synth.orb_pattern(0)
+    assert p.shape == (256, 4) and p.dtype == np.int8
+    r2 = p[:, 0].astype(int) ** 2 + p[:, 1].astype(int) ** 2
+    assert (r2 <= 169).all() and ((p[:, 2].astype(int) ** 2 + p[:, 3].astype(int) ** 2) <= 169).all()
+    assert np.array_equal(p, synth.orb_pattern(0)) and not np.array_equal(p, synth.orb_pattern(1))
+    assert 4.0 < np.abs(p.astype(float)).mean() < 6.0
