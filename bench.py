@@ -345,6 +345,45 @@ def solver_study(args, torch, tt, sc, frames, dframes):
     return out
 
 
+def orb_bench(args, torch, tt, sc):
+    """Uniform ORB front end on config 2's textured 640 x 480 frames: device time per image
+    (HIP events around the detection on the detector's stream) and keypoints per image."""
+    from paper_2007_08576_amd import synth
+    dev = torch.device("cuda:0")
+    imgs = [sc.image(t) for t in (0, 1, 2)]
+    p = tt.orb_params()
+    det = tt.Orb(p, sc.intr.width, sc.intr.height, synth.orb_pattern(0))
+    K = tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy)
+    dimgs = [(torch.from_numpy(i).to(dev), torch.from_numpy(d).to(dev)) for d, i in imgs]
+    mx = p.max_features
+    kp = torch.zeros((mx, 2), dtype=torch.int32, device=dev)
+    xyz = torch.zeros((mx, 3), dtype=torch.float32, device=dev)
+    desc = torch.zeros((mx, 32), dtype=torch.uint8, device=dev)
+    ang = torch.zeros(mx, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(2, dtype=torch.int32, device=dev)
+    ext = torch.cuda.ExternalStream(det.hip_stream())
+    torch.cuda.synchronize()
+    for k in range(5):
+        i, d = dimgs[k % 3]
+        det.detect_device(i, d, K, kp, xyz, desc, ang, cnt)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    reps = args.orb_reps
+    e0.record(ext)
+    for k in range(reps):
+        i, d = dimgs[k % 3]
+        det.detect_device(i, d, K, kp, xyz, desc, ang, cnt)
+    e1.record(ext)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    counts = [len(det.detect(i, d, K)["kp"]) for d, i in imgs]
+    det.destroy()
+    log(f"  orb front end {us:.1f} us per 640x480 image, {np.mean(counts):.0f} keypoints per image")
+    return {"us_per_image": us, "keypoints_per_image": float(np.mean(counts)), "images": "config2 textured frames 0-2",
+            "params": {"fast_threshold": p.fast_threshold, "nms_radius": p.nms_radius,
+                       "max_features": p.max_features}}
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_chol_dataflow_config2_traffic.json")
 CHOL_SRC = os.path.join(ROOT, "paper_2007_08576_amd", "csrc", "tt_chol.hip")
 
@@ -421,6 +460,8 @@ def main():
     ap.add_argument("--solver", type=int, default=1,
                     help="also compare the per-node solve with the coupled dense solve (0 = skip)")
     ap.add_argument("--solver-steps", type=int, default=30)
+    ap.add_argument("--orb", type=int, default=1, help="also time the uniform ORB front end (0 = skip)")
+    ap.add_argument("--orb-reps", type=int, default=50)
     ap.add_argument("--precision-steps", type=int, default=10)
     ap.add_argument("--precision-config3", type=int, default=1)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -561,6 +602,8 @@ def main():
         out["precision_forms"] = precision_study(args, torch, tt, sc, dframes, vo_oracle)
     if args.solver:
         out["solver_forms"] = solver_study(args, torch, tt, sc, frames, dframes)
+    if args.orb:
+        out["orb_front_end"] = orb_bench(args, torch, tt, sc)
     print(json.dumps(out), flush=True)
     if args.copy_calibration_mib > 0:
         nf = args.copy_calibration_mib * (1 << 20) // 4

@@ -246,6 +246,59 @@ int tt_destroy(tt_stream* s);
 
 const char* tt_strerror(int code);
 
+/* ---- Uniform ORB features (Sec. 2.1) ------------------------------------------------------
+ * The paper detects FAST corners for every pixel in parallel on the GPU and suppresses a corner
+ * when a neighbouring pixel has a larger corner response, so that features spread over low-
+ * texture areas too, then describes them as ORB features. Definitions (all integer except the
+ * orientation bin, which is taken in FP64 from integer moments):
+ *   corner    FAST-9: of the 16 pixels of the radius-3 circle, 9 or more contiguous (cyclic) are
+ *             all brighter than I_p + t or all darker than I_p - t; response = max(sum over the
+ *             brighter of (I - I_p - t), sum over the darker of (I_p - I - t)), else 0;
+ *   region    pixels at least TT_ORB_BORDER from every image border;
+ *   kept      no other corner in the (2r+1)^2 window has a larger response (ties: the lower
+ *             pixel index wins); keypoints in raster order, at most max_features of them;
+ *   angle     intensity centroid atan2(m01, m10) over the disc of radius 15, in 30 bins of 12
+ *             degrees, rounded to the nearest bin;
+ *   desc      256 tests on the 5x5 box sums S of the image: bit k (byte k / 8, bit k % 8 from
+ *             the least significant) = S(p + a_k) < S(p + b_k), (a_k, b_k) = pattern row k =
+ *             (x1, y1, x2, y2) rotated by the angle bin and rounded half away from zero;
+ *   xyz       the back-projection of the depth at the keypoint (NaN when invalid or no depth).
+ * These descriptors and points are what tt_set_template / tt_track_frame take as features. */
+#define TT_ORB_BORDER 18
+
+typedef struct tt_orb tt_orb;
+
+typedef struct {
+  int fast_threshold; /* t, 0..255; default 20 */
+  int nms_radius;     /* r, 0..16; default 1 (the 8 neighbouring pixels) */
+  int max_features;   /* cap on keypoints, 0..2^20; default 4096 */
+} tt_orb_params;
+
+void tt_orb_default_params(tt_orb_params* p);
+
+/* A detector for width x height 8-bit images. pattern: [256][4] int8 host array of point
+ * pairs (x1, y1, x2, y2), each point within radius 13 of the keypoint (TT_EINVAL otherwise);
+ * copied. hip_stream: a hipStream_t for the work (NULL: the detector creates its own). */
+int tt_orb_create(const tt_orb_params* p, int width, int height, const int8_t* pattern, void* hip_stream,
+                  tt_orb** out);
+
+/* Device-memory detection, queued on the detector's HIP stream (returns without waiting).
+ * d_image [height][width] uint8; d_depth [height][width] float32 or NULL (then K may be NULL);
+ * outputs d_kp [max][2] int32 (u, v), d_desc [max][32], d_xyz [max][3] float32 (or NULL),
+ * d_angle [max] int32 bins (or NULL), d_count [2] int32: keypoints written, corners kept before
+ * the cap. Entries past d_count[0] are left as they were. */
+int tt_orb_detect_device(tt_orb* o, const uint8_t* d_image, const float* d_depth, const tt_intrinsics* K,
+                         int32_t* d_kp, float* d_xyz, uint8_t* d_desc, int32_t* d_angle, int32_t* d_count);
+
+/* The same from and to host memory (outputs sized for max_features), synchronous. */
+int tt_orb_detect(tt_orb* o, const uint8_t* image, const float* depth, const tt_intrinsics* K, int32_t* kp,
+                  float* xyz, uint8_t* desc, int32_t* angle, int32_t* count);
+
+/* The detector's hipStream_t. */
+void* tt_orb_hip_stream(tt_orb* o);
+
+int tt_orb_destroy(tt_orb* o);
+
 #ifdef __cplusplus
 }
 #endif

@@ -47,6 +47,13 @@ _DEBUG_FIELDS = ("match_idx", "match_dist", "wstar", "preselected", "hyp_k0", "h
                  "cost_new", "lambda_", "accepted", "delta0")
 
 
+class OrbParams(C.Structure):
+    _fields_ = [("fast_threshold", C.c_int), ("nms_radius", C.c_int), ("max_features", C.c_int)]
+
+
+TT_ORB_BORDER = 18
+
+
 class FrameDebug(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in _DEBUG_FIELDS]
 
@@ -92,6 +99,14 @@ def lib():
         L.tt_destroy.argtypes = [vp]
         L.tt_strerror.argtypes = [C.c_int]
         L.tt_strerror.restype = C.c_char_p
+        L.tt_orb_default_params.argtypes = [C.POINTER(OrbParams)]
+        L.tt_orb_default_params.restype = None
+        L.tt_orb_create.argtypes = [C.POINTER(OrbParams), C.c_int, C.c_int, vp, vp, C.POINTER(vp)]
+        L.tt_orb_detect_device.argtypes = [vp, vp, vp, C.POINTER(Intrinsics), vp, vp, vp, vp, vp]
+        L.tt_orb_detect.argtypes = [vp, vp, vp, C.POINTER(Intrinsics), vp, vp, vp, vp, vp]
+        L.tt_orb_hip_stream.argtypes = [vp]
+        L.tt_orb_hip_stream.restype = vp
+        L.tt_orb_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -298,3 +313,62 @@ def track_batch_device(streams, frames):
 
 def create_stream(params, intr, hip_stream=None):
     return Stream(params, intr, hip_stream)
+
+
+def orb_params(**kw):
+    p = OrbParams()
+    lib().tt_orb_default_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class Orb:
+    """Uniform ORB detector for width x height 8-bit images (tt_orb_*)."""
+
+    def __init__(self, params, width, height, pattern, hip_stream=None):
+        self.params = params
+        self.W, self.H = int(width), int(height)
+        self._pattern = _c(pattern, np.int8)
+        h = C.c_void_p()
+        _check(lib().tt_orb_create(C.byref(params), self.W, self.H, _ptr(self._pattern),
+                                   C.c_void_p(hip_stream) if hip_stream else None, C.byref(h)), "tt_orb_create")
+        self.h = h
+
+    def detect(self, image, depth=None, intr=None):
+        """Host arrays in and out: dict(kp [n,2] int32, xyz [n,3] float32, desc [n,32] uint8,
+        angle_bin [n] int32, total)."""
+        img = _c(image, np.uint8)
+        mx = max(self.params.max_features, 1)
+        kp = np.zeros((mx, 2), np.int32)
+        xyz = np.zeros((mx, 3), np.float32)
+        desc = np.zeros((mx, 32), np.uint8)
+        ang = np.zeros(mx, np.int32)
+        cnt = np.zeros(2, np.int32)
+        d = _c(depth, np.float32) if depth is not None else None
+        _check(lib().tt_orb_detect(self.h, _ptr(img), _ptr(d), C.byref(intr) if intr is not None else None,
+                                   _ptr(kp), _ptr(xyz), _ptr(desc), _ptr(ang), _ptr(cnt)), "tt_orb_detect")
+        n = int(cnt[0])
+        return dict(kp=kp[:n].copy(), xyz=xyz[:n].copy(), desc=desc[:n].copy(), angle_bin=ang[:n].copy(),
+                    total=int(cnt[1]))
+
+    def detect_device(self, image, depth, intr, kp, xyz, desc, angle, count):
+        """Device tensors (or addresses); queued on the detector's HIP stream."""
+        _check(lib().tt_orb_detect_device(self.h, _dev_ptr(image), _dev_ptr(depth),
+                                          C.byref(intr) if intr is not None else None, _dev_ptr(kp),
+                                          _dev_ptr(xyz), _dev_ptr(desc), _dev_ptr(angle), _dev_ptr(count)),
+               "tt_orb_detect_device")
+
+    def hip_stream(self):
+        return lib().tt_orb_hip_stream(self.h)
+
+    def destroy(self):
+        if self.h:
+            lib().tt_orb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
