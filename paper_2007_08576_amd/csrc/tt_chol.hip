@@ -419,7 +419,12 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
 //                then factor and invert C_jj (publishes L_{j,j-1} and Linv_j); all CRIT steps run
 //                on one workgroup, which keeps Linv_j in LDS from one step to the next
 //   DIAGP(j)     C_jj = A_jj - sum_{k <= j-2} L_jk L_jk^T            (j >= 2; finished by CRIT(j))
-//   SUBP(j)      C_{j,j-1} = A_{j,j-1} - sum_{k <= j-2} L_jk L_{j-1,k}^T  (j >= 2; finished by CRIT(j))
+//   SUBP(j)      C_{j,j-1} = A_{j,j-1} - sum_{k <= j-2} L_jk L_{j-1,k}^T  (j >= 2; finished by CRIT(j)).
+//                The last term does not wait for the chain: L_{j-1,j-2} = C_{j-1,j-2} Linv_{j-2}^T is
+//                formed here again from SUBP(j-1)'s tile and Linv_{j-2}, so SUBP(j) is ready while
+//                CRIT(j-1) is still factoring. C_{j,j-1} is kept in the unused upper-triangle tile
+//                (j-1, j) of A, so that CRIT(j) can overwrite tile (j, j-1) with L while SUBP(j+1)
+//                may still read C_{j,j-1}.
 //   FULL(i, c)   L_ic = (A_ic - sum_{k < c} L_ik L_ck^T) Linv_c^T   (i >= c + 2, and the right-hand side)
 // Order: for j = 0, 1, ...: DIAGP(j), SUBP(j), CRIT(j), FULL(j+2 .. nb-1, j), FULL(nb, j). Every task
 // waits only on tasks with smaller tickets, which were claimed by running workgroups (the chain
@@ -761,14 +766,16 @@ __device__ __forceinline__ int crit_ticket(int j, int nb) { return group_start(j
 
 enum { MODE_TASK = 0, MODE_CRIT = 1, MODE_RETRY = 2 };
 
-// The chain's inputs for step j: C_{j,j-1} (tile layout) and C_jj (accumulator layout). For j <= 1
-// these are the raw, not yet equilibrated blocks of A; later they are the partial tiles.
-__device__ __forceinline__ void chain_load(const CholArgs& P, int j, float4 va[4], floatx4 cp[2][2]) {
+// C_{j,j-1} (j >= 1) in tile layout: for j = 1 the raw block A_{1,0}, equilibrated here; later
+// SUBP(j)'s partial tile, kept in the upper-triangle tile (j-1, j).
+__device__ __forceinline__ void csub_load(const CholArgs& P, int j, float4 va[4]) {
   const size_t rj = (size_t)NB * j;
-  acc_load(P.A, P.ld, rj, rj, P.dscale, j <= 1, cp);
-  if (j == 0) return;
+  if (j >= 2) {
+    tile_load(P.A, P.ld, rj - NB, rj, va);
+    return;
+  }
   tile_load(P.A, P.ld, rj, rj - NB, va);
-  if (j == 1) {
+  {
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       const int e = threadIdx.x + 256 * q;
@@ -780,6 +787,14 @@ __device__ __forceinline__ void chain_load(const CholArgs& P, int j, float4 va[4
       va[q].w *= sr * P.dscale[cc + 3];
     }
   }
+}
+
+// The chain's inputs for step j: C_{j,j-1} (tile layout) and C_jj (accumulator layout). For j <= 1
+// these are the raw, not yet equilibrated blocks of A; later they are the partial tiles.
+__device__ __forceinline__ void chain_load(const CholArgs& P, int j, float4 va[4], floatx4 cp[2][2]) {
+  const size_t rj = (size_t)NB * j;
+  acc_load(P.A, P.ld, rj, rj, P.dscale, j <= 1, cp);
+  if (j >= 1) csub_load(P, j, va);
 }
 
 // Up to kMaxCholBatch independent systems per launch, passed by value (no upload per solve).
@@ -997,8 +1012,9 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
       }
       continue;
     }
-    // DIAGP / SUBP / FULL: accumulate the finished columns k < nk into the tile
-    const int nk = (kind == TASK_DIAGP) ? c - 1 : c;
+    // DIAGP / SUBP / FULL: accumulate the finished columns k < nk into the tile (SUBP's last
+    // column, k = c - 1, follows below)
+    const int nk = (kind == TASK_FULL) ? c : c - 1;
     const size_t ri = (i < nb) ? (size_t)NB * i : (size_t)P.npad;
     const size_t rc = (size_t)NB * c;
     const bool same = (i == c);
@@ -1023,19 +1039,24 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         tile16_to_lds(X16, va);
         if (!same) tile16_to_lds(Y16, vb);
         __syncthreads();
-        if (k + 1 < nk) {
-          if (k + 1 >= kr) {
-            const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, deadline, &s_val);
-            if (more == 0) {
-              ok = false;
-              break;
-            }
-            kr = k + 1 + more;
-          }
+        // the next column's loads overlap this product if it is known final; otherwise the
+        // product runs first and the wait follows
+        const bool next = k + 1 < nk, known = k + 1 < kr;
+        if (next && known) {
           tile_load16(P.A16, ld, ri, (size_t)NB * (k + 1), va);
           if (!same) tile_load16(P.A16, ld, rc, (size_t)NB * (k + 1), vb);
         }
         mma64_acc16(X16, same ? X16 : Y16, acc, P.prec);
+        if (next && !known) {
+          const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, deadline, &s_val);
+          if (more == 0) {
+            ok = false;
+            break;
+          }
+          kr = k + 1 + more;
+          tile_load16(P.A16, ld, ri, (size_t)NB * (k + 1), va);
+          if (!same) tile_load16(P.A16, ld, rc, (size_t)NB * (k + 1), vb);
+        }
       }
     } else if (nk > 0) {
       int kr = block_ready_prefix(fi, fc, 0, nk, epoch, S, deadline, &s_val);
@@ -1050,29 +1071,60 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         tile_to_lds(X, va);
         if (!same) tile_to_lds(Y, vb);
         __syncthreads();
-        if (k + 1 < nk) {
-          if (k + 1 >= kr) {
-            const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, deadline, &s_val);
-            if (more == 0) {
-              ok = false;
-              break;
-            }
-            kr = k + 1 + more;
-          }
+        const bool next = k + 1 < nk, known = k + 1 < kr;
+        if (next && known) {
           tile_load(P.A, ld, ri, (size_t)NB * (k + 1), va);
           if (!same) tile_load(P.A, ld, rc, (size_t)NB * (k + 1), vb);
         }
         if (same) mma64_acc(X, X, acc);
         else mma64_acc(X, Y, acc);
+        if (next && !known) {
+          const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, deadline, &s_val);
+          if (more == 0) {
+            ok = false;
+            break;
+          }
+          kr = k + 1 + more;
+          tile_load(P.A, ld, ri, (size_t)NB * (k + 1), va);
+          if (!same) tile_load(P.A, ld, rc, (size_t)NB * (k + 1), vb);
+        }
       }
     }
     if (!ok) continue;
+    if (kind == TASK_SUBP) {
+      // last column m = c - 1 = i - 2: V = C_{c,m} Linv_m^T (= L_{c,m}) from SUBP(c)'s tile (or
+      // the raw A_{1,0} for c = 1) and Linv_m, then acc += L_{i,m} V^T once FULL(i, m) is final
+      const int m = c - 1;
+      if (!block_wait(S.dinv + m, c >= 2 ? S.psub + c : nullptr, nullptr, epoch, S, deadline, &s_val)) continue;
+      {
+        float4 va[4], vb[4];
+        csub_load(P, c, va);
+        tile_load(P.Linv + (size_t)m * NB * NB, NB, 0, 0, vb);
+        __syncthreads();
+        tile_to_lds(X, va);
+        tile_to_lds(Y, vb);
+      }
+      __syncthreads();
+      floatx4 vt[2][2];
+      acc_zero(vt);
+      mma64_acc(X, Y, vt);
+      if (!block_wait(fi + m, nullptr, nullptr, epoch, S, deadline, &s_val)) continue;
+      {
+        float4 va[4];
+        tile_load(P.A, ld, ri, (size_t)NB * m, va);
+        acc_to_lds(Y, vt, false);
+        tile_to_lds(X, va);
+      }
+      __syncthreads();
+      mma64_acc(X, Y, acc);
+    }
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
       for (int b = 0; b < 2; b++) cpre[a][b] -= acc[a][b];
     if (kind != TASK_FULL) {
-      acc_store(P.A, ld, ri, rc, cpre);
+      if (kind == TASK_DIAGP) acc_store(P.A, ld, ri, rc, cpre);
+      else acc_store(P.A, ld, rc, ri, cpre);  // upper-triangle tile (i - 1, i)
       block_publish(kind == TASK_DIAGP ? S.pdiag + i : S.psub + i, epoch);
       continue;
     }
