@@ -29,28 +29,6 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // modifier, no LDS traffic). n must fold to a constant (the callers' loops are fully unrolled).
 // Written as inline assembly so that the broadcast and the multiply-add are one v_fmac_f32_dpp; the
 // leading s_nop gives the two wait states a DPP source needs after a VALU write to it.
-__device__ __forceinline__ float bcast16(float v, int n) {  // returns v of lane n of the row
-  float d;
-  switch (n) {
-    case 0: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:0 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 1: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:1 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 2: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:2 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 3: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:3 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 4: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:4 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 5: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:5 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 6: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:6 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 7: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:7 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 8: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:8 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 9: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:9 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 10: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:10 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 11: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:11 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 12: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:12 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 13: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:13 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 14: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:14 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-    case 15: asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:15 row_mask:0xf bank_mask:0xf" : "=v"(d) : "v"(v)); break;
-  }
-  return d;
-}
 __device__ __forceinline__ void fmac_bcast16(float& acc, float src, float mul, int n, bool guard) {
   // acc += (src of lane n of the row) * mul
   if (guard) {
@@ -467,9 +445,6 @@ __host__ __device__ inline CholSync chol_sync(int* base, int nb) {
 //   g(j) = (j >= 2 ? 2 : 0) + 1 + max(nb - j - 2, 0) + 1
 // tasks. group_start(j) = g(0) + ... + g(j - 1) in closed form: g(0) = 2 + max(nb - 2, 0),
 // g(1) = 2 + max(nb - 3, 0), g(q) = nb + 2 - q for 2 <= q <= nb - 2 and g(nb - 1) = 4 (nb >= 3).
-__host__ __device__ inline int group_size(int j, int nb) {
-  return (j >= 2 ? 2 : 0) + 1 + (nb - j - 2 > 0 ? nb - j - 2 : 0) + 1;
-}
 __host__ __device__ inline int group_start(int j, int nb) {
   if (j <= 0) return 0;
   const int g0 = 2 + (nb - 2 > 0 ? nb - 2 : 0);
