@@ -799,7 +799,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
   __shared__ __attribute__((aligned(16))) float Y[NB][LDS_LD];
   __shared__ __attribute__((aligned(16))) float Z[NB][LDS_LD];  // the chain's Linv_{j-1} between CRIT steps
   static_assert(POTRF_SCRATCH_FLOATS <= NB * LDS_LD, "factorisation scratch must fit in one tile buffer");
-  __shared__ int s_task, s_val, s_mode, s_prob, s_ctr, s_pubcnt;
+  __shared__ int s_task, s_val, s_mode, s_prob, s_ctr, s_pubcnt, s_fast;
   const int tid = threadIdx.x;
   const uint64_t deadline = __builtin_amdgcn_s_memrealtime() + kDeadlineTicks;
   if (tid == 0) s_pubcnt = 0;
@@ -895,82 +895,97 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
     }
     floatx4 acc[2][2], cpre[2][2];
     if (mode == MODE_CRIT) {
-      const int j = chain;
-      const size_t rj = (size_t)NB * j;
-      chain = (j + 1 < nb) ? j + 1 : -1;
-      if (!have_pref) {
-        if (j >= 2 && !block_wait(S.pdiag + j, S.psub + j, nullptr, epoch, S, deadline, &s_val)) {
-          chain = -1;
-          continue;
-        }
-        chain_load(P, j, cva, ccp);
-      }
-      have_pref = false;
-      acc_to_lds(Y, ccp, true);
-      if (j >= 1) tile_to_lds(X, cva);
-      __syncthreads();
-      if (j >= 1) {
-        // L_{j,j-1} = C_{j,j-1} Linv_{j-1}^T: wavefront g computes rows 16 g .. 16 g + 15 (four
-        // 16 x 16 tiles), then overwrites those rows of X and stores them. Linv is lower
-        // triangular, so column block c only sums over the blocks k0 <= 16 c.
-        const int g = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
-        floatx4 t4[4];
-#pragma unroll
-        for (int c = 0; c < 4; c++) {
-          t4[c] = mm16_abt<LDS_LD, LDS_LD>(&X[16 * g][0], &Z[16 * c][0], floatx4{0.f, 0.f, 0.f, 0.f}, c + 1);
-        }
-#pragma unroll
-        for (int c = 0; c < 4; c++)
-#pragma unroll
-          for (int q = 0; q < 4; q++) {
-            const int row = 16 * g + 4 * lk + q, col = 16 * c + li;
-            const float v = t4[c][q];
-            X[row][col] = v;
-            P.A[(rj + row) * ld + rj - NB + col] = v;
-            if (P.prec != TT_FP32) P.A16[(rj + row) * ld + rj - NB + col] = (P.prec == TT_BF16_IR) ? to_bf16(v) : to_f16(v);
+      // Consecutive chain steps run back to back without the claim at the top of the loop while
+      // the next step's partial tiles are already loaded and the ticket counter (as last read)
+      // has passed its CRIT ticket, i.e. while the claim would only confirm the chain's turn.
+      for (int j = chain;;) {
+        const size_t rj = (size_t)NB * j;
+        chain = (j + 1 < nb) ? j + 1 : -1;
+        if (!have_pref) {
+          if (j >= 2 && !block_wait(S.pdiag + j, S.psub + j, nullptr, epoch, S, deadline, &s_val)) {
+            chain = -1;
+            break;
           }
+          chain_load(P, j, cva, ccp);
+        }
+        have_pref = false;
+        acc_to_lds(Y, ccp, true);
+        if (j >= 1) tile_to_lds(X, cva);
         __syncthreads();
-      }
-      // Z = Linv_j, kept for step j + 1; for j >= 1 the update C_jj -= L_{j,j-1} L_{j,j-1}^T is folded
-      // into the factorisation's first phase, which also publishes L_{j,j-1}
-      // the look ahead: the next step's partial tiles (from step 2 on) and the ticket counter
-      ChainPoll poll;
-      poll.f0 = (j + 1 >= 2 && j + 1 < nb) ? S.pdiag + j + 1 : nullptr;
-      poll.f1 = (j + 1 >= 2 && j + 1 < nb) ? S.psub + j + 1 : nullptr;
-      poll.ctr = S.ctr;
-      poll.epoch = epoch;
-      poll.s_ready = &s_val;
-      poll.s_ctr = &s_ctr;
-      const bool ok = (j >= 1) ? potrf_trtri64(Y, Z, &X[0][0], X, S.fin + (size_t)j * nb + (j - 1), epoch, &poll, &s_pubcnt)
-                               : potrf_trtri64(Y, Z, &X[0][0], nullptr, nullptr, 0, &poll);
-      float* Lj = P.Linv + (size_t)j * NB * NB;
-      for (int e = tid; e < NB * NB / 4; e += 256) {
-        const int r = e >> 4, cc = 4 * (e & 15);
-        *reinterpret_cast<float4*>(Lj + r * NB + cc) = make_float4(Z[r][cc], Z[r][cc + 1], Z[r][cc + 2], Z[r][cc + 3]);
-      }
-      if (tid == 0 && !ok) P.sc->chol_fail = 1;
-      // If the look ahead did not find the next step's partial tiles ready, look once more; if they
-      // are, their loads overlap the completion of the Linv_j stores that the publication below
-      // waits for.
-      if (j + 1 < nb) {
-        bool ready = s_val != 0;
-        if (!ready) {
-          __syncthreads();  // every thread has read s_val
-          if (tid == 0) {
-            const int v0 = ld_flag(S.pdiag + j + 1), v1 = ld_flag(S.psub + j + 1);
-            const bool r = (v0 == epoch) && (v1 == epoch);
-            if (r) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            s_val = r ? 1 : 0;
+        if (j >= 1) {
+          // L_{j,j-1} = C_{j,j-1} Linv_{j-1}^T: wavefront g computes rows 16 g .. 16 g + 15 (four
+          // 16 x 16 tiles), then overwrites those rows of X and stores them. Linv is lower
+          // triangular, so column block c only sums over the blocks k0 <= 16 c.
+          const int g = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+          floatx4 t4[4];
+  #pragma unroll
+          for (int c = 0; c < 4; c++) {
+            t4[c] = mm16_abt<LDS_LD, LDS_LD>(&X[16 * g][0], &Z[16 * c][0], floatx4{0.f, 0.f, 0.f, 0.f}, c + 1);
           }
+  #pragma unroll
+          for (int c = 0; c < 4; c++)
+  #pragma unroll
+            for (int q = 0; q < 4; q++) {
+              const int row = 16 * g + 4 * lk + q, col = 16 * c + li;
+              const float v = t4[c][q];
+              X[row][col] = v;
+              P.A[(rj + row) * ld + rj - NB + col] = v;
+              if (P.prec != TT_FP32) P.A16[(rj + row) * ld + rj - NB + col] = (P.prec == TT_BF16_IR) ? to_bf16(v) : to_f16(v);
+            }
           __syncthreads();
-          ready = s_val != 0;
         }
-        if (ready) {
-          chain_load(P, j + 1, cva, ccp);
-          have_pref = true;
+        // Z = Linv_j, kept for step j + 1; for j >= 1 the update C_jj -= L_{j,j-1} L_{j,j-1}^T is folded
+        // into the factorisation's first phase, which also publishes L_{j,j-1}
+        // the look ahead: the next step's partial tiles (from step 2 on) and the ticket counter
+        ChainPoll poll;
+        poll.f0 = (j + 1 >= 2 && j + 1 < nb) ? S.pdiag + j + 1 : nullptr;
+        poll.f1 = (j + 1 >= 2 && j + 1 < nb) ? S.psub + j + 1 : nullptr;
+        poll.ctr = S.ctr;
+        poll.epoch = epoch;
+        poll.s_ready = &s_val;
+        poll.s_ctr = &s_ctr;
+        const bool ok = (j >= 1) ? potrf_trtri64(Y, Z, &X[0][0], X, S.fin + (size_t)j * nb + (j - 1), epoch, &poll, &s_pubcnt)
+                                 : potrf_trtri64(Y, Z, &X[0][0], nullptr, nullptr, 0, &poll);
+        float* Lj = P.Linv + (size_t)j * NB * NB;
+        for (int e = tid; e < NB * NB / 4; e += 256) {
+          const int r = e >> 4, cc = 4 * (e & 15);
+          *reinterpret_cast<float4*>(Lj + r * NB + cc) = make_float4(Z[r][cc], Z[r][cc + 1], Z[r][cc + 2], Z[r][cc + 3]);
         }
+        if (tid == 0 && !ok) P.sc->chol_fail = 1;
+        // If the look ahead did not find the next step's partial tiles ready, look once more; if they
+        // are, their loads overlap the completion of the Linv_j stores that the publication below
+        // waits for.
+        if (j + 1 < nb) {
+          bool ready = s_val != 0;
+          if (!ready) {
+            __syncthreads();  // every thread has read s_val
+            if (tid == 0) {
+              const int v0 = ld_flag(S.pdiag + j + 1), v1 = ld_flag(S.psub + j + 1);
+              const bool r = (v0 == epoch) && (v1 == epoch);
+              if (r) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+              s_val = r ? 1 : 0;
+            }
+            __syncthreads();
+            ready = s_val != 0;
+          }
+          if (ready) {
+            chain_load(P, j + 1, cva, ccp);
+            have_pref = true;
+          }
+        }
+        if (tid == 0) {
+          bool f = false;
+          if (chain >= 0 && have_pref) {
+            const int need = crit_ticket(chain, qc.nb);
+            if (ctr_seen < need) ctr_seen = max(ctr_seen, s_ctr);
+            f = ctr_seen >= need;
+          }
+          s_fast = f ? 1 : 0;
+        }
+        block_publish(S.dinv + j, epoch);  // its barrier also shares s_fast
+        if (!s_fast) break;
+        j = chain;
       }
-      block_publish(S.dinv + j, epoch);
       continue;
     }
     int kind, i, c;
