@@ -298,7 +298,45 @@ def precision_study(args, torch, tt, sc2, dframes2, vo_oracle):
             out["config3"][name] = entry
             log(f"  config3 {name:8s} {fps:7.2f} frames/s, factor {fac:8.1f} us, solve+refine {sol:7.1f} us, "
                 f"rms vs fp32 {entry['rms_vs_fp32_form_mm']:.2e} mm")
+        out["assembly_config3"] = assembly_roofline(torch, tt, sc3, dfr3)
+    out["assembly_config2"] = assembly_roofline(torch, tt, sc2, dframes2)
     return out
+
+
+def assembly_roofline(torch, tt, sc, dfr):
+    """HBM fraction of one LM iteration's assembly (rows, dense ARAP, data blocks): algorithmic
+    bytes = the FP32 lower triangle of A, n (n + 1) / 2 * 4 B, plus g and the inputs read once
+    (44 B per template point, 16 B of gathered depth/normal per point, 44 B per node, 56 B per
+    feature), over the summed stage times (HIP events on the library's stream)."""
+    dev = torch.device("cuda:0")
+    N, M, K = sc.num_control_points, sc.pts.shape[0], sc.feat_xyz.shape[0]
+    n = 6 * N
+    s = tt.Stream(tt.default_params(num_control_points=N, seed=2),
+                  tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy))
+    s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    ov = torch.empty((M, 3), dtype=torch.float32, device=dev)
+    oq = torch.empty((N, 8), dtype=torch.float32, device=dev)
+    d = dfr[0]
+    s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], ov, oq)
+    s.sync()
+    s.get_timing()
+    s.set_timing(True, stages=("rows", "arap", "data"))
+    for k in range(2):
+        d = dfr[(k + 1) % len(dfr)]
+        s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], ov, oq)
+    s.sync()
+    s.set_timing(False)
+    ms, cnt = s.get_timing()
+    s.destroy()
+    per = {name: float(ms[tt.STAGES.index(name)] / max(cnt[tt.STAGES.index(name)], 1)) * 1e3
+           for name in ("rows", "arap", "data")}
+    t_us = sum(per.values())
+    nbytes = n * (n + 1) / 2 * 4 + n * 4 + M * (44 + 16) + N * 44 + K * 56
+    gbs = nbytes / (t_us * 1e-6) / 1e9
+    log(f"  assembly n={n}: {t_us:.1f} us per iteration (rows {per['rows']:.1f}, arap {per['arap']:.1f}, "
+        f"data {per['data']:.1f}), {nbytes / 1e6:.1f} MB -> {gbs:.0f} GB/s = {100 * gbs / 8000:.1f} % of 8 TB/s")
+    return {"n": n, "us_per_iteration": t_us, "stage_us": per, "algorithmic_bytes": nbytes,
+            "achieved_GBps": gbs, "frac_of_hbm_peak": gbs / 8000.0, "peak_GBps": 8000.0}
 
 
 def solver_study(args, torch, tt, sc, frames, dframes):
