@@ -81,7 +81,8 @@ struct Busy {
 
 // Build the static block-CSR of data-term node pairs: for each template point (kind 0) and
 // feature (kind 1) and each ordered slot pair (s, t) with node[s] >= node[t], one entry in
-// block (node[s], node[t]). Entries of a block are in (kind, index, s, t) order.
+// block (node[s], node[t]). Entries of a block are in (kind, index, s, t) order; blocks are in
+// decreasing order of their entry counts.
 void build_csr(const std::vector<int4>& knn, const std::vector<int4>& fknn, int N, std::vector<int2>& blk_ab,
                std::vector<int>& blk_ptr, std::vector<uint32_t>& ent) {
   struct E {
@@ -115,6 +116,28 @@ void build_csr(const std::vector<int4>& knn, const std::vector<int4>& fknn, int 
     ent.push_back(all[i].e);
   }
   blk_ptr.push_back((int)all.size());
+  // launch order: blocks with more entries first (less tail when the grid drains); each block's
+  // entries keep their order, so every block's sum is unchanged
+  const int nb = (int)blk_ab.size();
+  std::vector<int> order(nb);
+  for (int b = 0; b < nb; b++) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return blk_ptr[x + 1] - blk_ptr[x] > blk_ptr[y + 1] - blk_ptr[y];
+  });
+  std::vector<int2> ab2(nb);
+  std::vector<int> ptr2(nb + 1, 0);
+  std::vector<uint32_t> ent2;
+  ent2.reserve(ent.size());
+  for (int q = 0; q < nb; q++) {
+    const int b = order[q];
+    ab2[q] = blk_ab[b];
+    ptr2[q] = (int)ent2.size();
+    ent2.insert(ent2.end(), ent.begin() + blk_ptr[b], ent.begin() + blk_ptr[b + 1]);
+  }
+  ptr2[nb] = (int)ent2.size();
+  blk_ab.swap(ab2);
+  blk_ptr.swap(ptr2);
+  ent.swap(ent2);
 }
 
 int ensure_k2(tt_stream* s, int K2) {
