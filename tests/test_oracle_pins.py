@@ -1008,6 +1008,8 @@ def test_fast_segment_test_cases(O):
     # 9 brighter split 5 + 4 by a darker pixel is no run of 9; the response is only taken by a corner
     split = [200] * 5 + [50] + [200] * 4 + [100] * 6
     assert O.fast_response(_ring_patch(split), 4, 4, t) == 0
+    # 9 pixels exactly at the threshold and 7 above: no run of 9 strictly brighter pixels
+    assert O.fast_response(_ring_patch([120] * 9 + [200] * 7), 4, 4, t) == 0
     # both classes present: the larger sum is the response
     mixed = [200] * 9 + [50] * 7
     assert O.fast_response(_ring_patch(mixed), 4, 4, t) == max(9 * 80, 7 * 30)
@@ -1114,3 +1116,85 @@ def test_orb_matches_follow_the_surface(O):
             good += 1
     assert seen >= 0.8 * len(a["kp"])
     assert good >= 0.5 * seen, (good, seen)
+
+
+def test_sparse_arap_graph_ties_go_to_the_lower_index(O):
+    """Control points on a square lattice have many equal rest distances; the k nearest are then
+    the lowest-indexed of the tied nodes (brute force with a stable sort)."""
+    pts, feats, R, t = scenes.lattice_scene()
+    rng = np.random.default_rng(35)
+    desc = rng.integers(0, 256, (25, 32), dtype=np.uint8)
+    for k in (1, 2, 3):
+        s = O.Stream(O.default_params(num_control_points=12, arap_knn=k), O.intrinsics(16, 16, 20.0, 20.0, 8.0, 8.0))
+        s.set_template(pts.astype(np.float32), feats.astype(np.float32), desc)
+        info = s.template_info()
+        C = pts.astype(np.float32).astype(np.float64)[info["node_idx"]]
+        adj, D2 = _graph(C, k)
+        d = D2 + np.diag(np.full(12, np.inf))
+        assert any(np.sum(d[a] == np.sort(d[a])[k - 1]) > 1 for a in range(12))  # ties at the k-th
+        sa = 2.0 * info["sbar"]
+        want = np.exp(-D2 / (2 * sa * sa))[adj].sum()
+        assert abs(info["s_arap"] - want) <= 1e-12 * want
+
+
+def test_orb_descriptor_of_an_unrotated_keypoint_by_brute_force(O):
+    """A keypoint whose orientation bin is 0 uses the pattern as drawn: its descriptor is the
+    256 comparisons of 5 x 5 box sums at p + (x1, y1) and p + (x2, y2), bit k in byte k // 8 from
+    the least significant bit."""
+    pat = synth.orb_pattern(0)
+    u = np.arange(64)[None, :] - 32.0
+    v = np.arange(64)[:, None] - 32.0
+    rng = np.random.default_rng(36)
+    img = np.clip(np.floor(100 + 2.5 * u + rng.integers(-6, 7, (64, 64)) + 0.5), 0, 255).astype(np.uint8)
+    img[32, 32] = 255
+    r = O.orb_detect(img, pat, fast_threshold=40)
+    k = [i for i, (x, y) in enumerate(r["kp"].tolist()) if (x, y) == (32, 32)]
+    assert k and r["angle_bin"][k[0]] == 0
+    I = img.astype(np.int64)
+    box = lambda x, y: int(I[y - 2:y + 3, x - 2:x + 3].sum())
+    want = np.zeros(32, np.uint8)
+    for b in range(256):
+        x1, y1, x2, y2 = (int(q) for q in pat[b])
+        if box(32 + x1, 32 + y1) < box(32 + x2, 32 + y2):
+            want[b // 8] |= np.uint8(1 << (b % 8))
+    assert np.array_equal(r["desc"][k[0]], want)
+
+
+def test_orb_descriptor_nearly_invariant_to_a_quarter_turn(O):
+    """A quarter turn maps the keypoints onto each other exactly and turns the orientation by -7.5
+    bins, so the steered pattern is off by 6 degrees: the descriptors of corresponding keypoints
+    still agree in most bits (about 15 of 256 differ), far from the 128 of unrelated ones. A pattern
+    steered the wrong way round would not agree."""
+    sc = synth.make_small_sequence(seed=12, M=500, N=8, K1=40, width=160, height=120, n_frames=1,
+                                   max_step_mm=2.0)
+    _, img = sc.image(0)
+    pat = synth.orb_pattern(0)
+    a = O.orb_detect(img, pat)
+    b = O.orb_detect(np.rot90(img).copy(), pat)
+    W = img.shape[1]
+    mb = {(x, y): i for i, (x, y) in enumerate(b["kp"].tolist())}
+    diff = []
+    for i, (x, y) in enumerate(a["kp"].tolist()):
+        j = mb.get((y, W - 1 - x))
+        if j is None:
+            continue
+        # (x, y) -> (y, W - 1 - x) turns every offset (dx, dy) into (dy, -dx): minus 90 degrees
+        assert (b["angle_bin"][j] - a["angle_bin"][i]) % 30 in (22, 23)
+        diff.append(int(np.unpackbits(a["desc"][i] ^ b["desc"][j]).sum()))
+    assert len(diff) >= 0.9 * len(a["kp"])
+    assert np.mean(diff) < 30
+
+
+def test_orb_points_project_back_onto_their_keypoints(O):
+    sc = synth.make_small_sequence(seed=12, M=500, N=8, K1=40, width=160, height=120, n_frames=1,
+                                   max_step_mm=2.0)
+    depth, img = sc.image(1)
+    r = O.orb_detect(img, synth.orb_pattern(0), depth, _intr(O, sc.intr))
+    X = r["xyz"].astype(np.float64)
+    ok = np.isfinite(X).all(1)
+    assert ok.mean() > 0.9
+    K = sc.intr
+    u = K.fx * X[ok, 0] / X[ok, 2] + K.cx
+    v = K.fy * X[ok, 1] / X[ok, 2] + K.cy
+    assert np.abs(u - r["kp"][ok, 0]).max() < 1e-3 and np.abs(v - r["kp"][ok, 1]).max() < 1e-3
+    assert np.array_equal(X[ok, 2].astype(np.float32), depth[r["kp"][ok, 1], r["kp"][ok, 0]])
