@@ -375,3 +375,39 @@ def test_precision_forms_vertices(O, T, prec):
     rms = _rms(vg, vo)
     print(f"{prec}: config 1 vertex rms vs FP64 oracle {rms:.2e} mm", flush=True)
     assert rms <= RMS_TOL_MM
+
+
+# ------------------------------------------------------------------------------------------------
+# the smallest systems: one to three control points (fewer than the 4 blend slots; one 64-block
+# factorisation), with each solver option
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("opt", ["dense", "node", "arap_knn1", "zbuffer"])
+def test_fewest_control_points(O, T, N, opt):
+    sc = synth.make_small_sequence(seed=13, M=600, N=N, K1=30, width=96, height=72, n_frames=1,
+                                   max_step_mm=2.0)
+    fr = sc.frame(1)
+    kw = dict(seed=4)
+    if opt == "node":
+        kwo, kwg = dict(kw, solver=O.SOLVE_NODE), dict(kw, solver=T.TT_SOLVE_NODE)
+    elif opt == "arap_knn1":
+        kwo, kwg = dict(kw, arap_knn=1), dict(kw, arap_knn=1)
+    elif opt == "zbuffer":
+        kwo, kwg = dict(kw, assoc_zbuffer=1), dict(kw, assoc_zbuffer=1)
+    else:
+        kwo, kwg = kw, kw
+    so = O.Stream(_params(O, num_control_points=N, **kwo), _intr(O, sc.intr))
+    sg = T.Stream(_params(T, num_control_points=N, **kwg), _intr(T, sc.intr))
+    so.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    sg.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    vo, qo, do = so.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+    vg, qg, dg = sg.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+    assert np.array_equal(do["match_idx"], dg["match_idx"])
+    assert np.array_equal(do["corr0"], dg["corr0"])
+    Ao = do["A0"]
+    if opt == "node":  # the per-node solve assembles only the diagonal blocks
+        mask = np.kron(np.eye(N), np.ones((6, 6))) > 0
+        Ao = np.where(mask, Ao, 0.0)
+    ea = np.linalg.norm(Ao - dg["A0"]) / np.linalg.norm(Ao)
+    assert ea < NE_TOL, ea
+    assert _rms(vo, vg) <= RMS_TOL_MM
