@@ -294,6 +294,9 @@ int tt_orb_detect_device(tt_orb* o, const uint8_t* d_image, const float* d_depth
 int tt_orb_detect(tt_orb* o, const uint8_t* image, const float* depth, const tt_intrinsics* K, int32_t* kp,
                   float* xyz, uint8_t* desc, int32_t* angle, int32_t* count);
 
+/* Calls on one detector must not overlap (TT_EBUSY); different detectors may be used from
+ * different host threads. */
+
 /* The detector's hipStream_t. */
 void* tt_orb_hip_stream(tt_orb* o);
 

@@ -16,6 +16,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -236,6 +237,7 @@ __global__ __launch_bounds__(64) void k_orb_describe(const uint8_t* __restrict__
 }  // namespace
 
 struct tt_orb {
+  std::mutex mu;  // one call at a time (the working buffers are the detector's)
   tt_orb_params P;
   int W = 0, H = 0;
   hipStream_t st = nullptr;
@@ -257,6 +259,15 @@ struct tt_orb {
 };
 
 namespace {
+
+struct OrbBusy {
+  tt_orb* o;
+  bool ok;
+  explicit OrbBusy(tt_orb* o_) : o(o_), ok(o_->mu.try_lock()) {}
+  ~OrbBusy() {
+    if (ok) o->mu.unlock();
+  }
+};
 
 void orb_free(tt_orb* o) {
   void* ps[] = {o->R, o->S, o->flags, o->rowcnt, o->rowoff, o->rotpat, o->img, o->depth, o->kp, o->xyz, o->desc,
@@ -363,6 +374,8 @@ int tt_orb_detect_device(tt_orb* o, const uint8_t* d_image, const float* d_depth
   if (!o || !d_image || !d_count || (d_depth && !K) || (o->P.max_features > 0 && (!d_kp || !d_desc)))
     return TT_EINVAL;
   if (K && (K->width != o->W || K->height != o->H || !(K->fx > 0) || !(K->fy > 0))) return TT_EINVAL;
+  OrbBusy busy(o);
+  if (!busy.ok) return TT_EBUSY;
   return orb_enqueue(o, d_image, d_depth, K, d_kp, d_xyz, d_desc, d_angle, d_count);
 }
 
@@ -370,6 +383,8 @@ int tt_orb_detect(tt_orb* o, const uint8_t* image, const float* depth, const tt_
                   float* xyz, uint8_t* desc, int32_t* angle, int32_t* count) {
   if (!o || !image || !count || (depth && !K) || (o->P.max_features > 0 && (!kp || !desc))) return TT_EINVAL;
   if (K && (K->width != o->W || K->height != o->H || !(K->fx > 0) || !(K->fy > 0))) return TT_EINVAL;
+  OrbBusy busy(o);
+  if (!busy.ok) return TT_EBUSY;
   const size_t HW = (size_t)o->W * o->H;
   hipStream_t st = o->st;
   if (hipMemcpyAsync(o->img, image, HW, hipMemcpyHostToDevice, st) != hipSuccess) return TT_EDEVICE;
@@ -398,6 +413,10 @@ void* tt_orb_hip_stream(tt_orb* o) { return o ? static_cast<void*>(o->st) : null
 
 int tt_orb_destroy(tt_orb* o) {
   if (!o) return TT_EINVAL;
+  {
+    OrbBusy busy(o);
+    if (!busy.ok) return TT_EBUSY;
+  }
   (void)hipStreamSynchronize(o->st);
   orb_free(o);
   if (o->own_stream) (void)hipStreamDestroy(o->st);
