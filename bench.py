@@ -287,6 +287,7 @@ def precision_study(args, torch, tt, sc2, dframes2, vo_oracle):
         sc3 = synth.make_config3(seed=3, n_frames=300)
         dfr3 = [tuple(torch.from_numpy(a).to(dev) for a in (f.depth, f.feat_xyz, f.feat_desc))
                 for f in (sc3.frame(t) for t in (1, 2))]
+        torch.cuda.synchronize()  # the uploads are complete before the library's stream reads them
         log(f"config 3 generated in {time.time() - t0:.1f} s")
         ref = None
         for name, prec in forms:
@@ -521,6 +522,7 @@ def main():
     dev = torch.device("cuda:0")
     dframes = [(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.feat_xyz).to(dev),
                 torch.from_numpy(f.feat_desc).to(dev)) for f in frames]
+    torch.cuda.synchronize()
     order = list(range(len(frames))) + list(range(len(frames) - 2, 0, -1))
     stream = torch.cuda.Stream()
     N, M = sc.num_control_points, sc.pts.shape[0]

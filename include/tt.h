@@ -149,7 +149,10 @@ int tt_track_frame(tt_stream* s, const float* depth, const float* feat_xyz, cons
 
 /* Same solve with every array in device memory (d_depth [height][width], d_feat_xyz [K2][3],
  * d_feat_desc [K2][32]; outputs d_out_vertices [M][3] and d_out_dq [N][8] float32, either may
- * be NULL). Queued on the stream's HIP stream and returns without waiting. */
+ * be NULL). Queued on the stream's HIP stream and returns without waiting. The inputs must be
+ * complete when the call is made, or ordered before the stream's work by the caller (work on
+ * another HIP stream, e.g. an upload still in flight, is not waited for; see
+ * tt_track_frame_device_ev). */
 int tt_track_frame_device(tt_stream* s, const float* d_depth, const float* d_feat_xyz,
                           const uint8_t* d_feat_desc, int K2, float* d_out_vertices, float* d_out_dq);
 

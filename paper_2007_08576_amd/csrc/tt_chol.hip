@@ -400,7 +400,8 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
 //   SUBP(j)      C_{j,j-1} = A_{j,j-1} - sum_{k <= j-2} L_jk L_{j-1,k}^T  (j >= 2; finished by CRIT(j)).
 //                The last term does not wait for the chain: L_{j-1,j-2} = C_{j-1,j-2} Linv_{j-2}^T is
 //                formed here again from SUBP(j-1)'s tile and Linv_{j-2}, so SUBP(j) is ready while
-//                CRIT(j-1) is still factoring. C_{j,j-1} is kept in the unused upper-triangle tile
+//                CRIT(j-1) is still factoring (for j = 2 the term L_{1,0} is read once CRIT(1) has
+//                published it: CRIT(1) overwrites the raw A_{1,0} it would be formed from). C_{j,j-1} is kept in the unused upper-triangle tile
 //                (j-1, j) of A, so that CRIT(j) can overwrite tile (j, j-1) with L while SUBP(j+1)
 //                may still read C_{j,j-1}.
 //   FULL(i, c)   L_ic = (A_ic - sum_{k < c} L_ik L_ck^T) Linv_c^T   (i >= c + 2, and the right-hand side)
@@ -741,8 +742,9 @@ __device__ __forceinline__ int crit_ticket(int j, int nb) { return group_start(j
 
 enum { MODE_TASK = 0, MODE_CRIT = 1, MODE_RETRY = 2 };
 
-// C_{j,j-1} (j >= 1) in tile layout: for j = 1 the raw block A_{1,0}, equilibrated here; later
-// SUBP(j)'s partial tile, kept in the upper-triangle tile (j-1, j).
+// C_{j,j-1} (j >= 1) in tile layout: for j = 1 the raw block A_{1,0}, equilibrated here (only the
+// chain reads it: its own step 1 overwrites the tile with L_{1,0}); later SUBP(j)'s partial tile,
+// kept in the upper-triangle tile (j-1, j).
 __device__ __forceinline__ void csub_load(const CholArgs& P, int j, float4 va[4]) {
   const size_t rj = (size_t)NB * j;
   if (j >= 2) {
@@ -1082,27 +1084,37 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
     }
     if (!ok) continue;
     if (kind == TASK_SUBP) {
-      // last column m = c - 1 = i - 2: V = C_{c,m} Linv_m^T (= L_{c,m}) from SUBP(c)'s tile (or
-      // the raw A_{1,0} for c = 1) and Linv_m, then acc += L_{i,m} V^T once FULL(i, m) is final
+      // last column m = c - 1 = i - 2: acc += L_{i,m} V^T with V = L_{c,m}, once FULL(i, m) is final.
+      // For c >= 2, V = C_{c,m} Linv_m^T is formed here from SUBP(c)'s tile and Linv_m. For c = 1
+      // the raw A_{1,0} is not there to form it from once CRIT(1) has begun (it overwrites tile
+      // (1, 0) with L_{1,0}), so V is that tile, read once CRIT(1) has published it.
       const int m = c - 1;
-      if (!block_wait(S.dinv + m, c >= 2 ? S.psub + c : nullptr, nullptr, epoch, S, deadline, &s_val)) continue;
-      {
-        float4 va[4], vb[4];
-        csub_load(P, c, va);
-        tile_load(P.Linv + (size_t)m * NB * NB, NB, 0, 0, vb);
-        __syncthreads();
-        tile_to_lds(X, va);
-        tile_to_lds(Y, vb);
-      }
-      __syncthreads();
       floatx4 vt[2][2];
-      acc_zero(vt);
-      mma64_acc(X, Y, vt);
-      if (!block_wait(fi + m, nullptr, nullptr, epoch, S, deadline, &s_val)) continue;
+      if (c >= 2) {
+        if (!block_wait(S.dinv + m, S.psub + c, nullptr, epoch, S, deadline, &s_val)) continue;
+        {
+          float4 va[4], vb[4];
+          csub_load(P, c, va);
+          tile_load(P.Linv + (size_t)m * NB * NB, NB, 0, 0, vb);
+          __syncthreads();
+          tile_to_lds(X, va);
+          tile_to_lds(Y, vb);
+        }
+        __syncthreads();
+        acc_zero(vt);
+        mma64_acc(X, Y, vt);
+      }
+      if (!block_wait(fi + m, c == 1 ? fc + m : nullptr, nullptr, epoch, S, deadline, &s_val)) continue;
       {
         float4 va[4];
         tile_load(P.A, ld, ri, (size_t)NB * m, va);
-        acc_to_lds(Y, vt, false);
+        if (c >= 2) {
+          acc_to_lds(Y, vt, false);
+        } else {
+          float4 vb[4];
+          tile_load(P.A, ld, rc, (size_t)NB * m, vb);
+          tile_to_lds(Y, vb);
+        }
         tile_to_lds(X, va);
       }
       __syncthreads();

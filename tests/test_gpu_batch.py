@@ -41,8 +41,12 @@ def _stream(tt, sc, precision=0, solver=0):
 
 
 def _dev_frame(torch, fr, dev):
-    return (torch.from_numpy(fr.depth).to(dev), torch.from_numpy(fr.feat_xyz).to(dev),
-            torch.from_numpy(fr.feat_desc).to(dev))
+    """The frame's arrays on the device, complete before the library's stream reads them (a copy
+    from pageable host memory may still be in flight when .to() returns)."""
+    out = (torch.from_numpy(fr.depth).to(dev), torch.from_numpy(fr.feat_xyz).to(dev),
+           torch.from_numpy(fr.feat_desc).to(dev))
+    torch.cuda.synchronize()
+    return out
 
 
 def test_batch_equals_alone(env):
