@@ -77,3 +77,22 @@ def test_cholesky_refinement_converges(T, prec):
     print(f"{prec}: errors by refinement steps 0,1,2,4,8: {['%.1e' % e for e in errs]}; FP32 {e32:.1e}", flush=True)
     assert errs[1] < errs[0] and errs[2] < errs[1]
     assert errs[-1] < max(10 * e32, 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n", [200, 700])
+def test_cholesky_repeatable(T, prec, n):
+    """Every tile of the factorisation is summed in a fixed order whichever workgroup computes it and
+    whenever its inputs arrive, so solves of one system agree bit for bit from run to run; a task
+    that read a tile unordered with a write of it would show here as differences between runs."""
+    p = T.TT_BF16_IR if prec == "bf16" else T.TT_FP32
+    rng = np.random.default_rng(n + 29)
+    B = rng.normal(size=(n, n))
+    A = B @ B.T / n + np.eye(n)
+    b = rng.normal(size=n)
+    ref, fail = T.debug_cholesky_solve(A, b, precision=p, ir_iters=2)
+    assert not fail
+    for rep in range(12):
+        x, fail = T.debug_cholesky_solve(A, b, precision=p, ir_iters=2)
+        assert not fail
+        assert np.array_equal(x, ref), f"run {rep + 1} differs from the first"
