@@ -281,13 +281,20 @@ int enqueue_assemble(tt_stream* s, DevState& dd, int it, bool dbg, hipStream_t s
   DevState& d = s->d;
   const tt_params& P = s->P;
   Intr K = intr_of(s);
-  {
-    StageTimer tm(s, TT_STAGE_ROWS, st);
-    HIPCHK(launch_lm_rows(dd, P, K, it, st));
-  }
-  {
-    StageTimer tm(s, TT_STAGE_ARAP, st);
-    HIPCHK(launch_lm_arap(dd, P, st));
+  // after the first iteration the rows and the ARAP blocks share one launch, unless either stage
+  // is being timed (then each keeps its own launch between its timing events)
+  const bool fuse = it > 0 && !((s->timing >> TT_STAGE_ROWS) & 1u) && !((s->timing >> TT_STAGE_ARAP) & 1u);
+  if (fuse) {
+    HIPCHK(launch_lm_rows_arap(dd, P, K, it, st));
+  } else {
+    {
+      StageTimer tm(s, TT_STAGE_ROWS, st);
+      HIPCHK(launch_lm_rows(dd, P, K, it, st));
+    }
+    {
+      StageTimer tm(s, TT_STAGE_ARAP, st);
+      HIPCHK(launch_lm_arap(dd, P, st));
+    }
   }
   {
     StageTimer tm(s, TT_STAGE_DATA, st);

@@ -199,6 +199,9 @@ hipError_t launch_preselect(const DevState& d, int R, int iters, double H, uint6
 hipError_t launch_lm_begin(DevState& d, double lambda0, hipStream_t st);
 hipError_t launch_lm_rows(DevState& d, const tt_params& P, const Intr& K, int it, hipStream_t st);
 hipError_t launch_lm_arap(DevState& d, const tt_params& P, hipStream_t st);
+// Rows and dense ARAP blocks in one launch; iterations after the first only (the ARAP weight is set
+// by iteration 0's rows).
+hipError_t launch_lm_rows_arap(DevState& d, const tt_params& P, const Intr& K, int it, hipStream_t st);
 hipError_t launch_lm_data(DevState& d, hipStream_t st);
 hipError_t launch_lm_damp(DevState& d, hipStream_t st);
 hipError_t launch_node_solve(DevState& d, hipStream_t st);

@@ -11,6 +11,8 @@
 //   k_arap_assemble    dense ARAP (Sec. 2.2, Eqs. (5)-(6)) over all control-point pairs: one
 //                      workgroup per node row writes the row's off-diagonal 6x6 blocks once and
 //                      reduces its diagonal block and gradient in LDS
+//   k_rows_arap        from the second iteration on (the ARAP weight then fixed), k_arap_assemble
+//                      and k_data_rows as one launch (unless their stage timers are on)
 //   k_data_assemble    adds the ICP and feature rows into the node-pair blocks through the
 //                      static block-CSR (deterministic, no atomics)
 //   k_damp             Marquardt damping A + lambda diag(A) + eps I and the right-hand side
@@ -196,13 +198,13 @@ __global__ __launch_bounds__(kRowThreads) void k_zbuffer(RowArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kRowThreads) void k_data_rows(RowArgs a, int it) {
+__device__ __forceinline__ void data_rows_body(const RowArgs& a, int it, int bx) {
   __shared__ double sh[kRowThreads];
   const int tid = threadIdx.x;
   double s0 = 0.0, s1 = 0.0;
-  if ((int)blockIdx.x < a.P.nbp) {
+  if (bx < a.P.nbp) {
     // ---- ICP rows of template points
-    int j = blockIdx.x * kRowThreads + tid;
+    int j = bx * kRowThreads + tid;
     if (j < a.M) {
       int4 nb = a.knn[j];
       float4 al = a.alpha[j];
@@ -269,12 +271,12 @@ __global__ __launch_bounds__(kRowThreads) void k_data_rows(RowArgs a, int it) {
     double t0 = block_sum_d<kRowThreads>(s0, sh);
     double t1 = block_sum_d<kRowThreads>(s1, sh);
     if (tid == 0) {
-      a.part[a.P.pts + 2 * blockIdx.x] = t0;
-      a.part[a.P.pts + 2 * blockIdx.x + 1] = t1;
+      a.part[a.P.pts + 2 * bx] = t0;
+      a.part[a.P.pts + 2 * bx + 1] = t1;
     }
   } else {
     // ---- feature rows of template features
-    int fb = blockIdx.x - a.P.nbp;
+    int fb = bx - a.P.nbp;
     int k = fb * kRowThreads + tid;
     if (k < a.K1) {
       float4 o = a.o2[k];
@@ -337,6 +339,7 @@ __global__ __launch_bounds__(kRowThreads) void k_data_rows(RowArgs a, int it) {
     }
   }
 }
+__global__ __launch_bounds__(kRowThreads) void k_data_rows(RowArgs a, int it) { data_rows_body(a, it, (int)blockIdx.x); }
 
 // Dynamic ARAP weight, once per frame (iteration 0): lambda_arap times the summed ICP (Tukey)
 // and feature (w_ORB w_k) weights over the summed pair weights.
@@ -451,11 +454,10 @@ constexpr int kArapAcc = 36 + 6;
 // kOff: also write the off-diagonal blocks (the coupled solve); the per-node solve reads only the
 // diagonal blocks and g.
 template <bool kOff>
-__global__ __launch_bounds__(kArapThreads) void k_arap_assemble(ArapArgs a) {
+__device__ __forceinline__ void arap_body(const ArapArgs& a, int i) {
   __shared__ float red[kArapAcc][kArapThreads + 1];
   __shared__ float wsum[kArapThreads / 64][kArapAcc];
   __shared__ double shd[kArapThreads];
-  const int i = blockIdx.x;
   const int tid = threadIdx.x;
   const float w_arap = (float)a.sc->w_arap;
   float qi[8];
@@ -595,6 +597,20 @@ __global__ __launch_bounds__(kArapThreads) void k_arap_assemble(ArapArgs a) {
     for (int l = 0; l < kArapThreads; l++) c += shd[l];
     a.part[a.P.arap + i] = c;
   }
+}
+template <bool kOff>
+__global__ __launch_bounds__(kArapThreads) void k_arap_assemble(ArapArgs a) { arap_body<kOff>(a, (int)blockIdx.x); }
+
+// From the second LM iteration of a frame on, the ARAP weight is fixed and the dense ARAP blocks and
+// the data rows touch disjoint buffers (A, g and the ARAP cost partials; the correspondences,
+// residuals, Jacobian rows and data cost partials), so one launch runs both: the N ARAP workgroups
+// first (rows of unequal length), then the short rows workgroups, which fill the CUs beside them
+// instead of running before them. Each workgroup computes exactly what it computes in its own launch.
+static_assert(kRowThreads == kArapThreads, "one block shape for both bodies");
+template <bool kOff>
+__global__ __launch_bounds__(kArapThreads) void k_rows_arap(ArapArgs aa, RowArgs ra, int it) {
+  if ((int)blockIdx.x < aa.N) arap_body<kOff>(aa, (int)blockIdx.x);
+  else data_rows_body(ra, it, (int)blockIdx.x - aa.N);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1011,6 +1027,22 @@ hipError_t launch_lm_rows(DevState& d, const tt_params& P, const Intr& K, int it
   if (it == 0)
     hipLaunchKernelGGL(k_lm_scalars, dim3(1), dim3(256), 0, st, d.partial, ra.P, P.lambda_arap, P.w_orb, d.s_arap,
                        d.sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_lm_rows_arap(DevState& d, const tt_params& P, const Intr& K, int it, hipStream_t st) {
+  if (it == 0) return hipErrorInvalidValue;  // the ARAP weight comes from iteration 0's rows
+  RowArgs ra = row_args(d, P, K);
+  ArapArgs aa = arap_args(d, P);
+  if (d.zbuf) {
+    hipLaunchKernelGGL(k_zfill, dim3((d.HW + 255) / 256), dim3(256), 0, st, d.zbuf, d.HW);
+    hipLaunchKernelGGL(k_zbuffer, dim3((d.M + kRowThreads - 1) / kRowThreads), dim3(kRowThreads), 0, st, ra);
+  }
+  const dim3 grid(d.N + ra.P.nbp + ra.P.nbf);
+  if (d.solver == TT_SOLVE_NODE)
+    hipLaunchKernelGGL(k_rows_arap<false>, grid, dim3(kArapThreads), 0, st, aa, ra, it);
+  else
+    hipLaunchKernelGGL(k_rows_arap<true>, grid, dim3(kArapThreads), 0, st, aa, ra, it);
   return hipGetLastError();
 }
 

@@ -141,3 +141,28 @@ def test_stage_timer_selection(env):
     ms, n = s.get_timing()
     assert not n.any()
     s.destroy()
+
+
+@pytest.mark.parametrize("solver", ["dense", "node"])
+def test_fused_rows_arap_equals_separate(env, solver):
+    """From the second LM iteration on, the rows and the ARAP blocks run as one launch unless either
+    stage is timed; each workgroup computes what it computes in its own launch, so the frames come
+    out bit for bit the same either way."""
+    tt, torch = env
+    sc = _scenes()[1]
+    sv = tt.TT_SOLVE_NODE if solver == "node" else tt.TT_SOLVE_DENSE
+    res = []
+    for timed in (True, False):
+        s = _stream(tt, sc, solver=sv)
+        if timed:
+            s.set_timing(True, stages=("rows",))  # keeps the rows in a launch of their own
+        out = []
+        for t in (1, 2):
+            fr = sc.frame(t)
+            v, q = s.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc)[:2]
+            out.append((np.array(v), np.array(q)))
+        s.destroy()
+        res.append(out)
+    for t in range(2):
+        assert np.array_equal(res[0][t][0], res[1][t][0]), f"frame {t + 1}: vertices differ"
+        assert np.array_equal(res[0][t][1], res[1][t][1]), f"frame {t + 1}: warps differ"
