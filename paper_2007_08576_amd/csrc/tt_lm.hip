@@ -20,7 +20,8 @@
 //   k_node_solve       one 6x6 FP64 Cholesky per node on its diagonal block (only the diagonal
 //                      blocks are assembled then)
 //   k_update           candidate warps W' = Delta(delta_i) W_i (node-centred increments)
-//   k_cost_data/arap   FP64 cost of the candidate with correspondences and weights frozen
+//   k_cost             FP64 cost of the candidate with correspondences and weights frozen (data
+//                      and ARAP passes in one launch)
 //   k_accept           accept if the cost drops (lambda / 10), else reject (lambda * 10)
 //
 // Residual rows (all weights frozen within an iteration):
@@ -831,12 +832,12 @@ __global__ void k_update(const float* __restrict__ W, const float4* __restrict__
 
 // FP64 cost of the candidate with the correspondences, Tukey weights and feature weights of the
 // iterate (points: omega (n . (v' - q))^2; features: w_ORB w |DQB(o1) - o2|^2).
-__global__ __launch_bounds__(kRowThreads) void k_cost_data(RowArgs a, const float* __restrict__ Wc) {
+__device__ __forceinline__ void cost_data_body(const RowArgs& a, const float* __restrict__ Wc, int bx) {
   __shared__ double sh[kRowThreads];
   const int tid = threadIdx.x;
   double s = 0.0;
-  if ((int)blockIdx.x < a.P.nbp) {
-    int j = blockIdx.x * kRowThreads + tid;
+  if (bx < a.P.nbp) {
+    int j = bx * kRowThreads + tid;
     if (j < a.M) {
       int pix = a.corr[j];
       float om = a.omega[j];
@@ -857,7 +858,7 @@ __global__ __launch_bounds__(kRowThreads) void k_cost_data(RowArgs a, const floa
       }
     }
   } else {
-    int k = (blockIdx.x - a.P.nbp) * kRowThreads + tid;
+    int k = (bx - a.P.nbp) * kRowThreads + tid;
     if (k < a.K1) {
       float w = a.orbw[k];
       float4 o = a.o2[k];
@@ -879,13 +880,12 @@ __global__ __launch_bounds__(kRowThreads) void k_cost_data(RowArgs a, const floa
     }
   }
   double t = block_sum_d<kRowThreads>(s, sh);
-  if (tid == 0) a.part[a.P.cdata + blockIdx.x] = t;
+  if (tid == 0) a.part[a.P.cdata + bx] = t;
 }
 
-__global__ __launch_bounds__(kArapThreads) void k_cost_arap(ArapArgs a, const float* __restrict__ Wc,
-                                                            const float4* __restrict__ ndispc) {
+__device__ __forceinline__ void cost_arap_body(const ArapArgs& a, const float* __restrict__ Wc,
+                                               const float4* __restrict__ ndispc, int i) {
   __shared__ double sh[kArapThreads];
-  const int i = blockIdx.x;
   const float w_arap = (float)a.sc->w_arap;
   float qi[8];
   load_dq(Wc, i, qi);
@@ -900,6 +900,15 @@ __global__ __launch_bounds__(kArapThreads) void k_cost_arap(ArapArgs a, const fl
   }
   double t = block_sum_d<kArapThreads>(cost, sh);
   if (threadIdx.x == 0) a.part[a.P.carap + i] = t;
+}
+
+// The candidate's data and ARAP cost passes read the frozen correspondences and weights and the
+// candidate warps and write disjoint partial sums: one launch, the N ARAP workgroups first.
+static_assert(kRowThreads == kArapThreads, "one block shape for both bodies");
+__global__ __launch_bounds__(kArapThreads) void k_cost(ArapArgs aa, RowArgs ra, const float* __restrict__ Wc,
+                                                       const float4* __restrict__ ndispc) {
+  if ((int)blockIdx.x < aa.N) cost_arap_body(aa, Wc, ndispc, (int)blockIdx.x);
+  else cost_data_body(ra, Wc, (int)blockIdx.x - aa.N);
 }
 
 // Accept / reject on the device: accept iff the factorisation succeeded and the candidate's
@@ -1079,9 +1088,8 @@ hipError_t launch_lm_finish(DevState& d, const tt_params& P, const Intr& K, hipS
   hipLaunchKernelGGL(k_update, dim3((d.N + 63) / 64), dim3(64), 0, st, d.W, d.pos, d.c0, d.x, d.dscale, d.N, d.Wc,
                      d.posc, d.ndispc);
   RowArgs ra = row_args(d, P, K);
-  hipLaunchKernelGGL(k_cost_data, dim3(ra.P.nbp + ra.P.nbf), dim3(kRowThreads), 0, st, ra, d.Wc);
   ArapArgs aa = arap_args(d, P);
-  hipLaunchKernelGGL(k_cost_arap, dim3(d.N), dim3(kArapThreads), 0, st, aa, d.Wc, d.ndispc);
+  hipLaunchKernelGGL(k_cost, dim3(d.N + ra.P.nbp + ra.P.nbf), dim3(kArapThreads), 0, st, aa, ra, d.Wc, d.ndispc);
   hipLaunchKernelGGL(k_accept, dim3(1), dim3(256), 0, st, d.partial, ra.P, d.N, d.sc, d.W, d.Wc, d.pos, d.posc,
                      d.ndisp, d.ndispc, d.log_cost_old, d.log_cost_new, d.log_lambda, d.log_accept);
   return hipGetLastError();
