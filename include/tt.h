@@ -220,7 +220,9 @@ int tt_set_state(tt_stream* s, const double* dq, int64_t frame);
 
 /* Selects the stages whose GPU time is measured: bit i of stages (0 <= stages <= TT_TIMING_ALL)
  * times stage i, 0 turns the timers off. Each timed stage records two HIP events on the stream
- * per call, so time only what is needed where the throughput itself is measured.
+ * per call, so time only what is needed where the throughput itself is measured. Untimed, the
+ * rows and the ARAP assembly of every LM iteration after the first run as one launch; timing
+ * either of the two stages keeps them as two launches (same results, each between its own events).
  * TT_EINVAL for a bit outside the stages. */
 int tt_set_timing(tt_stream* s, int stages);
 
