@@ -359,6 +359,50 @@ def test_config2_full_size(O, T):
     assert _rms(vo, vg) <= RMS_TOL_MM
 
 
+def test_config3_full_size_iteration0(O, T):
+    """Config 3 (N = 1,500, n = 9,000, M = 100,000, 640 x 480) frame 1 from the identity, in the
+    benchmark's launch configuration. The oracle cannot run this frame's ten FP64 solves in a test,
+    so the checks are what it (or the mathematics) fixes at this size: the matches bit for bit, the
+    iteration-0 normal equations against the oracle's assembly at the identity (no solve), and the
+    iteration-0 step by its backward error on the GPU's own damped system, which bounds the FP32
+    factorisation and substitutions whatever the condition number."""
+    sc = synth.make_config3(seed=3, n_frames=300)
+    fr = sc.frame(1)
+    so, sg = _pair(O, T, sc, seed=3)
+    vg, qg, dg = sg.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+    idx, dist = O.hamming_match(sc.feat_desc, fr.feat_desc)
+    assert np.array_equal(idx, dg["match_idx"]) and np.array_equal(dist, dg["match_dist"])
+    N = sc.num_control_points
+    ident = np.zeros((N, 8))
+    ident[:, 0] = 1.0
+    so.frame_begin(fr.depth, fr.feat_xyz, fr.feat_desc)
+    Ao, go = so.normal_equations(ident)
+    Ag, gg = dg["A0"], dg["g0"]
+    ea = np.linalg.norm(Ao - Ag) / np.linalg.norm(Ao)
+    eg = np.linalg.norm(go - gg) / np.linalg.norm(go)
+    del Ao
+    # the damped system of iteration 0 (Marquardt damping from the frame's initial lambda, and the
+    # eps I of 1e-12 times the largest diagonal entry), the GPU's step, and its backward error
+    d = np.diag(Ag).copy()
+    lam = _params(T).lm_lambda0
+    Ad = Ag
+    Ad[np.diag_indices_from(Ad)] = d * (1.0 + lam) + 1e-12 * d.max()
+    x = dg["delta0"]
+    assert np.isfinite(x).all()
+    res = Ad @ x + gg
+    eta = np.linalg.norm(res) / (np.linalg.norm(Ad) * np.linalg.norm(x) + np.linalg.norm(gg))
+    # componentwise (Oettli-Prager) backward error, against n u = 5.4e-4 for FP32 at this size
+    omega = float(np.max(np.abs(res) / (np.abs(Ad) @ np.abs(x) + np.abs(gg))))
+    print(f"config 3: |dA|/|A| {ea:.2e}, |dg|/|g| {eg:.2e}, step backward error normwise {eta:.2e}, "
+          f"componentwise {omega:.2e}", flush=True)
+    assert ea < NE_TOL and eg < NE_TOL
+    assert eta < 1e-5
+    assert omega < 9000 * 2.0 ** -24
+    assert np.isfinite(vg).all()
+    acc = dg["accepted"].astype(bool)
+    assert acc.any() and np.all(dg["cost_new"][acc] < dg["cost_old"][acc])
+
+
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_precision_forms_vertices(O, T, prec):
     """The 16-bit solve forms track config 1 within the 0.01 mm RMS bar of the FP64 oracle."""
