@@ -903,8 +903,8 @@ __device__ __forceinline__ void cost_arap_body(const ArapArgs& a, const float* _
 }
 
 // The candidate's data and ARAP cost passes read the frozen correspondences and weights and the
-// candidate warps and write disjoint partial sums: one launch, the N ARAP workgroups first.
-static_assert(kRowThreads == kArapThreads, "one block shape for both bodies");
+// candidate warps and write disjoint partial sums: one launch, the N ARAP workgroups first (the
+// block shape is the one k_rows_arap shares).
 __global__ __launch_bounds__(kArapThreads) void k_cost(ArapArgs aa, RowArgs ra, const float* __restrict__ Wc,
                                                        const float4* __restrict__ ndispc) {
   if ((int)blockIdx.x < aa.N) cost_arap_body(aa, Wc, ndispc, (int)blockIdx.x);
