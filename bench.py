@@ -304,6 +304,36 @@ def precision_study(args, torch, tt, sc2, dframes2, vo_oracle):
     return out
 
 
+def host_buffers_bench(args, tt, sc, frames):
+    """The host-memory entry point (tt_track_frame) on the headline workload. Each call copies the
+    frame's depth map and features to the device, tracks the frame and copies the vertices and warps
+    back before it returns. So the copies over PCIe are inside the time, and the front stage cannot
+    overlap the previous frame's solve."""
+    K = sc.intr
+    s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=2),
+                  tt.intrinsics(K.width, K.height, K.fx, K.fy, K.cx, K.cy))
+    s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    order = list(range(len(frames))) + list(range(len(frames) - 2, 0, -1))
+    for k in range(2):
+        f = frames[order[k % len(order)]]
+        s.track_frame(f.depth, f.feat_xyz, f.feat_desc)
+    n = args.host_steps
+    t0 = time.perf_counter()
+    for k in range(n):
+        f = frames[order[(k + 2) % len(order)]]
+        s.track_frame(f.depth, f.feat_xyz, f.feat_desc)
+    dt = time.perf_counter() - t0
+    s.destroy()
+    f = frames[0]
+    b_in = f.depth.nbytes + f.feat_xyz.astype(np.float32).nbytes + f.feat_desc.nbytes
+    b_out = 4 * (3 * sc.pts.shape[0] + 8 * sc.num_control_points)
+    log(f"  host buffers: {n / dt:.1f} frames/s ({1e3 * dt / n:.2f} ms per frame, PCIe copies included)")
+    return {"frames_per_s": n / dt, "ms_per_frame": 1e3 * dt / n, "frames": n,
+            "bytes_in_per_frame": int(b_in), "bytes_out_per_frame": int(b_out),
+            "note": "tt_track_frame with host arrays, one call per frame: uploads, front stage, 10 LM "
+                    "iterations and the download in sequence (no overlap with the previous frame)"}
+
+
 def assembly_roofline(torch, tt, sc, dfr):
     """HBM fraction of one LM iteration's assembly (rows, dense ARAP, data blocks): algorithmic
     bytes = the FP32 lower triangle of A, n (n + 1) / 2 * 4 B, plus g and the inputs read once
@@ -501,6 +531,8 @@ def main():
     ap.add_argument("--solver-steps", type=int, default=30)
     ap.add_argument("--orb", type=int, default=1, help="also time the uniform ORB front end (0 = skip)")
     ap.add_argument("--orb-reps", type=int, default=50)
+    ap.add_argument("--host", type=int, default=1, help="also time the host-memory entry point (0 = skip)")
+    ap.add_argument("--host-steps", type=int, default=40)
     ap.add_argument("--precision-steps", type=int, default=10)
     ap.add_argument("--precision-config3", type=int, default=1)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -620,6 +652,8 @@ def main():
         "roofline": roof,
     }
 
+    if args.host:
+        out["host_buffers"] = host_buffers_bench(args, tt, sc, frames)
     if args.serving:
         out["batched"] = serving_bench(args, torch, tt)
     if args.stress:
