@@ -9,7 +9,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtt_oracle.so")
+# TT_ORACLE_LIB names another build of the same source (the mutation check loads planted copies)
+LIB_PATH = os.environ.get("TT_ORACLE_LIB") or os.path.join(HERE, "libtt_oracle.so")
 
 _lib = None
 
@@ -56,7 +57,7 @@ class FrameDebug(C.Structure):
     _fields_ = [(n, _P) for n in (
         "match_idx", "match_dist", "wstar", "preselected", "hyp_k0", "hyp_W", "hyp_nin",
         "hyp_kept", "corr0", "r0", "omega0", "orbw0", "A0", "g0", "w_arap", "cost_old",
-        "cost_new", "lambda_", "accepted", "delta0")]
+        "cost_new", "lambda_", "accepted", "delta0", "w_arap_iter")]
 
 
 def _declare(L):
@@ -209,7 +210,8 @@ class Stream:
                        hyp_kept=np.zeros(R, np.uint8), corr0=np.zeros(M, np.int32), r0=np.zeros(M),
                        omega0=np.zeros(M), orbw0=np.zeros(K1), A0=np.zeros((n, n)), g0=np.zeros(n),
                        w_arap=np.zeros(1), cost_old=np.zeros(T), cost_new=np.zeros(T),
-                       lambda_=np.zeros(T), accepted=np.zeros(T, np.uint8), delta0=np.full(n, np.nan))
+                       lambda_=np.zeros(T), accepted=np.zeros(T, np.uint8), delta0=np.full(n, np.nan),
+                       w_arap_iter=np.zeros(T))
             dbg = FrameDebug(**{k: _ptr(v) for k, v in out.items()})
         rc = lib().tto_track_frame(self.h, _ptr(depth), _ptr(feat_xyz), _ptr(feat_desc), K2,
                                    _ptr(verts), _ptr(dq), C.byref(dbg) if dbg is not None else None)

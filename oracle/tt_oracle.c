@@ -1397,6 +1397,7 @@ int tto_track_frame(tto_stream* s, const float* depth_mm, const float* feat_xyz,
     associate(s, s->dq, &a, t == 0);
     if (t == 0) w_arap = a.w_arap;
     a.w_arap = w_arap;
+    if (dbg && dbg->w_arap_iter) dbg->w_arap_iter[t] = a.w_arap;
     residual_rows(s, s->dq, &a, r, NULL);
     double e_old = sumsq(r, rows);
     normal_equations_sparse(s, s->dq, &a, A, g);

@@ -93,6 +93,7 @@ typedef struct {
   double* lambda;         /* [T] damping used in the step */
   uint8_t* accepted;      /* [T] 1 if the candidate was accepted */
   double* delta0;         /* [n] iteration-0 step (left unwritten if the factorisation failed) */
+  double* w_arap_iter;    /* [T] ARAP weight each iteration's costs and normal equations use */
 } tto_frame_debug;
 
 void tto_default_params(tto_params* p);

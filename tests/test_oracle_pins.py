@@ -1198,3 +1198,137 @@ def test_orb_points_project_back_onto_their_keypoints(O):
     v = K.fy * X[ok, 1] / X[ok, 2] + K.cy
     assert np.abs(u - r["kp"][ok, 0]).max() < 1e-3 and np.abs(v - r["kp"][ok, 1]).max() < 1e-3
     assert np.array_equal(X[ok, 2].astype(np.float32), depth[r["kp"][ok, 1], r["kp"][ok, 0]])
+
+
+# ------------------------------------------------------------------------------------------------
+# the LM step rule, the pre-selection thresholds and the per-frame ARAP weight, each on a case
+# that takes the branch in question
+
+def _lm_lambdas(lam0, accepted):
+    """Damping sequence of Sec. 2's Levenberg-Marquardt rule: /10 after an accepted step, x10
+    after a rejected one, kept in [1e-10, 1e10]."""
+    lam = [lam0]
+    for a in accepted[:-1]:
+        lam.append(max(lam[-1] / 10.0, 1e-10) if a else min(lam[-1] * 10.0, 1e10))
+    return np.array(lam)
+
+
+def test_lm_rejects_a_step_that_does_not_lower_the_cost(O):
+    """At an exact fixed point (target = template on the dyadic plane) every residual and every
+    step is exactly 0, so the candidate's cost equals the iterate's. The iterate is replaced only
+    for a strictly lower cost: every step is rejected and the damping grows tenfold each time."""
+    K, depth, P = scenes.dyadic_plane()
+    pts = P[2:-2, 2:-2].reshape(-1, 3).astype(np.float32)
+    rng = np.random.default_rng(22)
+    fi = rng.choice(len(pts), 12, replace=False)
+    desc = rng.integers(0, 256, (12, 32), dtype=np.uint8)
+    s = O.Stream(O.default_params(num_control_points=8, lm_iters=6), _intr(O, K))
+    s.set_template(pts, pts[fi], desc)
+    _, dq, d = s.track_frame(depth, pts[fi], desc, debug=True)
+    assert np.all(d["cost_old"] == 0.0) and np.all(d["cost_new"] == 0.0)
+    assert not d["accepted"].any()
+    assert np.array_equal(d["lambda"], [1e-4, 1e-3, 1e-2, 1e-1, 1.0, 10.0])
+    assert np.array_equal(dq, np.tile(np.r_[1.0, 0, 0, 0, 0, 0, 0, 0], (8, 1)))
+
+
+def test_lm_rejected_steps_keep_the_iterate_and_raise_the_damping(O):
+    """The rigid lattice (features only) converges to rounding level within seven iterations;
+    the steps after that do not lower the cost and are rejected in the middle of the frame.
+    After a rejected step the damping is multiplied by 10 and the next iteration starts from the
+    same warps, so its cost at the iterate is the same number; after an accepted one it is divided
+    by 10, down to 1e-10."""
+    pts, feats, R, t = scenes.lattice_scene()
+    o2 = feats @ R.T + t
+    K = synth.Intrinsics(16, 16, 20.0, 20.0, 8.0, 8.0)
+    rng = np.random.default_rng(23)
+    desc = rng.integers(0, 256, (25, 32), dtype=np.uint8)
+    s = O.Stream(O.default_params(num_control_points=12, lm_iters=10), _intr(O, K))
+    s.set_template(pts.astype(np.float32), feats.astype(np.float32), desc)
+    _, _, d = s.track_frame(np.zeros((16, 16), np.float32), o2.astype(np.float32), desc, debug=True)
+    acc, lam, c0, c1 = d["accepted"], d["lambda"], d["cost_old"], d["cost_new"]
+    T = len(acc)
+    mid_rejects = [i for i in range(T - 1) if not acc[i]]
+    assert len(mid_rejects) >= 2, acc
+    # the lower clamp is reached: an accepted step whose tenth would fall below 1e-10
+    assert any(acc[i] and lam[i] / 10.0 < 1e-10 and lam[i + 1] == 1e-10 for i in range(T - 1)), lam
+    assert np.array_equal(lam, _lm_lambdas(1e-4, acc))
+    for i in range(T):
+        assert bool(acc[i]) == bool(c1[i] < c0[i])
+    for i in mid_rejects:
+        assert c0[i + 1] == c0[i]
+    assert c0[0] > 1e6 and c0[-1] < 1e-20
+
+
+def test_arap_weight_is_fixed_for_the_whole_frame(O):
+    """The dynamic ARAP weight (Sec. 2, after Eq. (1)) is set once per frame from the
+    iteration-0 weight sums and used unchanged by every iteration, although the Tukey and feature
+    weights move as the surface is re-associated (checked: the iteration-0 and final costs are
+    far apart)."""
+    sc = synth.make_config1(1)
+    fr = sc.frame(1)
+    s = O.Stream(O.default_params(num_control_points=64, seed=1, lambda_arap=1.5), _intr(O, sc.intr))
+    s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    _, _, d = s.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+    want = 1.5 * (d["omega0"].sum() + 10.0 * d["orbw0"].sum()) / s.template_info()["s_arap"]
+    assert abs(d["w_arap"] - want) < 1e-12 * want
+    assert np.all(d["w_arap_iter"] == d["w_arap"])
+    assert d["cost_old"][-1] < 0.1 * d["cost_old"][0]
+    # a second frame sets its own weight from its own iteration-0 sums
+    s2 = O.Stream(O.default_params(num_control_points=64, seed=1, lambda_arap=1.5), _intr(O, sc.intr))
+    s2.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    s2.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc)
+    _, _, e = s2.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+    want2 = 1.5 * (e["omega0"].sum() + 10.0 * e["orbw0"].sum()) / s2.template_info()["s_arap"]
+    assert abs(e["w_arap"] - want2) < 1e-12 * want2 and e["w_arap"] != d["w_arap"]
+    assert np.all(e["w_arap_iter"] == e["w_arap"])
+
+
+def test_preselect_drops_hypotheses_scoring_below_half_of_the_best(O):
+    """Sec. 2.1: a reference whose hypothesis collects a small sum of weights is taken for an
+    outlier. Two locally rigid clusters as in the keep test, the second one smaller (12 matches):
+    started from unit weights, the alternation leaves its hypotheses with scores on both sides of
+    half the best one, several of them between 0.4 and 0.5. Exactly the hypotheses below one half
+    are dropped."""
+    rng = np.random.default_rng(31)
+    H = 3.0
+    A = rng.uniform(-10, 10, size=(30, 3))
+    B = rng.uniform(-10, 10, size=(12, 3)) + np.array([100.0, 0, 0])
+    R = scenes.quat_to_matrix(np.r_[1.0, 0.1, -0.05, 0.0])
+    o1 = np.vstack([A, B, rng.uniform(-50, 50, size=(4, 3))])
+    o2 = np.vstack([A @ R.T, B @ R.T + np.array([0.0, 40.0, 0.0]),
+                    rng.uniform(-50, 50, size=(4, 3)) + 300])
+    r = O.preselect(o1, o2, np.ones(46, np.uint8), H, refs=0, iters=10)
+    valid = r["hyp_kept"][:46] != 2
+    ratio = r["hyp_W"][:46] / r["hyp_W"][:46][valid].max()
+    assert valid.all()
+    assert np.any((ratio > 0.4) & (ratio < 0.5)), ratio
+    assert np.any((ratio >= 0.5) & (ratio < 0.6)), ratio
+    assert np.array_equal(r["hyp_kept"][:46], (ratio >= 0.5).astype(np.uint8))
+    assert np.all(r["hyp_kept"][:30] == 1) and np.all(r["hyp_kept"][42:46] == 0)
+
+
+def test_preselect_threshold_is_half(O):
+    """Sec. 2.1: a match belongs to the pre-selected set when its weight in some kept hypothesis
+    reaches 1/2, i.e. it lies within 2H of that hypothesis's rigid image. Two matches are moved
+    off an exact rigid motion by 2.2 H and 1.8 H; with references drawn among the other 20
+    (seed 2 of the sampler), their weights (Eq. (4), H / d, d nudged by the weighted rotation fit)
+    are about 0.47 and 0.59: the first stays out, the second is in. Neither is within H, so
+    neither counts as an inlier of any hypothesis."""
+    rng = np.random.default_rng(32)
+    H = 3.0
+    o1 = rng.uniform(-30, 30, size=(22, 3))
+    R = scenes.quat_to_matrix(np.r_[1.0, -0.03, 0.08, 0.02])
+    o2 = o1 @ R.T + np.array([4.0, -2.0, 1.0])
+    u = _unit(rng, 2)
+    o2[20] += 2.2 * H * u[0]
+    o2[21] += 1.8 * H * u[1]
+    r = O.preselect(o1, o2, np.ones(22, np.uint8), H, refs=12, iters=10, seed=2)
+    assert 20 not in r["hyp_k0"][:12] and 21 not in r["hyp_k0"][:12]
+    assert np.all(r["hyp_kept"][:12] == 1)
+    assert 0.42 < r["wstar"][20] < 0.48, r["wstar"][20]
+    assert 0.52 < r["wstar"][21] < 0.62, r["wstar"][21]
+    assert not r["preselected"][20] and r["preselected"][21]
+    assert r["preselected"][:20].all()
+    # each hypothesis counts the matches within H of its rigid image: the 20 exact ones, not the
+    # one at 1.8 H
+    assert np.all(r["hyp_nin"][:12] == 20), r["hyp_nin"][:12]
