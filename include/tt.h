@@ -122,6 +122,7 @@ typedef struct {
   double* lambda;       /* [T] damping used */
   uint8_t* accepted;    /* [T] 1 if the candidate was accepted */
   double* delta0;       /* [n] iteration-0 step, node-centred (omega_i, tau_i) per node; unwritten if the factorisation failed */
+  double* w_arap_iter;  /* [T] ARAP weight that each iteration's costs and normal equations use */
 } tt_frame_debug;
 
 /* Fills every field with the paper's constants and this library's defaults. */
@@ -193,6 +194,13 @@ int tt_track_batch_device(tt_stream* const* streams, int S, const tt_frame_devic
 
 /* Waits for the stream's queued work; returns TT_EDEVICE if a device-side check failed. */
 int tt_sync(tt_stream* s);
+
+/* The LM record of the stream's last frame (Sec. 2: one Levenberg-Marquardt step per iteration),
+ * each array [lm_iters] or NULL: the cost at the iterate and at the candidate (NaN where the
+ * factorisation failed), the damping, 1 where the candidate was accepted, the ARAP weight of each
+ * iteration, 1 where the factorisation failed. Waits for the stream's queued work first. */
+int tt_get_frame_log(tt_stream* s, double* cost_old, double* cost_new, double* lambda, uint8_t* accepted,
+                     double* w_arap, int32_t* chol_fail);
 
 /* The hipStream_t the stream queues on. */
 void* tt_hip_stream(tt_stream* s);

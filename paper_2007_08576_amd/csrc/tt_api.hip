@@ -60,13 +60,14 @@ void free_template(tt_stream* s) {
   float* f2xyz = d.f2xyz;
   uint32_t* f2desc = d.f2desc;
   LMScalars* sc = d.sc;
-  double *lo = d.log_cost_old, *ln = d.log_cost_new, *ll = d.log_lambda;
-  int* la = d.log_accept;
-  const int cus = d.num_cus, prec = d.prec, ir = d.ir_iters, solver = d.solver;
+  double *lo = d.log_cost_old, *ln = d.log_cost_new, *ll = d.log_lambda, *lw = d.log_w_arap;
+  int *la = d.log_accept, *lf = d.log_fail;
+  const int cus = d.num_cus, wkhz = d.wall_khz, prec = d.prec, ir = d.ir_iters, solver = d.solver;
   d = DevState();
-  d.num_cus = cus; d.prec = prec; d.ir_iters = ir; d.solver = solver;
+  d.num_cus = cus; d.wall_khz = wkhz; d.prec = prec; d.ir_iters = ir; d.solver = solver;
   d.HW = HW; d.K2cap = K2cap; d.depth = depth; d.nmap_b = nmap; d.nmap = nmap; d.f2xyz = f2xyz; d.f2desc = f2desc;
   d.sc = sc; d.log_cost_old = lo; d.log_cost_new = ln; d.log_lambda = ll; d.log_accept = la;
+  d.log_w_arap = lw; d.log_fail = lf;
   s->has_template = false;
 }
 
@@ -534,13 +535,14 @@ int copy_debug(tt_stream* s, tt_frame_debug* dbg) {
   }
   LMScalars sc;
   HIPCHK(hipMemcpyAsync(&sc, d.sc, sizeof(sc), hipMemcpyDeviceToHost, st));
-  std::vector<double> lo(T), ln(T), ll(T);
+  std::vector<double> lo(T), ln(T), ll(T), lw(T);
   std::vector<int> la(T);
   if (T > 0) {
     if (d2h(lo.data(), d.log_cost_old, T, st)) return TT_EDEVICE;
     if (d2h(ln.data(), d.log_cost_new, T, st)) return TT_EDEVICE;
     if (d2h(ll.data(), d.log_lambda, T, st)) return TT_EDEVICE;
     if (d2h(la.data(), d.log_accept, T, st)) return TT_EDEVICE;
+    if (d2h(lw.data(), d.log_w_arap, T, st)) return TT_EDEVICE;
   }
   HIPCHK(hipStreamSynchronize(st));
   for (int h = 0; h < R; h++) {
@@ -572,6 +574,7 @@ int copy_debug(tt_stream* s, tt_frame_debug* dbg) {
     if (dbg->cost_new) dbg->cost_new[t] = ln[t];
     if (dbg->lambda) dbg->lambda[t] = ll[t];
     if (dbg->accepted) dbg->accepted[t] = (uint8_t)la[t];
+    if (dbg->w_arap_iter) dbg->w_arap_iter[t] = lw[t];
   }
   return TT_OK;
 }
@@ -627,6 +630,14 @@ static int device_cus() {
   return cus;
 }
 
+// Rate of the constant clock that s_memrealtime reads (kHz), 0 if unknown.
+static int device_wall_khz() {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
+  return khz;
+}
+
 int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_stream, tt_stream** out) {
   if (!p || !K || !out) return TT_EINVAL;
   *out = nullptr;
@@ -656,6 +667,7 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
   DevState& d = s->d;
   d.HW = K->width * K->height;
   d.num_cus = device_cus();
+  d.wall_khz = device_wall_khz();
   d.solver = p->solver;
   d.prec = (p->solver == TT_SOLVE_NODE) ? TT_FP32 : p->precision;
   d.ir_iters = (d.prec == TT_FP32) ? 0 : p->ir_iters;
@@ -669,6 +681,8 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_cost_new, (size_t)T);
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_lambda, (size_t)T);
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_accept, (size_t)T);
+  rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_w_arap, (size_t)T);
+  rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_fail, (size_t)T);
   if (rc) {
     tt_destroy(s);
     return rc;
@@ -715,6 +729,7 @@ int tt_debug_cholesky_solve_ex(int n, const float* A, const float* b, float* x, 
     return TT_EINVAL;
   DevState d;
   d.num_cus = device_cus();
+  d.wall_khz = device_wall_khz();
   d.n = n;
   d.npad = ((n + TT_NB - 1) / TT_NB) * TT_NB;
   d.nb = d.npad / TT_NB;
@@ -751,6 +766,7 @@ int tt_debug_cholesky_solve_ex(int n, const float* A, const float* b, float* x, 
     LMScalars sc;
     memset(&sc, 0, sizeof(sc));
     int epoch = 1, e2 = 2;
+    sc.solve_epoch = epoch;
     DevState* dp[1] = {&d};
     bool ok = hipMemcpyAsync(d.A, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
               hipMemsetAsync(d.flags, 0, sizeof(int) * chol_flag_ints(d.nb), st) == hipSuccess &&
@@ -828,6 +844,26 @@ static int take_device_error(tt_stream* s) {
   (void)hipMemcpyAsync(&s->d.sc->err, &zero, sizeof(int), hipMemcpyHostToDevice, s->st);
   (void)hipStreamSynchronize(s->st);
   return TT_EDEVICE;
+}
+
+int tt_get_frame_log(tt_stream* s, double* cost_old, double* cost_new, double* lambda, uint8_t* accepted,
+                     double* w_arap, int32_t* chol_fail) {
+  if (!s) return TT_EINVAL;
+  Busy busy(s);
+  if (!busy.ok) return TT_EBUSY;
+  const int T = s->P.lm_iters;
+  if (T <= 0) return TT_OK;
+  const DevState& d = s->d;
+  std::vector<int> la(T);
+  hipStream_t st = s->st;
+  if (d2h(cost_old, d.log_cost_old, T, st) || d2h(cost_new, d.log_cost_new, T, st) ||
+      d2h(lambda, d.log_lambda, T, st) || d2h(la.data(), d.log_accept, T, st) || d2h(w_arap, d.log_w_arap, T, st) ||
+      d2h(chol_fail, d.log_fail, T, st))
+    return TT_EDEVICE;
+  HIPCHK(hipStreamSynchronize(st));
+  if (accepted)
+    for (int t = 0; t < T; t++) accepted[t] = (uint8_t)la[t];
+  return TT_OK;
 }
 
 int tt_sync(tt_stream* s) {
@@ -995,6 +1031,7 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
     HIPCHK(hipMemsetAsync(d.x, 0, sizeof(float) * d.npad, st));
     HIPCHK(hipMemsetAsync(d.flags, 0, sizeof(int) * chol_flag_ints(d.nb), st));
     HIPCHK(hipMemsetAsync(d.tw, 0, sizeof(uint64_t) * d.npad, st));
+    HIPCHK(hipMemsetAsync(&d.sc->solve_epoch, 0, sizeof(int), st));
     s->solve_epoch = 0;
     HIPCHK(hipStreamSynchronize(st));
   }

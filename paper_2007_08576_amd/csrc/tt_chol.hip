@@ -19,6 +19,24 @@
 
 namespace {
 
+// Hand-over between workgroups (possibly on different XCDs, each with its own L2) through memory:
+// the producer writes back its L2 before it raises a flag, the consumer invalidates its caches
+// after it has seen the flag. Both cache operations are asynchronous: the flag store may not be
+// issued before the write-back has completed, and the consumer's loads (its own or, after a
+// barrier, those of other wavefronts) not before the invalidation has. The explicit wait after each
+// fence is what enforces that: the compiler's own wait after these fences is dropped when no load
+// or store is outstanding before them, and without it a consumer on another XCD can see the flag
+// ahead of some of the tile's cache lines.
+__device__ __forceinline__ void acquire_done() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);
+}
+__device__ __forceinline__ void release_flag(int* f, int v) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);
+  __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int NB = TT_NB;
 constexpr int LDS_LD = NB + 2;  // conflict-free for the 16 x 4 MFMA operand reads
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -239,7 +257,7 @@ __device__ __forceinline__ void chain_poll(const ChainPoll& q) {
     const int v0 = __hip_atomic_load(q.f0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int v1 = __hip_atomic_load(q.f1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     r = (v0 == q.epoch) && (v1 == q.epoch);
-    if (r) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (r) acquire_done();
   }
   *q.s_ctr = c;
   *q.s_ready = r ? 1 : 0;
@@ -254,7 +272,7 @@ __device__ __forceinline__ void wave_publish(int* cnt, int* flag, int epoch) {
     const int prev = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (prev == 3) {
       __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      release_flag(flag, epoch);
     }
   }
 }
@@ -411,10 +429,11 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
 // resident workgroups. Only CRIT steps lie on the critical path: the accumulations run ahead on
 // the other workgroups.
 //
-// Hand-over: a producer's stores complete (s_waitcnt), then one thread releases at agent scope
-// (L2 write-back) and stores the tile's flag (the solve's epoch); a consumer polls the flag with
-// agent-scope loads and acquires at agent scope before reading the tile. A wait that outlasts a
-// deadline aborts the whole solve (all workgroups drain, the step is marked failed).
+// Hand-over: a producer's stores complete (s_waitcnt), then one thread writes back its L2, waits
+// for the write-back and stores the tile's flag (the solve's epoch); a consumer polls the flag with
+// agent-scope loads, invalidates its caches and waits for the invalidation before any wavefront
+// reads the tile (release_flag / acquire_done). A wait that outlasts its deadline aborts the whole
+// solve (all workgroups drain, the step is marked failed and reported).
 enum { TASK_CRIT = 0, TASK_DIAGP = 1, TASK_SUBP = 2, TASK_FULL = 3 };
 
 struct CholSync {
@@ -487,17 +506,27 @@ __device__ __forceinline__ void decode_task(int t, int nb, int& kind, int& i, in
   c = j;
 }
 
-constexpr uint64_t kDeadlineTicks = 25000000ull;  // 0.25 s of the 100 MHz constant clock
-
 __device__ __forceinline__ int ld_flag(const int* f) {
   return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A wait that gives up (its deadline passed, or another wait of the solve gave up) marks the solve
+// failed: the abort word stops every other wait of the solve, and the step is rejected and
+// reported (TT_DEVERR_CHOL_SYNC), whichever task gave up and whether or not any ticket is left to
+// claim.
+__device__ __forceinline__ void mark_failed(const CholSync& S, LMScalars* sc, int epoch) {
+  __hip_atomic_store(S.abort_, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  sc->chol_fail = 1;
+  sc->err = TT_DEVERR_CHOL_SYNC;
+}
+
 // Thread 0 waits until every non-null flag equals epoch (the flags are read together, one round
-// trip per poll), then acquires; the block learns the result.
+// trip per poll), then acquires; the block learns the result. The wait gives up wait_ticks
+// (constant-clock ticks) after it began.
 __device__ bool block_wait(const int* f0, const int* f1, const int* f2, int epoch, const CholSync& S,
-                           uint64_t deadline, int* s_ok) {
+                           LMScalars* sc, uint64_t wait_ticks, int* s_ok) {
   if (threadIdx.x == 0) {
+    const uint64_t deadline = __builtin_amdgcn_s_memrealtime() + wait_ticks;
     bool ok = true;
     const int* g0 = f0 ? f0 : S.abort_;
     const int* g1 = f1 ? f1 : S.abort_;
@@ -512,8 +541,8 @@ __device__ bool block_wait(const int* f0, const int* f1, const int* f2, int epoc
       }
       __builtin_amdgcn_s_sleep(2);
     }
-    if (!ok) __hip_atomic_store(S.abort_, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!ok) mark_failed(S, sc, epoch);
+    acquire_done();
     *s_ok = ok ? 1 : 0;
   }
   __syncthreads();
@@ -523,9 +552,10 @@ __device__ bool block_wait(const int* f0, const int* f1, const int* f2, int epoc
 // Wavefront 0 finds how many consecutive k >= k0 (< nk) have both tiles fi[k] and fc[k] final,
 // waiting until at least one has; then acquires. Returns 0 if the solve was aborted.
 __device__ int block_ready_prefix(const int* fi, const int* fc, int k0, int nk, int epoch, const CholSync& S,
-                                  uint64_t deadline, int* s_val) {
+                                  LMScalars* sc, uint64_t wait_ticks, int* s_val) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
+    const uint64_t deadline = __builtin_amdgcn_s_memrealtime() + wait_ticks;
     int pre = 0, spins = 0;
     for (;;) {
       const int k = k0 + lane;
@@ -536,13 +566,13 @@ __device__ int block_ready_prefix(const int* fi, const int* fc, int k0, int nk, 
       if (pre > 0) break;
       if ((++spins & 15) == 0 &&
           (ld_flag(S.abort_) == epoch || __builtin_amdgcn_s_memrealtime() > deadline)) {
-        if (lane == 0) __hip_atomic_store(S.abort_, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) mark_failed(S, sc, epoch);
         break;
       }
       __builtin_amdgcn_s_sleep(2);
     }
     if (lane == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      acquire_done();
       *s_val = pre;
     }
   }
@@ -554,7 +584,7 @@ __device__ int block_ready_prefix(const int* fi, const int* fc, int k0, int nk, 
 __device__ __forceinline__ void block_publish(int* f, int epoch) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(f, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) release_flag(f, epoch);
 }
 
 // acc += X Y^T for 64 x 64 tiles X, Y in LDS (leading dimension LDS_LD). Four wavefronts each
@@ -778,6 +808,7 @@ __device__ __forceinline__ void chain_load(const CholArgs& P, int j, float4 va[4
 constexpr int kMaxCholBatch = 32;
 struct CholBatch {
   int nprob;
+  uint64_t wait_ticks;  // how long one hand-over wait may last, in constant-clock ticks
   CholArgs p[kMaxCholBatch];
 };
 
@@ -803,7 +834,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
   static_assert(POTRF_SCRATCH_FLOATS <= NB * LDS_LD, "factorisation scratch must fit in one tile buffer");
   __shared__ int s_task, s_val, s_mode, s_prob, s_ctr, s_pubcnt, s_fast;
   const int tid = threadIdx.x;
-  const uint64_t deadline = __builtin_amdgcn_s_memrealtime() + kDeadlineTicks;
+  const uint64_t wt = B.wait_ticks;
   if (tid == 0) s_pubcnt = 0;
   // Each system has its own ticket counter and task order. A workgroup visits the systems in a
   // cyclic order starting at blockIdx % nprob, claiming tasks from one until its counter runs out
@@ -904,7 +935,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         const size_t rj = (size_t)NB * j;
         chain = (j + 1 < nb) ? j + 1 : -1;
         if (!have_pref) {
-          if (j >= 2 && !block_wait(S.pdiag + j, S.psub + j, nullptr, epoch, S, deadline, &s_val)) {
+          if (j >= 2 && !block_wait(S.pdiag + j, S.psub + j, nullptr, epoch, S, P.sc, wt, &s_val)) {
             chain = -1;
             break;
           }
@@ -964,7 +995,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
             if (tid == 0) {
               const int v0 = ld_flag(S.pdiag + j + 1), v1 = ld_flag(S.psub + j + 1);
               const bool r = (v0 == epoch) && (v1 == epoch);
-              if (r) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+              if (r) acquire_done();
               s_val = r ? 1 : 0;
             }
             __syncthreads();
@@ -1019,7 +1050,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
       // 16-bit operand tiles (half the bytes), one step ahead in registers
       uint16_t* X16 = reinterpret_cast<uint16_t*>(&X[0][0]);
       uint16_t* Y16 = reinterpret_cast<uint16_t*>(&Y[0][0]);
-      int kr = block_ready_prefix(fi, fc, 0, nk, epoch, S, deadline, &s_val);
+      int kr = block_ready_prefix(fi, fc, 0, nk, epoch, S, P.sc, wt, &s_val);
       ok = kr > 0;
       uint4 va[2], vb[2];
       if (ok) {
@@ -1040,7 +1071,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         }
         mma64_acc16(X16, same ? X16 : Y16, acc, P.prec);
         if (next && !known) {
-          const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, deadline, &s_val);
+          const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, P.sc, wt, &s_val);
           if (more == 0) {
             ok = false;
             break;
@@ -1051,7 +1082,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         }
       }
     } else if (nk > 0) {
-      int kr = block_ready_prefix(fi, fc, 0, nk, epoch, S, deadline, &s_val);
+      int kr = block_ready_prefix(fi, fc, 0, nk, epoch, S, P.sc, wt, &s_val);
       ok = kr > 0;
       float4 va[4], vb[4];
       if (ok) {
@@ -1071,7 +1102,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         if (same) mma64_acc(X, X, acc);
         else mma64_acc(X, Y, acc);
         if (next && !known) {
-          const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, deadline, &s_val);
+          const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, P.sc, wt, &s_val);
           if (more == 0) {
             ok = false;
             break;
@@ -1091,7 +1122,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
       const int m = c - 1;
       floatx4 vt[2][2];
       if (c >= 2) {
-        if (!block_wait(S.dinv + m, S.psub + c, nullptr, epoch, S, deadline, &s_val)) continue;
+        if (!block_wait(S.dinv + m, S.psub + c, nullptr, epoch, S, P.sc, wt, &s_val)) continue;
         {
           float4 va[4], vb[4];
           csub_load(P, c, va);
@@ -1104,7 +1135,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         acc_zero(vt);
         mma64_acc(X, Y, vt);
       }
-      if (!block_wait(fi + m, c == 1 ? fc + m : nullptr, nullptr, epoch, S, deadline, &s_val)) continue;
+      if (!block_wait(fi + m, c == 1 ? fc + m : nullptr, nullptr, epoch, S, P.sc, wt, &s_val)) continue;
       {
         float4 va[4];
         tile_load(P.A, ld, ri, (size_t)NB * m, va);
@@ -1130,7 +1161,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
       block_publish(kind == TASK_DIAGP ? S.pdiag + i : S.psub + i, epoch);
       continue;
     }
-    if (!block_wait(S.dinv + c, nullptr, nullptr, epoch, S, deadline, &s_val)) continue;
+    if (!block_wait(S.dinv + c, nullptr, nullptr, epoch, S, P.sc, wt, &s_val)) continue;
     {
       float4 vb[4];
       tile_load(P.Linv + (size_t)c * NB * NB, NB, 0, 0, vb);
@@ -1337,16 +1368,22 @@ static CholArgs chol_args(const DevState& d, int epoch) {
   return P;
 }
 
+// A hand-over wait of the factorisation gives up after this long (then the step is rejected and
+// the failure reported): far beyond any wait of a working solve, short enough to end a broken one.
+constexpr double kWaitSeconds = 1.0;
+
 hipError_t launch_cholesky_factor_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st) {
   for (int b0 = 0; b0 < S; b0 += kMaxCholBatch) {
     CholBatch B;
     B.nprob = (S - b0 < kMaxCholBatch) ? S - b0 : kMaxCholBatch;
-    int tasks = 0, cus = 256;
+    int tasks = 0, cus = 256, khz = 100000;  // the constant clock runs at 100 MHz unless the device says otherwise
     for (int q = 0; q < B.nprob; q++) {
       B.p[q] = chol_args(*ds[b0 + q], epochs[b0 + q]);
       tasks += B.p[q].ntasks;
       if (ds[b0 + q]->num_cus > 0) cus = ds[b0 + q]->num_cus;
+      if (ds[b0 + q]->wall_khz > 0) khz = ds[b0 + q]->wall_khz;
     }
+    B.wait_ticks = (uint64_t)(kWaitSeconds * 1000.0 * khz);
     const int grid = tasks < 2 * cus ? tasks : 2 * cus;
     hipLaunchKernelGGL(k_chol_dataflow, dim3(grid), dim3(256), 0, st, B);
   }

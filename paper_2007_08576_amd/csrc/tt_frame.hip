@@ -399,6 +399,7 @@ __global__ __launch_bounds__(kHypThreads) void k_ransac_hyp(const float* __restr
   for (int k = tid; k < K1; k += kHypThreads) w[k] = (o2[k].w > 0.0f) ? 1.0 : 0.0;
   if (tid == 0) degenerate = 0;
   __syncthreads();
+  int cnt = 0;  // this thread's matches with d_k <= H in the last w-step
   for (int it = 0; it < iters; it++) {
     double c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = tid; k < K1; k += kHypThreads) {
@@ -439,6 +440,7 @@ __global__ __launch_bounds__(kHypThreads) void k_ransac_hyp(const float* __restr
       double e2 = s2[2] - (Rs[6] * s1[0] + Rs[7] * s1[1] + Rs[8] * s1[2]);
       double d = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
       w[k] = (d > H) ? H / d : 1.0;
+      if (it == iters - 1 && d <= H) cnt++;
     }
     __syncthreads();
   }
@@ -450,13 +452,12 @@ __global__ __launch_bounds__(kHypThreads) void k_ransac_hyp(const float* __restr
     }
     return;
   }
-  // W = sum w_k ; n_in = #{d_k <= H} = #{w_k == 1} among usable (w_k = 1 exactly when d <= H)
+  // W = sum w_k over usable matches; n_in = #{d_k <= H} as counted in the last w-step (H / d_k can
+  // round to 1 for d_k just above H, so the weight does not decide it)
   double acc = 0.0;
-  int cnt = 0;
   for (int k = tid; k < K1; k += kHypThreads) {
     if (o2[k].w <= 0.0f) continue;
     acc += w[k];
-    cnt += (w[k] == 1.0) ? 1 : 0;
   }
   red[0][tid] = acc;
   // integer count per wavefront by ballot-free shuffles, then across waves

@@ -43,6 +43,7 @@ struct LMScalars {
   int accept;        // decision of the last iteration
   int it;            // iteration counter
   int err;           // device-side error bits (TT_DEVERR_*), reported as TT_EDEVICE
+  int solve_epoch;   // epoch of the current solve (set by the damping kernel)
 };
 
 #define TT_DEVERR_CHOL_SYNC 1  // a hand-over wait of the factorisation passed its deadline
@@ -116,6 +117,7 @@ struct DevState {
   float* Linv = nullptr;     // [nb][TT_NB][TT_NB]
   int* flags = nullptr;      // [chol_flag_ints(nb)] factorisation and back-substitution flags
   int num_cus = 0;           // compute units of the device (persistent launch size)
+  int wall_khz = 0;          // rate of the device's constant clock (s_memrealtime), kHz
   int prec = TT_FP32;        // precision form of the solve
   int ir_iters = 0;          // refinement steps per solve (16-bit forms)
   int solver = TT_SOLVE_DENSE; // coupled dense solve or one 6 x 6 solve per node
@@ -131,6 +133,8 @@ struct DevState {
   double* log_cost_new = nullptr;
   double* log_lambda = nullptr;
   int* log_accept = nullptr;
+  double* log_w_arap = nullptr;   // [T] ARAP weight used by each iteration of the last frame
+  int* log_fail = nullptr;        // [T] 1 where the iteration's factorisation failed
   // debug copies
   float* A_dbg = nullptr;
   float* g_dbg = nullptr;

@@ -757,6 +757,7 @@ __global__ __launch_bounds__(1024) void k_damp(float* __restrict__ A, const floa
     sc->e_old = shd[0];
     sc->eps = (double)eps;
     sc->chol_fail = 0;
+    sc->solve_epoch = (sc->solve_epoch == 0x7FFFFFFF) ? 1 : sc->solve_epoch + 1;
   }
 }
 
@@ -918,7 +919,7 @@ __global__ __launch_bounds__(256) void k_accept(const double* __restrict__ part,
                                                 float4* __restrict__ pos, const float4* __restrict__ posc,
                                                 float4* __restrict__ ndisp, const float4* __restrict__ ndispc,
                                                 double* log_old, double* log_new, double* log_lambda,
-                                                int* log_acc) {
+                                                int* log_acc, double* log_w_arap, int* log_fail) {
   __shared__ double sh[256];
   __shared__ int acc_s;
   double e = 0.0;
@@ -934,6 +935,8 @@ __global__ __launch_bounds__(256) void k_accept(const double* __restrict__ part,
     log_new[it] = e_new;
     log_lambda[it] = sc->lambda;
     log_acc[it] = acc ? 1 : 0;
+    log_w_arap[it] = sc->w_arap;
+    log_fail[it] = fail ? 1 : 0;
     sc->e_new = e_new;
     sc->accept = acc ? 1 : 0;
     sc->lambda = acc ? fmax(sc->lambda / 10.0, 1e-10) : fmin(sc->lambda * 10.0, 1e10);
@@ -1091,7 +1094,8 @@ hipError_t launch_lm_finish(DevState& d, const tt_params& P, const Intr& K, hipS
   ArapArgs aa = arap_args(d, P);
   hipLaunchKernelGGL(k_cost, dim3(d.N + ra.P.nbp + ra.P.nbf), dim3(kArapThreads), 0, st, aa, ra, d.Wc, d.ndispc);
   hipLaunchKernelGGL(k_accept, dim3(1), dim3(256), 0, st, d.partial, ra.P, d.N, d.sc, d.W, d.Wc, d.pos, d.posc,
-                     d.ndisp, d.ndispc, d.log_cost_old, d.log_cost_new, d.log_lambda, d.log_accept);
+                     d.ndisp, d.ndispc, d.log_cost_old, d.log_cost_new, d.log_lambda, d.log_accept,
+                     d.log_w_arap, d.log_fail);
   return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ class Params(C.Structure):
 
 _DEBUG_FIELDS = ("match_idx", "match_dist", "wstar", "preselected", "hyp_k0", "hyp_W", "hyp_nin",
                  "hyp_kept", "corr0", "r0", "omega0", "orbw0", "A0", "g0", "w_arap", "cost_old",
-                 "cost_new", "lambda_", "accepted", "delta0")
+                 "cost_new", "lambda_", "accepted", "delta0", "w_arap_iter")
 
 
 class OrbParams(C.Structure):
@@ -86,6 +86,7 @@ def lib():
         L.tt_track_frame_device_ev.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp, vp]
         L.tt_track_batch_device.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(FrameDevice)]
         L.tt_sync.argtypes = [vp]
+        L.tt_get_frame_log.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.tt_hip_stream.argtypes = [vp]
         L.tt_hip_stream.restype = vp
         L.tt_get_template_info.argtypes = [vp] + [vp] * 7
@@ -200,7 +201,8 @@ class Stream:
                        hyp_kept=np.zeros(R, np.uint8), corr0=np.zeros(M, np.int32), r0=np.zeros(M),
                        omega0=np.zeros(M), orbw0=np.zeros(K1), A0=np.zeros((n, n)), g0=np.zeros(n),
                        w_arap=np.zeros(1), cost_old=np.zeros(T), cost_new=np.zeros(T),
-                       lambda_=np.zeros(T), accepted=np.zeros(T, np.uint8), delta0=np.full(n, np.nan))
+                       lambda_=np.zeros(T), accepted=np.zeros(T, np.uint8), delta0=np.full(n, np.nan),
+                       w_arap_iter=np.zeros(T))
             dbg = FrameDebug(**{k: _ptr(v) for k, v in out.items()})
         rc = lib().tt_track_frame(self.h, _ptr(depth), _ptr(feat_xyz), _ptr(feat_desc), feat_xyz.shape[0],
                                   _ptr(verts), _ptr(dq), C.byref(dbg) if dbg is not None else None)
@@ -227,6 +229,16 @@ class Stream:
 
     def sync(self):
         _check(lib().tt_sync(self.h), "tt_sync")
+
+    def frame_log(self):
+        """LM record of the last frame: cost at the iterate and candidate, damping, accepted,
+        ARAP weight and factorisation failure per iteration."""
+        T = self.params.lm_iters
+        out = dict(cost_old=np.zeros(T), cost_new=np.zeros(T), lambda_=np.zeros(T), accepted=np.zeros(T, np.uint8),
+                   w_arap=np.zeros(T), chol_fail=np.zeros(T, np.int32))
+        _check(lib().tt_get_frame_log(self.h, *[_ptr(v) for v in out.values()]), "tt_get_frame_log")
+        out["lambda"] = out.pop("lambda_")
+        return out
 
     def hip_stream(self):
         return lib().tt_hip_stream(self.h)

@@ -166,3 +166,65 @@ def test_fused_rows_arap_equals_separate(env, solver):
     for t in range(2):
         assert np.array_equal(res[0][t][0], res[1][t][0]), f"frame {t + 1}: vertices differ"
         assert np.array_equal(res[0][t][1], res[1][t][1]), f"frame {t + 1}: warps differ"
+
+
+def test_config4_mix_is_the_same_alone_concurrent_and_batched(env):
+    """The 16-stream serving mix (control points 123-772, 320x240 to 640x480, 540-2,900
+    features), first two frames, in FP32 and in the bfloat16 form with refinement: each stream's
+    vertices and warps are bit for bit the same when it is tracked alone (synchronised after every
+    frame), when all streams are queued at once on their own HIP streams (their persistent
+    factorisations then run side by side on the device), and in one batch. The smallest streams
+    are then compared with the FP64 oracle (0.01 mm RMS, Sec. 2)."""
+    from oracle import oracle as O
+    tt, torch = env
+    dev = torch.device("cuda:0")
+    scenes = synth.make_config4(seed=4, n_streams=16, n_frames=300)
+    frames = [[_dev_frame(torch, sc.frame(t), dev) for t in (1, 2)] for sc in scenes]
+    S = len(scenes)
+    first = {}
+    for prec in (tt.TT_FP32, tt.TT_BF16_IR):
+        res = {}
+        for mode in ("alone", "concurrent", "batch"):
+            streams = [tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=4, precision=prec),
+                                 tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx,
+                                               sc.intr.cy)) for sc in scenes]
+            for s, sc in zip(streams, scenes):
+                s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+            ov = [torch.zeros((sc.pts.shape[0], 3), dtype=torch.float32, device=dev) for sc in scenes]
+            oq = [torch.zeros((sc.num_control_points, 8), dtype=torch.float32, device=dev) for sc in scenes]
+            out = []
+            for t in range(2):
+                args = [(frames[q][t][0], frames[q][t][1], frames[q][t][2], frames[q][t][1].shape[0], ov[q], oq[q])
+                        for q in range(S)]
+                if mode == "batch":
+                    tt.track_batch_device(streams, args)
+                else:
+                    for q in range(S):
+                        streams[q].track_frame_device(*args[q])
+                        if mode == "alone":
+                            streams[q].sync()
+                for s in streams:
+                    s.sync()
+                out.append([(ov[q].cpu().numpy().copy(), oq[q].cpu().numpy().copy()) for q in range(S)])
+            res[mode] = out
+            for s in streams:
+                s.destroy()
+        for mode in ("concurrent", "batch"):
+            for t in range(2):
+                for q in range(S):
+                    a, b = res["alone"][t][q], res[mode][t][q]
+                    assert np.isfinite(a[0]).all()
+                    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), \
+                        f"precision {prec}, {mode}: stream {q} (N={scenes[q].num_control_points}) differs at frame {t + 1}"
+        first[prec] = [res["alone"][0][q][0] for q in range(S)]
+    # the three streams with the fewest control points against the FP64 oracle, frame 1 from identity
+    for q in sorted(range(S), key=lambda i: scenes[i].num_control_points)[:3]:
+        sc = scenes[q]
+        so = O.Stream(O.default_params(num_control_points=sc.num_control_points, seed=4),
+                      O.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy))
+        so.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+        fr = sc.frame(1)
+        vo = so.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc)[0]
+        for prec, v in first.items():
+            rms = float(np.sqrt(((v[q].astype(np.float64) - vo) ** 2).sum(1).mean()))
+            assert rms <= 0.01, f"stream {q}, precision {prec}: {rms:.3g} mm RMS from the oracle"

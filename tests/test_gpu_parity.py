@@ -140,6 +140,20 @@ def test_lm_bookkeeping(c1):
     assert np.allclose(c1["do"]["cost_old"][0], dg["cost_old"][0], rtol=1e-5)
 
 
+def test_frame_log_and_arap_weight_per_iteration(c1):
+    """The per-iteration record the library keeps for the last frame (tt_get_frame_log) is the one
+    the debug taps report, and every iteration uses the iteration-0 ARAP weight (Sec. 2, after
+    Eq. (1): set once per frame), as the oracle does."""
+    dg, do, sg = c1["dg"], c1["do"], c1["sg"]
+    log = sg.frame_log()
+    for k in ("cost_old", "cost_new", "lambda", "accepted"):
+        assert np.array_equal(np.asarray(log[k], np.float64), np.asarray(dg[k], np.float64), equal_nan=True), k
+    assert not log["chol_fail"].any()
+    assert np.all(log["w_arap"] == dg["w_arap"]) and np.all(dg["w_arap_iter"] == dg["w_arap"])
+    assert np.all(do["w_arap_iter"] == do["w_arap"])
+    assert np.allclose(dg["w_arap_iter"], do["w_arap_iter"], rtol=1e-6, atol=0)
+
+
 def test_repeatable_bit_for_bit(c1, T):
     sc, fr = c1["sc"], c1["fr"]
     sg = T.Stream(_params(T, num_control_points=sc.num_control_points, seed=1), _intr(T, sc.intr))
