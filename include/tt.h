@@ -254,6 +254,21 @@ int tt_debug_cholesky_solve_ex(int n, const float* A, const float* b, float* x, 
 /* Device bytes held by the stream. */
 int tt_device_bytes(tt_stream* s, uint64_t* bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops): the FP32 form of tt_debug_cholesky_solve_ex on device buffers, allocating nothing. Every
+ * workspace (padded working matrix, inverse diagonal blocks, hand-over flags, scalars, scaling,
+ * solution) lives in one static device array of TT_NOALLOC_SCRATCH_BYTES that each GPU the library
+ * runs on holds until the process ends; the first call on a GPU resolves its address once.
+ * d_A [n][n] row-major, SPD, lower triangle read; d_b [n]; d_x [n] receives x; d_status [2]
+ * receives (1 if a pivot was not positive, device error bits). All device memory, caller-owned.
+ * Queued on hip_stream (a hipStream_t; NULL: the null stream), returns without waiting.
+ * TT_EINVAL: n outside 1..TT_NOALLOC_MAX_N or a NULL buffer. Calls on one GPU share the array, which
+ * keeps the last call's contents: calls that overlap on one GPU race (queue them on one stream). */
+#define TT_NOALLOC_MAX_N 1024
+#define TT_NOALLOC_SCRATCH_BYTES 4736768
+int tt_cholesky_solve_noalloc(int n, const float* d_A, const float* d_b, float* d_x, int32_t* d_status,
+                              void* hip_stream);
+
 /* Destroys the stream and frees its device memory. */
 int tt_destroy(tt_stream* s);
 

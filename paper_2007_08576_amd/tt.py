@@ -96,6 +96,7 @@ def lib():
         L.tt_set_timing.argtypes = [vp, C.c_int]
         L.tt_debug_cholesky_solve.argtypes = [C.c_int, vp, vp, vp, C.POINTER(C.c_int)]
         L.tt_debug_cholesky_solve_ex.argtypes = [C.c_int, vp, vp, vp, C.POINTER(C.c_int), C.c_int, C.c_int]
+        L.tt_cholesky_solve_noalloc.argtypes = [C.c_int, vp, vp, vp, vp, vp]
         L.tt_get_timing.argtypes = [vp, vp, vp]
         L.tt_destroy.argtypes = [vp]
         L.tt_strerror.argtypes = [C.c_int]
@@ -298,6 +299,14 @@ def debug_cholesky_solve(A, b, precision=TT_FP32, ir_iters=2):
     _check(lib().tt_debug_cholesky_solve_ex(int(b.shape[0]), _ptr(A), _ptr(b), _ptr(x), C.byref(fail),
                                             int(precision), int(ir_iters)), "tt_debug_cholesky_solve_ex")
     return x, bool(fail.value)
+
+
+def cholesky_solve_noalloc(n, d_A, d_b, d_x, d_status, hip_stream=None):
+    """tt_cholesky_solve_noalloc on device buffers (torch tensors or addresses); queued, not waited
+    for."""
+    _check(lib().tt_cholesky_solve_noalloc(int(n), _dev_ptr(d_A), _dev_ptr(d_b), _dev_ptr(d_x), _dev_ptr(d_status),
+                                           None if hip_stream is None else C.c_void_p(hip_stream)),
+           "tt_cholesky_solve_noalloc")
 
 
 def _event_ptr(ev):
