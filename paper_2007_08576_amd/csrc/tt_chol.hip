@@ -19,20 +19,28 @@
 
 namespace {
 
-// Hand-over between workgroups (possibly on different XCDs, each with its own L2) through memory:
-// the producer writes back its L2 before it raises a flag, the consumer invalidates its caches
-// after it has seen the flag. Both cache operations are asynchronous: the flag store may not be
-// issued before the write-back has completed, and the consumer's loads (its own or, after a
-// barrier, those of other wavefronts) not before the invalidation has. The explicit wait after each
-// fence is what enforces that: the compiler's own wait after these fences is dropped when no load
-// or store is outstanding before them, and without it a consumer on another XCD can see the flag
-// ahead of some of the tile's cache lines.
+// Hand-over between workgroups (possibly on different XCDs, each with its own L2) through memory.
+// Every store of hand-over data (tiles, partial tiles, inverse blocks) is device-coherent (sc1): it
+// writes through the L2 to memory, so a publication waits only for its own workgroup's stores
+// (s_waitcnt, then the barrier) before it stores the flag, and no write-back of the whole L2 sits on
+// the critical path. The consumer polls the flag, invalidates its caches (stale copies of a tile's
+// lines that its XCD read or wrote earlier) and waits for the invalidation before any wavefront
+// reads the tile. That wait is explicit: the compiler's own wait after the fence is dropped when no
+// load or store is outstanding before it, and a load racing the invalidation can hit a stale line.
 __device__ __forceinline__ void acquire_done() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __builtin_amdgcn_s_waitcnt(0);
 }
-__device__ __forceinline__ void release_flag(int* f, int v) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+__device__ __forceinline__ void st_coh(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh16(uint16_t* p, uint16_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// The calling thread's device-coherent stores (and, after a barrier, the workgroup's) are complete
+// when the flag is stored.
+__device__ __forceinline__ void publish_flag(int* f, int v) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_waitcnt(0);
   __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -236,7 +244,7 @@ constexpr int POTRF_SCRATCH_FLOATS = 12 * 16 * XS;
 // Optionally (U non-null) the block is first updated, L -= U U^T with U the 64 x 64 tile in LDS:
 // wavefront 0 updates only tile (0, 0) before leaf 0 and the others update the remaining nine lower
 // tiles meanwhile. When pub is non-null, each wavefront completes its earlier global stores as soon
-// as its part of that first phase is done, and the last of the four raises *pub = epoch (release,
+// as its part of that first phase is done, and the last of the four raises *pub = epoch (arrivals
 // counted in the LDS word *pub_cnt, which must be 0 on entry and is 0 again on return). Scratch is
 // first written after that phase, so U may share its memory.
 // A look ahead that one idle thread runs during the factorisation's fourth phase: it reads the
@@ -263,16 +271,16 @@ __device__ __forceinline__ void chain_poll(const ChainPoll& q) {
   *q.s_ready = r ? 1 : 0;
 }
 
-// One wavefront's share of a block-wide publication: its stores complete, then it counts itself in
-// *cnt (LDS); the fourth to arrive resets the count and raises *flag = epoch (release at agent
-// scope, which writes back the L2 that holds every wavefront's completed stores).
+// One wavefront's share of a block-wide publication: its device-coherent stores complete, then it
+// counts itself in *cnt (LDS); the fourth to arrive resets the count and raises *flag = epoch, by
+// which time every wavefront's stores have reached memory.
 __device__ __forceinline__ void wave_publish(int* cnt, int* flag, int epoch) {
   __builtin_amdgcn_s_waitcnt(0);
   if ((threadIdx.x & 63) == 0) {
     const int prev = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (prev == 3) {
       __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      release_flag(flag, epoch);
+      publish_flag(flag, epoch);
     }
   }
 }
@@ -580,11 +588,11 @@ __device__ int block_ready_prefix(const int* fi, const int* fc, int k0, int nk, 
   return *s_val;
 }
 
-// All stores of the block complete, then thread 0 releases at agent scope and raises the flag.
+// All stores of the block complete, then thread 0 raises the flag.
 __device__ __forceinline__ void block_publish(int* f, int epoch) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) release_flag(f, epoch);
+  if (threadIdx.x == 0) publish_flag(f, epoch);
 }
 
 // acc += X Y^T for 64 x 64 tiles X, Y in LDS (leading dimension LDS_LD). Four wavefronts each
@@ -658,7 +666,7 @@ __device__ __forceinline__ void acc_store(float* __restrict__ A, int ld, size_t 
 #pragma unroll
     for (int b = 0; b < 2; b++)
 #pragma unroll
-      for (int r = 0; r < 4; r++) A[(r0 + acc_row(a, r)) * ld + c0 + acc_col(b)] = v[a][b][r];
+      for (int r = 0; r < 4; r++) st_coh(&A[(r0 + acc_row(a, r)) * ld + c0 + acc_col(b)], v[a][b][r]);
 }
 __device__ __forceinline__ void acc_to_lds(float (*X)[LDS_LD], const floatx4 v[2][2], bool lower_only) {
 #pragma unroll
@@ -703,7 +711,7 @@ __device__ __forceinline__ void acc_store16(uint16_t* __restrict__ A16, int ld, 
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const float f = v[a][b][r];
-        A16[(r0 + acc_row(a, r)) * ld + c0 + acc_col(b)] = (prec == TT_BF16_IR) ? to_bf16(f) : to_f16(f);
+        st_coh16(&A16[(r0 + acc_row(a, r)) * ld + c0 + acc_col(b)], (prec == TT_BF16_IR) ? to_bf16(f) : to_f16(f));
       }
 }
 
@@ -962,8 +970,9 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
               const int row = 16 * g + 4 * lk + q, col = 16 * c + li;
               const float v = t4[c][q];
               X[row][col] = v;
-              P.A[(rj + row) * ld + rj - NB + col] = v;
-              if (P.prec != TT_FP32) P.A16[(rj + row) * ld + rj - NB + col] = (P.prec == TT_BF16_IR) ? to_bf16(v) : to_f16(v);
+              st_coh(&P.A[(rj + row) * ld + rj - NB + col], v);
+              if (P.prec != TT_FP32)
+                st_coh16(&P.A16[(rj + row) * ld + rj - NB + col], (P.prec == TT_BF16_IR) ? to_bf16(v) : to_f16(v));
             }
           __syncthreads();
         }
@@ -982,7 +991,10 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         float* Lj = P.Linv + (size_t)j * NB * NB;
         for (int e = tid; e < NB * NB / 4; e += 256) {
           const int r = e >> 4, cc = 4 * (e & 15);
-          *reinterpret_cast<float4*>(Lj + r * NB + cc) = make_float4(Z[r][cc], Z[r][cc + 1], Z[r][cc + 2], Z[r][cc + 3]);
+          st_coh(Lj + r * NB + cc, Z[r][cc]);
+          st_coh(Lj + r * NB + cc + 1, Z[r][cc + 1]);
+          st_coh(Lj + r * NB + cc + 2, Z[r][cc + 2]);
+          st_coh(Lj + r * NB + cc + 3, Z[r][cc + 3]);
         }
         if (tid == 0 && !ok) P.sc->chol_fail = 1;
         // If the look ahead did not find the next step's partial tiles ready, look once more; if they
