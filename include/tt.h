@@ -97,6 +97,10 @@ typedef struct {
                               that project to one pixel only the nearest to the camera (smallest
                               z as float32, ties to the lower index) takes it, the others have no
                               ICP row in that iteration */
+  int graph;               /* 0 (default): the LM iterations of each frame are launched kernel by
+                              kernel; 1: they are captured once per front-buffer parity into a HIP
+                              graph and replayed on later frames (single-stream calls without
+                              debug taps or stage timers; the results are the same bit for bit) */
 } tt_params;
 
 /* Optional per-frame outputs of tt_track_frame; each pointer may be NULL. Sizes: K1 template

@@ -52,6 +52,11 @@ void free_list(std::vector<void*>& list, uint64_t& bytes) {
 void free_template(tt_stream* s) {
   if (s->st) (void)hipStreamSynchronize(s->st);
   if (s->st_front) (void)hipStreamSynchronize(s->st_front);
+  for (int f = 0; f < 2; f++)  // captured against the buffers freed below
+    if (s->lm_graph[f]) {
+      (void)hipGraphExecDestroy(s->lm_graph[f]);
+      s->lm_graph[f] = nullptr;
+    }
   free_list(s->allocs_template, s->bytes_template);
   DevState& d = s->d;
   int HW = d.HW, K2cap = d.K2cap;
@@ -267,7 +272,6 @@ int enqueue_front(tt_stream* s, DevState& dd, int K2, hipStream_t st, const void
   }
   HIPCHK(hipEventRecord(s->ev_front_done[f], sf));
   HIPCHK(hipStreamWaitEvent(st, s->ev_front_done[f], 0));
-  HIPCHK(launch_lm_begin(s->d, P.lm_lambda0, st));
   return TT_OK;
 }
 
@@ -277,8 +281,9 @@ int enqueue_lm_done(tt_stream* s, hipStream_t st) {
   return TT_OK;
 }
 
-// One LM iteration up to the damped system: rows, assembly, damping; returns the solve's epoch.
-int enqueue_assemble(tt_stream* s, DevState& dd, int it, bool dbg, hipStream_t st, int* epoch) {
+// One LM iteration up to the damped system: rows, assembly, damping (which also advances the
+// solve's epoch on the device).
+int enqueue_assemble(tt_stream* s, DevState& dd, int it, bool dbg, hipStream_t st) {
   DevState& d = s->d;
   const tt_params& P = s->P;
   Intr K = intr_of(s);
@@ -309,8 +314,6 @@ int enqueue_assemble(tt_stream* s, DevState& dd, int it, bool dbg, hipStream_t s
     HIPCHK(hipMemcpyAsync(d.omega_dbg, d.omega, sizeof(float) * d.M, hipMemcpyDeviceToDevice, st));
     if (d.K1) HIPCHK(hipMemcpyAsync(d.orbw_dbg, d.orbw, sizeof(float) * d.K1, hipMemcpyDeviceToDevice, st));
   }
-  s->solve_epoch = (s->solve_epoch == 0x7FFFFFFF) ? 1 : s->solve_epoch + 1;
-  *epoch = s->solve_epoch;
   {
     StageTimer tm(s, TT_STAGE_SOLVE, st);
     HIPCHK(launch_lm_damp(dd, st));
@@ -319,21 +322,14 @@ int enqueue_assemble(tt_stream* s, DevState& dd, int it, bool dbg, hipStream_t s
   return TT_OK;
 }
 
-static int next_subst(tt_stream* s) {
-  s->subst_epoch = (s->subst_epoch == 0x7FFFFFFF) ? 1 : s->subst_epoch + 1;
-  return s->subst_epoch;
-}
-
 // Factorisation, substitutions and (16-bit forms) refinement of S systems at once.
-int enqueue_solve(tt_stream* const* ss, DevState* const* dp, const int* epochs, int S, hipStream_t st) {
-  std::vector<int> be(S), fe(S);
+int enqueue_solve(tt_stream* const* ss, DevState* const* dp, int S, hipStream_t st) {
   {
     StageTimer tm(ss[0], TT_STAGE_FACTOR, st);
-    HIPCHK(launch_cholesky_factor_batch(dp, epochs, S, st));
+    HIPCHK(launch_cholesky_factor_batch(dp, S, st));
   }
   StageTimer tm(ss[0], TT_STAGE_SOLVE, st);
-  for (int q = 0; q < S; q++) be[q] = next_subst(ss[q]);
-  HIPCHK(launch_cholesky_backsolve_batch(dp, be.data(), S, st));
+  HIPCHK(launch_cholesky_backsolve_batch(dp, 0, S, st));
   // refinement for the systems in a 16-bit form
   std::vector<DevState*> ir;
   std::vector<tt_stream*> irs;
@@ -348,14 +344,9 @@ int enqueue_solve(tt_stream* const* ss, DevState* const* dp, const int* epochs, 
   HIPCHK(launch_ir_accum_batch(ir.data(), (int)ir.size(), 0, st));
   for (int t = 0; t < steps; t++) {
     std::vector<DevState*> act;
-    std::vector<int> f, b;
     for (size_t q = 0; q < ir.size(); q++)
-      if (t < ir[q]->ir_iters) {
-        act.push_back(ir[q]);
-        f.push_back(next_subst(irs[q]));
-        b.push_back(next_subst(irs[q]));
-      }
-    HIPCHK(launch_ir_step_batch(act.data(), f.data(), b.data(), (int)act.size(), st));
+      if (t < ir[q]->ir_iters) act.push_back(ir[q]);
+    HIPCHK(launch_ir_step_batch(act.data(), t, (int)act.size(), st));
   }
   return TT_OK;
 }
@@ -382,6 +373,24 @@ int enqueue_finish(tt_stream* s, DevState& dd, hipStream_t st) {
   return TT_OK;
 }
 
+// The frame's LM set-up and iterations on st (they read the stream's own buffers and the front
+// outputs of the frame's set, never the caller's frame buffers).
+static int enqueue_lm_iterations(tt_stream* s, DevState& dd, bool dbg, hipStream_t st) {
+  HIPCHK(launch_lm_begin(s->d, s->P.lm_lambda0, st));
+  for (int it = 0; it < s->P.lm_iters; it++) {
+    int rc = enqueue_assemble(s, dd, it, dbg, st);
+    if (rc) return rc;
+    DevState* dp[1] = {&dd};
+    rc = (s->P.solver == TT_SOLVE_NODE) ? enqueue_node_solve(s, dd, st) : enqueue_solve(&s, dp, 1, st);
+    if (rc) return rc;
+    if (dbg && it == 0) rc = enqueue_step_debug(s, st);
+    if (rc) return rc;
+    rc = enqueue_finish(s, dd, st);
+    if (rc) return rc;
+  }
+  return TT_OK;
+}
+
 // Queue the whole frame. depth/xyz/desc are device pointers.
 int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint8_t* desc, int K2, float* out_xyz,
                   float* out_dq, bool dbg, const void* inputs_ready = nullptr) {
@@ -389,16 +398,27 @@ int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint
   DevState dd = frame_view(s, depth, xyz, desc);
   int rc = enqueue_front(s, dd, K2, st, inputs_ready);
   if (rc) return rc;
-  for (int it = 0; it < s->P.lm_iters; it++) {
-    int epoch = 0;
-    rc = enqueue_assemble(s, dd, it, dbg, st, &epoch);
-    if (rc) return rc;
-    DevState* dp[1] = {&dd};
-    rc = (s->P.solver == TT_SOLVE_NODE) ? enqueue_node_solve(s, dd, st) : enqueue_solve(&s, dp, &epoch, 1, st);
-    if (rc) return rc;
-    if (dbg && it == 0) rc = enqueue_step_debug(s, st);
-    if (rc) return rc;
-    rc = enqueue_finish(s, dd, st);
+  if (s->P.graph && !dbg && s->timing == 0) {
+    const int f = (int)(s->frame & 1);
+    if (!s->lm_graph[f]) {
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_lm_iterations(s, dd, false, st);
+      const hipError_t e = hipStreamEndCapture(st, &g);
+      if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : TT_EDEVICE;
+      }
+      const hipError_t ei = hipGraphInstantiate(&s->lm_graph[f], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        s->lm_graph[f] = nullptr;
+        return TT_EDEVICE;
+      }
+    }
+    HIPCHK(hipGraphLaunch(s->lm_graph[f], st));
+  } else {
+    rc = enqueue_lm_iterations(s, dd, dbg, st);
     if (rc) return rc;
   }
   HIPCHK(launch_deform_out(s->d, out_xyz, out_dq, st));
@@ -416,7 +436,6 @@ int enqueue_frame(tt_stream* s, const float* depth, const float* xyz, const uint
 int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStream_t batch_st) {
   std::vector<DevState> dd(S);
   std::vector<DevState*> dp(S);
-  std::vector<int> epochs(S);
   std::vector<hipStream_t> qs(S);
   for (int q = 0; q < S; q++) {
     dd[q] = frame_view(ss[q], fr[q].depth, fr[q].feat_xyz, fr[q].feat_desc);
@@ -446,28 +465,26 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
     return TT_OK;
   };
   int rc = fork();
-  for (int q = 0; q < S && !rc; q++) rc = enqueue_front(ss[q], dd[q], fr[q].K2, qs[q], fr[q].inputs_ready);
+  for (int q = 0; q < S && !rc; q++) {
+    rc = enqueue_front(ss[q], dd[q], fr[q].K2, qs[q], fr[q].inputs_ready);
+    if (!rc && launch_lm_begin(ss[q]->d, ss[q]->P.lm_lambda0, qs[q]) != hipSuccess) rc = TT_EDEVICE;
+  }
   // the streams whose systems go to the batched factorisation
   std::vector<tt_stream*> cs;
   std::vector<DevState*> cp;
-  std::vector<int> ce;
   for (int q = 0; q < S; q++)
     if (ss[q]->P.solver != TT_SOLVE_NODE) {
       cs.push_back(ss[q]);
       cp.push_back(dp[q]);
     }
-  ce.resize(cs.size());
   for (int it = 0; it < ss[0]->P.lm_iters && !rc; it++) {
-    for (int q = 0, c = 0; q < S && !rc; q++) {
-      rc = enqueue_assemble(ss[q], dd[q], it, false, qs[q], &epochs[q]);
+    for (int q = 0; q < S && !rc; q++) {
+      rc = enqueue_assemble(ss[q], dd[q], it, false, qs[q]);
       if (rc) break;
-      if (ss[q]->P.solver == TT_SOLVE_NODE)
-        rc = enqueue_node_solve(ss[q], dd[q], qs[q]);
-      else
-        ce[c++] = epochs[q];
+      if (ss[q]->P.solver == TT_SOLVE_NODE) rc = enqueue_node_solve(ss[q], dd[q], qs[q]);
     }
     if (!rc) rc = join();
-    if (!rc && !cs.empty()) rc = enqueue_solve(cs.data(), cp.data(), ce.data(), (int)cs.size(), batch_st);
+    if (!rc && !cs.empty()) rc = enqueue_solve(cs.data(), cp.data(), (int)cs.size(), batch_st);
     if (!rc) rc = fork();
     for (int q = 0; q < S && !rc; q++) rc = enqueue_finish(ss[q], dd[q], qs[q]);
   }
@@ -608,6 +625,7 @@ void tt_default_params(tt_params* p) {
   p->solver = TT_SOLVE_DENSE;
   p->arap_knn = 0;
   p->assoc_zbuffer = 0;
+  p->graph = 0;
 }
 
 const char* tt_strerror(int code) {
@@ -646,7 +664,8 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
       !(p->w_orb >= 0) || !(p->w_angle >= 0) || !(p->w_rotation >= 0) || !(p->lambda_arap >= 0) ||
       !(p->lm_lambda0 > 0) || p->precision < TT_FP32 || p->precision > TT_FP16_IR || p->ir_iters < 0 ||
       p->ir_iters > 8 || (p->solver != TT_SOLVE_DENSE && p->solver != TT_SOLVE_NODE) ||
-      p->arap_knn < 0 || p->arap_knn > 32 || (p->assoc_zbuffer != 0 && p->assoc_zbuffer != 1))
+      p->arap_knn < 0 || p->arap_knn > 32 || (p->assoc_zbuffer != 0 && p->assoc_zbuffer != 1) ||
+      (p->graph != 0 && p->graph != 1))
     return TT_EINVAL;
   if (K->width < 3 || K->height < 3 || !(K->fx > 0) || !(K->fy > 0) || !isfinite(K->cx) || !isfinite(K->cy) ||
       (int64_t)K->width * K->height > (1 << 28))
@@ -765,8 +784,7 @@ int tt_debug_cholesky_solve_ex(int n, const float* A, const float* b, float* x, 
     std::vector<float> hx(d.npad), ones(d.npad, 1.0f);  // no equilibration in this diagnostic
     LMScalars sc;
     memset(&sc, 0, sizeof(sc));
-    int epoch = 1, e2 = 2;
-    sc.solve_epoch = epoch;
+    sc.solve_epoch = 1;
     DevState* dp[1] = {&d};
     bool ok = hipMemcpyAsync(d.A, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
               hipMemsetAsync(d.flags, 0, sizeof(int) * chol_flag_ints(d.nb), st) == hipSuccess &&
@@ -774,13 +792,10 @@ int tt_debug_cholesky_solve_ex(int n, const float* A, const float* b, float* x, 
               hipMemcpyAsync(d.dscale, ones.data(), sizeof(float) * d.npad, hipMemcpyHostToDevice, st) == hipSuccess &&
               hipMemcpyAsync(d.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, st) == hipSuccess;
     if (ok && precision != TT_FP32) ok = launch_ir_prepare(d, st) == hipSuccess;
-    ok = ok && launch_cholesky_factor(d, epoch, st) == hipSuccess && launch_cholesky_backsolve(d, epoch, st) == hipSuccess;
+    ok = ok && launch_cholesky_factor(d, st) == hipSuccess && launch_cholesky_backsolve(d, 0, st) == hipSuccess;
     if (ok && d.ir_iters > 0) {
       ok = launch_ir_accum_batch(dp, 1, 0, st) == hipSuccess;
-      for (int t = 0; ok && t < d.ir_iters; t++, e2 += 2) {
-        int fe = e2, be = e2 + 1;
-        ok = launch_ir_step_batch(dp, &fe, &be, 1, st) == hipSuccess;
-      }
+      for (int t = 0; ok && t < d.ir_iters; t++) ok = launch_ir_step_batch(dp, t, 1, st) == hipSuccess;
     }
     ok = ok && hipMemcpyAsync(hx.data(), d.x, sizeof(float) * d.npad, hipMemcpyDeviceToHost, st) == hipSuccess &&
          hipMemcpyAsync(&sc, d.sc, sizeof(sc), hipMemcpyDeviceToHost, st) == hipSuccess &&
@@ -1032,7 +1047,6 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
     HIPCHK(hipMemsetAsync(d.flags, 0, sizeof(int) * chol_flag_ints(d.nb), st));
     HIPCHK(hipMemsetAsync(d.tw, 0, sizeof(uint64_t) * d.npad, st));
     HIPCHK(hipMemsetAsync(&d.sc->solve_epoch, 0, sizeof(int), st));
-    s->solve_epoch = 0;
     HIPCHK(hipStreamSynchronize(st));
   }
   s->frame = 0;

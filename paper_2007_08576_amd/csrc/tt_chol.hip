@@ -761,7 +761,8 @@ __device__ __forceinline__ void mma64_acc16(const uint16_t* X, const uint16_t* Y
 
 struct CholArgs {
   float* A;
-  int ld, npad, nb, ntasks, epoch;
+  int ld, npad, nb, ntasks;
+  int which;         // substitutions: index of the launch within the solve (tags its entries)
   const float* dscale;
   float* Linv;
   int* flags;
@@ -832,7 +833,9 @@ struct SysRef {
 __device__ __forceinline__ SysRef sys_ref(const CholBatch& B, int q) {
   const CholArgs& Q = B.p[q];
   const CholSync S = chol_sync(Q.flags, Q.nb);
-  return SysRef{S.ctr, S.abort_, Q.ntasks, Q.epoch, Q.nb};
+  // the solve's epoch, set by the damping kernel that ran before this launch
+  const int epoch = __hip_atomic_load(&Q.sc->solve_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return SysRef{S.ctr, S.abort_, Q.ntasks, epoch, Q.nb};
 }
 
 __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
@@ -840,7 +843,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
   __shared__ __attribute__((aligned(16))) float Y[NB][LDS_LD];
   __shared__ __attribute__((aligned(16))) float Z[NB][LDS_LD];  // the chain's Linv_{j-1} between CRIT steps
   static_assert(POTRF_SCRATCH_FLOATS <= NB * LDS_LD, "factorisation scratch must fit in one tile buffer");
-  __shared__ int s_task, s_val, s_mode, s_prob, s_ctr, s_pubcnt, s_fast;
+  __shared__ int s_task, s_val, s_mode, s_prob, s_ctr, s_pubcnt, s_fast, s_ep;
   const int tid = threadIdx.x;
   const uint64_t wt = B.wait_ticks;
   if (tid == 0) s_pubcnt = 0;
@@ -915,6 +918,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
       s_task = t;
       s_mode = mode;
       s_prob = prob;
+      s_ep = (chain >= 0) ? qc.epoch : qh.epoch;  // the claimed task's system (MODE_TASK, MODE_CRIT)
       // the chain's waits watch the abort word themselves; a task the chain claims checks it here
       if (chain >= 0) s_val = (chain_fast || mode != MODE_TASK) ? 0 : (ld_flag(qc.abort_) == qc.epoch);
     }
@@ -924,7 +928,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
     if (mode == MODE_EXIT) break;
     if (mode == MODE_RETRY) continue;
     const CholArgs& P = B.p[prob];
-    const int nb = P.nb, ld = P.ld, epoch = P.epoch;
+    const int nb = P.nb, ld = P.ld, epoch = s_ep;
     const CholSync S = chol_sync(P.flags, nb);
     if (aborted) {
       if (tid == 0) {
@@ -1191,14 +1195,24 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
 
 constexpr long long kSpinLimit = 1ll << 22;
 
+// Tag of the entries one substitution launch exchanges: the solve's epoch (set on the device by
+// the damping kernel) and the launch's index within the solve (0: the back substitution of the
+// factored right-hand side; 1 + 2t, 2 + 2t: forward and back substitution of refinement step t).
+// Different launches of one solve, and launches of the previous solve, never share a tag; the tag
+// is never 0 (the value the entries are cleared to).
+__device__ __forceinline__ uint32_t subst_tag(const LMScalars* sc, int which) {
+  const int e = __hip_atomic_load(&sc->solve_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return ((uint32_t)(e & 0x3FFFFFF) << 5) + (uint32_t)which + 1u;
+}
+
 // Hand-over between the workgroups of a substitution: each solution entry travels as one 64-bit
 // word (epoch << 32 | float bits) written and read with agent-scope atomics, so a consumer lane
 // polls the entry it needs and gets the value with the same read that tells it the value is there
 // (one memory round trip per block step, no separate flag). A bounded spin marks the solve failed.
-__device__ __forceinline__ float wait_tagged(const uint64_t* w, int epoch, bool& ok) {
+__device__ __forceinline__ float wait_tagged(const uint64_t* w, uint32_t tag, bool& ok) {
   long long spins = 0;
   uint64_t v;
-  while (((v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != (uint32_t)epoch) {
+  while (((v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != tag) {
     if (++spins > kSpinLimit) {
       ok = false;
       break;
@@ -1207,8 +1221,8 @@ __device__ __forceinline__ float wait_tagged(const uint64_t* w, int epoch, bool&
   }
   return __uint_as_float((uint32_t)v);
 }
-__device__ __forceinline__ void put_tagged(uint64_t* w, float x, int epoch) {
-  __hip_atomic_store(w, ((uint64_t)(uint32_t)epoch << 32) | __float_as_uint(x), __ATOMIC_RELAXED,
+__device__ __forceinline__ void put_tagged(uint64_t* w, float x, uint32_t tag) {
+  __hip_atomic_store(w, ((uint64_t)tag << 32) | __float_as_uint(x), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -1227,7 +1241,8 @@ __global__ __launch_bounds__(64) void k_chol_backsolve(const BackBatch B) {
   int q = 0;
   while (q + 1 < B.nprob && (int)blockIdx.x >= B.wg0[q + 1]) q++;
   const CholArgs& P = B.p[q];
-  const int nb = P.nb, ld = P.ld, epoch = P.epoch;
+  const int nb = P.nb, ld = P.ld;
+  const uint32_t tag = subst_tag(P.sc, P.which);
   const float* __restrict__ A = P.A;
   const int j = nb - 1 - ((int)blockIdx.x - B.wg0[q]);
   const int c = threadIdx.x;
@@ -1244,7 +1259,7 @@ __global__ __launch_bounds__(64) void k_chol_backsolve(const BackBatch B) {
     float col[NB];
 #pragma unroll
     for (int m = 0; m < NB; m++) col[m] = A[(size_t)(NB * k + m) * ld + NB * j + c];
-    xs[c] = wait_tagged(P.tw + NB * k + c, epoch, ok);
+    xs[c] = wait_tagged(P.tw + NB * k + c, tag, ok);
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < NB; m++) acc += col[m] * xs[m];
@@ -1256,7 +1271,7 @@ __global__ __launch_bounds__(64) void k_chol_backsolve(const BackBatch B) {
 #pragma unroll
   for (int m = 0; m < NB; m++) s += lic[m] * rs[m];
   P.x[NB * j + c] = s;
-  put_tagged(P.tw + NB * j + c, s, epoch);
+  put_tagged(P.tw + NB * j + c, s, tag);
   if (!ok) {
     P.sc->chol_fail = 1;
     P.sc->err = TT_DEVERR_CHOL_SYNC;
@@ -1272,7 +1287,8 @@ __global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
   int q = 0;
   while (q + 1 < B.nprob && (int)blockIdx.x >= B.wg0[q + 1]) q++;
   const CholArgs& P = B.p[q];
-  const int ld = P.ld, epoch = P.epoch;
+  const int ld = P.ld;
+  const uint32_t tag = subst_tag(P.sc, P.which);
   float* row = P.A + (size_t)P.npad * ld;
   const int j = (int)blockIdx.x - B.wg0[q];
   const int c = threadIdx.x;
@@ -1286,7 +1302,7 @@ __global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
     float4 lr[NB / 4];
 #pragma unroll
     for (int m = 0; m < NB / 4; m++) lr[m] = Lr[m];
-    ys[c] = wait_tagged(P.tw + NB * k + c, epoch, ok);
+    ys[c] = wait_tagged(P.tw + NB * k + c, tag, ok);
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < NB / 4; m++)
@@ -1299,7 +1315,7 @@ __global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
 #pragma unroll
   for (int m = 0; m < NB; m++) y += Li[m] * rs[m];
   row[NB * j + c] = y;  // read by the back substitution, a later launch
-  put_tagged(P.tw + NB * j + c, y, epoch);
+  put_tagged(P.tw + NB * j + c, y, tag);
   if (!ok) {
     P.sc->chol_fail = 1;
     P.sc->err = TT_DEVERR_CHOL_SYNC;
@@ -1358,14 +1374,14 @@ __global__ __launch_bounds__(64) void k_ir_accum(const BackBatch B, int mode) {
 
 size_t chol_flag_ints(int nb) { return (size_t)nb + (size_t)(nb + 1) * nb + 4 * (size_t)nb + 2; }
 
-static CholArgs chol_args(const DevState& d, int epoch) {
+static CholArgs chol_args(const DevState& d, int which) {
   CholArgs P;
   P.A = d.A;
   P.ld = d.ld;
   P.npad = d.npad;
   P.nb = d.nb;
   P.ntasks = chol_task_count(d.nb);
-  P.epoch = epoch;
+  P.which = which;
   P.dscale = d.dscale;
   P.Linv = d.Linv;
   P.flags = d.flags;
@@ -1384,13 +1400,13 @@ static CholArgs chol_args(const DevState& d, int epoch) {
 // the failure reported): far beyond any wait of a working solve, short enough to end a broken one.
 constexpr double kWaitSeconds = 1.0;
 
-hipError_t launch_cholesky_factor_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st) {
+hipError_t launch_cholesky_factor_batch(DevState* const* ds, int S, hipStream_t st) {
   for (int b0 = 0; b0 < S; b0 += kMaxCholBatch) {
     CholBatch B;
     B.nprob = (S - b0 < kMaxCholBatch) ? S - b0 : kMaxCholBatch;
     int tasks = 0, cus = 256, khz = 100000;  // the constant clock runs at 100 MHz unless the device says otherwise
     for (int q = 0; q < B.nprob; q++) {
-      B.p[q] = chol_args(*ds[b0 + q], epochs[b0 + q]);
+      B.p[q] = chol_args(*ds[b0 + q], 0);
       tasks += B.p[q].ntasks;
       if (ds[b0 + q]->num_cus > 0) cus = ds[b0 + q]->num_cus;
       if (ds[b0 + q]->wall_khz > 0) khz = ds[b0 + q]->wall_khz;
@@ -1402,20 +1418,20 @@ hipError_t launch_cholesky_factor_batch(DevState* const* ds, const int* epochs, 
   return hipGetLastError();
 }
 
-hipError_t launch_cholesky_factor(DevState& d, int epoch, hipStream_t st) {
+hipError_t launch_cholesky_factor(DevState& d, hipStream_t st) {
   DevState* ds[1] = {&d};
-  return launch_cholesky_factor_batch(ds, &epoch, 1, st);
+  return launch_cholesky_factor_batch(ds, 1, st);
 }
 
 // One launch per (up to) 32 systems of a per-block-row kernel (grid: 64-row blocks of every system).
 template <typename F>
-static hipError_t launch_rows_batch(DevState* const* ds, const int* epochs, int S, F launch) {
+static hipError_t launch_rows_batch(DevState* const* ds, int which, int S, F launch) {
   for (int b0 = 0; b0 < S; b0 += kMaxCholBatch) {
     BackBatch B;
     B.nprob = (S - b0 < kMaxCholBatch) ? S - b0 : kMaxCholBatch;
     B.wg0[0] = 0;
     for (int q = 0; q < B.nprob; q++) {
-      B.p[q] = chol_args(*ds[b0 + q], epochs ? epochs[b0 + q] : 0);
+      B.p[q] = chol_args(*ds[b0 + q], which);
       B.wg0[q + 1] = B.wg0[q] + ds[b0 + q]->nb;
     }
     launch(B);
@@ -1423,15 +1439,15 @@ static hipError_t launch_rows_batch(DevState* const* ds, const int* epochs, int 
   return hipGetLastError();
 }
 
-hipError_t launch_cholesky_backsolve_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st) {
-  return launch_rows_batch(ds, epochs, S, [&](const BackBatch& B) {
+hipError_t launch_cholesky_backsolve_batch(DevState* const* ds, int which, int S, hipStream_t st) {
+  return launch_rows_batch(ds, which, S, [&](const BackBatch& B) {
     hipLaunchKernelGGL(k_chol_backsolve, dim3(B.wg0[B.nprob]), dim3(64), 0, st, B);
   });
 }
 
-hipError_t launch_cholesky_backsolve(DevState& d, int epoch, hipStream_t st) {
+hipError_t launch_cholesky_backsolve(DevState& d, int which, hipStream_t st) {
   DevState* ds[1] = {&d};
-  return launch_cholesky_backsolve_batch(ds, &epoch, 1, st);
+  return launch_cholesky_backsolve_batch(ds, which, 1, st);
 }
 
 hipError_t launch_ir_prepare(DevState& d, hipStream_t st) {
@@ -1440,23 +1456,22 @@ hipError_t launch_ir_prepare(DevState& d, hipStream_t st) {
   return hipMemcpyAsync(d.cvec, d.A + (size_t)d.npad * d.ld, sizeof(float) * d.npad, hipMemcpyDeviceToDevice, st);
 }
 
-hipError_t launch_ir_step_batch(DevState* const* ds, const int* fwd_epochs, const int* back_epochs, int S,
-                                hipStream_t st) {
-  hipError_t e = launch_rows_batch(ds, nullptr, S, [&](const BackBatch& B) {
+hipError_t launch_ir_step_batch(DevState* const* ds, int step, int S, hipStream_t st) {
+  hipError_t e = launch_rows_batch(ds, 0, S, [&](const BackBatch& B) {
     hipLaunchKernelGGL(k_ir_resid, dim3(B.wg0[B.nprob]), dim3(256), 0, st, B);
   });
   if (e != hipSuccess) return e;
-  e = launch_rows_batch(ds, fwd_epochs, S, [&](const BackBatch& B) {
+  e = launch_rows_batch(ds, 1 + 2 * step, S, [&](const BackBatch& B) {
     hipLaunchKernelGGL(k_chol_fwdsolve, dim3(B.wg0[B.nprob]), dim3(64), 0, st, B);
   });
   if (e != hipSuccess) return e;
-  e = launch_cholesky_backsolve_batch(ds, back_epochs, S, st);
+  e = launch_cholesky_backsolve_batch(ds, 2 + 2 * step, S, st);
   if (e != hipSuccess) return e;
   return launch_ir_accum_batch(ds, S, 1, st);
 }
 
 hipError_t launch_ir_accum_batch(DevState* const* ds, int S, int mode, hipStream_t st) {
-  return launch_rows_batch(ds, nullptr, S, [&](const BackBatch& B) {
+  return launch_rows_batch(ds, 0, S, [&](const BackBatch& B) {
     hipLaunchKernelGGL(k_ir_accum, dim3(B.wg0[B.nprob]), dim3(64), 0, st, B, mode);
   });
 }

@@ -152,8 +152,6 @@ struct tt_stream {
   bool own_stream = false;
   bool has_template = false;
   int64_t frame = 0;
-  int solve_epoch = 0;  // increments per factorisation; its tile flags match it
-  int subst_epoch = 0;  // increments per forward / back substitution; their block flags match it
   std::mutex mu;
   DevState d;
   std::vector<void*> allocs_template;  // freed on re-template / destroy
@@ -172,6 +170,9 @@ struct tt_stream {
   hipStream_t st_front = nullptr;
   hipEvent_t ev_front_done[2] = {nullptr, nullptr};
   hipEvent_t ev_lm_done[2] = {nullptr, nullptr};
+  // graph mode: the frame's LM iterations captured once per front-buffer set (they read only the
+  // stream's own buffers, so a replay does the same work on the next frame of that parity)
+  hipGraphExec_t lm_graph[2] = {nullptr, nullptr};
 };
 
 // Points d's front outputs at buffer set f (0 or 1).
@@ -215,16 +216,17 @@ hipError_t launch_deform_out(const DevState& d, float* out_xyz, float* out_dq, h
 // Ints of the flag area used by one Cholesky solve (tile flags, ticket counters, abort word).
 size_t chol_flag_ints(int nb);
 // Factorisation of the damped, equilibrated system (forward substitution included), then the back
-// substitution into d.x; epoch tags this solve's flags.
-hipError_t launch_cholesky_factor(DevState& d, int epoch, hipStream_t st);
-hipError_t launch_cholesky_backsolve(DevState& d, int epoch, hipStream_t st);
+// substitution into d.x. The solve's flags carry the epoch in d.sc->solve_epoch (set on the device
+// by the damping kernel), so a launch's arguments stay the same from one solve to the next; `which`
+// numbers a substitution launch within the solve (0: the back substitution after the factorisation).
+hipError_t launch_cholesky_factor(DevState& d, hipStream_t st);
+hipError_t launch_cholesky_backsolve(DevState& d, int which, hipStream_t st);
 // The same for S independent systems at once (one launch per 32 systems).
-hipError_t launch_cholesky_factor_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st);
-hipError_t launch_cholesky_backsolve_batch(DevState* const* ds, const int* epochs, int S, hipStream_t st);
+hipError_t launch_cholesky_factor_batch(DevState* const* ds, int S, hipStream_t st);
+hipError_t launch_cholesky_backsolve_batch(DevState* const* ds, int which, int S, hipStream_t st);
 // Refinement (16-bit forms): keep the damped matrix and right-hand side before the factorisation;
-// xd = x (mode 0) or xd += x, x = xd (mode 1); one step = FP64 residual, forward and back
-// substitution, accumulation.
+// xd = x (mode 0) or xd += x, x = xd (mode 1); refinement step `step` (0, 1, ...) = FP64 residual,
+// forward and back substitution, accumulation.
 hipError_t launch_ir_prepare(DevState& d, hipStream_t st);
 hipError_t launch_ir_accum_batch(DevState* const* ds, int S, int mode, hipStream_t st);
-hipError_t launch_ir_step_batch(DevState* const* ds, const int* fwd_epochs, const int* back_epochs, int S,
-                                hipStream_t st);
+hipError_t launch_ir_step_batch(DevState* const* ds, int step, int S, hipStream_t st);

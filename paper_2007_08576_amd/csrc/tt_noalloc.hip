@@ -139,8 +139,8 @@ extern "C" int tt_cholesky_solve_noalloc(int n, const float* d_A, const float* d
   hipLaunchKernelGGL(k_noalloc_setup, dim3(256), dim3(256), 0, st, d.A, d_A, d_b, n, d.npad, d.dscale, d.flags,
                      nflags, d.tw, d.sc);
   if (hipGetLastError() != hipSuccess) return TT_EDEVICE;
-  if (launch_cholesky_factor(d, 1, st) != hipSuccess) return TT_EDEVICE;
-  if (launch_cholesky_backsolve(d, 1, st) != hipSuccess) return TT_EDEVICE;
+  if (launch_cholesky_factor(d, st) != hipSuccess) return TT_EDEVICE;
+  if (launch_cholesky_backsolve(d, 0, st) != hipSuccess) return TT_EDEVICE;
   hipLaunchKernelGGL(k_noalloc_finish, dim3((n + 255) / 256), dim3(256), 0, st, d.x, d_x, n, d.sc, d_status);
   return hipGetLastError() == hipSuccess ? TT_OK : TT_EDEVICE;
 }
