@@ -296,6 +296,8 @@ def precision_study(args, torch, tt, sc2, dframes2, vo_oracle):
                 ref = v1
             entry = {"frames_per_s": fps, "factor_us": fac, "damp_substitutions_refinement_us": sol,
                      "rms_vs_fp32_form_mm": float(np.sqrt(((v1 - ref) ** 2).sum(1).mean()))}
+            if name == "fp32":
+                entry["roofline"] = chol_roofline(6 * sc3.num_control_points, fac * 1e-3)
             out["config3"][name] = entry
             log(f"  config3 {name:8s} {fps:7.2f} frames/s, factor {fac:8.1f} us, solve+refine {sol:7.1f} us, "
                 f"rms vs fp32 {entry['rms_vs_fp32_form_mm']:.2e} mm")
@@ -457,6 +459,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_chol_dataflow_config2_traffic.j
 CHOL_SRC = os.path.join(ROOT, "paper_2007_08576_amd", "csrc", "tt_chol.hip")
 
 
+def chol_roofline(n, fac_ms, traffic=None):
+    """Roofline record of one k_chol_dataflow launch on an n x n system (FP32 matrix cores)."""
+    flops = n ** 3 / 3.0 + float(n) * n  # Cholesky of the n x n system + the forward substitution
+    achieved = flops / (fac_ms * 1e-3) / 1e12
+    return dict(kernel="k_chol_dataflow", bound="mfma", achieved=achieved, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=achieved / FP32_PEAK_TFLOPS, traffic=traffic,
+                algorithmic=f"n^3/3 + n^2 = {flops:.4e} FLOP per launch (one factorisation, n = {n}), "
+                            "dense FP32 matrix-core peak",
+                avg_duration_us=fac_ms * 1e3)
+
+
 def _src_hash():
     import hashlib
     with open(CHOL_SRC, "rb") as f:
@@ -512,6 +525,7 @@ def main():
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=8, help="distinct synthetic frames (replayed ping-pong)")
+    ap.add_argument("--graph", type=int, default=1, help="replay each frame's LM iterations as one HIP graph")
     ap.add_argument("--cpu-lm-sample", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving", type=int, default=1, help="also run the config 4 serving mix (0 = skip)")
@@ -558,7 +572,7 @@ def main():
     order = list(range(len(frames))) + list(range(len(frames) - 2, 0, -1))
     stream = torch.cuda.Stream()
     N, M = sc.num_control_points, sc.pts.shape[0]
-    params = tt.default_params(num_control_points=N, seed=2)
+    params = tt.default_params(num_control_points=N, seed=2, graph=args.graph)
     intr = tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy)
     s = tt.Stream(params, intr, hip_stream=stream.cuda_stream)
     s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
@@ -574,36 +588,58 @@ def main():
         d = dframes[order[k % len(order)]]
         s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], ov, oq, inputs_ready=inputs_ready)
 
+    def timed(k0, steps):
+        ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            ev0[k].record(stream)
+            step(k0 + k)
+            ev1[k].record(stream)
+        s.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return steps / wall, np.array([ev0[k].elapsed_time(ev1[k]) for k in range(steps)])
+
     for k in range(args.warmup):
         step(k)
     s.sync()
     torch.cuda.synchronize()
     s.get_timing()  # reset
-    # only the dominant kernel's launch is bracketed in the timed region (for the roofline); the
-    # per-stage breakdown comes from a separate pass below
+    # headline: with graph replay on, each frame's LM set-up and iterations replay one captured
+    # graph (a stage timer would force kernel-by-kernel launches, so none is on here)
+    fps, lat = timed(args.warmup, args.steps)
+    log(f"{fps:.1f} frames/s ({'graph replay' if args.graph else 'kernel launches'}), "
+        f"p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
+    # roofline pass: the same frames launched kernel by kernel with only the factorisation's launch
+    # bracketed by events on the library's stream (the stage timer)
+    k0 = args.warmup + args.steps
     s.set_timing(True, stages=("factor",))
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev0[k].record(stream)
-        step(args.warmup + k)
-        ev1[k].record(stream)
-    s.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    fps_kl, _ = timed(k0, args.steps)
     s.set_timing(False)
-    wall = t1 - t0
-    fps = args.steps / wall
-    lat = np.array([ev0[k].elapsed_time(ev1[k]) for k in range(args.steps)])
     stage_ms, stage_n = s.get_timing()
     fac_ms = float(stage_ms[tt.STAGES.index("factor")] / max(stage_n[tt.STAGES.index("factor")], 1))
-    log(f"{fps:.1f} frames/s, p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
+    fac_calls = int(stage_n[tt.STAGES.index("factor")])
+    log(f"{fps_kl:.1f} frames/s kernel by kernel with the factor timer; factorisation {fac_ms * 1e3:.1f} us "
+        f"x {fac_calls}")
+    # unloaded end-to-end latency: one frame at a time, from the host call to its outputs on the
+    # device, the front stage (normal map, matching, pre-selection) included
+    k0 += args.steps
+    e2e = []
+    for k in range(min(args.steps, 30)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(k0 + k)
+        s.sync()
+        e2e.append((time.perf_counter() - t0) * 1e3)
+    e2e = np.array(e2e)
+    log(f"unloaded end-to-end latency p50 {np.percentile(e2e, 50):.3f} ms, p99 {np.percentile(e2e, 99):.3f} ms")
     # stage breakdown: a few more frames with every stage bracketed by events (outside the timed region)
+    k0 += len(e2e)
     s.set_timing(True)
     for k in range(min(args.steps, 10)):
-        step(args.warmup + args.steps + k)
+        step(k0 + k)
     s.sync()
     s.set_timing(False)
     stage_ms, stage_n = s.get_timing()
@@ -616,13 +652,8 @@ def main():
     # timer brackets exactly that launch on the library's HIP stream)
     n = 6 * N
     pairs = N * (N - 1) // 2
-    flops = n ** 3 / 3.0 + float(n) * n  # Cholesky of the n x n system + the forward substitution
-    achieved = flops / (fac_ms * 1e-3) / 1e12
-    roof = dict(kernel="k_chol_dataflow", bound="mfma", achieved=achieved, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                frac=achieved / FP32_PEAK_TFLOPS, traffic=measured_traffic(),
-                algorithmic=f"n^3/3 + n^2 = {flops:.4e} FLOP per launch (one factorisation, n = {n}), "
-                            "dense FP32 matrix-core peak",
-                avg_duration_us=fac_ms * 1e3)
+    roof = chol_roofline(n, fac_ms, traffic=measured_traffic())
+    roof["timed_launches"] = fac_calls
 
     out = {
         "metric": METRIC,
@@ -640,12 +671,17 @@ def main():
         "config": {"workload": "config2: plain FP32 single stream; 640x480 depth, M=30000 template points, "
                                "N=400 control points (79800 ARAP pairs, 2400x2400 normal matrix), "
                                "K=2000 features (30% outliers), 10 LM iterations per frame",
-                   "mode": "plain", "frames_replayed": len(frames)},
+                   "mode": "plain, " + ("graph replay of the LM iterations" if args.graph else "kernel launches"),
+                   "frames_replayed": len(frames)},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
-        "latency_note": "p50/p99: events on the library's stream before and after each frame's call, i.e. the "
-                        "frame's LM solve; its matching and pre-selection (front stage) run on a second HIP "
-                        "stream overlapping the previous frame and are in stage_us['front']",
+        "latency_note": "p50/p99: events on the library's stream before and after each frame's call in the "
+                        "timed region, i.e. the frame's LM solve; its matching and pre-selection (front stage) "
+                        "run on a second HIP stream overlapping the previous frame. e2e_*: one frame at a time, "
+                        "host call to outputs ready, front stage included",
+        "e2e_p50_ms": float(np.percentile(e2e, 50)),
+        "e2e_p99_ms": float(np.percentile(e2e, 99)),
+        "frames_per_s_kernel_launches": fps_kl,
         "gn_iters_per_s": fps * params.lm_iters,
         "arap_pairs_per_s": fps * params.lm_iters * pairs,
         "stage_us": {k: v["ms_per_call"] * 1e3 for k, v in stages.items()},

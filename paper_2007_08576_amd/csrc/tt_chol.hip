@@ -37,6 +37,16 @@ __device__ __forceinline__ void st_coh(float* p, float v) {
 __device__ __forceinline__ void st_coh16(uint16_t* p, uint16_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Four consecutive floats (16-byte aligned) written through to memory in one instruction (the
+// trailing s_nop keeps the data registers unchanged for the cycle after the store reads them).
+__device__ __forceinline__ void st_coh4(float* p, float4 v) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const v4f d = {v.x, v.y, v.z, v.w};
+  asm volatile("global_store_dwordx4 %0, %1, off sc1\n\ts_nop 1" : : "v"(p), "v"(d) : "memory");
+}
+__device__ __forceinline__ void st_coh16x4(uint16_t* p, uint64_t v) {  // four 16-bit values, 8-byte aligned
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 // The calling thread's device-coherent stores (and, after a barrier, the workgroup's) are complete
 // when the flag is stored.
 __device__ __forceinline__ void publish_flag(int* f, int v) {
@@ -238,18 +248,26 @@ constexpr int POTRF_SCRATCH_FLOATS = 12 * 16 * XS;
 // From L Li = I, the block below the diagonal is Li_rc = -Li_rr S_rc with
 // S_rc = sum_{c <= m < r} X_rm Li_mc; every S_rc is complete when leaf 3 ends, so only the three
 // products Li_3c = -Li_33 S_3c follow the chain. Five barriers.
-// L's off-diagonal tiles are left as the updated T (only Li is an output); scratch holds
+// L's off-diagonal tiles are left as the updated T (only Li is an output; its six tiles above the
+// diagonal are neither read nor written and must hold zeros, which the caller sets once); scratch holds
 // POTRF_SCRATCH_FLOATS floats of LDS. Returns false if a pivot is not positive (a diagonal entry
 // of Li that is not positive and finite). All 256 threads must call it.
 // Optionally (U non-null) the block is first updated, L -= U U^T with U the 64 x 64 tile in LDS:
 // wavefront 0 updates only tile (0, 0) before leaf 0 and the others update the remaining nine lower
-// tiles meanwhile. When pub is non-null, each wavefront completes its earlier global stores as soon
-// as its part of that first phase is done, and the last of the four raises *pub = epoch (arrivals
-// counted in the LDS word *pub_cnt, which must be 0 on entry and is 0 again on return). Scratch is
-// first written after that phase, so U may share its memory.
+// tiles meanwhile. When pub is non-null, wavefronts 1-3 then run ustore() (the caller's stores of U
+// to global memory); at the start of the second phase they complete those stores and the last of
+// the three raises *pub = epoch (arrivals counted in the LDS word *pub_cnt, which must be 0 on entry
+// and is 0 again on return); wavefront 0, on the critical path, neither stores nor waits. Scratch is first written after that phase, so U may share
+// its memory. pre() runs on every thread right after the barrier that ends the fourth phase (the
+// look ahead's results are in LDS by then), before the three products of the last phase.
+struct NoOp {
+  __device__ void operator()() const {}
+};
 // A look ahead that one idle thread runs during the factorisation's fourth phase: it reads the
 // ticket counter into *s_ctr and whether both flags f0, f1 (if non-null) equal epoch into *s_ready,
-// acquiring when they do; the results are in LDS for the whole block once the call returns.
+// acquiring when they do; the results are in LDS for the whole block once the call returns. If the
+// flags were not yet raised, an idle thread of the fifth phase looks again and leaves the answer in
+// *s_ready2 (0 when the first look succeeded), in LDS once the factorisation returns.
 struct ChainPoll {
   const int* f0;
   const int* f1;
@@ -257,6 +275,7 @@ struct ChainPoll {
   int epoch;
   int* s_ready;
   int* s_ctr;
+  int* s_ready2;
 };
 __device__ __forceinline__ void chain_poll(const ChainPoll& q) {
   const int c = __hip_atomic_load(q.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -271,24 +290,25 @@ __device__ __forceinline__ void chain_poll(const ChainPoll& q) {
   *q.s_ready = r ? 1 : 0;
 }
 
-// One wavefront's share of a block-wide publication: its device-coherent stores complete, then it
-// counts itself in *cnt (LDS); the fourth to arrive resets the count and raises *flag = epoch, by
-// which time every wavefront's stores have reached memory.
-__device__ __forceinline__ void wave_publish(int* cnt, int* flag, int epoch) {
+// One wavefront's share of a publication by n wavefronts: its device-coherent stores complete, then
+// it counts itself in *cnt (LDS); the n-th to arrive resets the count and raises *flag = epoch, by
+// which time every one of those wavefronts' stores has reached memory.
+__device__ __forceinline__ void wave_publish(int* cnt, int* flag, int epoch, int n = 4) {
   __builtin_amdgcn_s_waitcnt(0);
   if ((threadIdx.x & 63) == 0) {
     const int prev = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (prev == 3) {
+    if (prev == n - 1) {
       __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       publish_flag(flag, epoch);
     }
   }
 }
 
+template <typename UStore = NoOp, typename Pre = NoOp>
 __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LDS_LD], float* scratch,
                                               const float (*U)[LDS_LD] = nullptr, int* pub = nullptr,
                                               int pub_epoch = 0, const ChainPoll* poll = nullptr,
-                                              int* pub_cnt = nullptr) {
+                                              int* pub_cnt = nullptr, UStore ustore = UStore(), Pre pre = Pre()) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // scratch tiles: 0 = X10, 1 = X20, 2 = X30, 3 = X21, 4 = X31, 5 = X32, then the sums S_rc
   enum { S10 = 6, S20, S21, S30, S31, S32 };
@@ -313,7 +333,6 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
   // the upper tiles of Li
   if (wave == 0) {
     if (U) updU(0, 0);
-    if (pub) wave_publish(pub_cnt, pub, pub_epoch);
     leaf16(L, Li, 0);
   } else {
     if (U) {
@@ -331,15 +350,11 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
         updU(3, 3);
       }
     }
-    if (pub) wave_publish(pub_cnt, pub, pub_epoch);
-    for (int e = tid - 64; e < 6 * 256; e += 192) {
-      const int t = e >> 8, w = e & 255;
-      const int r = (t < 3) ? 0 : (t < 5 ? 1 : 2);
-      const int c = (t < 3) ? 1 + t : (t < 5 ? t - 1 : 3);
-      Li[16 * r + (w >> 4)][16 * c + (w & 15)] = 0.0f;
-    }
+    if (pub) ustore();
   }
   __syncthreads();
+  // the stores of U were issued a phase ago: completing them and raising the flag costs little now
+  if (pub && wave != 0) wave_publish(pub_cnt, pub, pub_epoch, 3);
   // phase 2: leaf 1; X_r0, trailing updates
   if (wave == 0) {
     makeX(1, 0, 0);
@@ -401,6 +416,7 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
     if (poll && lane == 0) chain_poll(*poll);
   }
   __syncthreads();
+  pre();
   // phase 5: Li_3c = -Li_33 S_3c
   if (wave == 1) {
     finish(3, 1, S31);
@@ -408,6 +424,14 @@ __device__ __forceinline__ bool potrf_trtri64(float (*L)[LDS_LD], float (*Li)[LD
     finish(3, 0, S30);
   } else if (wave == 3) {
     finish(3, 2, S32);
+  } else if (poll && lane == 0) {
+    int r2 = 0;
+    if (!*poll->s_ready) {
+      ChainPoll q = *poll;
+      q.s_ready = &r2;
+      chain_poll(q);
+    }
+    *poll->s_ready2 = r2;
   }
   __syncthreads();
   // every wavefront checks all 64 diagonal entries of the inverse (1 / the pivots' square roots)
@@ -806,10 +830,22 @@ __device__ __forceinline__ void csub_load(const CholArgs& P, int j, float4 va[4]
 }
 
 // The chain's inputs for step j: C_{j,j-1} (tile layout) and C_jj (accumulator layout). For j <= 1
-// these are the raw, not yet equilibrated blocks of A; later they are the partial tiles.
+// these are the raw, not yet equilibrated blocks of A; later they are the partial tiles, loaded as
+// they are (no arithmetic on the loaded values, so that a prefetch leaves them in flight until the
+// step uses them).
 __device__ __forceinline__ void chain_load(const CholArgs& P, int j, float4 va[4], floatx4 cp[2][2]) {
   const size_t rj = (size_t)NB * j;
-  acc_load(P.A, P.ld, rj, rj, P.dscale, j <= 1, cp);
+  if (j >= 2) {
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int b = 0; b < 2; b++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) cp[a][b][r] = P.A[(rj + acc_row(a, r)) * P.ld + rj + acc_col(b)];
+    tile_load(P.A, P.ld, rj - NB, rj, va);
+    return;
+  }
+  acc_load(P.A, P.ld, rj, rj, P.dscale, true, cp);
   if (j >= 1) csub_load(P, j, va);
 }
 
@@ -843,10 +879,18 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
   __shared__ __attribute__((aligned(16))) float Y[NB][LDS_LD];
   __shared__ __attribute__((aligned(16))) float Z[NB][LDS_LD];  // the chain's Linv_{j-1} between CRIT steps
   static_assert(POTRF_SCRATCH_FLOATS <= NB * LDS_LD, "factorisation scratch must fit in one tile buffer");
-  __shared__ int s_task, s_val, s_mode, s_prob, s_ctr, s_pubcnt, s_fast, s_ep;
+  __shared__ int s_task, s_val, s_val2, s_mode, s_prob, s_ctr, s_pubcnt, s_fast, s_ep;
   const int tid = threadIdx.x;
   const uint64_t wt = B.wait_ticks;
   if (tid == 0) s_pubcnt = 0;
+  // the six tiles above the diagonal of the chain's inverse stay zero: the factorisation writes only
+  // the lower ones, and nothing else writes Z (the first barrier of the loop orders this)
+  for (int e = tid; e < 6 * 256; e += 256) {
+    const int t = e >> 8, w = e & 255;
+    const int r = (t < 3) ? 0 : (t < 5 ? 1 : 2);
+    const int c = (t < 3) ? 1 + t : (t < 5 ? t - 1 : 3);
+    Z[16 * r + (w >> 4)][16 * c + (w & 15)] = 0.0f;
+  }
   // Each system has its own ticket counter and task order. A workgroup visits the systems in a
   // cyclic order starting at blockIdx % nprob, claiming tasks from one until its counter runs out
   // (one failing claim per system per workgroup, so the claim that returns ntasks + gridDim - 1
@@ -959,8 +1003,9 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         __syncthreads();
         if (j >= 1) {
           // L_{j,j-1} = C_{j,j-1} Linv_{j-1}^T: wavefront g computes rows 16 g .. 16 g + 15 (four
-          // 16 x 16 tiles), then overwrites those rows of X and stores them. Linv is lower
-          // triangular, so column block c only sums over the blocks k0 <= 16 c.
+          // 16 x 16 tiles), then overwrites those rows of X (wavefronts 1-3 store the whole tile
+          // during the factorisation's first phase). Linv is lower triangular, so column block c
+          // only sums over the blocks k0 <= 16 c.
           const int g = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
           floatx4 t4[4];
   #pragma unroll
@@ -971,12 +1016,7 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
           for (int c = 0; c < 4; c++)
   #pragma unroll
             for (int q = 0; q < 4; q++) {
-              const int row = 16 * g + 4 * lk + q, col = 16 * c + li;
-              const float v = t4[c][q];
-              X[row][col] = v;
-              st_coh(&P.A[(rj + row) * ld + rj - NB + col], v);
-              if (P.prec != TT_FP32)
-                st_coh16(&P.A16[(rj + row) * ld + rj - NB + col], (P.prec == TT_BF16_IR) ? to_bf16(v) : to_f16(v));
+              X[16 * g + 4 * lk + q][16 * c + li] = t4[c][q];
             }
           __syncthreads();
         }
@@ -990,22 +1030,78 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
         poll.epoch = epoch;
         poll.s_ready = &s_val;
         poll.s_ctr = &s_ctr;
-        const bool ok = (j >= 1) ? potrf_trtri64(Y, Z, &X[0][0], X, S.fin + (size_t)j * nb + (j - 1), epoch, &poll, &s_pubcnt)
-                                 : potrf_trtri64(Y, Z, &X[0][0], nullptr, nullptr, 0, &poll);
-        float* Lj = P.Linv + (size_t)j * NB * NB;
-        for (int e = tid; e < NB * NB / 4; e += 256) {
-          const int r = e >> 4, cc = 4 * (e & 15);
-          st_coh(Lj + r * NB + cc, Z[r][cc]);
-          st_coh(Lj + r * NB + cc + 1, Z[r][cc + 1]);
-          st_coh(Lj + r * NB + cc + 2, Z[r][cc + 2]);
-          st_coh(Lj + r * NB + cc + 3, Z[r][cc + 3]);
+        poll.s_ready2 = &s_val2;
+        // wavefronts 1-3: L_{j,j-1} (X) to tile (j, j-1) of A and of its 16-bit copy
+        // (every LDS read is issued before the first store, and the pointers are locals: the stores'
+        // memory clobber would otherwise order each read after the previous store)
+        auto ustore = [&]() {
+          const size_t o0 = rj * ld + rj - NB;
+          float* const A = P.A + o0;
+          const int prec = P.prec;
+          uint16_t* const A16 = (prec != TT_FP32) ? P.A16 + o0 : nullptr;
+          const int e0 = tid - 64;
+          float4 v[6];
+#pragma unroll
+          for (int k = 0; k < 6; k++) {
+            const int e = min(e0 + 192 * k, NB * NB / 4 - 1), row = e >> 4, c4 = 4 * (e & 15);
+            const float2 lo = *reinterpret_cast<const float2*>(&X[row][c4]);
+            const float2 hi = *reinterpret_cast<const float2*>(&X[row][c4 + 2]);
+            v[k] = make_float4(lo.x, lo.y, hi.x, hi.y);
+          }
+#pragma unroll
+          for (int k = 0; k < 6; k++) {
+            const int e = e0 + 192 * k;
+            if (e < NB * NB / 4) {
+              const size_t o = (size_t)(e >> 4) * ld + 4 * (e & 15);
+              st_coh4(A + o, v[k]);
+              if (prec != TT_FP32) {
+                const bool b = prec == TT_BF16_IR;
+                const uint64_t h0 = b ? to_bf16(v[k].x) : to_f16(v[k].x), h1 = b ? to_bf16(v[k].y) : to_f16(v[k].y);
+                const uint64_t h2 = b ? to_bf16(v[k].z) : to_f16(v[k].z), h3 = b ? to_bf16(v[k].w) : to_f16(v[k].w);
+                st_coh16x4(A16 + o, h0 | (h1 << 16) | (h2 << 32) | (h3 << 48));
+              }
+            }
+          }
+        };
+        // once the look ahead (fourth phase) has found the next step's partial tiles published, their
+        // loads are issued at once and overlap the last phase and the stores of Linv_j
+        bool early = false;
+        auto pre = [&]() {
+          if (j + 1 >= 2 && j + 1 < nb && s_val) {
+            chain_load(P, j + 1, cva, ccp);
+            early = true;
+          }
+        };
+        const bool ok = (j >= 1) ? potrf_trtri64(Y, Z, &X[0][0], X, S.fin + (size_t)j * nb + (j - 1), epoch, &poll,
+                                                 &s_pubcnt, ustore, pre)
+                                 : potrf_trtri64(Y, Z, &X[0][0], nullptr, nullptr, 0, &poll, nullptr, NoOp(), pre);
+        // the second look (fifth phase) found them: their loads overlap the stores of Linv_j
+        if (!early && j + 1 >= 2 && j + 1 < nb && s_val2) {
+          chain_load(P, j + 1, cva, ccp);
+          early = true;
+        }
+        {
+          float* const Lj = P.Linv + (size_t)j * NB * NB;
+          float4 v[4];
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const int e = tid + 256 * k, r = e >> 4, cc = 4 * (e & 15);
+            const float2 lo = *reinterpret_cast<const float2*>(&Z[r][cc]);
+            const float2 hi = *reinterpret_cast<const float2*>(&Z[r][cc + 2]);
+            v[k] = make_float4(lo.x, lo.y, hi.x, hi.y);
+          }
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const int e = tid + 256 * k;
+            st_coh4(Lj + (e >> 4) * NB + 4 * (e & 15), v[k]);
+          }
         }
         if (tid == 0 && !ok) P.sc->chol_fail = 1;
         // If the look ahead did not find the next step's partial tiles ready, look once more; if they
         // are, their loads overlap the completion of the Linv_j stores that the publication below
         // waits for.
         if (j + 1 < nb) {
-          bool ready = s_val != 0;
+          bool ready = early;
           if (!ready) {
             __syncthreads();  // every thread has read s_val
             if (tid == 0) {
@@ -1016,11 +1112,9 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
             }
             __syncthreads();
             ready = s_val != 0;
+            if (ready) chain_load(P, j + 1, cva, ccp);
           }
-          if (ready) {
-            chain_load(P, j + 1, cva, ccp);
-            have_pref = true;
-          }
+          have_pref = ready;
         }
         if (tid == 0) {
           bool f = false;
