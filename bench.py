@@ -84,25 +84,45 @@ def _streams_for(tt, scenes, precision, budget):
     return streams, idx, used
 
 
-def _serving_compare(args, torch, tt, scenes, frames_np, order, hz_list, seconds):
+def _serving_compare(args, torch, tt, scenes, frames_np, order, hz_list, seconds, poisson_forms=("fp32",)):
     """Plain per-stream path (each stream on its own HIP stream through tt_track_frame_device_ev, FP32)
-    against the batched path (tt_track_batch_device over every stream with a frame waiting) in FP32
-    and in the mixed form (bfloat16 tile products + FP64-residual refinement): frames/s at
-    saturation, and the mixed form's vertices against the plain FP32 ones on the first frame. Then
-    Poisson-arrival runs (one per rate in hz_list, frames per second per stream) of the batched FP32
-    path (the faster form) with continuous batching: whenever the device finishes a batch, every
-    stream whose next frame has arrived joins the next one; latency is completion minus arrival.
-    frames_np[q] holds stream q's frames (depth, feat_xyz, feat_desc), replayed in `order`."""
+    against whole-frame batches (tt_track_batch_device over every stream) and against the library's
+    serving loop (tt_server_*: streams admitted under the HBM budget, frames batched at LM-iteration
+    boundaries), the last two in FP32 and in the mixed form (bfloat16 tile products + FP64-residual
+    refinement): frames/s at saturation, and each form's first-frame vertices against the plain FP32
+    ones. Then Poisson-arrival runs through the serving loop (one per rate in hz_list, frames per
+    second per stream; 0 = 70 % of the served saturation rate): latency is completion minus the
+    scheduled arrival. frames_np[q] holds stream q's frames (depth, feat_xyz, feat_desc), replayed in
+    `order`."""
     dev = torch.device("cuda:0")
     frames = [[tuple(torch.from_numpy(a).to(dev) for a in f) for f in fl] for fl in frames_np]
-    inputs_ready = torch.cuda.Event()  # the replayed inputs are resident from here on
+    torch.cuda.synchronize()  # resident before any library stream reads them
+    inputs_ready = torch.cuda.Event()
     inputs_ready.record()
-    budget = args.serving_hbm_gib * (1 << 30)
-    res, first, used_bytes, poisson = {}, {}, {}, []
+    budget = int(args.serving_hbm_gib * (1 << 30))
+    res, first, used_bytes, poisson = {}, {}, {}, {}
     S = None
-    for name, prec, batched in (("plain", tt.TT_FP32, False), ("batched_fp32", tt.TT_FP32, True),
-                                ("batched_mixed", tt.TT_BF16_IR, True)):
-        streams, idx, used = _streams_for(tt, scenes, prec, budget)
+    for name, prec, mode in (("plain", tt.TT_FP32, "plain"), ("batched_fp32", tt.TT_FP32, "batch"),
+                             ("batched_mixed", tt.TT_BF16_IR, "batch"), ("served_fp32", tt.TT_FP32, "serve"),
+                             ("served_mixed", tt.TT_BF16_IR, "serve")):
+        if mode == "serve":
+            sv = tt.Server(hbm_budget_bytes=budget)
+            streams, idx = [], []
+            for i, sc in enumerate(scenes):
+                try:
+                    streams.append(sv.open(tt.default_params(num_control_points=sc.num_control_points, seed=4,
+                                                             precision=prec),
+                                           tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy,
+                                                         sc.intr.cx, sc.intr.cy),
+                                           sc.pts, sc.feat_xyz, sc.feat_desc,
+                                           K2max=max(f[1].shape[0] for f in frames[i]), wait_s=0.0))
+                    idx.append(i)
+                except tt.TTError as e:  # no room left under the budget
+                    if e.code not in (tt.TT_EBUSY, tt.TT_ENOMEM):
+                        raise
+            used = sv.stats()["reserved_bytes"]
+        else:
+            streams, idx, used = _streams_for(tt, scenes, prec, budget)
         S = len(streams)
         used_bytes[name] = used
         outs = [(torch.empty((scenes[i].pts.shape[0], 3), dtype=torch.float32, device=dev),
@@ -114,41 +134,69 @@ def _serving_compare(args, torch, tt, scenes, frames_np, order, hz_list, seconds
 
         def one_round(k, sel=None):
             sel = list(range(S)) if sel is None else sel
-            if batched:
+            if mode == "batch":
                 tt.track_batch_device([streams[q] for q in sel], [fr(q, k) for q in sel])
-            else:
+            elif mode == "plain":
                 for q in sel:
                     streams[q].track_frame_device(*fr(q, k))
+            else:
+                return [sv.submit(streams[q], *fr(q, k)[:6]) for q in sel]
 
-        one_round(0)
-        for s_ in streams:
-            s_.sync()
+        def drain(tickets=None):
+            if mode == "serve":
+                for t in tickets:
+                    sv.wait(t, 120.0)
+            else:
+                for s_ in streams:
+                    s_.sync()
+
+        drain(one_round(0))
         first[name] = {i: outs[q][0].cpu().numpy().copy() for q, i in enumerate(idx)}
         t1 = time.perf_counter()
-        rounds = args.serving_rounds
-        for k in range(rounds):
-            one_round(k + 1)
-        for s_ in streams:
-            s_.sync()
-        res[name] = S * rounds / (time.perf_counter() - t1)
+        tickets = []
+        for k in range(args.serving_rounds):
+            tickets += one_round(k + 1) or []
+        drain(tickets)
+        res[name] = S * args.serving_rounds / (time.perf_counter() - t1)
         log(f"  {name:14s} {res[name]:8.1f} frames/s over {S} streams")
-        if name == "batched_fp32":
-            for hz in hz_list:
-                hz = hz if hz > 0 else 0.7 * res[name] / S  # 0: 70 % of the measured saturation rate
-                poisson.append(_poisson_run(streams, one_round, S, hz, seconds))
-        for s_ in streams:
-            s_.destroy()
-    common = [i for i in first["batched_mixed"] if i in first["plain"]]
-    rms_mixed = max(float(np.sqrt(((first["batched_mixed"][i].astype(np.float64) - first["plain"][i]) ** 2)
-                                  .sum(1).mean())) for i in common)
-    return {"streams": S, "device_bytes_fp32": used_bytes["plain"], "device_bytes_mixed": used_bytes["batched_mixed"],
-            "plain_fp32_frames_per_s": res["plain"], "batched_fp32_frames_per_s": res["batched_fp32"],
-            "batched_mixed_frames_per_s": res["batched_mixed"],
-            "batched_fp32_over_plain": res["batched_fp32"] / res["plain"],
-            "batched_mixed_over_plain": res["batched_mixed"] / res["plain"],
-            "mixed_form": "bf16 tile products, FP32 accumulation, 2 FP64-residual refinement steps",
-            "mixed_vs_plain_fp32_max_stream_rms_mm": rms_mixed,
-            "poisson_batched_fp32": poisson if len(poisson) > 1 else poisson[0]}
+        if mode == "serve":
+            st = sv.stats()
+            res[name + "_frames_per_round"] = st["frame_iterations"] / max(st["rounds"], 1)
+            form = name.split("_", 1)[1]
+            if form in poisson_forms:
+                poisson[form] = []
+                for hz in hz_list:
+                    hz = hz if hz > 0 else 0.7 * res[name] / S
+                    poisson[form].append(_poisson_served(sv, streams, lambda q, k: fr(q, k)[:6], S, hz, seconds))
+            for s_ in streams:
+                sv.close(s_)
+            sv.destroy()
+        else:
+            for s_ in streams:
+                s_.destroy()
+
+    def rms_vs_plain(name):
+        common = [i for i in first[name] if i in first["plain"]]
+        return max(float(np.sqrt(((first[name][i].astype(np.float64) - first["plain"][i]) ** 2).sum(1).mean()))
+                   for i in common)
+
+    out = {"streams": S, "device_bytes_fp32": used_bytes["plain"], "device_bytes_mixed": used_bytes["batched_mixed"],
+           "plain_fp32_frames_per_s": res["plain"], "batched_fp32_frames_per_s": res["batched_fp32"],
+           "batched_mixed_frames_per_s": res["batched_mixed"], "served_fp32_frames_per_s": res["served_fp32"],
+           "served_mixed_frames_per_s": res["served_mixed"],
+           "served_fp32_frames_per_round": res["served_fp32_frames_per_round"],
+           "batched_fp32_over_plain": res["batched_fp32"] / res["plain"],
+           "batched_mixed_over_plain": res["batched_mixed"] / res["plain"],
+           "served_fp32_over_plain": res["served_fp32"] / res["plain"],
+           "served_mixed_over_plain": res["served_mixed"] / res["plain"],
+           "mixed_form": "bf16 tile products, FP32 accumulation, 2 FP64-residual refinement steps",
+           "mixed_vs_plain_fp32_max_stream_rms_mm": rms_vs_plain("batched_mixed"),
+           "served_mixed_vs_plain_fp32_max_stream_rms_mm": rms_vs_plain("served_mixed"),
+           "served_fp32_vs_plain_fp32_max_stream_rms_mm": rms_vs_plain("served_fp32"),
+           "batched_fp32_vs_plain_fp32_max_stream_rms_mm": rms_vs_plain("batched_fp32")}
+    for form, runs in poisson.items():
+        out[f"poisson_served_{form}"] = runs if len(runs) > 1 else runs[0]
+    return out
 
 
 def serving_bench(args, torch, tt):
@@ -159,7 +207,8 @@ def serving_bench(args, torch, tt):
     scenes = synth.make_config4(seed=4, n_streams=args.serving_streams, n_frames=300)
     frames_np = [[(f.depth, f.feat_xyz, f.feat_desc) for f in (sc.frame(t) for t in range(1, 4))] for sc in scenes]
     log(f"serving mix generated in {time.time() - t0:.1f} s")
-    out = _serving_compare(args, torch, tt, scenes, frames_np, [0, 1, 2, 1], [args.serving_hz], args.serving_seconds)
+    out = _serving_compare(args, torch, tt, scenes, frames_np, [0, 1, 2, 1], [args.serving_hz], args.serving_seconds,
+                           poisson_forms=("fp32", "mixed"))
     out["workload"] = (f"config4: {out['streams']} streams, N 100-800, depth 320x240..640x480, K 500-3000, "
                        "20-40% outliers, 10 LM iterations per frame")
     return out
@@ -188,54 +237,50 @@ def stress_bench(args, torch, tt):
     out = _serving_compare(args, torch, tt, scenes, frames_np, order, [0.0], args.serving_seconds)
     # the configured arrival rate, against what the batched path sustains at saturation
     offered = args.stress_hz * out["streams"]
+    best = max(out["batched_fp32_frames_per_s"], out["served_fp32_frames_per_s"])
     out["configured_rate"] = {"rate_hz_per_stream": args.stress_hz, "offered_frames_per_s": offered,
-                              "sustainable": bool(out["batched_fp32_frames_per_s"] >= offered)}
-    log(f"  configured {args.stress_hz:.1f} Hz/stream offers {offered:.0f} frames/s; batched saturation "
-        f"{out['batched_fp32_frames_per_s']:.1f} frames/s")
+                              "sustainable": bool(best >= offered)}
+    log(f"  configured {args.stress_hz:.1f} Hz/stream offers {offered:.0f} frames/s; saturation "
+        f"{best:.1f} frames/s")
     out["workload"] = (f"config5: {out['streams']} streams, N 200-1500, 640x480, K 2000, 30% outliers; "
                        f"{n_stressed} of {nfr * len(gen)} replayed frames stressed (60% outliers, 30% pixels "
                        "occluded, 10 deg / 20 mm camera jump); 10 LM iterations per frame")
     return out
 
 
-def _poisson_run(streams, one_round, S, hz, dur):
+def _poisson_served(sv, streams, frame_of, S, hz, dur):
+    """Open-loop Poisson arrivals (rate hz per stream) submitted to the serving loop at their arrival
+    times; latency = (submission - arrival) + the server's submit-to-completion time."""
     rng = np.random.default_rng(4)
-    arrivals = []
+    events = []
     for q in range(S):
-        t, a = 0.0, []
-        while t < dur:
+        t = 0.0
+        while True:
             t += rng.exponential(1.0 / hz)
-            if t < dur:
-                a.append(t)
-        arrivals.append(a)
-    nxt = [0] * S
-    lat = []
-    done = 0
-    total = sum(len(a) for a in arrivals)
+            if t >= dur:
+                break
+            events.append((t, q))
+    events.sort()
+    count = [0] * S
+    tickets = []
     t_start = time.perf_counter()
-    k = 0
-    while done < total:
+    for t, q in events:
         now = time.perf_counter() - t_start
-        ready = [q for q in range(S) if nxt[q] < len(arrivals[q]) and arrivals[q][nxt[q]] <= now]
-        if not ready:
-            soon = min(arrivals[q][nxt[q]] for q in range(S) if nxt[q] < len(arrivals[q]))
-            time.sleep(max(0.0, soon - now))
-            continue
-        one_round(k, ready)
-        k += 1
-        streams[ready[0]].sync()
-        t_end = time.perf_counter() - t_start
-        for q in ready:
-            lat.append(t_end - arrivals[q][nxt[q]])
-            nxt[q] += 1
-            done += 1
+        if t > now:
+            time.sleep(t - now)
+        late = max(0.0, time.perf_counter() - t_start - t)
+        tickets.append((sv.submit(streams[q], *frame_of(q, count[q])), late))
+        count[q] += 1
+    lat = np.array([late * 1e3 + sv.wait(tk, 120.0) for tk, late in tickets])
     wall = time.perf_counter() - t_start
-    lat = np.array(lat) * 1e3
-    log(f"  poisson {hz:.1f} Hz/stream: {total / wall:.1f} frames/s (offered {S * hz:.1f}), "
+    total = len(events)
+    log(f"  poisson {hz:.1f} Hz/stream (served): {total / wall:.1f} frames/s (offered {S * hz:.1f}), "
         f"p50 {np.percentile(lat, 50):.1f} ms, p99 {np.percentile(lat, 99):.1f} ms")
     return {"rate_hz_per_stream": hz, "offered_frames_per_s": S * hz, "seconds": dur, "frames": int(total),
             "frames_per_s": total / wall, "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max())}
+            "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
+            "loop": "tt_server (library scheduler thread, LM-iteration rounds)",
+            "latency": "scheduled arrival to completion seen by the server, front stage included"}
 
 
 def precision_study(args, torch, tt, sc2, dframes2, vo_oracle):

@@ -276,6 +276,66 @@ int tt_cholesky_solve_noalloc(int n, const float* d_A, const float* d_b, float* 
 /* Destroys the stream and frees its device memory. */
 int tt_destroy(tt_stream* s);
 
+/* ---- Serving: many streams under one HBM budget, continuous batching ----------------------
+ * The per-frame solve of Sec. 2 for many independent streams at once. A server owns the streams it
+ * opens (other calls on them return TT_EBUSY until tt_server_close) and runs one scheduler thread
+ * that queues the streams' work in rounds of one LM iteration: in a round every frame in flight
+ * assembles its normal system on its stream's HIP stream, all those systems are factored and solved
+ * together (one batched launch per up to 32 systems, on the server's HIP stream), and every frame
+ * takes its update. A submitted frame first has its normal map, matching and pre-selection queued on
+ * its stream's side queue; it joins the rounds at the first LM-iteration boundary after that stage
+ * has finished, and leaves after its lm_iters-th iteration, so frames of different streams enter
+ * and leave at iteration boundaries rather than in whole-frame batches. Frames of one stream run in
+ * submission order. Each frame's result is the same as when its stream is tracked alone.
+ *
+ * Admission: every open stream holds its device bytes (tt_device_bytes, with the feature buffers
+ * sized for K2max at open) against the server's hbm_budget_bytes. An open that does not fit waits,
+ * in arrival order, until tt_server_close releases enough bytes or wait_s runs out (TT_EBUSY); one
+ * that could not fit even in an empty server returns TT_ENOMEM.
+ * Latency: from tt_server_submit to the moment the scheduler sees the frame's last kernel complete
+ * (front stage included), on the host's steady clock. */
+typedef struct tt_server tt_server;
+typedef struct {
+  uint64_t hbm_budget_bytes; /* device bytes all open streams may hold together; 0 = unlimited   */
+  int max_rounds_ahead;      /* rounds queued ahead of the device (1..8; 0 = 2): a new frame joins
+                                after at most this many rounds already queued                      */
+} tt_server_params;
+
+typedef struct {
+  int streams_open;          /* admitted streams                                                  */
+  int opens_waiting;         /* tt_server_open calls waiting for budget                           */
+  uint64_t reserved_bytes;   /* device bytes held by the open streams                             */
+  int64_t frames_submitted;
+  int64_t frames_done;
+  int64_t rounds;            /* LM-iteration rounds queued                                        */
+  int64_t frame_iterations;  /* sum over rounds of the frames in that round                       */
+} tt_server_stats;
+
+void tt_server_default_params(tt_server_params* p);
+/* hip_stream: the HIP stream the batched solves run on (NULL: the server creates one). The device
+ * current at this call is the one the scheduler thread uses. */
+int tt_server_create(const tt_server_params* p, void* hip_stream, tt_server** out);
+/* tt_create_stream + tt_set_template under the budget (arguments as there; K2max: the most
+ * features any frame of this stream will have). On success *out is open and owned by the server. */
+int tt_server_open(tt_server* sv, const tt_params* p, const tt_intrinsics* K, const float* pts_xyz, int M,
+                   const float* feat_xyz, const uint8_t* feat_desc, int K1, int K2max, double wait_s,
+                   tt_stream** out);
+/* Queues one frame of an open stream (device arrays as tt_frame_device; they must stay unchanged
+ * until the frame is reported done; K2 <= K2max). *ticket identifies it for tt_server_poll/_wait.
+ * Returns at once. TT_EINVAL: bad arguments or a stream this server does not own. */
+int tt_server_submit(tt_server* sv, tt_stream* s, const tt_frame_device* f, uint64_t* ticket);
+/* *done = 1 once the frame's outputs are written; its latency (ms) in *latency_ms, and the return
+ * value is the frame's status (TT_EDEVICE if a device-side check failed). A ticket is forgotten once
+ * reported done. TT_EINVAL: unknown ticket. */
+int tt_server_poll(tt_server* sv, uint64_t ticket, int* done, double* latency_ms);
+/* As tt_server_poll, blocking until done or wait_s has passed (then TT_EBUSY). */
+int tt_server_wait(tt_server* sv, uint64_t ticket, double wait_s, double* latency_ms);
+/* Waits for the stream's frames, destroys it and releases its bytes to waiting opens. */
+int tt_server_close(tt_server* sv, tt_stream* s);
+int tt_server_get_stats(tt_server* sv, tt_server_stats* out);
+/* Waits for every frame, closes every open stream, stops the scheduler. */
+int tt_server_destroy(tt_server* sv);
+
 const char* tt_strerror(int code);
 
 /* ---- Uniform ORB features (Sec. 2.1) ------------------------------------------------------

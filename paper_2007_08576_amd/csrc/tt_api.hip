@@ -79,7 +79,7 @@ void free_template(tt_stream* s) {
 struct Busy {
   tt_stream* s;
   bool ok;
-  explicit Busy(tt_stream* s_) : s(s_), ok(s_->mu.try_lock()) {}
+  explicit Busy(tt_stream* s_) : s(s_), ok(!s_->served.load() && s_->mu.try_lock()) {}
   ~Busy() {
     if (ok) s->mu.unlock();
   }
@@ -816,6 +816,7 @@ int tt_debug_cholesky_solve_ex(int n, const float* A, const float* b, float* x, 
 
 int tt_destroy(tt_stream* s) {
   if (!s) return TT_EINVAL;
+  if (s->served.load()) return TT_EBUSY;  // tt_server_close destroys it
   {
     std::lock_guard<std::mutex> g(s->mu);
     (void)timing_flush(s);
@@ -1083,7 +1084,7 @@ int tt_track_batch_device(tt_stream* const* streams, int S, const tt_frame_devic
   // lock every stream (all or none)
   int locked = 0;
   for (; locked < S; locked++)
-    if (!streams[locked]->mu.try_lock()) break;
+    if (streams[locked]->served.load() || !streams[locked]->mu.try_lock()) break;
   int rc = TT_OK;
   if (locked < S) rc = TT_EBUSY;
   for (int q = 0; q < S && !rc; q++)
@@ -1219,3 +1220,33 @@ int tt_set_state(tt_stream* s, const double* dq, int64_t frame) {
 }
 
 }  // extern "C"
+
+// ---- per-frame queueing steps for the serving loop ----------------------------------------------
+namespace ttx {
+DevState frame_view(tt_stream* s, const float* depth, const float* xyz, const uint8_t* desc) {
+  return ::frame_view(s, depth, xyz, desc);
+}
+int ensure_k2(tt_stream* s, int K2) { return ::ensure_k2(s, K2); }
+int enqueue_front(tt_stream* s, DevState& dd, int K2, hipStream_t st, const void* inputs_ready) {
+  return ::enqueue_front(s, dd, K2, st, inputs_ready);
+}
+hipEvent_t front_done_event(tt_stream* s) { return s->ev_front_done[s->frame & 1]; }
+int enqueue_lm_begin(tt_stream* s, hipStream_t st) {
+  return launch_lm_begin(s->d, s->P.lm_lambda0, st) == hipSuccess ? TT_OK : TT_EDEVICE;
+}
+int enqueue_assemble(tt_stream* s, DevState& dd, int it, hipStream_t st) { return ::enqueue_assemble(s, dd, it, false, st); }
+int enqueue_solve(tt_stream* const* ss, DevState* const* dp, int S, hipStream_t st) {
+  return ::enqueue_solve(ss, dp, S, st);
+}
+int enqueue_node_solve(tt_stream* s, DevState& dd, hipStream_t st) { return ::enqueue_node_solve(s, dd, st); }
+int enqueue_finish(tt_stream* s, DevState& dd, hipStream_t st) { return ::enqueue_finish(s, dd, st); }
+int enqueue_frame_end(tt_stream* s, float* out_xyz, float* out_dq, hipStream_t st) {
+  HIPCHK(launch_deform_out(s->d, out_xyz, out_dq, st));
+  const int rc = enqueue_lm_done(s, st);
+  if (rc) return rc;
+  s->frame += 1;
+  return TT_OK;
+}
+hipError_t ev_sync_get(tt_stream* s, hipEvent_t* e) { return ::ev_sync_get(s, e); }
+void ev_sync_put(tt_stream* s, hipEvent_t e) { s->ev_sync_pool.push_back(e); }
+}  // namespace ttx

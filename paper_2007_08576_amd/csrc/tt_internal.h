@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -153,6 +154,7 @@ struct tt_stream {
   bool has_template = false;
   int64_t frame = 0;
   std::mutex mu;
+  std::atomic<bool> served{false};  // owned by a tt_server: the stream's own entry points return TT_EBUSY
   DevState d;
   std::vector<void*> allocs_template;  // freed on re-template / destroy
   std::vector<void*> allocs_frame;     // frame-size buffers (created with the stream)
@@ -230,3 +232,23 @@ hipError_t launch_cholesky_backsolve_batch(DevState* const* ds, int which, int S
 hipError_t launch_ir_prepare(DevState& d, hipStream_t st);
 hipError_t launch_ir_accum_batch(DevState* const* ds, int S, int mode, hipStream_t st);
 hipError_t launch_ir_step_batch(DevState* const* ds, int step, int S, hipStream_t st);
+
+// ---- per-frame queueing steps, shared with the serving loop (defined in tt_api.hip) -----------
+// The same steps the single-stream and batched paths queue, in the same order: front (normal map,
+// matching, pre-selection on the stream's side queue), LM set-up, per iteration assemble -> solve
+// (batched over systems) -> finish, then the deformed outputs. The caller holds the stream's lock.
+namespace ttx {
+DevState frame_view(tt_stream* s, const float* depth, const float* xyz, const uint8_t* desc);
+int ensure_k2(tt_stream* s, int K2);
+int enqueue_front(tt_stream* s, DevState& dd, int K2, hipStream_t st, const void* inputs_ready);
+hipEvent_t front_done_event(tt_stream* s);  // the event enqueue_front recorded for the stream's current frame
+int enqueue_lm_begin(tt_stream* s, hipStream_t st);
+int enqueue_assemble(tt_stream* s, DevState& dd, int it, hipStream_t st);
+int enqueue_solve(tt_stream* const* ss, DevState* const* dp, int S, hipStream_t st);
+int enqueue_node_solve(tt_stream* s, DevState& dd, hipStream_t st);
+int enqueue_finish(tt_stream* s, DevState& dd, hipStream_t st);
+// deformed outputs, the frame's buffer set released, frame counter advanced
+int enqueue_frame_end(tt_stream* s, float* out_xyz, float* out_dq, hipStream_t st);
+hipError_t ev_sync_get(tt_stream* s, hipEvent_t* e);
+void ev_sync_put(tt_stream* s, hipEvent_t e);
+}  // namespace ttx

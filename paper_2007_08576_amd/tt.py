@@ -63,6 +63,16 @@ class FrameDevice(C.Structure):
                 ("out_vertices", C.c_void_p), ("out_dq", C.c_void_p), ("inputs_ready", C.c_void_p)]
 
 
+class ServerParams(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_rounds_ahead", C.c_int)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("streams_open", C.c_int), ("opens_waiting", C.c_int), ("reserved_bytes", C.c_uint64),
+                ("frames_submitted", C.c_int64), ("frames_done", C.c_int64), ("rounds", C.c_int64),
+                ("frame_iterations", C.c_int64)]
+
+
 def lib():
     """The loaded library (raises if it has not been built)."""
     global _lib
@@ -101,6 +111,17 @@ def lib():
         L.tt_destroy.argtypes = [vp]
         L.tt_strerror.argtypes = [C.c_int]
         L.tt_strerror.restype = C.c_char_p
+        L.tt_server_default_params.argtypes = [C.POINTER(ServerParams)]
+        L.tt_server_default_params.restype = None
+        L.tt_server_create.argtypes = [C.POINTER(ServerParams), vp, C.POINTER(vp)]
+        L.tt_server_open.argtypes = [vp, C.POINTER(Params), C.POINTER(Intrinsics), vp, C.c_int, vp, vp, C.c_int,
+                                     C.c_int, C.c_double, C.POINTER(vp)]
+        L.tt_server_submit.argtypes = [vp, vp, C.POINTER(FrameDevice), C.POINTER(C.c_uint64)]
+        L.tt_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.tt_server_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(C.c_double)]
+        L.tt_server_close.argtypes = [vp, vp]
+        L.tt_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.tt_server_destroy.argtypes = [vp]
         L.tt_orb_default_params.argtypes = [C.POINTER(OrbParams)]
         L.tt_orb_default_params.restype = None
         L.tt_orb_create.argtypes = [C.POINTER(OrbParams), C.c_int, C.c_int, vp, vp, C.POINTER(vp)]
@@ -330,6 +351,82 @@ def track_batch_device(streams, frames):
         fr[q] = FrameDevice(_dev_ptr(depth), _dev_ptr(xyz), _dev_ptr(desc), int(K2), _dev_ptr(ov), _dev_ptr(oq),
                             ev.value if ev is not None else None)
     _check(lib().tt_track_batch_device(hs, S, fr), "tt_track_batch_device")
+
+
+class ServedStream:
+    """A stream opened by a Server (the server owns it until Server.close)."""
+
+    def __init__(self, server, h, params, M, K1, K2max):
+        self.server, self.h, self.params = server, h, params
+        self.M, self.K1, self.N, self.K2max = M, K1, params.num_control_points, K2max
+
+
+class Server:
+    """Many streams on one GPU (tt_server_*): streams admitted against one HBM budget, their frames
+    batched at LM-iteration boundaries by the library's scheduler thread."""
+
+    def __init__(self, hbm_budget_bytes=0, max_rounds_ahead=2, hip_stream=None):
+        p = ServerParams()
+        lib().tt_server_default_params(C.byref(p))
+        p.hbm_budget_bytes = int(hbm_budget_bytes)
+        p.max_rounds_ahead = int(max_rounds_ahead)
+        h = C.c_void_p()
+        _check(lib().tt_server_create(C.byref(p), None if hip_stream is None else C.c_void_p(hip_stream),
+                                      C.byref(h)), "tt_server_create")
+        self.h = h
+
+    def open(self, params, intr, pts, feat_xyz, feat_desc, K2max, wait_s=0.0):
+        """tt_server_open: raises TTError (TT_EBUSY) if no room was made within wait_s seconds."""
+        pts = _c(pts, np.float32).reshape(-1, 3)
+        feat_xyz = _c(feat_xyz, np.float32).reshape(-1, 3)
+        feat_desc = _c(feat_desc, np.uint8).reshape(-1, 32)
+        h = C.c_void_p()
+        _check(lib().tt_server_open(self.h, C.byref(params), C.byref(intr), _ptr(pts), pts.shape[0], _ptr(feat_xyz),
+                                    _ptr(feat_desc), feat_xyz.shape[0], int(K2max), float(wait_s), C.byref(h)),
+               "tt_server_open")
+        return ServedStream(self, h, params, pts.shape[0], feat_xyz.shape[0], int(K2max))
+
+    def submit(self, stream, depth, feat_xyz, feat_desc, K2, out_vertices=None, out_dq=None, inputs_ready=None):
+        """Queues one frame (device tensors or addresses, kept unchanged until it is done); returns
+        its ticket."""
+        ev = _event_ptr(inputs_ready)
+        fr = FrameDevice(_dev_ptr(depth), _dev_ptr(feat_xyz), _dev_ptr(feat_desc), int(K2), _dev_ptr(out_vertices),
+                         _dev_ptr(out_dq), ev.value if ev is not None else None)
+        t = C.c_uint64()
+        _check(lib().tt_server_submit(self.h, stream.h, C.byref(fr), C.byref(t)), "tt_server_submit")
+        return t.value
+
+    def poll(self, ticket):
+        """(done, latency_ms or None); raises TTError if the frame failed."""
+        done, lat = C.c_int(), C.c_double()
+        _check(lib().tt_server_poll(self.h, int(ticket), C.byref(done), C.byref(lat)), "tt_server_poll")
+        return bool(done.value), (lat.value if done.value else None)
+
+    def wait(self, ticket, wait_s=60.0):
+        lat = C.c_double()
+        _check(lib().tt_server_wait(self.h, int(ticket), float(wait_s), C.byref(lat)), "tt_server_wait")
+        return lat.value
+
+    def close(self, stream):
+        if stream.h:
+            _check(lib().tt_server_close(self.h, stream.h), "tt_server_close")
+            stream.h = None
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().tt_server_get_stats(self.h, C.byref(st)), "tt_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def destroy(self):
+        if self.h:
+            _check(lib().tt_server_destroy(self.h), "tt_server_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def create_stream(params, intr, hip_stream=None):
