@@ -521,33 +521,79 @@ def _src_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
+def _pmc_rows(path):
+    """(kernel, grid work-items, counter value) per dispatch of a rocprofv3 --pmc CSV."""
+    import csv
+    import re
+    rows = []
+    for r in csv.DictReader(open(path)):
+        k = re.sub(r"\(anonymous namespace\)::", "", r["Kernel_Name"])
+        k = re.sub(r"^void ", "", k).split("(")[0].split("<")[0]
+        grid = int(float(r.get("Grid_Size") or r.get("Grid_Size_X") or 0))
+        rows.append((k, grid, float(r["Counter_Value"])))
+    return rows
+
+
+def _calibration(f, w, copy_mib):
+    """Counter readings of the largest copy dispatch against its true size (KiB)."""
+    true_kib = copy_mib * 1024.0
+    fcopy = max(v for k, _, v in f if k == "__amd_rocclr_copyBuffer")
+    wcopy = max(v for k, _, v in w if k == "__amd_rocclr_copyBuffer")
+    return {"copy_mib": copy_mib, "fetch_size_kib_read_for_copy": fcopy, "write_size_kib_read_for_copy": wcopy,
+            "fetch_factor": true_kib / fcopy, "write_factor": true_kib / wcopy}
+
+
 def pmc_summary(fetch_csv, write_csv, copy_mib, cmd):
     """HBM bytes per k_chol_dataflow launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
     WRITE_SIZE; KiB per dispatch), each scaled by what the same counter reads for the plain copy of
     copy_mib MiB that bench.py --copy-calibration-mib runs (largest copy dispatch)."""
-    import csv
-    import re
-
-    def per_kernel(path):
-        agg = {}
-        for r in csv.DictReader(open(path)):
-            k = re.sub(r"\(anonymous namespace\)::", "", r["Kernel_Name"]).split("(")[0]
-            agg.setdefault(k, []).append(float(r["Counter_Value"]))
-        return agg
-
-    f, w = per_kernel(fetch_csv), per_kernel(write_csv)
-    true_kib = copy_mib * 1024.0
-    fcopy = max(f["__amd_rocclr_copyBuffer"])
-    wcopy = max(w["__amd_rocclr_copyBuffer"])
-    ff, wf = true_kib / fcopy, true_kib / wcopy
-    fk = float(np.mean(f["k_chol_dataflow"])) * ff * 1024.0
-    wk = float(np.mean(w["k_chol_dataflow"])) * wf * 1024.0
+    f, w = _pmc_rows(fetch_csv), _pmc_rows(write_csv)
+    cal = _calibration(f, w, copy_mib)
+    fv = [v for k, _, v in f if k == "k_chol_dataflow"]
+    wv = [v for k, _, v in w if k == "k_chol_dataflow"]
+    fk = float(np.mean(fv)) * cal["fetch_factor"] * 1024.0
+    wk = float(np.mean(wv)) * cal["write_factor"] * 1024.0
     rec = {"kernel": "k_chol_dataflow", "workload": "config2 plain FP32 (n = 2400)", "source_sha256": _src_hash(),
            "fetch_bytes_per_launch": fk, "write_bytes_per_launch": wk, "traffic_bytes_per_launch": fk + wk,
-           "calibration": {"copy_mib": copy_mib, "fetch_size_kib_read_for_copy": fcopy,
-                           "write_size_kib_read_for_copy": wcopy, "fetch_factor": ff, "write_factor": wf},
-           "launches": len(f["k_chol_dataflow"]), "commands": cmd}
+           "calibration": cal, "launches": len(fv), "commands": cmd}
     with open(TRAFFIC_FILE, "w") as fo:
+        json.dump(rec, fo, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+ASM_KERNELS = ("k_data_rows", "k_arap_assemble", "k_data_assemble")
+
+
+def pmc_assembly_summary(fetch_csv, write_csv, trace_csv, copy_mib, out_path, cmd):
+    """HBM bytes and time per dispatch of the assembly kernels (bench.py --assembly-only: config 2,
+    then config 3), from FETCH_SIZE / WRITE_SIZE runs calibrated on a copy of known size and a kernel
+    trace of the same command; dispatches grouped by kernel and grid size."""
+    import csv
+    import re
+    f, w = _pmc_rows(fetch_csv), _pmc_rows(write_csv)
+    cal = _calibration(f, w, copy_mib)
+    dur = {}
+    for r in csv.DictReader(open(trace_csv)):
+        k = re.sub(r"\(anonymous namespace\)::", "", r["Kernel_Name"])
+        k = re.sub(r"^void ", "", k).split("(")[0].split("<")[0]
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        dur.setdefault((k, grid), []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    groups = []
+    for k in ASM_KERNELS:
+        grids = []
+        for kk, g, _ in f:
+            if kk == k and g not in grids:
+                grids.append(g)
+        for ci, g in enumerate(grids):
+            fb = float(np.mean([v for kk, gg, v in f if kk == k and gg == g])) * cal["fetch_factor"] * 1024.0
+            wb = float(np.mean([v for kk, gg, v in w if kk == k and gg == g])) * cal["write_factor"] * 1024.0
+            us = float(np.mean(dur.get((k, g), [np.nan])))
+            groups.append({"kernel": k, "workload": ("config2", "config3")[ci] if len(grids) == 2 else f"grid {g}",
+                           "grid_work_items": g, "fetch_bytes": fb, "write_bytes": wb, "avg_us": us,
+                           "dispatches": len([1 for kk, gg, _ in f if kk == k and gg == g]),
+                           "hbm_GBps": (fb + wb) / (us * 1e-6) / 1e9 if us == us else None})
+    rec = {"kernels": groups, "calibration": cal, "commands": cmd}
+    with open(out_path, "w") as fo:
         json.dump(rec, fo, indent=1)
     print(json.dumps(rec, indent=1))
 
@@ -561,9 +607,24 @@ def measured_traffic():
     return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == _src_hash() else None
 
 
+def _copy_calibration(args, torch):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counter readings."""
+    if args.copy_calibration_mib > 0:
+        nf = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(nf, dtype=torch.float32, device=torch.device("cuda:0"))
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {args.copy_calibration_mib} MiB read + written")
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--pmc-summary":
         pmc_summary(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--pmc-assembly-summary":
+        pmc_assembly_summary(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6], sys.argv[7])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -571,6 +632,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=8, help="distinct synthetic frames (replayed ping-pong)")
     ap.add_argument("--graph", type=int, default=1, help="replay each frame's LM iterations as one HIP graph")
+    ap.add_argument("--assembly-only", type=int, default=0,
+                    help="only the assembly roofline of configs 2 and 3 (for the counter runs); no headline line")
     ap.add_argument("--cpu-lm-sample", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving", type=int, default=1, help="also run the config 4 serving mix (0 = skip)")
@@ -606,6 +669,20 @@ def main():
 
     import torch
     from paper_2007_08576_amd import tt
+
+    if args.assembly_only:
+        from paper_2007_08576_amd import synth
+        dev = torch.device("cuda:0")
+        res = {}
+        for name, sc in (("config2", synth.make_config2(seed=2, n_frames=300)),
+                         ("config3", synth.make_config3(seed=3, n_frames=300))):
+            dfr = [tuple(torch.from_numpy(a).to(dev) for a in (f.depth, f.feat_xyz, f.feat_desc))
+                   for f in (sc.frame(t) for t in (1, 2))]
+            torch.cuda.synchronize()
+            res[name] = assembly_roofline(torch, tt, sc, dfr)
+        _copy_calibration(args, torch)
+        print(json.dumps({"assembly": res}), flush=True)
+        return
 
     t0 = time.time()
     sc, frames = make_workload(args.frames)
@@ -760,14 +837,7 @@ def main():
     if args.orb:
         out["orb_front_end"] = orb_bench(args, torch, tt, sc)
     print(json.dumps(out), flush=True)
-    if args.copy_calibration_mib > 0:
-        nf = args.copy_calibration_mib * (1 << 20) // 4
-        src = torch.ones(nf, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy calibration: 3 x {args.copy_calibration_mib} MiB read + written")
+    _copy_calibration(args, torch)
 
 
 if __name__ == "__main__":
