@@ -132,8 +132,16 @@ typedef struct {
 /* Fills every field with the paper's constants and this library's defaults. */
 void tt_default_params(tt_params* p);
 
-/* Creates a stream. hip_stream is a hipStream_t to queue work on (NULL: the library creates
- * its own at default priority). Allocates the frame-size device buffers. */
+/* Creates a stream: the state of one tracked surface across the frames of a video (Sec. 2: the
+ * template of the first frame and the per-control-point warps carried from frame to frame, each
+ * frame's solve starting from the previous warps). p: weights and iteration counts of Eqs. (1)-(6)
+ * and Sec. 2.1 (tt_default_params gives the paper's); K: the pinhole camera of the depth maps.
+ * hip_stream is a hipStream_t to queue work on (NULL: the library creates its own at default
+ * priority) -- an argument the paper has no counterpart for: the caller's queue, so that the
+ * solve orders against the caller's own device work without a host round trip. Allocates the
+ * frame-size device buffers (the stream owns them; tt_destroy frees them). TT_EINVAL: NULL or
+ * out-of-range parameters or intrinsics; TT_ENOMEM / TT_EDEVICE: allocation or stream creation
+ * failed (nothing is left allocated). */
 int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_stream, tt_stream** out);
 
 /* Template (Sec. 2, generated from the first frame): pts_xyz [M][3], feat_xyz [K1][3] and
@@ -146,9 +154,15 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
                     const uint8_t* feat_desc, int K1);
 
 /* One frame from host memory: depth [height][width], feat_xyz [K2][3] (NaN = no depth),
- * feat_desc [K2][32]. Runs matching, pre-selection and lm_iters LM iterations, then writes the
- * deformed template out_vertices [M][3] and the warps out_dq [N][8] (either may be NULL) and
- * the optional debug taps. Synchronous; advances the frame counter. */
+ * feat_desc [K2][32]. Runs the per-frame solve of Sec. 2: the normal map of the depth, Hamming
+ * matching of the template's ORB features and their 1-point RANSAC + reweighting pre-selection
+ * (Sec. 2.1, Eq. (4)), then lm_iters Levenberg-Marquardt iterations on the cost of Eq. (1)
+ * (point-to-plane ICP, ORB and dense ARAP terms, Eqs. (2)-(6)), each a Gauss-Newton system solved
+ * by Cholesky factorisation; then writes the deformed template out_vertices [M][3] and the warps
+ * out_dq [N][8] (either may be NULL; caller-owned host memory) and the optional debug taps.
+ * Synchronous; advances the frame counter. TT_EINVAL: NULL inputs or K2 out of range; TT_ESTATE:
+ * no template; TT_EBUSY: another call on the stream; TT_EDEVICE: a HIP call or a device-side
+ * check failed. */
 int tt_track_frame(tt_stream* s, const float* depth, const float* feat_xyz, const uint8_t* feat_desc,
                    int K2, double* out_vertices, double* out_dq, tt_frame_debug* dbg);
 
@@ -273,7 +287,9 @@ int tt_device_bytes(tt_stream* s, uint64_t* bytes);
 int tt_cholesky_solve_noalloc(int n, const float* d_A, const float* d_b, float* d_x, int32_t* d_status,
                               void* hip_stream);
 
-/* Destroys the stream and frees its device memory. */
+/* Destroys the stream (the surface of Sec. 2 it tracked: template, warps, frame buffers) after its
+ * queued work has finished, and frees its device memory and, if the library created it, its HIP
+ * stream. TT_EINVAL: NULL; TT_EBUSY: a server owns the stream (tt_server_close destroys it). */
 int tt_destroy(tt_stream* s);
 
 /* ---- Serving: many streams under one HBM budget, continuous batching ----------------------
