@@ -287,6 +287,32 @@ int tt_device_bytes(tt_stream* s, uint64_t* bytes);
 int tt_cholesky_solve_noalloc(int n, const float* d_A, const float* d_b, float* d_x, int32_t* d_status,
                               void* hip_stream);
 
+/* ---- Tuning ------------------------------------------------------------------------------
+ * Launch shapes of the per-frame solve that do not change what it computes: the width of the
+ * factorisation's persistent launch, the size of the dense-ARAP workgroups and whether the rows
+ * and ARAP kernels share one launch after the first LM iteration. The factorisation and the fusion
+ * leave every result bit for bit the same; the ARAP workgroup size changes the order in which a
+ * node's diagonal block and gradient terms are summed (FP32 rounding only). */
+typedef struct {
+  int chol_grid_pct;  /* workgroups of the factorisation launch, in percent of the compute units
+                         (25..400; default 200; at most one workgroup per task)               */
+  int arap_threads;   /* 128 or 256 (default) threads per dense-ARAP workgroup                   */
+  int fuse_rows_arap; /* 1 (default): rows and ARAP in one launch from the second LM iteration on
+                         (needs arap_threads 256); 0: separate launches                          */
+  double frame_ms;    /* tt_autotune: mean time per frame of this configuration, else 0          */
+} tt_tuning;
+int tt_get_tuning(tt_stream* s, tt_tuning* out);
+/* TT_EINVAL: a field out of range. Captured LM graphs are dropped and recaptured with the new shapes. */
+int tt_set_tuning(tt_stream* s, const tt_tuning* t);
+/* Project-written autotuner: times the whole per-frame solve of one of the caller's frames (device
+ * arrays as tt_track_frame_device) under each candidate -- launch width 50 / 100 / 200 % x (ARAP
+ * 256 fused, 256 unfused, 128 unfused) -- one untimed and reps timed frames each (1..100), every
+ * frame starting from the stream's warps and frame counter as they were, which are restored
+ * afterwards; keeps the fastest, returns it in *best with its time. Synchronous. TT_ESTATE: no
+ * template. */
+int tt_autotune(tt_stream* s, const float* d_depth, const float* d_feat_xyz, const uint8_t* d_feat_desc, int K2,
+                int reps, tt_tuning* best);
+
 /* Destroys the stream (the surface of Sec. 2 it tracked: template, warps, frame buffers) after its
  * queued work has finished, and frees its device memory and, if the library created it, its HIP
  * stream. TT_EINVAL: NULL; TT_EBUSY: a server owns the stream (tt_server_close destroys it). */

@@ -68,8 +68,10 @@ void free_template(tt_stream* s) {
   double *lo = d.log_cost_old, *ln = d.log_cost_new, *ll = d.log_lambda, *lw = d.log_w_arap;
   int *la = d.log_accept, *lf = d.log_fail;
   const int cus = d.num_cus, wkhz = d.wall_khz, prec = d.prec, ir = d.ir_iters, solver = d.solver;
+  const int tg = d.chol_grid_pct, ta = d.arap_threads, tf = d.fuse_rows_arap;
   d = DevState();
   d.num_cus = cus; d.wall_khz = wkhz; d.prec = prec; d.ir_iters = ir; d.solver = solver;
+  d.chol_grid_pct = tg; d.arap_threads = ta; d.fuse_rows_arap = tf;
   d.HW = HW; d.K2cap = K2cap; d.depth = depth; d.nmap_b = nmap; d.nmap = nmap; d.f2xyz = f2xyz; d.f2desc = f2desc;
   d.sc = sc; d.log_cost_old = lo; d.log_cost_new = ln; d.log_lambda = ll; d.log_accept = la;
   d.log_w_arap = lw; d.log_fail = lf;
@@ -289,7 +291,8 @@ int enqueue_assemble(tt_stream* s, DevState& dd, int it, bool dbg, hipStream_t s
   Intr K = intr_of(s);
   // after the first iteration the rows and the ARAP blocks share one launch, unless either stage
   // is being timed (then each keeps its own launch between its timing events)
-  const bool fuse = it > 0 && !((s->timing >> TT_STAGE_ROWS) & 1u) && !((s->timing >> TT_STAGE_ARAP) & 1u);
+  const bool fuse = it > 0 && d.fuse_rows_arap && d.arap_threads == 256 && !((s->timing >> TT_STAGE_ROWS) & 1u) &&
+                    !((s->timing >> TT_STAGE_ARAP) & 1u);
   if (fuse) {
     HIPCHK(launch_lm_rows_arap(dd, P, K, it, st));
   } else {
@@ -1198,6 +1201,115 @@ int tt_get_state(tt_stream* s, double* dq, int64_t* frame) {
   }
   if (frame) *frame = s->frame;
   return TT_OK;
+}
+
+static bool tuning_ok(const tt_tuning* t) {
+  return t && t->chol_grid_pct >= 25 && t->chol_grid_pct <= 400 && (t->arap_threads == 128 || t->arap_threads == 256) &&
+         (t->fuse_rows_arap == 0 || (t->fuse_rows_arap == 1 && t->arap_threads == 256));
+}
+
+// The captured LM graphs hold the launch shapes of the tuning they were captured with.
+static void drop_graphs(tt_stream* s) {
+  for (int f = 0; f < 2; f++)
+    if (s->lm_graph[f]) {
+      (void)hipStreamSynchronize(s->st);
+      (void)hipGraphExecDestroy(s->lm_graph[f]);
+      s->lm_graph[f] = nullptr;
+    }
+}
+
+static void apply_tuning(tt_stream* s, const tt_tuning* t) {
+  s->d.chol_grid_pct = t->chol_grid_pct;
+  s->d.arap_threads = t->arap_threads;
+  s->d.fuse_rows_arap = t->fuse_rows_arap;
+  drop_graphs(s);
+}
+
+int tt_get_tuning(tt_stream* s, tt_tuning* out) {
+  if (!s || !out) return TT_EINVAL;
+  out->chol_grid_pct = s->d.chol_grid_pct;
+  out->arap_threads = s->d.arap_threads;
+  out->fuse_rows_arap = s->d.fuse_rows_arap;
+  out->frame_ms = 0.0;
+  return TT_OK;
+}
+
+int tt_set_tuning(tt_stream* s, const tt_tuning* t) {
+  if (!s || !tuning_ok(t)) return TT_EINVAL;
+  Busy busy(s);
+  if (!busy.ok) return TT_EBUSY;
+  apply_tuning(s, t);
+  return TT_OK;
+}
+
+int tt_autotune(tt_stream* s, const float* d_depth, const float* d_feat_xyz, const uint8_t* d_feat_desc, int K2,
+                int reps, tt_tuning* best) {
+  if (!s || !d_depth || !best || reps < 1 || reps > 100 || K2 < 0 || K2 > (1 << 23) ||
+      (K2 > 0 && (!d_feat_xyz || !d_feat_desc)))
+    return TT_EINVAL;
+  if (K2 > 0 && (uintptr_t)d_feat_desc % 16 != 0) return TT_EINVAL;
+  Busy busy(s);
+  if (!busy.ok) return TT_EBUSY;
+  if (!s->has_template) return TT_ESTATE;
+  int rc = ensure_k2(s, K2);
+  if (rc) return rc;
+  DevState& d = s->d;
+  hipStream_t st = s->st;
+  const size_t wbytes = sizeof(float) * 8 * (size_t)d.N;
+  float* W0 = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipMalloc(&W0, wbytes) != hipSuccess) return TT_ENOMEM;
+  const int64_t f0 = s->frame;
+  const int graph = s->P.graph;
+  const unsigned timing = s->timing;
+  tt_tuning start;
+  (void)tt_get_tuning(s, &start);
+  rc = (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+        hipMemcpyAsync(W0, d.W, wbytes, hipMemcpyDeviceToDevice, st) == hipSuccess)
+           ? TT_OK
+           : TT_EDEVICE;
+  s->P.graph = 0;  // trials launch kernel by kernel, untimed by the stage timers
+  s->timing = 0;
+  // candidates: launch width of the factorisation x (ARAP workgroup size, rows + ARAP fused)
+  const int pcts[3] = {50, 100, 200};
+  const int shapes[3][2] = {{256, 1}, {256, 0}, {128, 0}};
+  tt_tuning top = start;
+  top.frame_ms = 1e300;
+  for (int a = 0; a < 3 && !rc; a++)
+    for (int b = 0; b < 3 && !rc; b++) {
+      tt_tuning t;
+      t.chol_grid_pct = pcts[a];
+      t.arap_threads = shapes[b][0];
+      t.fuse_rows_arap = shapes[b][1];
+      t.frame_ms = 0.0;
+      apply_tuning(s, &t);
+      // one untimed frame, then reps timed frames, each from the same warps and frame counter
+      for (int r = 0; r <= reps && !rc; r++) {
+        if (hipMemcpyAsync(d.W, W0, wbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) rc = TT_EDEVICE;
+        s->frame = f0;
+        if (!rc && r == 1 && hipEventRecord(e0, st) != hipSuccess) rc = TT_EDEVICE;
+        if (!rc) rc = enqueue_frame(s, d_depth, d_feat_xyz, d_feat_desc, K2, nullptr, nullptr, false);
+      }
+      float ms = 0.0f;
+      if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = TT_EDEVICE;
+      t.frame_ms = ms / reps;
+      if (!rc && t.frame_ms < top.frame_ms) top = t;
+    }
+  // the stream as it was, with the fastest tuning (or the one it had, on failure)
+  apply_tuning(s, rc ? &start : &top);
+  if (hipMemcpyAsync(d.W, W0, wbytes, hipMemcpyDeviceToDevice, st) != hipSuccess && !rc) rc = TT_EDEVICE;
+  s->frame = f0;
+  s->P.graph = graph;
+  s->timing = timing;
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = TT_EDEVICE;
+  if (!rc) rc = take_device_error(s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(W0);
+  if (!rc) *best = top;
+  return rc;
 }
 
 int tt_set_state(tt_stream* s, const double* dq, int64_t frame) {

@@ -1499,14 +1499,18 @@ hipError_t launch_cholesky_factor_batch(DevState* const* ds, int S, hipStream_t 
     CholBatch B;
     B.nprob = (S - b0 < kMaxCholBatch) ? S - b0 : kMaxCholBatch;
     int tasks = 0, cus = 256, khz = 100000;  // the constant clock runs at 100 MHz unless the device says otherwise
+    int pct = 200;                           // launch width in percent of the compute units (first system's tuning)
     for (int q = 0; q < B.nprob; q++) {
       B.p[q] = chol_args(*ds[b0 + q], 0);
       tasks += B.p[q].ntasks;
       if (ds[b0 + q]->num_cus > 0) cus = ds[b0 + q]->num_cus;
       if (ds[b0 + q]->wall_khz > 0) khz = ds[b0 + q]->wall_khz;
     }
+    if (ds[b0]->chol_grid_pct >= 25 && ds[b0]->chol_grid_pct <= 400) pct = ds[b0]->chol_grid_pct;
     B.wait_ticks = (uint64_t)(kWaitSeconds * 1000.0 * khz);
-    const int grid = tasks < 2 * cus ? tasks : 2 * cus;
+    // any width is safe: a task waits only on smaller tickets, which running workgroups claimed
+    const int width = (cus * pct + 99) / 100;
+    const int grid = tasks < width ? tasks : width;
     hipLaunchKernelGGL(k_chol_dataflow, dim3(grid), dim3(256), 0, st, B);
   }
   return hipGetLastError();

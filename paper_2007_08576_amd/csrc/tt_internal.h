@@ -119,6 +119,11 @@ struct DevState {
   int* flags = nullptr;      // [chol_flag_ints(nb)] factorisation and back-substitution flags
   int num_cus = 0;           // compute units of the device (persistent launch size)
   int wall_khz = 0;          // rate of the device's constant clock (s_memrealtime), kHz
+  // tuning (tt_set_tuning / tt_autotune): width of the factorisation launch in percent of the compute
+  // units, threads per dense-ARAP workgroup, and whether rows and ARAP share a launch after iteration 0
+  int chol_grid_pct = 200;
+  int arap_threads = 256;
+  int fuse_rows_arap = 1;
   int prec = TT_FP32;        // precision form of the solve
   int ir_iters = 0;          // refinement steps per solve (16-bit forms)
   int solver = TT_SOLVE_DENSE; // coupled dense solve or one 6 x 6 solve per node

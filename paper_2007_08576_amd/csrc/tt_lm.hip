@@ -453,12 +453,13 @@ constexpr int kArapThreads = 256;
 constexpr int kArapAcc = 36 + 6;
 
 // kOff: also write the off-diagonal blocks (the coupled solve); the per-node solve reads only the
-// diagonal blocks and g.
-template <bool kOff>
+// diagonal blocks and g. kT: threads of the workgroup (128 or 256, a tuning choice).
+template <bool kOff, int kT = kArapThreads>
 __device__ __forceinline__ void arap_body(const ArapArgs& a, int i) {
-  __shared__ float red[kArapAcc][kArapThreads + 1];
-  __shared__ float wsum[kArapThreads / 64][kArapAcc];
-  __shared__ double shd[kArapThreads];
+  static_assert(kT == 128 || kT == 256, "two or four wavefronts");
+  __shared__ float red[kArapAcc][kT + 1];
+  __shared__ float wsum[kT / 64][kArapAcc];
+  __shared__ double shd[kT];
   const int tid = threadIdx.x;
   const float w_arap = (float)a.sc->w_arap;
   float qi[8];
@@ -473,7 +474,7 @@ __device__ __forceinline__ void arap_body(const ArapArgs& a, int i) {
   float Gi[12];
   gmat(qi, Gi);
   const float qi2 = qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3];
-  for (int j = tid; j < a.N; j += kArapThreads) {
+  for (int j = tid; j < a.N; j += kT) {
     if (j == i) continue;
     float qj[8];
     load_dq(a.W, j, qj);
@@ -586,7 +587,9 @@ __device__ __forceinline__ void arap_body(const ArapArgs& a, int i) {
   }
   __syncthreads();
   if (tid < kArapAcc) {
-    const float v = (wsum[0][tid] + wsum[1][tid]) + (wsum[2][tid] + wsum[3][tid]);
+    float v;
+    if constexpr (kT == 256) v = (wsum[0][tid] + wsum[1][tid]) + (wsum[2][tid] + wsum[3][tid]);
+    else v = wsum[0][tid] + wsum[1][tid];
     if (tid < 36) {
       const int r = tid / 6, c = tid % 6;
       a.A[(size_t)(6 * i + r) * a.ld + 6 * i + c] = v;
@@ -595,15 +598,15 @@ __device__ __forceinline__ void arap_body(const ArapArgs& a, int i) {
     }
   } else if (tid == 64) {
     double c = 0.0;
-    for (int l = 0; l < kArapThreads; l++) c += shd[l];
+    for (int l = 0; l < kT; l++) c += shd[l];
     a.part[a.P.arap + i] = c;
   }
 }
-template <bool kOff>
 // Row i writes i off-diagonal blocks: the longest rows are dispatched first, so that the short ones
 // fill the tail instead of the long ones.
-__global__ __launch_bounds__(kArapThreads) void k_arap_assemble(ArapArgs a) {
-  arap_body<kOff>(a, a.N - 1 - (int)blockIdx.x);
+template <bool kOff, int kT>
+__global__ __launch_bounds__(kT) void k_arap_assemble(ArapArgs a) {
+  arap_body<kOff, kT>(a, a.N - 1 - (int)blockIdx.x);
 }
 
 // From the second LM iteration of a frame on, the ARAP weight is fixed and the dense ARAP blocks and
@@ -1064,10 +1067,14 @@ hipError_t launch_lm_rows_arap(DevState& d, const tt_params& P, const Intr& K, i
 
 hipError_t launch_lm_arap(DevState& d, const tt_params& P, hipStream_t st) {
   ArapArgs aa = arap_args(d, P);
-  if (d.solver == TT_SOLVE_NODE)
-    hipLaunchKernelGGL(k_arap_assemble<false>, dim3(d.N), dim3(kArapThreads), 0, st, aa);
-  else
-    hipLaunchKernelGGL(k_arap_assemble<true>, dim3(d.N), dim3(kArapThreads), 0, st, aa);
+  const bool off = d.solver != TT_SOLVE_NODE;
+  if (d.arap_threads == 128) {
+    if (off) hipLaunchKernelGGL((k_arap_assemble<true, 128>), dim3(d.N), dim3(128), 0, st, aa);
+    else hipLaunchKernelGGL((k_arap_assemble<false, 128>), dim3(d.N), dim3(128), 0, st, aa);
+  } else {
+    if (off) hipLaunchKernelGGL((k_arap_assemble<true, kArapThreads>), dim3(d.N), dim3(kArapThreads), 0, st, aa);
+    else hipLaunchKernelGGL((k_arap_assemble<false, kArapThreads>), dim3(d.N), dim3(kArapThreads), 0, st, aa);
+  }
   return hipGetLastError();
 }
 

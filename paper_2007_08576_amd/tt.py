@@ -63,6 +63,11 @@ class FrameDevice(C.Structure):
                 ("out_vertices", C.c_void_p), ("out_dq", C.c_void_p), ("inputs_ready", C.c_void_p)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("chol_grid_pct", C.c_int), ("arap_threads", C.c_int), ("fuse_rows_arap", C.c_int),
+                ("frame_ms", C.c_double)]
+
+
 class ServerParams(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_rounds_ahead", C.c_int)]
 
@@ -111,6 +116,9 @@ def lib():
         L.tt_destroy.argtypes = [vp]
         L.tt_strerror.argtypes = [C.c_int]
         L.tt_strerror.restype = C.c_char_p
+        L.tt_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.tt_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.tt_autotune.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.POINTER(Tuning)]
         L.tt_server_default_params.argtypes = [C.POINTER(ServerParams)]
         L.tt_server_default_params.restype = None
         L.tt_server_create.argtypes = [C.POINTER(ServerParams), vp, C.POINTER(vp)]
@@ -303,6 +311,22 @@ class Stream:
         n = np.zeros(len(STAGES), np.int64)
         _check(lib().tt_get_timing(self.h, _ptr(ms), _ptr(n)), "tt_get_timing")
         return ms, n
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(lib().tt_get_tuning(self.h, C.byref(t)), "tt_get_tuning")
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+    def set_tuning(self, chol_grid_pct=200, arap_threads=256, fuse_rows_arap=1):
+        t = Tuning(int(chol_grid_pct), int(arap_threads), int(fuse_rows_arap), 0.0)
+        _check(lib().tt_set_tuning(self.h, C.byref(t)), "tt_set_tuning")
+
+    def autotune(self, depth, feat_xyz, feat_desc, K2, reps=3):
+        """tt_autotune on one device-memory frame; returns the chosen tuning (with its frame time)."""
+        t = Tuning()
+        _check(lib().tt_autotune(self.h, _dev_ptr(depth), _dev_ptr(feat_xyz), _dev_ptr(feat_desc), int(K2), int(reps),
+                                 C.byref(t)), "tt_autotune")
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
 
     def device_bytes(self):
         b = C.c_uint64()
