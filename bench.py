@@ -632,6 +632,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=8, help="distinct synthetic frames (replayed ping-pong)")
     ap.add_argument("--graph", type=int, default=1, help="replay each frame's LM iterations as one HIP graph")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="run the library's autotuner (tt_autotune) on the first frame before the warm-up")
     ap.add_argument("--assembly-only", type=int, default=0,
                     help="only the assembly roofline of configs 2 and 3 (for the counter runs); no headline line")
     ap.add_argument("--cpu-lm-sample", type=int, default=3)
@@ -724,6 +726,12 @@ def main():
         wall = time.perf_counter() - t0
         return steps / wall, np.array([ev0[k].elapsed_time(ev1[k]) for k in range(steps)])
 
+    tuning = s.get_tuning()
+    if args.autotune:
+        d = dframes[0]
+        tuning = s.autotune(d[0], d[1], d[2], d[1].shape[0], reps=3)
+        log(f"autotuned: factorisation launch {tuning['chol_grid_pct']} % of the CUs, ARAP workgroups of "
+            f"{tuning['arap_threads']}, rows + ARAP fused {tuning['fuse_rows_arap']} ({tuning['frame_ms']:.3f} ms per frame)")
     for k in range(args.warmup):
         step(k)
     s.sync()
@@ -807,6 +815,7 @@ def main():
         "gn_iters_per_s": fps * params.lm_iters,
         "arap_pairs_per_s": fps * params.lm_iters * pairs,
         "stage_us": {k: v["ms_per_call"] * 1e3 for k, v in stages.items()},
+        "tuning": dict(tuning, source="tt_autotune on frame 1" if args.autotune else "defaults"),
         "roofline": roof,
     }
 

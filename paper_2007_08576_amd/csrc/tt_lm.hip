@@ -602,11 +602,9 @@ __device__ __forceinline__ void arap_body(const ArapArgs& a, int i) {
     a.part[a.P.arap + i] = c;
   }
 }
-// Row i writes i off-diagonal blocks: the longest rows are dispatched first, so that the short ones
-// fill the tail instead of the long ones.
 template <bool kOff, int kT>
 __global__ __launch_bounds__(kT) void k_arap_assemble(ArapArgs a) {
-  arap_body<kOff, kT>(a, a.N - 1 - (int)blockIdx.x);
+  arap_body<kOff, kT>(a, (int)blockIdx.x);
 }
 
 // From the second LM iteration of a frame on, the ARAP weight is fixed and the dense ARAP blocks and
@@ -617,7 +615,7 @@ __global__ __launch_bounds__(kT) void k_arap_assemble(ArapArgs a) {
 static_assert(kRowThreads == kArapThreads, "one block shape for both bodies");
 template <bool kOff>
 __global__ __launch_bounds__(kArapThreads) void k_rows_arap(ArapArgs aa, RowArgs ra, int it) {
-  if ((int)blockIdx.x < aa.N) arap_body<kOff>(aa, aa.N - 1 - (int)blockIdx.x);
+  if ((int)blockIdx.x < aa.N) arap_body<kOff>(aa, (int)blockIdx.x);
   else data_rows_body(ra, it, (int)blockIdx.x - aa.N);
 }
 
