@@ -424,15 +424,20 @@ def solver_study(args, torch, tt, sc, frames, dframes):
     each, and how far each gets in the frame's 10 LM iterations: frames 1..F tracked in sequence
     from the identity (warm-started), vertex RMS against the generator's ground truth and the cost
     left after the last iteration (the sparse graph's cost has fewer ARAP terms); and the
-    z-buffered association (nearest template point per pixel) with the dense solve."""
+    z-buffered association (nearest template point per pixel) and the closest-point association
+    through the per-frame kd-tree (the search Sec. 2 says its re-projection beats) with the dense
+    solve; for the last two and the projective default also the per-frame front stage (where the
+    kd-tree is built) and the per-iteration rows kernel (where the association runs), from the
+    stage timers."""
     dev = torch.device("cuda:0")
     out = {}
     intr = tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy)
-    for name, solver, knn, zb in (("dense", tt.TT_SOLVE_DENSE, 0, 0), ("node", tt.TT_SOLVE_NODE, 0, 0),
-                                  ("dense_arap_knn8", tt.TT_SOLVE_DENSE, 8, 0),
-                                  ("dense_zbuffer", tt.TT_SOLVE_DENSE, 0, 1)):
+    for name, solver, knn, zb, kd in (("dense", tt.TT_SOLVE_DENSE, 0, 0, 0), ("node", tt.TT_SOLVE_NODE, 0, 0, 0),
+                                      ("dense_arap_knn8", tt.TT_SOLVE_DENSE, 8, 0, 0),
+                                      ("dense_zbuffer", tt.TT_SOLVE_DENSE, 0, 1, 0),
+                                      ("dense_kdtree", tt.TT_SOLVE_DENSE, 0, 0, 1)):
         s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=2, solver=solver,
-                                        arap_knn=knn, assoc_zbuffer=zb), intr)
+                                        arap_knn=knn, assoc_zbuffer=zb, assoc_kdtree=kd), intr)
         s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
         rms, cost = [], []
         for fr in frames:
@@ -451,9 +456,24 @@ def solver_study(args, torch, tt, sc, frames, dframes):
             s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], ov, oq)
         s.sync()
         fps = args.solver_steps / (time.perf_counter() - t0)
+        assoc = None
+        if name in ("dense", "dense_zbuffer", "dense_kdtree"):
+            s.get_timing()
+            s.set_timing(True, stages=("front", "rows"))
+            for k in range(5):
+                d = dframes[k % len(dframes)]
+                s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], ov, oq)
+            s.sync()
+            s.set_timing(False)
+            ms, n = s.get_timing()
+            assoc = {st: float(ms[tt.STAGES.index(st)] / max(n[tt.STAGES.index(st)], 1)) * 1e3
+                     for st in ("front", "rows")}
         s.destroy()
         out[name] = {"frames_per_s": fps, "truth_rms_mm_per_frame": rms, "final_cost_per_frame": cost,
                      "mean_truth_rms_mm": float(np.mean(rms))}
+        if assoc:
+            out[name]["stage_us"] = assoc
+            log(f"    front stage {assoc['front']:.1f} us per frame, rows {assoc['rows']:.1f} us per iteration")
         log(f"  solver {name:15s} {fps:7.1f} frames/s, truth rms over {len(frames)} frames {np.mean(rms):.3f} mm "
             f"(last {rms[-1]:.3f}), final cost of frame 1 {cost[0]:.4g}")
     out["note"] = ("frames 1..F of config 2 tracked in sequence from the identity, 10 LM iterations each; "

@@ -101,6 +101,12 @@ typedef struct {
                               kernel; 1: they are captured once per front-buffer parity into a HIP
                               graph and replayed on later frames (single-stream calls without
                               debug taps or stage timers; the results are the same bit for bit) */
+  int assoc_kdtree;        /* 0 (default): projective association (Sec. 2's re-projection); 1: the
+                              closest-point comparator the paper contrasts it with -- each deformed
+                              template point corresponds to the nearest frame point in 3D (float32
+                              squared distance, ties to the lower pixel index) among the pixels that
+                              have a normal, found through a kd-tree built on the device every frame.
+                              Not with assoc_zbuffer. */
 } tt_params;
 
 /* Optional per-frame outputs of tt_track_frame; each pointer may be NULL. Sizes: K1 template

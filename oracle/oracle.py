@@ -37,7 +37,7 @@ class Params(C.Structure):
                 ("tukey_c", C.c_double), ("H", C.c_double), ("ransac_refs", C.c_int),
                 ("ransac_iters", C.c_int), ("lm_iters", C.c_int), ("max_hamming", C.c_int),
                 ("lm_lambda0", C.c_double), ("seed", C.c_uint64), ("solver", C.c_int),
-                ("arap_knn", C.c_int), ("assoc_zbuffer", C.c_int)]
+                ("arap_knn", C.c_int), ("assoc_zbuffer", C.c_int), ("assoc_kdtree", C.c_int)]
 
 
 SOLVE_DENSE, SOLVE_NODE = 0, 1

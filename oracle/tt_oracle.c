@@ -292,6 +292,7 @@ void tto_default_params(tto_params* p) {
   p->solver = TTO_SOLVE_DENSE;
   p->arap_knn = 0;
   p->assoc_zbuffer = 0;
+  p->assoc_kdtree = 0;
 }
 
 static void free_frame(tto_stream* s) {
@@ -318,7 +319,8 @@ int tto_create_stream(const tto_params* p, const tto_intrinsics* K, tto_stream**
       p->ransac_iters < 1 || p->lm_iters < 0 || !(p->H > 0) || !(p->tukey_c > 0) ||
       !(p->w_orb >= 0) || !(p->w_angle >= 0) || !(p->w_rotation >= 0) || !(p->lambda_arap >= 0) ||
       !(p->lm_lambda0 > 0) || (p->solver != TTO_SOLVE_DENSE && p->solver != TTO_SOLVE_NODE) ||
-      p->arap_knn < 0 || p->arap_knn > 32 || (p->assoc_zbuffer != 0 && p->assoc_zbuffer != 1))
+      p->arap_knn < 0 || p->arap_knn > 32 || (p->assoc_zbuffer != 0 && p->assoc_zbuffer != 1) ||
+      (p->assoc_kdtree != 0 && p->assoc_kdtree != 1) || (p->assoc_kdtree && p->assoc_zbuffer))
     return TTO_EINVAL;
   if (K->width < 3 || K->height < 3 || !(K->fx > 0) || !(K->fy > 0) || !isfinite(K->cx) ||
       !isfinite(K->cy))
@@ -900,6 +902,24 @@ static int nearest_pixel(const tto_intrinsics* K, const double* v) {
   return (int)vr * K->width + (int)ur;
 }
 
+/* The closest-point alternative to re-projection (Sec. 2 names closest-point search in a kd-tree as
+ * the slower option): the pixel whose back-projected target point is nearest to v in 3D, over the
+ * pixels that have a normal (exhaustive search, FP64 squared distance, ties to the lower pixel
+ * index), or -1 if no pixel has one. */
+static int nearest_point(const tto_stream* s, const double* v) {
+  size_t HW = (size_t)s->K.width * s->K.height;
+  double best = INFINITY;
+  int arg = -1;
+  for (size_t p = 0; p < HW; p++) {
+    if (!s->nvalid[p]) continue;
+    const double* q = s->qpts + 3 * p;
+    double d[3] = {v[0] - q[0], v[1] - q[1], v[2] - q[2]};
+    double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (d2 < best) { best = d2; arg = (int)p; } /* equal: the lower index, found first, stays */
+  }
+  return arg;
+}
+
 /* current node positions p_i^t = W_i^t(p_i^0) */
 static void node_positions(const tto_stream* s, const double* dq, double* pos) {
   for (int i = 0; i < s->N; i++) dq_apply(dq + 8 * i, s->c0 + 3 * i, pos + 3 * i);
@@ -936,7 +956,7 @@ static void associate(const tto_stream* s, const double* dq, assoc_t* a, int set
     a->corr[j] = -1;
     a->omega[j] = 0.0;
     a->r_icp[j] = 0.0;
-    int pix = nearest_pixel(K, v);
+    int pix = s->P.assoc_kdtree ? nearest_point(s, v) : nearest_pixel(K, v);
     if (pix < 0) continue;
     if (a->zwin && a->zwin[pix] != j) continue; /* hidden behind another template point */
     if (!s->nvalid[pix]) continue;

@@ -66,6 +66,10 @@ typedef struct {
   int assoc_zbuffer;      /* 0: every deformed template point takes its nearest pixel; 1: of the
                              points that project to one pixel only the nearest to the camera
                              (smallest z as float32, ties to the lower index) takes it */
+  int assoc_kdtree;       /* 0: re-projection (Sec. 2); 1: the closest-point alternative the paper
+                             contrasts it with -- the nearest target point in 3D (FP64 distance,
+                             ties to the lower pixel index) among the pixels with a normal. Not
+                             with assoc_zbuffer. */
 } tto_params;
 
 typedef struct tto_stream tto_stream;

@@ -69,7 +69,12 @@ void free_template(tt_stream* s) {
   int *la = d.log_accept, *lf = d.log_fail;
   const int cus = d.num_cus, wkhz = d.wall_khz, prec = d.prec, ir = d.ir_iters, solver = d.solver;
   const int tg = d.chol_grid_pct, ta = d.arap_threads, tf = d.fuse_rows_arap;
+  const DevState keep = d;  // the frame-size kd-tree buffers (allocated with the stream)
   d = DevState();
+  d.kd_pts_b = keep.kd_pts_b; d.kd_split_b = keep.kd_split_b; d.kd_count_b = keep.kd_count_b;
+  d.kd_pts = keep.kd_pts; d.kd_split = keep.kd_split; d.kd_count = keep.kd_count; d.kd_levels = keep.kd_levels;
+  d.kd_flag = keep.kd_flag; d.kd_sel = keep.kd_sel; d.kd_xyz = keep.kd_xyz; d.kd_vals = keep.kd_vals;
+  d.kd_keys = keep.kd_keys; d.kd_temp = keep.kd_temp; d.kd_temp_bytes = keep.kd_temp_bytes;
   d.num_cus = cus; d.wall_khz = wkhz; d.prec = prec; d.ir_iters = ir; d.solver = solver;
   d.chol_grid_pct = tg; d.arap_threads = ta; d.fuse_rows_arap = tf;
   d.HW = HW; d.K2cap = K2cap; d.depth = depth; d.nmap_b = nmap; d.nmap = nmap; d.f2xyz = f2xyz; d.f2desc = f2desc;
@@ -267,6 +272,7 @@ int enqueue_front(tt_stream* s, DevState& dd, int K2, hipStream_t st, const void
   {
     StageTimer tm(s, TT_STAGE_FRONT, sf);
     HIPCHK(launch_normal_map(dd, K, sf));
+    if (dd.kd_pts_b) HIPCHK(launch_kd_build(dd, K, sf));
     if (s->d.K1 > 0) {
       HIPCHK(launch_match(dd, K2, P.max_hamming, sf));  // K2 == 0: every feature unmatched
       HIPCHK(launch_preselect(dd, P.ransac_refs, P.ransac_iters, P.H, P.seed, s->frame, sf));
@@ -668,7 +674,8 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
       !(p->lm_lambda0 > 0) || p->precision < TT_FP32 || p->precision > TT_FP16_IR || p->ir_iters < 0 ||
       p->ir_iters > 8 || (p->solver != TT_SOLVE_DENSE && p->solver != TT_SOLVE_NODE) ||
       p->arap_knn < 0 || p->arap_knn > 32 || (p->assoc_zbuffer != 0 && p->assoc_zbuffer != 1) ||
-      (p->graph != 0 && p->graph != 1))
+      (p->graph != 0 && p->graph != 1) || (p->assoc_kdtree != 0 && p->assoc_kdtree != 1) ||
+      (p->assoc_kdtree && p->assoc_zbuffer))
     return TT_EINVAL;
   if (K->width < 3 || K->height < 3 || !(K->fx > 0) || !(K->fy > 0) || !isfinite(K->cx) || !isfinite(K->cy) ||
       (int64_t)K->width * K->height > (1 << 28))
@@ -705,6 +712,25 @@ int tt_create_stream(const tt_params* p, const tt_intrinsics* K, void* hip_strea
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_accept, (size_t)T);
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_w_arap, (size_t)T);
   rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.log_fail, (size_t)T);
+  if (!rc && p->assoc_kdtree) {
+    // per-frame kd-tree of the frame's points: two buffer sets (front-stage parity) and build scratch
+    const size_t HW = (size_t)d.HW;
+    d.kd_levels = kd_levels_for(d.HW);
+    d.kd_temp_bytes = kd_scratch_bytes(d.HW);
+    if (!d.kd_temp_bytes) rc = TT_EDEVICE;
+    rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.kd_pts_b, 2 * HW);
+    rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.kd_split_b, (size_t)2 << d.kd_levels);
+    rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.kd_count_b, 2);
+    rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.kd_flag, HW);
+    rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.kd_sel, HW);
+    rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.kd_xyz, HW);
+    rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.kd_vals, 2 * HW);
+    rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &d.kd_keys, 2 * HW);
+    uint8_t* tmp = nullptr;
+    rc = rc ? rc : dalloc(s, s->allocs_frame, s->bytes_frame, &tmp, d.kd_temp_bytes);
+    d.kd_temp = tmp;
+    if (!rc) select_front_set(d, 0);
+  }
   if (rc) {
     tt_destroy(s);
     return rc;

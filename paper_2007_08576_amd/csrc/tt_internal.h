@@ -122,6 +122,22 @@ struct DevState {
   // tuning (tt_set_tuning / tt_autotune): width of the factorisation launch in percent of the compute
   // units, threads per dense-ARAP workgroup, and whether rows and ARAP share a launch after iteration 0
   int chol_grid_pct = 200;
+  // kd-tree association (assoc_kdtree): per front-buffer set the frame's points in tree order, the
+  // split values (heap order) and the point count; build scratch (tt_kdtree.hip)
+  float4* kd_pts_b = nullptr;
+  float* kd_split_b = nullptr;
+  int* kd_count_b = nullptr;
+  float4* kd_pts = nullptr;
+  float* kd_split = nullptr;
+  int* kd_count = nullptr;
+  int kd_levels = 0;
+  uint8_t* kd_flag = nullptr;
+  int* kd_sel = nullptr;
+  float4* kd_xyz = nullptr;
+  uint32_t* kd_vals = nullptr;  // [2][HW]
+  uint64_t* kd_keys = nullptr;  // [2][HW]
+  void* kd_temp = nullptr;
+  size_t kd_temp_bytes = 0;
   int arap_threads = 256;
   int fuse_rows_arap = 1;
   int prec = TT_FP32;        // precision form of the solve
@@ -185,6 +201,11 @@ struct tt_stream {
 // Points d's front outputs at buffer set f (0 or 1).
 inline void select_front_set(DevState& d, int f) {
   d.nmap = d.nmap_b + (size_t)f * d.HW;
+  if (d.kd_pts_b) {
+    d.kd_pts = d.kd_pts_b + (size_t)f * d.HW;
+    d.kd_split = d.kd_split_b + ((size_t)f << d.kd_levels);
+    d.kd_count = d.kd_count_b + f;
+  }
   if (d.o2_b) {
     d.o2 = d.o2_b + (size_t)f * d.K1a;
     d.wstar = d.wstar_b + (size_t)f * d.K1a;
@@ -204,6 +225,11 @@ hipError_t launch_node_graph(DevState& d, int k, hipStream_t st);
 hipError_t launch_knn(const DevState& d, double sbar, hipStream_t st);
 
 hipError_t launch_normal_map(const DevState& d, const Intr& K, hipStream_t st);
+// kd-tree of the frame's points (assoc_kdtree), into the current front-buffer set
+constexpr int kKdLeaf = 16;  // most points in a leaf
+int kd_levels_for(int HW);
+size_t kd_scratch_bytes(int HW);
+hipError_t launch_kd_build(DevState& d, const Intr& K, hipStream_t st);
 hipError_t launch_match(const DevState& d, int K2, int max_hamming, hipStream_t st);
 hipError_t launch_preselect(const DevState& d, int R, int iters, double H, uint64_t seed, int64_t frame,
                             hipStream_t st);

@@ -33,6 +33,7 @@
 #include <float.h>
 
 #include "tt_internal.h"
+#include "tt_kdtree.h"
 #include "tt_math.h"
 
 namespace {
@@ -135,6 +136,7 @@ struct RowArgs {
   // z-buffered association (nullptr: every point takes its nearest pixel)
   unsigned long long* zbuf;
   int* zpix;
+  KdArgs kd;  // closest-point association (kd.pts null: off)
   // outputs
   int* corr;
   float *rres, *omega, *jac, *wres;
@@ -223,6 +225,9 @@ __device__ __forceinline__ void data_rows_body(const RowArgs& a, int it, int bx)
       if (a.zbuf) {
         pix = a.zpix[j];  // the pixel of the z-buffer pass; kept only by the point nearest the camera
         if (pix >= 0 && (unsigned)(a.zbuf[pix] & 0xffffffffull) != (unsigned)j) pix = -1;
+      } else if (a.kd.pts) {
+        const f3 v = p + dp;  // closest-point comparator: the nearest frame point in 3D
+        pix = kd_nearest(a.kd, v.x, v.y, v.z);
       } else {
         pix = project_pixel(p, dp, a);
       }
@@ -1003,6 +1008,7 @@ RowArgs row_args(DevState& d, const tt_params& P, const Intr& K) {
   a.P = parts_of(d.M, d.K1, d.N);
   a.zbuf = d.zbuf;
   a.zpix = d.zpix;
+  a.kd = KdArgs{d.kd_pts_b ? d.kd_pts : nullptr, d.kd_split, d.kd_count, d.kd_levels};
   return a;
 }
 

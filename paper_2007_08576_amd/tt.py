@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("lm_lambda0", C.c_double), ("precision", C.c_int), ("seed", C.c_uint64),
                 ("hbm_budget_bytes", C.c_uint64), ("ir_iters", C.c_int),
                 ("solver", C.c_int), ("arap_knn", C.c_int),
-                ("assoc_zbuffer", C.c_int), ("graph", C.c_int)]
+                ("assoc_zbuffer", C.c_int), ("graph", C.c_int), ("assoc_kdtree", C.c_int)]
 
 
 _DEBUG_FIELDS = ("match_idx", "match_dist", "wstar", "preselected", "hyp_k0", "hyp_W", "hyp_nin",

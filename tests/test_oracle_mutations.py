@@ -122,6 +122,11 @@ MUTANTS = [
     ("pattern rotation sign", "rot[b][k][2 * h] = (int)lround(x * cs - y * sn);",
      "rot[b][k][2 * h] = (int)lround(x * cs + y * sn);"),
     ("box sum 5x3", "for (int dx = -2; dx <= 2; dx++) acc += img", "for (int dx = -1; dx <= 1; dx++) acc += img"),
+    # closest-point association (the kd-tree alternative of Sec. 2)
+    ("closest point ignores normal validity", "    if (!s->nvalid[p]) continue;\n    const double* q = s->qpts + 3 * p;",
+     "    const double* q = s->qpts + 3 * p;"),
+    ("closest point drops z", "double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];",
+     "double d2 = d[0] * d[0] + d[1] * d[1];"),
 ]
 
 

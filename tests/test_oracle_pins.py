@@ -975,6 +975,46 @@ def test_zbuffer_without_collisions_changes_nothing(O):
 
 
 # ------------------------------------------------------------------------------------------------
+# closest-point association (the kd-tree search Sec. 2 contrasts with its re-projection)
+
+def test_closest_point_association_is_the_nearest_neighbour_of_a_library_kdtree(O):
+    """At the identity the deformed template points are the template points; the association must
+    pick, for every one of them, the pixel whose back-projected point is nearest in 3D among the
+    pixels with a normal -- as scipy's kd-tree finds it (distances equal; pixels equal wherever the
+    nearest point is unique to 1e-9 relative)."""
+    from scipy.spatial import cKDTree
+    sc = synth.make_config1(1)
+    fr = sc.frame(1)
+    K = sc.intr
+    s = O.Stream(O.default_params(num_control_points=64, seed=1, lm_iters=1, assoc_kdtree=1), _intr(O, K))
+    s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    _, _, d = s.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
+    corr = d["corr0"]
+    _, val = O.normal_map(fr.depth, _intr(O, K))
+    valid = np.flatnonzero(val.reshape(-1))
+    u, v = valid % K.width, valid // K.width
+    z = fr.depth.reshape(-1)[valid].astype(np.float64)
+    q = np.stack([(u - K.cx) / K.fx * z, (v - K.cy) / K.fy * z, z], axis=1)
+    dist, idx = cKDTree(q).query(sc.pts.astype(np.float64), k=2)
+    assert (corr >= 0).all()
+    pos = np.searchsorted(valid, corr)
+    assert np.array_equal(valid[pos], corr), "a point was matched to a pixel without a normal"
+    dsel = np.linalg.norm(q[pos] - sc.pts.astype(np.float64), axis=1)
+    assert np.allclose(dsel, dist[:, 0], rtol=1e-12, atol=1e-12)
+    unique = dist[:, 1] > dist[:, 0] * (1 + 1e-9)
+    assert unique.mean() > 0.99
+    assert np.array_equal(corr[unique], valid[idx[unique, 0]])
+    # the residual is the point-to-plane distance at that pixel, as with re-projection
+    assert np.isfinite(d["r0"]).all()
+
+
+def test_closest_point_and_zbuffer_are_exclusive(O):
+    with pytest.raises(O.OracleError):
+        O.Stream(O.default_params(num_control_points=8, assoc_kdtree=1, assoc_zbuffer=1),
+                 O.intrinsics(16, 12, 10, 10, 8, 6))
+
+
+# ------------------------------------------------------------------------------------------------
 # uniform ORB features (Sec. 2.1): FAST corners, neighbour suppression, oriented binary descriptors
 
 _CIRCLE = [(0, -3), (1, -3), (2, -2), (3, -1), (3, 0), (3, 1), (2, 2), (1, 3),
