@@ -542,7 +542,8 @@ def _src_hash():
 
 
 def _pmc_rows(path):
-    """(kernel, grid work-items, counter value) per dispatch of a rocprofv3 --pmc CSV."""
+    """(kernel, grid work-items, counter value) per dispatch of a rocprofv3 --pmc CSV, in dispatch
+    order."""
     import csv
     import re
     rows = []
@@ -550,15 +551,17 @@ def _pmc_rows(path):
         k = re.sub(r"\(anonymous namespace\)::", "", r["Kernel_Name"])
         k = re.sub(r"^void ", "", k).split("(")[0].split("<")[0]
         grid = int(float(r.get("Grid_Size") or r.get("Grid_Size_X") or 0))
-        rows.append((k, grid, float(r["Counter_Value"])))
-    return rows
+        rows.append((int(r["Dispatch_Id"]), k, grid, float(r["Counter_Value"])))
+    rows.sort()
+    return [r[1:] for r in rows]
 
 
 def _calibration(f, w, copy_mib):
-    """Counter readings of the largest copy dispatch against its true size (KiB)."""
+    """Counter readings of the calibration copy (the last copy dispatch: the benchmark runs it after
+    everything else) against its true size (KiB)."""
     true_kib = copy_mib * 1024.0
-    fcopy = max(v for k, _, v in f if k == "__amd_rocclr_copyBuffer")
-    wcopy = max(v for k, _, v in w if k == "__amd_rocclr_copyBuffer")
+    fcopy = [v for k, _, v in f if k == "__amd_rocclr_copyBuffer"][-1]
+    wcopy = [v for k, _, v in w if k == "__amd_rocclr_copyBuffer"][-1]
     return {"copy_mib": copy_mib, "fetch_size_kib_read_for_copy": fcopy, "write_size_kib_read_for_copy": wcopy,
             "fetch_factor": true_kib / fcopy, "write_factor": true_kib / wcopy}
 
@@ -654,6 +657,8 @@ def main():
     ap.add_argument("--graph", type=int, default=1, help="replay each frame's LM iterations as one HIP graph")
     ap.add_argument("--autotune", type=int, default=1,
                     help="run the library's autotuner (tt_autotune) on the first frame before the warm-up")
+    ap.add_argument("--precision-only", type=int, default=0,
+                    help="only config 3 in the FP32 then the BF16-IR form, two frames each (for the counter runs)")
     ap.add_argument("--assembly-only", type=int, default=0,
                     help="only the assembly roofline of configs 2 and 3 (for the counter runs); no headline line")
     ap.add_argument("--cpu-lm-sample", type=int, default=3)
@@ -691,6 +696,30 @@ def main():
 
     import torch
     from paper_2007_08576_amd import tt
+
+    if args.precision_only:
+        from paper_2007_08576_amd import synth
+        dev = torch.device("cuda:0")
+        sc3 = synth.make_config3(seed=3, n_frames=300)
+        dfr3 = [tuple(torch.from_numpy(a).to(dev) for a in (f.depth, f.feat_xyz, f.feat_desc))
+                for f in (sc3.frame(t) for t in (1, 2))]
+        torch.cuda.synchronize()
+        res = {}
+        for name, prec in (("fp32", tt.TT_FP32), ("bf16_ir", tt.TT_BF16_IR)):
+            s3 = tt.Stream(tt.default_params(num_control_points=sc3.num_control_points, seed=2, precision=prec),
+                           tt.intrinsics(sc3.intr.width, sc3.intr.height, sc3.intr.fx, sc3.intr.fy, sc3.intr.cx,
+                                         sc3.intr.cy))
+            s3.set_template(sc3.pts, sc3.feat_xyz, sc3.feat_desc)
+            t0 = time.perf_counter()
+            for d in dfr3:
+                s3.track_frame_device(d[0], d[1], d[2], d[1].shape[0], None, None)
+            s3.sync()
+            res[name] = {"frames": len(dfr3), "seconds": time.perf_counter() - t0}
+            s3.destroy()
+            log(f"config3 {name}: {len(dfr3)} frames in {res[name]['seconds']:.3f} s")
+        _copy_calibration(args, torch)
+        print(json.dumps({"precision_config3": res}), flush=True)
+        return
 
     if args.assembly_only:
         from paper_2007_08576_amd import synth
