@@ -345,8 +345,9 @@ int tt_destroy(tt_stream* s);
 typedef struct tt_server tt_server;
 typedef struct {
   uint64_t hbm_budget_bytes; /* device bytes all open streams may hold together; 0 = unlimited   */
-  int max_rounds_ahead;      /* rounds queued ahead of the device (1..8; 0 = 2): a new frame joins
-                                after at most this many rounds already queued                      */
+  int max_rounds_ahead;      /* rounds queued ahead of the device (1..8; 0 = the default, 1): a new
+                                frame joins after at most this many rounds already queued; more
+                                run-ahead only makes the rounds smaller (measured at config 4)     */
 } tt_server_params;
 
 typedef struct {

@@ -56,7 +56,7 @@ struct tt_server {
   hipStream_t st = nullptr;
   bool own_st = false;
   uint64_t budget = 0, reserved = 0;
-  int ahead = 2;
+  int ahead = 1;
   std::mutex mu;
   std::condition_variable cv;  // every change of state: submissions, completions, releases
   std::deque<uint64_t> admit_q;
@@ -363,7 +363,7 @@ extern "C" {
 void tt_server_default_params(tt_server_params* p) {
   if (!p) return;
   p->hbm_budget_bytes = 0;
-  p->max_rounds_ahead = 2;
+  p->max_rounds_ahead = 1;
 }
 
 int tt_server_create(const tt_server_params* p, void* hip_stream, tt_server** out) {
@@ -376,7 +376,7 @@ int tt_server_create(const tt_server_params* p, void* hip_stream, tt_server** ou
     return TT_EDEVICE;
   }
   sv->budget = p->hbm_budget_bytes;
-  sv->ahead = p->max_rounds_ahead ? p->max_rounds_ahead : 2;
+  sv->ahead = p->max_rounds_ahead ? p->max_rounds_ahead : 1;
   if (hip_stream) {
     sv->st = static_cast<hipStream_t>(hip_stream);
   } else {

@@ -389,7 +389,7 @@ class Server:
     """Many streams on one GPU (tt_server_*): streams admitted against one HBM budget, their frames
     batched at LM-iteration boundaries by the library's scheduler thread."""
 
-    def __init__(self, hbm_budget_bytes=0, max_rounds_ahead=2, hip_stream=None):
+    def __init__(self, hbm_budget_bytes=0, max_rounds_ahead=1, hip_stream=None):
         p = ServerParams()
         lib().tt_server_default_params(C.byref(p))
         p.hbm_budget_bytes = int(hbm_budget_bytes)
