@@ -223,10 +223,17 @@ def test_sequence_teacher_forced(O, T):
     sc = synth.make_small_sequence(seed=11, M=2500, N=45, K1=300, width=160, height=120, n_frames=3,
                                    max_step_mm=3.0)
     so, sg = _pair(O, T, sc, seed=5)
+    # a second oracle stream evaluates the normal equations at the teacher-forced state with the GPU's
+    # ARAP weight (which depends on every data weight, so one changed pixel shifts it slightly)
+    sr = O.Stream(_params(O, num_control_points=sc.num_control_points, seed=5), _intr(O, sc.intr))
+    sr.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    knn = sr.template_info()["knn_pts"]
+    N = sc.num_control_points
     for t in range(1, 4):
         fr = sc.frame(t)
         dq, f = so.get_state()
         sg.set_state(dq, f)
+        sr.set_state(dq, f)
         vo, qo, do = so.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
         vg, qg, dg = sg.track_frame(fr.depth, fr.feat_xyz, fr.feat_desc, debug=True)
         print(f"frame {t}: rms {_rms(vo, vg):.2e} mm, truth rms gpu {_rms(vg, fr.gt_vertices):.3f}", flush=True)
@@ -240,6 +247,26 @@ def test_sequence_teacher_forced(O, T):
         assert same.mean() > 0.995, same.mean()
         ea = np.linalg.norm(do["A0"] - dg["A0"]) / np.linalg.norm(do["A0"])
         assert ea < 1e-4, ea
+        # what is unique: every 6 x 6 block and node gradient that no changed pixel touches, against
+        # the oracle's assembly at the same state with the same ARAP weight, at the 1e-5 bar
+        sr.frame_begin(fr.depth, fr.feat_xyz, fr.feat_desc)
+        Ar, gr = sr.normal_equations(dq, w_arap=dg["w_arap"])
+        touched = np.zeros((N, N), bool)
+        for j in np.flatnonzero(~same):
+            nb = knn[j]
+            touched[np.ix_(nb, nb)] = True
+        tn = touched.any(axis=1)
+        Bo = Ar.reshape(N, 6, N, 6)
+        Bd = (dg["A0"] - Ar).reshape(N, 6, N, 6)
+        no = np.sqrt(np.einsum("iajb,iajb->ij", Bo, Bo))
+        nd = np.sqrt(np.einsum("iajb,iajb->ij", Bd, Bd))
+        wb = float(np.max(np.where(touched, 0.0, nd / (no + 1e-6 * np.max(np.diag(no))))))
+        gno = np.linalg.norm(gr.reshape(N, 6), axis=1)
+        gnd = np.linalg.norm((dg["g0"] - gr).reshape(N, 6), axis=1)
+        wn = float(np.max(np.where(tn, 0.0, gnd / (gno + 1e-2 * gno.max()))))
+        print(f"frame {t}: {int((~same).sum())} pixels changed, {int(touched.sum())} of {N * N} blocks touched; "
+              f"worst untouched block {wb:.2e}, node {wn:.2e}", flush=True)
+        assert wb < NE_TOL and wn < NE_TOL
         assert _rms(vo, vg) <= RMS_TOL_MM
 
 
