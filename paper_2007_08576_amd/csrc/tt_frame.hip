@@ -326,12 +326,15 @@ __global__ __launch_bounds__(kMatchThreads) void k_hamming(const uint4* __restri
 // seed + golden * (frame + 1).
 
 constexpr int kSampleThreads = 1024;
+constexpr int kSampleLds = 12288;  // usable matches kept in LDS for the shuffle (else it runs in memory)
 
 __global__ __launch_bounds__(kSampleThreads) void k_ransac_sample(const float4* __restrict__ o2, int K1, int R,
                                                                  unsigned long long seed, long long frame,
                                                                  int* __restrict__ ulist, int* __restrict__ refs) {
   __shared__ int scan[kSampleThreads];
   __shared__ int total;
+  __shared__ int lst[kSampleLds];
+  const bool in_lds = K1 <= kSampleLds;
   if (threadIdx.x == 0) total = 0;
   __syncthreads();
   for (int base = 0; base < K1; base += kSampleThreads) {
@@ -345,22 +348,28 @@ __global__ __launch_bounds__(kSampleThreads) void k_ransac_sample(const float4* 
       scan[threadIdx.x] += v;
       __syncthreads();
     }
-    if (f) ulist[total + scan[threadIdx.x] - 1] = k;
+    if (f) {
+      if (in_lds) lst[total + scan[threadIdx.x] - 1] = k;
+      else ulist[total + scan[threadIdx.x] - 1] = k;
+    }
     __syncthreads();
     if (threadIdx.x == 0) total += scan[kSampleThreads - 1];
     __syncthreads();
   }
+  // partial Fisher-Yates over the compacted list, one thread (the draws are sequential); in LDS when
+  // the list fits, so that the swaps are not memory round trips
   if (threadIdx.x == 0) {
+    int* L = in_lds ? lst : ulist;
     int Ku = total;
     int nh = R < Ku ? R : Ku;
     unsigned long long st = seed + 0x9E3779B97F4A7C15ULL * (unsigned long long)(frame + 1);
     for (int i = 0; i < nh; i++) {
       unsigned long long r = splitmix64_next(&st);
       int j = i + (int)(r % (unsigned long long)(Ku - i));
-      int t = ulist[i];
-      ulist[i] = ulist[j];
-      ulist[j] = t;
-      refs[i] = ulist[i];
+      int t = L[i];
+      L[i] = L[j];
+      L[j] = t;
+      refs[i] = L[i];
     }
     for (int i = nh; i < R; i++) refs[i] = -1;
   }
