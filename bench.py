@@ -417,6 +417,50 @@ def assembly_roofline(torch, tt, sc, dfr):
             "achieved_GBps": gbs, "frac_of_hbm_peak": gbs / 8000.0, "peak_GBps": 8000.0}
 
 
+def drift_study(args, torch, tt):
+    """Tracking over a long warm-started sequence: config 2's frames 1..F in order, each started from
+    the previous frame's warps (no reset, no teacher forcing), 10 LM iterations per frame, FP32 dense
+    solve; vertex RMS against the generator's ground truth per frame, summarised per 50 frames so
+    that a growing error would show. The frames are generated in worker processes."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    from paper_2007_08576_amd import synth
+    F = min(args.drift, 300)
+    t0 = time.time()
+    chunks = [list(range(a, min(a + 20, F + 1))) for a in range(1, F + 1, 20)]
+    with cf.ProcessPoolExecutor(max_workers=args.stress_workers, mp_context=mp.get_context("spawn")) as ex:
+        parts = list(ex.map(synth.config2_arrays, [2] * len(chunks), [300] * len(chunks), chunks))
+    frames = [f for part in parts for f in part]
+    sc = synth.make_config2(n_frames=300)
+    log(f"drift: {F} config-2 frames generated in {time.time() - t0:.1f} s")
+    intr = tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy)
+    s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=2), intr)
+    s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+    rms = []
+    t0 = time.perf_counter()
+    for k, (depth, fx, fd, gt) in enumerate(frames):
+        v = s.track_frame(depth, fx, fd)[0]
+        rms.append(float(np.sqrt(((v - gt) ** 2).sum(1).mean())))
+        if (k + 1) % 100 == 0:
+            log(f"  drift: frame {k + 1}, truth rms {rms[-1]:.3f} mm")
+    wall = time.perf_counter() - t0
+    s.destroy()
+    r = np.asarray(rms)
+    out = {"frames": F, "mean_truth_rms_mm": float(r.mean()), "p50_truth_rms_mm": float(np.percentile(r, 50)),
+           "p90_truth_rms_mm": float(np.percentile(r, 90)), "p99_truth_rms_mm": float(np.percentile(r, 99)),
+           "max_truth_rms_mm": float(r.max()), "max_at_frame": int(r.argmax()) + 1, "last_truth_rms_mm": float(r[-1]),
+           "first_10_truth_rms_mm": [round(float(x), 3) for x in r[:10]],
+           "mean_truth_rms_mm_per_50_frames": [round(float(r[i:i + 50].mean()), 3) for i in range(0, F, 50)],
+           "host_path_frames_per_s": F / wall,
+           "workload": "config2: N 400, M 30,000, K 2,000 (30% outliers), 640x480, max 15 mm per frame",
+           "note": ("frames tracked in order through the host-memory entry point, each warm-started from the "
+                    "previous frame's warps; vertex RMS against the generator's ground truth")}
+    log(f"drift over {F} frames: truth rms mean {out['mean_truth_rms_mm']:.3f} mm, p99 {out['p99_truth_rms_mm']:.3f}, "
+        f"max {out['max_truth_rms_mm']:.3f} (frame {out['max_at_frame']}), last {out['last_truth_rms_mm']:.3f}; "
+        f"per 50 frames {out['mean_truth_rms_mm_per_50_frames']}")
+    return out
+
+
 def solver_study(args, torch, tt, sc, frames, dframes):
     """The per-node solve (each control point's damped 6x6 diagonal block on its own, the literal
     reading of Sec. 2) and the sparse ARAP graph (8 nearest control points instead of Sec. 2.2's
@@ -682,6 +726,8 @@ def main():
     ap.add_argument("--orb-reps", type=int, default=50)
     ap.add_argument("--host", type=int, default=1, help="also time the host-memory entry point (0 = skip)")
     ap.add_argument("--host-steps", type=int, default=40)
+    ap.add_argument("--drift", type=int, default=300,
+                    help="frames of config 2 tracked in order for the drift study (0 = skip; at most 300)")
     ap.add_argument("--precision-steps", type=int, default=10)
     ap.add_argument("--precision-config3", type=int, default=1)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -894,6 +940,8 @@ def main():
         out["solver_forms"] = solver_study(args, torch, tt, sc, frames, dframes)
     if args.orb:
         out["orb_front_end"] = orb_bench(args, torch, tt, sc)
+    if args.drift:
+        out["drift"] = drift_study(args, torch, tt)
     print(json.dumps(out), flush=True)
     _copy_calibration(args, torch)
 

@@ -569,6 +569,13 @@ def config5_arrays(seed: int, q: int, n_frames: int):
     return spec, [(f.depth, f.feat_xyz, f.feat_desc) for f in frs], sum(f.stressed for f in frs)
 
 
+def config2_arrays(seed: int, n_frames: int, ts):
+    """Frames ts of make_config2(seed, n_frames) as plain arrays (depth, feat_xyz, feat_desc,
+    gt_vertices). For generating a long sequence in worker processes."""
+    sc = make_config2(seed=seed, n_frames=n_frames)
+    return [(f.depth, f.feat_xyz, f.feat_desc, f.gt_vertices) for f in (sc.frame(t) for t in ts)]
+
+
 def make_config5(seed: int = 5, n_streams: int = 64, n_frames: int = 300):
     """Stress serving (config 5): n_streams streams from config5_stream."""
     return [config5_stream(seed, q, n_frames) for q in range(n_streams)]
