@@ -801,7 +801,7 @@ int tt_debug_cholesky_solve_ex(int n, const float* A, const float* b, float* x, 
              al((void**)&d.dscale, sizeof(float) * d.npad);
   if (okm && precision != TT_FP32)
     okm = al((void**)&d.A16, sizeof(uint16_t) * rows * d.ld) && al((void**)&d.A0, sizeof(float) * d.npad * d.ld) &&
-          al((void**)&d.cvec, sizeof(float) * d.npad) && al((void**)&d.xd, sizeof(double) * d.npad);
+          al((void**)&d.cvec, sizeof(float) * d.npad) && al((void**)&d.xd, sizeof(double) * ir_xd_count(d.npad, d.nb));
   if (!okm) {
     rc = TT_ENOMEM;
   } else {
@@ -995,7 +995,7 @@ int tt_set_template(tt_stream* s, const float* pts_xyz, int M, const float* feat
     ALLOC(allocs_template, bytes_template, d.A16, (size_t)(d.npad + TT_NB) * d.ld);
     ALLOC(allocs_template, bytes_template, d.A0, (size_t)d.npad * d.ld);
     ALLOC(allocs_template, bytes_template, d.cvec, (size_t)d.npad);
-    ALLOC(allocs_template, bytes_template, d.xd, (size_t)d.npad);
+    ALLOC(allocs_template, bytes_template, d.xd, ir_xd_count(d.npad, d.nb));
   }
   ALLOC(allocs_template, bytes_template, d.dscale, (size_t)d.npad);
   d.npartial = partial_count(M, K1, N) + 8;

@@ -58,6 +58,9 @@ __device__ __forceinline__ void publish_flag(int* f, int v) {
 constexpr int NB = TT_NB;
 constexpr int LDS_LD = NB + 2;  // conflict-free for the 16 x 4 MFMA operand reads
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+// Eight 16-bit values as a native vector: copies of it are plain register moves (HIP's uint4 is a
+// struct copied by memcpy, which keeps arrays of it in private memory).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 #define MFMA16(a, b, c) __builtin_amdgcn_mfma_f32_16x16x4f32((a), (b), (c), 0, 0, 0)
 
@@ -612,6 +615,68 @@ __device__ int block_ready_prefix(const int* fi, const int* fc, int k0, int nk, 
   return *s_val;
 }
 
+// Operand tiles of one column k of a tile task in registers: rows of block i and of block c.
+struct Stage32 {
+  float4 v[4];
+};
+struct Stage16 {
+  u32x4 v[2];
+};
+
+// acc += sum over the finished columns k < nk of the tile task's products, in column order. The
+// operand tiles of the next two columns are in flight (two register stages, column k in stage
+// k mod 2) while the product of column k runs, so a column costs one memory latency only every
+// other step. A column is loaded only once both its tiles are known to be final (flags seen,
+// then acquired); one that is not yet known is waited for after the product before it. load(k,
+// a, b) issues column k's tiles into a stage, to_lds(a, b) moves a stage into the operand tiles
+// in LDS, mma() runs the product. Returns false if the solve was aborted while waiting.
+template <class T, class Load, class ToLds, class Mma>
+__device__ __forceinline__ bool accumulate_columns(int nk, const int* fi, const int* fc, int epoch, const CholSync& S,
+                                                   LMScalars* sc, uint64_t wt, int* s_val, Load load, ToLds to_lds,
+                                                   Mma mma) {
+  int kr = block_ready_prefix(fi, fc, 0, nk, epoch, S, sc, wt, s_val);  // columns < kr are known final
+  if (kr == 0) return false;
+  T a0, b0, a1, b1;
+  load(0, a0, b0);
+  int issued = 1;  // columns < issued are loaded or in flight
+  if (nk > 1 && kr > 1) {
+    load(1, a1, b1);
+    issued = 2;
+  }
+  // issued, kr and nk are the same in every thread, so every barrier below is reached by all
+  auto step = [&](int k, T& ca, T& cb, T& oa, T& ob) -> bool {
+    __syncthreads();
+    to_lds(ca, cb);
+    __syncthreads();
+    if (issued == k + 1 && k + 1 < nk && k + 1 < kr) {
+      load(k + 1, oa, ob);
+      issued = k + 2;
+    }
+    if (issued == k + 2 && k + 2 < nk && k + 2 < kr) {
+      load(k + 2, ca, cb);
+      issued = k + 3;
+    }
+    mma();
+    if (issued == k + 1 && k + 1 < nk) {
+      const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, sc, wt, s_val);
+      if (more == 0) return false;
+      kr = k + 1 + more;
+      load(k + 1, oa, ob);
+      issued = k + 2;
+      if (k + 2 < nk && k + 2 < kr) {
+        load(k + 2, ca, cb);
+        issued = k + 3;
+      }
+    }
+    return true;
+  };
+  for (int k = 0; k < nk; k += 2) {
+    if (!step(k, a0, b0, a1, b1)) return false;
+    if (k + 1 < nk && !step(k + 1, a1, b1, a0, b0)) return false;
+  }
+  return true;
+}
+
 // All stores of the block complete, then thread 0 raises the flag.
 __device__ __forceinline__ void block_publish(int* f, int epoch) {
   __builtin_amdgcn_s_waitcnt(0);
@@ -740,18 +805,18 @@ __device__ __forceinline__ void acc_store16(uint16_t* __restrict__ A16, int ld, 
 }
 
 // 64 x 64 16-bit tile at (r0, c0) into registers (two 16-byte pieces per thread) and into LDS.
-__device__ __forceinline__ void tile_load16(const uint16_t* __restrict__ M, int ld, size_t r0, size_t c0, uint4 v[2]) {
+__device__ __forceinline__ void tile_load16(const uint16_t* __restrict__ M, int ld, size_t r0, size_t c0, u32x4 v[2]) {
 #pragma unroll
   for (int q = 0; q < 2; q++) {
     const int e = threadIdx.x + 256 * q;  // 512 pieces of 8 elements: row e / 8, columns 8 (e % 8)
-    v[q] = *reinterpret_cast<const uint4*>(M + (r0 + (e >> 3)) * ld + c0 + 8 * (e & 7));
+    v[q] = *reinterpret_cast<const u32x4*>(M + (r0 + (e >> 3)) * ld + c0 + 8 * (e & 7));
   }
 }
-__device__ __forceinline__ void tile16_to_lds(uint16_t* X, const uint4 v[2]) {
+__device__ __forceinline__ void tile16_to_lds(uint16_t* X, const u32x4 v[2]) {
 #pragma unroll
   for (int q = 0; q < 2; q++) {
     const int e = threadIdx.x + 256 * q;
-    *reinterpret_cast<uint4*>(X + (e >> 3) * LD16 + 8 * (e & 7)) = v[q];
+    *reinterpret_cast<u32x4*>(X + (e >> 3) * LD16 + 8 * (e & 7)) = v[q];
   }
 }
 
@@ -764,11 +829,11 @@ __device__ __forceinline__ void mma64_acc16(const uint16_t* X, const uint16_t* Y
   const int li = lane % 16, k8 = 8 * (lane / 16);
 #pragma unroll
   for (int s = 0; s < 2; s++) {
-    uint4 av[2], bv[2];
+    u32x4 av[2], bv[2];
 #pragma unroll
-    for (int a = 0; a < 2; a++) av[a] = *reinterpret_cast<const uint4*>(X + (qr + 16 * a + li) * LD16 + 32 * s + k8);
+    for (int a = 0; a < 2; a++) av[a] = *reinterpret_cast<const u32x4*>(X + (qr + 16 * a + li) * LD16 + 32 * s + k8);
 #pragma unroll
-    for (int b = 0; b < 2; b++) bv[b] = *reinterpret_cast<const uint4*>(Y + (qc + 16 * b + li) * LD16 + 32 * s + k8);
+    for (int b = 0; b < 2; b++) bv[b] = *reinterpret_cast<const u32x4*>(Y + (qc + 16 * b + li) * LD16 + 32 * s + k8);
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
@@ -1157,71 +1222,35 @@ __global__ __launch_bounds__(256) void k_chol_dataflow(const CholBatch B) {
     const int* fc = S.fin + (size_t)c * nb;
     bool ok = true;
     if (nk > 0 && P.prec != TT_FP32) {
-      // 16-bit operand tiles (half the bytes), one step ahead in registers
+      // 16-bit operand tiles (half the bytes)
       uint16_t* X16 = reinterpret_cast<uint16_t*>(&X[0][0]);
       uint16_t* Y16 = reinterpret_cast<uint16_t*>(&Y[0][0]);
-      int kr = block_ready_prefix(fi, fc, 0, nk, epoch, S, P.sc, wt, &s_val);
-      ok = kr > 0;
-      uint4 va[2], vb[2];
-      if (ok) {
-        tile_load16(P.A16, ld, ri, 0, va);
-        if (!same) tile_load16(P.A16, ld, rc, 0, vb);
-      }
-      for (int k = 0; ok && k < nk; k++) {
-        __syncthreads();
-        tile16_to_lds(X16, va);
-        if (!same) tile16_to_lds(Y16, vb);
-        __syncthreads();
-        // the next column's loads overlap this product if it is known final; otherwise the
-        // product runs first and the wait follows
-        const bool next = k + 1 < nk, known = k + 1 < kr;
-        if (next && known) {
-          tile_load16(P.A16, ld, ri, (size_t)NB * (k + 1), va);
-          if (!same) tile_load16(P.A16, ld, rc, (size_t)NB * (k + 1), vb);
-        }
-        mma64_acc16(X16, same ? X16 : Y16, acc, P.prec);
-        if (next && !known) {
-          const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, P.sc, wt, &s_val);
-          if (more == 0) {
-            ok = false;
-            break;
-          }
-          kr = k + 1 + more;
-          tile_load16(P.A16, ld, ri, (size_t)NB * (k + 1), va);
-          if (!same) tile_load16(P.A16, ld, rc, (size_t)NB * (k + 1), vb);
-        }
-      }
+      ok = accumulate_columns<Stage16>(
+          nk, fi, fc, epoch, S, P.sc, wt, &s_val,
+          [&](int k, Stage16& a, Stage16& b) {
+            tile_load16(P.A16, ld, ri, (size_t)NB * k, a.v);
+            if (!same) tile_load16(P.A16, ld, rc, (size_t)NB * k, b.v);
+          },
+          [&](const Stage16& a, const Stage16& b) {
+            tile16_to_lds(X16, a.v);
+            if (!same) tile16_to_lds(Y16, b.v);
+          },
+          [&]() { mma64_acc16(X16, same ? X16 : Y16, acc, P.prec); });
     } else if (nk > 0) {
-      int kr = block_ready_prefix(fi, fc, 0, nk, epoch, S, P.sc, wt, &s_val);
-      ok = kr > 0;
-      float4 va[4], vb[4];
-      if (ok) {
-        tile_load(P.A, ld, ri, 0, va);
-        if (!same) tile_load(P.A, ld, rc, 0, vb);
-      }
-      for (int k = 0; ok && k < nk; k++) {
-        __syncthreads();
-        tile_to_lds(X, va);
-        if (!same) tile_to_lds(Y, vb);
-        __syncthreads();
-        const bool next = k + 1 < nk, known = k + 1 < kr;
-        if (next && known) {
-          tile_load(P.A, ld, ri, (size_t)NB * (k + 1), va);
-          if (!same) tile_load(P.A, ld, rc, (size_t)NB * (k + 1), vb);
-        }
-        if (same) mma64_acc(X, X, acc);
-        else mma64_acc(X, Y, acc);
-        if (next && !known) {
-          const int more = block_ready_prefix(fi, fc, k + 1, nk, epoch, S, P.sc, wt, &s_val);
-          if (more == 0) {
-            ok = false;
-            break;
-          }
-          kr = k + 1 + more;
-          tile_load(P.A, ld, ri, (size_t)NB * (k + 1), va);
-          if (!same) tile_load(P.A, ld, rc, (size_t)NB * (k + 1), vb);
-        }
-      }
+      ok = accumulate_columns<Stage32>(
+          nk, fi, fc, epoch, S, P.sc, wt, &s_val,
+          [&](int k, Stage32& a, Stage32& b) {
+            tile_load(P.A, ld, ri, (size_t)NB * k, a.v);
+            if (!same) tile_load(P.A, ld, rc, (size_t)NB * k, b.v);
+          },
+          [&](const Stage32& a, const Stage32& b) {
+            tile_to_lds(X, a.v);
+            if (!same) tile_to_lds(Y, b.v);
+          },
+          [&]() {
+            if (same) mma64_acc(X, X, acc);
+            else mma64_acc(X, Y, acc);
+          });
     }
     if (!ok) continue;
     if (kind == TASK_SUBP) {
@@ -1417,35 +1446,89 @@ __global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
 }
 
 // Refinement residual of the equilibrated system, r = c - D A0 D xd, formed in FP64 from the FP32
-// damped matrix A0 (lower triangle) and the FP64 solution; written (rounded to FP32) into the
-// right-hand-side row. One workgroup per block of 64 rows; thread (r, g) sums columns 16 g .. 16 g + 15
-// of every column block.
-__global__ __launch_bounds__(256) void k_ir_resid(const BackBatch B) {
-  __shared__ double part[4][NB];
+// damped matrix A0 (lower triangle) and the FP64 solution, in two launches. k_ir_resid_tiles: one
+// workgroup per lower-triangle tile (i, k), k <= i, which it reads once: its row sums against
+// (D xd) of block k are the part of block row i from block column k, and for k < i its column sums
+// against (D xd) of block i are the part of block row k from block column i (the diagonal tile
+// mirrors its lower triangle). Each part is stored in FP64 after the solution, at
+// xd[npad + (row block * nb + column block) * 64 + row]. k_ir_resid_sum: block row i adds its nb
+// parts in column order (the same order on every run) and writes r, rounded to FP32, into the
+// right-hand-side row.
+__device__ __forceinline__ int lower_tile_system(const BackBatch& B, int& t) {
+  int q = 0;
+  for (;;) {
+    const int nb = B.p[q].nb, nt = nb * (nb + 1) / 2;
+    if (t < nt || q + 1 >= B.nprob) return q;
+    t -= nt;
+    q++;
+  }
+}
+__device__ __forceinline__ void lower_tile_of(int t, int& i, int& k) {  // t = i (i + 1) / 2 + k, k <= i
+  i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) i++;
+  while (i * (i + 1) / 2 > t) i--;
+  k = t - i * (i + 1) / 2;
+}
+
+__global__ __launch_bounds__(256) void k_ir_resid_tiles(const BackBatch B) {
+  __shared__ float T[NB][NB + 1];
+  __shared__ double xr[NB], xc[NB];
+  int t = (int)blockIdx.x;
+  const CholArgs& P = B.p[lower_tile_system(B, t)];
+  const int ld = P.ld, nb = P.nb, tid = threadIdx.x;
+  int i, k;
+  lower_tile_of(t, i, k);
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int e = tid + 256 * u, r = e >> 4, c = 4 * (e & 15);
+    const float4 v = *reinterpret_cast<const float4*>(P.A0 + (size_t)(NB * i + r) * ld + NB * k + c);
+    T[r][c] = v.x;
+    T[r][c + 1] = v.y;
+    T[r][c + 2] = v.z;
+    T[r][c + 3] = v.w;
+  }
+  if (tid < NB) xc[tid] = (double)P.dscale[NB * k + tid] * P.xd[NB * k + tid];
+  else if (tid < 2 * NB) xr[tid - NB] = (double)P.dscale[NB * i + tid - NB] * P.xd[NB * i + tid - NB];
+  __syncthreads();
+  double* part = P.xd + P.npad;
+  if (tid < NB) {
+    const int r = tid;
+    double acc = 0.0;
+    for (int c = 0; c < NB; c++) acc += (double)((i != k || c <= r) ? T[r][c] : T[c][r]) * xc[c];
+    part[((size_t)i * nb + k) * NB + r] = acc;
+  } else if (tid < 2 * NB && i != k) {
+    const int c = tid - NB;
+    double acc = 0.0;
+    for (int r = 0; r < NB; r++) acc += (double)T[r][c] * xr[r];
+    part[((size_t)k * nb + i) * NB + c] = acc;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_ir_resid_sum(const BackBatch B) {
   int q = 0;
   while (q + 1 < B.nprob && (int)blockIdx.x >= B.wg0[q + 1]) q++;
   const CholArgs& P = B.p[q];
-  const int ld = P.ld, nb = P.nb;
-  const int ib = (int)blockIdx.x - B.wg0[q];
-  const int r = threadIdx.x % NB, g = threadIdx.x / NB;
-  const size_t gi = (size_t)NB * ib + r;
+  const int nb = P.nb, i = (int)blockIdx.x - B.wg0[q], r = threadIdx.x;
+  const double* part = P.xd + P.npad + (size_t)i * nb * NB;
   double acc = 0.0;
-  for (int jb = 0; jb < nb; jb++) {
-#pragma unroll 4
-    for (int cc = 0; cc < 16; cc++) {
-      const int col = 16 * g + cc;
-      const size_t gj = (size_t)NB * jb + col;
-      const bool lower = (jb < ib) || (jb == ib && col <= r);
-      const float a = lower ? P.A0[gi * ld + gj] : P.A0[gj * ld + gi];
-      acc += (double)a * ((double)P.dscale[gj] * P.xd[gj]);
-    }
-  }
-  part[g][r] = acc;
-  __syncthreads();
-  if (g == 0) {
-    const double sr = part[0][r] + part[1][r] + part[2][r] + part[3][r];
-    const double res = (double)P.c[gi] - (double)P.dscale[gi] * sr;
-    P.A[(size_t)P.npad * ld + gi] = (float)res;
+#pragma unroll 8
+  for (int k = 0; k < nb; k++) acc += part[(size_t)k * NB + r];
+  const size_t gi = (size_t)NB * i + r;
+  P.A[(size_t)P.npad * P.ld + gi] = (float)((double)P.c[gi] - (double)P.dscale[gi] * acc);
+}
+
+// A0 = the lower-triangle tiles of the damped matrix A (the only part the residual reads), before
+// the factorisation overwrites them; one workgroup per tile.
+__global__ __launch_bounds__(256) void k_ir_copy_lower(const BackBatch B) {
+  int t = (int)blockIdx.x;
+  const CholArgs& P = B.p[lower_tile_system(B, t)];
+  int i, k;
+  lower_tile_of(t, i, k);
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int e = threadIdx.x + 256 * u, r = e >> 4, c = 4 * (e & 15);
+    const size_t o = (size_t)(NB * i + r) * P.ld + NB * k + c;
+    *reinterpret_cast<float4*>(const_cast<float*>(P.A0) + o) = *reinterpret_cast<const float4*>(P.A + o);
   }
 }
 
@@ -1548,15 +1631,25 @@ hipError_t launch_cholesky_backsolve(DevState& d, int which, hipStream_t st) {
   return launch_cholesky_backsolve_batch(ds, which, 1, st);
 }
 
+static int lower_tiles(const BackBatch& B) {
+  int n = 0;
+  for (int q = 0; q < B.nprob; q++) n += B.p[q].nb * (B.p[q].nb + 1) / 2;
+  return n;
+}
+
 hipError_t launch_ir_prepare(DevState& d, hipStream_t st) {
-  hipError_t e = hipMemcpyAsync(d.A0, d.A, sizeof(float) * (size_t)d.npad * d.ld, hipMemcpyDeviceToDevice, st);
+  DevState* ds[1] = {&d};
+  hipError_t e = launch_rows_batch(ds, 0, 1, [&](const BackBatch& B) {
+    hipLaunchKernelGGL(k_ir_copy_lower, dim3(lower_tiles(B)), dim3(256), 0, st, B);
+  });
   if (e != hipSuccess) return e;
   return hipMemcpyAsync(d.cvec, d.A + (size_t)d.npad * d.ld, sizeof(float) * d.npad, hipMemcpyDeviceToDevice, st);
 }
 
 hipError_t launch_ir_step_batch(DevState* const* ds, int step, int S, hipStream_t st) {
   hipError_t e = launch_rows_batch(ds, 0, S, [&](const BackBatch& B) {
-    hipLaunchKernelGGL(k_ir_resid, dim3(B.wg0[B.nprob]), dim3(256), 0, st, B);
+    hipLaunchKernelGGL(k_ir_resid_tiles, dim3(lower_tiles(B)), dim3(256), 0, st, B);
+    hipLaunchKernelGGL(k_ir_resid_sum, dim3(B.wg0[B.nprob]), dim3(64), 0, st, B);
   });
   if (e != hipSuccess) return e;
   e = launch_rows_batch(ds, 1 + 2 * step, S, [&](const BackBatch& B) {

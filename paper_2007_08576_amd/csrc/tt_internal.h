@@ -146,7 +146,8 @@ struct DevState {
   uint16_t* A16 = nullptr;   // 16-bit copies of the finished L tiles [(npad + 64) * ld]
   float* A0 = nullptr;       // damped matrix before factorisation [npad * ld] (refinement)
   float* cvec = nullptr;     // equilibrated right-hand side [npad] (refinement)
-  double* xd = nullptr;      // FP64 solution of the refinement [npad]
+  double* xd = nullptr;      // FP64 solution of the refinement [npad], then the residual's partial sums
+                             // [nb * nb * 64] (ir_xd_count)
   uint64_t* tw = nullptr;    // [npad] tagged entries (epoch << 32 | float) of a running substitution
   double* partial = nullptr; // reduction partials
   int npartial = 0;
@@ -260,6 +261,8 @@ hipError_t launch_cholesky_backsolve_batch(DevState* const* ds, int which, int S
 // Refinement (16-bit forms): keep the damped matrix and right-hand side before the factorisation;
 // xd = x (mode 0) or xd += x, x = xd (mode 1); refinement step `step` (0, 1, ...) = FP64 residual,
 // forward and back substitution, accumulation.
+// doubles of the refinement's xd buffer: the solution and the residual's per-tile partial sums
+inline size_t ir_xd_count(int npad, int nb) { return (size_t)npad + (size_t)nb * nb * TT_NB; }
 hipError_t launch_ir_prepare(DevState& d, hipStream_t st);
 hipError_t launch_ir_accum_batch(DevState* const* ds, int S, int mode, hipStream_t st);
 hipError_t launch_ir_step_batch(DevState* const* ds, int step, int S, hipStream_t st);

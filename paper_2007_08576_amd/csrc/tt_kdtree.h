@@ -29,35 +29,37 @@ __device__ __forceinline__ float kd_d2(float4 p, float vx, float vy, float vz) {
   return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
 }
 
+// Positions [lo, hi) covered by node (depth d): the halvings from the root along its bits.
+__device__ __forceinline__ void kd_range(int node, int d, int P, int& lo, int& hi) {
+  lo = 0;
+  hi = P;
+  for (int s = d - 1; s >= 0; s--) {
+    const int mid = lo + (hi - lo) / 2;
+    if ((node >> s) & 1) lo = mid;
+    else hi = mid;
+  }
+}
+
 // Pixel of the nearest point by float32 squared distance (ties: the lower pixel index), -1 if the
 // frame has no point. Depth-first, near child first; a far child is visited unless its split gap
-// squared exceeds the best distance so far (equal gaps are visited, for the tie rule).
+// squared exceeds the best distance so far (equal gaps are visited, for the tie rule). No stack:
+// after a leaf the search climbs to the nearest ancestor that it left through its near child and
+// whose far child is not pruned (the gap is recomputed from the split), and descends there, which
+// visits the far children deepest first, as a stack would.
 __device__ __forceinline__ int kd_nearest(const KdArgs& kd, float vx, float vy, float vz) {
   const int P = *kd.count;
   if (P <= 0) return -1;
-  struct Entry {
-    int lo, hi, node, depth;
-    float gap2;
-  };
-  Entry stack[32];  // at most one pending far child per depth (levels <= 28)
-  int sp = 0;
   float best = __builtin_huge_valf();
   int bpix = 0x7fffffff;
-  stack[sp++] = Entry{0, P, 1, 0, 0.0f};
-  while (sp > 0) {
-    const Entry e = stack[--sp];
-    if (e.gap2 > best) continue;
-    int lo = e.lo, hi = e.hi, node = e.node, depth = e.depth;
+  int node = 1, depth = 0, lo = 0, hi = P;
+  for (;;) {
     while (depth < kd.levels) {
       const int mid = lo + (hi - lo) / 2;
       const float diff = __fsub_rn((depth & 1) ? vy : vx, kd.split[node]);
-      const float g2 = __fmul_rn(diff, diff);
       if (diff < 0.0f) {  // near: the lower half
-        if (g2 <= best && mid < hi) stack[sp++] = Entry{mid, hi, 2 * node + 1, depth + 1, g2};
         hi = mid;
         node = 2 * node;
       } else {
-        if (g2 <= best && lo < mid) stack[sp++] = Entry{lo, mid, 2 * node, depth + 1, g2};
         lo = mid;
         node = 2 * node + 1;
       }
@@ -72,6 +74,29 @@ __device__ __forceinline__ int kd_nearest(const KdArgs& kd, float vx, float vy, 
         bpix = pix;
       }
     }
+    bool down = false;
+    while (!down && depth > 0) {
+      const int parent = node >> 1, pd = depth - 1;
+      const float diff = __fsub_rn((pd & 1) ? vy : vx, kd.split[parent]);
+      const int near = (diff < 0.0f) ? 2 * parent : 2 * parent + 1;
+      if (node == near && __fmul_rn(diff, diff) <= best) {
+        int plo, phi;
+        kd_range(parent, pd, P, plo, phi);
+        const int mid = plo + (phi - plo) / 2;
+        const int far = near ^ 1;
+        lo = (far & 1) ? mid : plo;
+        hi = (far & 1) ? phi : mid;
+        if (lo < hi) {
+          node = far;
+          depth = pd + 1;
+          down = true;
+          continue;
+        }
+      }
+      node = parent;
+      depth = pd;
+    }
+    if (!down) break;
   }
   return bpix == 0x7fffffff ? -1 : bpix;
 }
