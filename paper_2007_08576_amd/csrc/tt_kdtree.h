@@ -43,19 +43,24 @@ __device__ __forceinline__ void kd_range(int node, int d, int P, int& lo, int& h
 // Pixel of the nearest point by float32 squared distance (ties: the lower pixel index), -1 if the
 // frame has no point. Depth-first, near child first; a far child is visited unless its split gap
 // squared exceeds the best distance so far (equal gaps are visited, for the tie rule). No stack:
-// after a leaf the search climbs to the nearest ancestor that it left through its near child and
-// whose far child is not pruned (the gap is recomputed from the split), and descends there, which
-// visits the far children deepest first, as a stack would.
+// bit t of `pend` marks that the current path took the near child at depth t while the far child
+// is not empty and was not pruned when the path passed; after a leaf the search resumes at the
+// deepest marked depth (the gap is recomputed from the split and checked again, the far child's
+// range recomputed from its node index), which visits the far children deepest first, as a stack
+// of them would.
 __device__ __forceinline__ int kd_nearest(const KdArgs& kd, float vx, float vy, float vz) {
   const int P = *kd.count;
   if (P <= 0) return -1;
   float best = __builtin_huge_valf();
   int bpix = 0x7fffffff;
   int node = 1, depth = 0, lo = 0, hi = P;
+  uint32_t pend = 0;
   for (;;) {
     while (depth < kd.levels) {
       const int mid = lo + (hi - lo) / 2;
       const float diff = __fsub_rn((depth & 1) ? vy : vx, kd.split[node]);
+      const bool far_nonempty = (diff < 0.0f) ? (mid < hi) : (lo < mid);
+      if (far_nonempty && __fmul_rn(diff, diff) <= best) pend |= 1u << depth;
       if (diff < 0.0f) {  // near: the lower half
         hi = mid;
         node = 2 * node;
@@ -75,26 +80,21 @@ __device__ __forceinline__ int kd_nearest(const KdArgs& kd, float vx, float vy, 
       }
     }
     bool down = false;
-    while (!down && depth > 0) {
-      const int parent = node >> 1, pd = depth - 1;
-      const float diff = __fsub_rn((pd & 1) ? vy : vx, kd.split[parent]);
-      const int near = (diff < 0.0f) ? 2 * parent : 2 * parent + 1;
-      if (node == near && __fmul_rn(diff, diff) <= best) {
-        int plo, phi;
-        kd_range(parent, pd, P, plo, phi);
-        const int mid = plo + (phi - plo) / 2;
-        const int far = near ^ 1;
-        lo = (far & 1) ? mid : plo;
-        hi = (far & 1) ? phi : mid;
-        if (lo < hi) {
-          node = far;
-          depth = pd + 1;
-          down = true;
-          continue;
-        }
-      }
-      node = parent;
-      depth = pd;
+    while (pend != 0u && !down) {
+      const int t = 31 - __builtin_clz(pend);
+      pend &= ~(1u << t);
+      const int parent = node >> (depth - t);
+      const float diff = __fsub_rn((t & 1) ? vy : vx, kd.split[parent]);
+      if (__fmul_rn(diff, diff) > best) continue;
+      int plo, phi;
+      kd_range(parent, t, P, plo, phi);
+      const int mid = plo + (phi - plo) / 2;
+      const bool far_right = diff < 0.0f;  // the near child was the lower half
+      lo = far_right ? mid : plo;
+      hi = far_right ? phi : mid;
+      node = 2 * parent + (far_right ? 1 : 0);
+      depth = t + 1;
+      down = true;
     }
     if (!down) break;
   }
