@@ -1416,7 +1416,12 @@ __global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
   const int j = (int)blockIdx.x - B.wg0[q];
   const int c = threadIdx.x;
   const float rj = row[NB * j + c];
-  const float* Li = P.Linv + (size_t)j * NB * NB + (size_t)c * NB;  // row c of Linv_jj
+  // row c of Linv_jj, read before any wait (it is final when the launch starts), so that the last
+  // block step after the wait reads only registers and LDS
+  const float* Li = P.Linv + (size_t)j * NB * NB + (size_t)c * NB;
+  float lir[NB];
+#pragma unroll
+  for (int m = 0; m < NB; m++) lir[m] = Li[m];
   float acc = 0.0f;
   bool ok = true;
   for (int k = 0; k < j; k++) {
@@ -1436,7 +1441,7 @@ __global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
   __syncthreads();
   float y = 0.0f;
 #pragma unroll
-  for (int m = 0; m < NB; m++) y += Li[m] * rs[m];
+  for (int m = 0; m < NB; m++) y += lir[m] * rs[m];
   row[NB * j + c] = y;  // read by the back substitution, a later launch
   put_tagged(P.tw + NB * j + c, y, tag);
   if (!ok) {
