@@ -1375,7 +1375,9 @@ __global__ __launch_bounds__(64) void k_chol_backsolve(const BackBatch B) {
   float lic[NB];
 #pragma unroll
   for (int m = 0; m < NB; m++) lic[m] = Li[m * NB + c];
-  float acc = 0.0f;
+  // four partial sums (entries m = 4 i + t into acc[t]) keep the dependent chain after each wait
+  // short; they are added in a fixed order
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   bool ok = true;
   for (int k = nb - 1; k > j; k--) {
     // the tile column is final (written by the factorisation): fetch it before waiting
@@ -1385,14 +1387,15 @@ __global__ __launch_bounds__(64) void k_chol_backsolve(const BackBatch B) {
     xs[c] = wait_tagged(P.tw + NB * k + c, tag, ok);
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < NB; m++) acc += col[m] * xs[m];
+    for (int m = 0; m < NB; m++) acc[m & 3] += col[m] * xs[m];
     __syncthreads();
   }
-  rs[c] = y - acc;
+  rs[c] = y - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
   __syncthreads();
-  float s = 0.0f;
+  float sp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int m = 0; m < NB; m++) s += lic[m] * rs[m];
+  for (int m = 0; m < NB; m++) sp[m & 3] += lic[m] * rs[m];
+  const float s = (sp[0] + sp[1]) + (sp[2] + sp[3]);
   P.x[NB * j + c] = s;
   put_tagged(P.tw + NB * j + c, s, tag);
   if (!ok) {
@@ -1422,7 +1425,7 @@ __global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
   float lir[NB];
 #pragma unroll
   for (int m = 0; m < NB; m++) lir[m] = Li[m];
-  float acc = 0.0f;
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // partial sums as in the back substitution
   bool ok = true;
   for (int k = 0; k < j; k++) {
     // row c of L_jk is final (written by the factorisation): fetch it before waiting
@@ -1433,15 +1436,20 @@ __global__ __launch_bounds__(64) void k_chol_fwdsolve(const BackBatch B) {
     ys[c] = wait_tagged(P.tw + NB * k + c, tag, ok);
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < NB / 4; m++)
-      acc += lr[m].x * ys[4 * m] + lr[m].y * ys[4 * m + 1] + lr[m].z * ys[4 * m + 2] + lr[m].w * ys[4 * m + 3];
+    for (int m = 0; m < NB / 4; m++) {
+      acc[0] += lr[m].x * ys[4 * m];
+      acc[1] += lr[m].y * ys[4 * m + 1];
+      acc[2] += lr[m].z * ys[4 * m + 2];
+      acc[3] += lr[m].w * ys[4 * m + 3];
+    }
     __syncthreads();
   }
-  rs[c] = rj - acc;
+  rs[c] = rj - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
   __syncthreads();
-  float y = 0.0f;
+  float yp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int m = 0; m < NB; m++) y += lir[m] * rs[m];
+  for (int m = 0; m < NB; m++) yp[m & 3] += lir[m] * rs[m];
+  const float y = (yp[0] + yp[1]) + (yp[2] + yp[3]);
   row[NB * j + c] = y;  // read by the back substitution, a later launch
   put_tagged(P.tw + NB * j + c, y, tag);
   if (!ok) {
