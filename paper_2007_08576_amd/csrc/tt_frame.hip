@@ -409,6 +409,7 @@ __global__ __launch_bounds__(kHypThreads) void k_ransac_hyp(const float* __restr
   if (tid == 0) degenerate = 0;
   __syncthreads();
   int cnt = 0;  // this thread's matches with d_k <= H in the last w-step
+  double Vw[16];  // thread 0: the previous fit's eigenvector basis (the fits warm-start from it)
   for (int it = 0; it < iters; it++) {
     double c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = tid; k < K1; k += kHypThreads) {
@@ -434,7 +435,7 @@ __global__ __launch_bounds__(kHypThreads) void k_ransac_hyp(const float* __restr
     if (tid == 0) {
       double C[9], R[9];
       for (int e = 0; e < 9; e++) C[e] = red[e][0];
-      if (rotation_fit_horn(C, R)) degenerate = 1;
+      if (rotation_fit_horn(C, R, Vw, it > 0)) degenerate = 1;
       for (int e = 0; e < 9; e++) Rs[e] = R[e];
     }
     __syncthreads();

@@ -243,7 +243,12 @@ TT_HD void jacobi_sym(double* A, double* V) {
 // +-s1 +- s2 +- s3 (s_i the singular values of C, signs with the parity of det C), so with them
 // sorted decreasingly s1 = (l1 + l2) / 2 and s2 = (l1 + l3) / 2. Returns 1 when s2 >= 1e-9 s1
 // fails (rotation not fixed), with R = I.
-TT_HD int rotation_fit_horn(const double* C, double* R) {
+//
+// Vw (optional) carries an eigenvector basis from one fit to the next: when warm is set, N is first
+// rotated into that basis (N' = Vw^T N Vw), where a slowly changing N is nearly diagonal and the
+// sweeps stop after one or two, and the eigenvectors are rotated back; Vw then receives this fit's
+// basis. The eigenvalues and the rotation agree with a cold start to rounding.
+TT_HD int rotation_fit_horn(const double* C, double* R, double* Vw = nullptr, bool warm = false) {
   // S_xy = sum a_x b_y = C[y][x]
   double Sxx = C[0], Syx = C[1], Szx = C[2];
   double Sxy = C[3], Syy = C[4], Szy = C[5];
@@ -253,7 +258,29 @@ TT_HD int rotation_fit_horn(const double* C, double* R) {
                   Szx - Sxz,       Sxy + Syx,        -Sxx + Syy - Szz, Syz + Szy,
                   Sxy - Syx,       Szx + Sxz,        Syz + Szy,        -Sxx - Syy + Szz};
   double V[16];
-  jacobi_sym<4>(N, V);
+  if (Vw && warm) {
+    double T[16], Np[16], U[16];
+    for (int i = 0; i < 4; i++)  // T = N Vw
+      for (int j = 0; j < 4; j++)
+        T[i * 4 + j] = N[i * 4 + 0] * Vw[0 * 4 + j] + N[i * 4 + 1] * Vw[1 * 4 + j] + N[i * 4 + 2] * Vw[2 * 4 + j] +
+                       N[i * 4 + 3] * Vw[3 * 4 + j];
+    for (int i = 0; i < 4; i++)  // N' = Vw^T T
+      for (int j = 0; j < 4; j++)
+        Np[i * 4 + j] = Vw[0 * 4 + i] * T[0 * 4 + j] + Vw[1 * 4 + i] * T[1 * 4 + j] + Vw[2 * 4 + i] * T[2 * 4 + j] +
+                        Vw[3 * 4 + i] * T[3 * 4 + j];
+    for (int i = 0; i < 4; i++)  // symmetric to rounding; make it exactly so
+      for (int j = i + 1; j < 4; j++) Np[j * 4 + i] = Np[i * 4 + j];
+    jacobi_sym<4>(Np, U);
+    for (int i = 0; i < 4; i++)  // V = Vw U
+      for (int j = 0; j < 4; j++)
+        V[i * 4 + j] = Vw[i * 4 + 0] * U[0 * 4 + j] + Vw[i * 4 + 1] * U[1 * 4 + j] + Vw[i * 4 + 2] * U[2 * 4 + j] +
+                       Vw[i * 4 + 3] * U[3 * 4 + j];
+    for (int i = 0; i < 16; i++) N[i] = Np[i];
+  } else {
+    jacobi_sym<4>(N, V);
+  }
+  if (Vw)
+    for (int i = 0; i < 16; i++) Vw[i] = V[i];
   double l[4] = {N[0], N[5], N[10], N[15]};
   int best = 0;
   for (int i = 1; i < 4; i++)
