@@ -625,8 +625,8 @@ struct Stage16 {
 
 // acc += sum over the finished columns k < nk of the tile task's products, in column order. The
 // operand tiles of the next two columns are in flight (two register stages, column k in stage
-// k mod 2) while the product of column k runs, so a column costs one memory latency only every
-// other step. A column is loaded only once both its tiles are known to be final (flags seen,
+// k mod 2) while the product of column k runs, so a column's loads are issued two products before
+// it is needed. A column is loaded only once both its tiles are known to be final (flags seen,
 // then acquired); one that is not yet known is waited for after the product before it. load(k,
 // a, b) issues column k's tiles into a stage, to_lds(a, b) moves a stage into the operand tiles
 // in LDS, mma() runs the product. Returns false if the solve was aborted while waiting.
@@ -861,7 +861,8 @@ struct CholArgs {
   uint16_t* A16;     // 16-bit copies of the finished L tiles (same layout as A), or null
   const float* A0;   // refinement: the damped matrix before factorisation (lower triangle), or null
   const float* c;    // refinement: the equilibrated right-hand side
-  double* xd;        // refinement: the solution accumulated in FP64
+  double* xd;        // refinement: the solution accumulated in FP64 [npad], then the residual's
+                     // partial sums [nb][nb][64]
   uint64_t* tw;      // [npad] tagged solution entries exchanged inside a substitution
 };
 
