@@ -66,12 +66,18 @@ def cpu_baseline(sc, frame, lm_sample):
                        f"({t_front * 1e3:.0f} ms + 10 x {t_iter * 1e3:.0f} ms)"), verts
 
 
-def _streams_for(tt, scenes, precision, budget):
+def _ir_iters(args, precision):
+    """Refinement steps of the serving runs' mixed form (the library default for FP32, which has none)."""
+    return 2 if precision == 0 else args.mixed_ir_iters
+
+
+def _streams_for(tt, scenes, precision, budget, ir_iters=2):
     """Library streams for the scenes (templates set), admitted while the device bytes fit budget;
     returns the streams, the indices of the admitted scenes and the bytes used."""
     streams, idx, used = [], [], 0
     for i, sc in enumerate(scenes):
-        s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=4, precision=precision),
+        s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=4, precision=precision,
+                                        ir_iters=ir_iters),
                       tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy))
         s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
         b = s.device_bytes()
@@ -88,8 +94,8 @@ def _serving_compare(args, torch, tt, scenes, frames_np, order, hz_list, seconds
     """Plain per-stream path (each stream on its own HIP stream through tt_track_frame_device_ev, FP32)
     against whole-frame batches (tt_track_batch_device over every stream) and against the library's
     serving loop (tt_server_*: streams admitted under the HBM budget, frames batched at LM-iteration
-    boundaries), the last two in FP32 and in the mixed form (bfloat16 tile products + FP64-residual
-    refinement): frames/s at saturation, and each form's first-frame vertices against the plain FP32
+    boundaries), the last two in FP32 and in the mixed form (16-bit tile products + FP64-residual
+    refinement; binary16 with one step by default): frames/s at saturation, and each form's first-frame vertices against the plain FP32
     ones. Then Poisson-arrival runs through the serving loop (one per rate in hz_list, frames per
     second per stream; 0 = 70 % of the served saturation rate): latency is completion minus the
     scheduled arrival. frames_np[q] holds stream q's frames (depth, feat_xyz, feat_desc), replayed in
@@ -102,16 +108,17 @@ def _serving_compare(args, torch, tt, scenes, frames_np, order, hz_list, seconds
     budget = int(args.serving_hbm_gib * (1 << 30))
     res, first, used_bytes, poisson = {}, {}, {}, {}
     S = None
+    mixed = tt.TT_FP16_IR if args.mixed_precision == "fp16" else tt.TT_BF16_IR
     for name, prec, mode in (("plain", tt.TT_FP32, "plain"), ("batched_fp32", tt.TT_FP32, "batch"),
-                             ("batched_mixed", tt.TT_BF16_IR, "batch"), ("served_fp32", tt.TT_FP32, "serve"),
-                             ("served_mixed", tt.TT_BF16_IR, "serve")):
+                             ("batched_mixed", mixed, "batch"), ("served_fp32", tt.TT_FP32, "serve"),
+                             ("served_mixed", mixed, "serve")):
         if mode == "serve":
             sv = tt.Server(hbm_budget_bytes=budget)
             streams, idx = [], []
             for i, sc in enumerate(scenes):
                 try:
                     streams.append(sv.open(tt.default_params(num_control_points=sc.num_control_points, seed=4,
-                                                             precision=prec),
+                                                             precision=prec, ir_iters=_ir_iters(args, prec)),
                                            tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy,
                                                          sc.intr.cx, sc.intr.cy),
                                            sc.pts, sc.feat_xyz, sc.feat_desc,
@@ -122,7 +129,7 @@ def _serving_compare(args, torch, tt, scenes, frames_np, order, hz_list, seconds
                         raise
             used = sv.stats()["reserved_bytes"]
         else:
-            streams, idx, used = _streams_for(tt, scenes, prec, budget)
+            streams, idx, used = _streams_for(tt, scenes, prec, budget, _ir_iters(args, prec))
         S = len(streams)
         used_bytes[name] = used
         outs = [(torch.empty((scenes[i].pts.shape[0], 3), dtype=torch.float32, device=dev),
@@ -189,7 +196,8 @@ def _serving_compare(args, torch, tt, scenes, frames_np, order, hz_list, seconds
            "batched_mixed_over_plain": res["batched_mixed"] / res["plain"],
            "served_fp32_over_plain": res["served_fp32"] / res["plain"],
            "served_mixed_over_plain": res["served_mixed"] / res["plain"],
-           "mixed_form": "bf16 tile products, FP32 accumulation, 2 FP64-residual refinement steps",
+           "mixed_form": (f"{args.mixed_precision} tile products, FP32 accumulation, {args.mixed_ir_iters} "
+                          "FP64-residual refinement steps"),
            "mixed_vs_plain_fp32_max_stream_rms_mm": rms_vs_plain("batched_mixed"),
            "served_mixed_vs_plain_fp32_max_stream_rms_mm": rms_vs_plain("served_mixed"),
            "served_fp32_vs_plain_fp32_max_stream_rms_mm": rms_vs_plain("served_fp32"),
@@ -718,6 +726,10 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=6.0)
     ap.add_argument("--serving-hz", type=float, default=15.0)
     ap.add_argument("--serving-hbm-gib", type=float, default=200.0)
+    ap.add_argument("--mixed-ir-iters", type=int, default=1,
+                    help="refinement steps per solve of the serving runs' mixed form")
+    ap.add_argument("--mixed-precision", choices=("bf16", "fp16"), default="fp16",
+                    help="16-bit input type of the serving runs' mixed form")
     ap.add_argument("--stress", type=int, default=1, help="also run the config 5 stress serving mix (0 = skip)")
     ap.add_argument("--stress-streams", type=int, default=64)
     ap.add_argument("--stress-frames", type=int, default=5, help="frames per stress stream (replayed ping-pong)")
