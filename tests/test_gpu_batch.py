@@ -170,7 +170,8 @@ def test_fused_rows_arap_equals_separate(env, solver):
 
 def test_config4_mix_is_the_same_alone_concurrent_and_batched(env):
     """The 16-stream serving mix (control points 123-772, 320x240 to 640x480, 540-2,900
-    features), first two frames, in FP32 and in the bfloat16 form with refinement: each stream's
+    features), first two frames, in FP32, in the bfloat16 form with two refinement steps and in the
+    binary16 form with one (the serving runs' mixed form): each stream's
     vertices and warps are bit for bit the same when it is tracked alone (synchronised after every
     frame), when all streams are queued at once on their own HIP streams (their persistent
     factorisations then run side by side on the device), and in one batch. The smallest streams
@@ -182,10 +183,11 @@ def test_config4_mix_is_the_same_alone_concurrent_and_batched(env):
     frames = [[_dev_frame(torch, sc.frame(t), dev) for t in (1, 2)] for sc in scenes]
     S = len(scenes)
     first = {}
-    for prec in (tt.TT_FP32, tt.TT_BF16_IR):
+    for prec, ir in ((tt.TT_FP32, 2), (tt.TT_BF16_IR, 2), (tt.TT_FP16_IR, 1)):
         res = {}
         for mode in ("alone", "concurrent", "batch"):
-            streams = [tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=4, precision=prec),
+            streams = [tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=4, precision=prec,
+                                                   ir_iters=ir),
                                  tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx,
                                                sc.intr.cy)) for sc in scenes]
             for s, sc in zip(streams, scenes):
@@ -216,7 +218,7 @@ def test_config4_mix_is_the_same_alone_concurrent_and_batched(env):
                     assert np.isfinite(a[0]).all()
                     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), \
                         f"precision {prec}, {mode}: stream {q} (N={scenes[q].num_control_points}) differs at frame {t + 1}"
-        first[prec] = [res["alone"][0][q][0] for q in range(S)]
+        first[(prec, ir)] = [res["alone"][0][q][0] for q in range(S)]
     # the three streams with the fewest control points against the FP64 oracle, frame 1 from identity
     for q in sorted(range(S), key=lambda i: scenes[i].num_control_points)[:3]:
         sc = scenes[q]
