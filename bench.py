@@ -430,6 +430,86 @@ def assembly_roofline(torch, tt, sc, dfr):
             "achieved_GBps": gbs, "frac_of_hbm_peak": gbs / 8000.0, "peak_GBps": 8000.0}
 
 
+def _assembly_bytes(N, M, K):
+    """Algorithmic bytes of one LM iteration's assembly of one system (as in assembly_roofline)."""
+    n = 6 * N
+    return n * (n + 1) / 2 * 4 + n * 4 + M * (44 + 16) + N * 44 + K * 56
+
+
+def assembly_batched_run(args, torch, tt):
+    """Whole-frame batches of the config 4 or config 5 serving mix in FP32 (one warm frame, then
+    args.assembly_batched_frames), for a kernel trace from which --assembly-batched-summary takes the
+    assembly windows; returns each stream's sizes."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    from paper_2007_08576_amd import synth
+    cfg = args.assembly_batched
+    if cfg == 4:
+        scenes = synth.make_config4(seed=4, n_streams=args.serving_streams, n_frames=300)
+        frames_np = [[(f.depth, f.feat_xyz, f.feat_desc) for f in (sc.frame(t) for t in (1, 2))] for sc in scenes]
+    else:
+        with cf.ProcessPoolExecutor(max_workers=args.stress_workers, mp_context=mp.get_context("spawn")) as ex:
+            gen = list(ex.map(synth.config5_arrays, [5] * args.stress_streams, range(args.stress_streams),
+                              [2] * args.stress_streams))
+        scenes, frames_np = [g[0] for g in gen], [g[1] for g in gen]
+    dev = torch.device("cuda:0")
+    frames = [[tuple(torch.from_numpy(a).to(dev) for a in f) for f in fl] for fl in frames_np]
+    torch.cuda.synchronize()
+    streams, idx, _ = _streams_for(tt, scenes, tt.TT_FP32, int(args.serving_hbm_gib * (1 << 30)))
+    outs = [(torch.empty((scenes[i].pts.shape[0], 3), dtype=torch.float32, device=dev),
+             torch.empty((scenes[i].num_control_points, 8), dtype=torch.float32, device=dev)) for i in idx]
+    for k in range(1 + args.assembly_batched_frames):
+        tt.track_batch_device(streams, [(frames[i][k % 2][0], frames[i][k % 2][1], frames[i][k % 2][2],
+                                         frames[i][k % 2][1].shape[0], outs[q][0], outs[q][1])
+                                        for q, i in enumerate(idx)])
+        for s_ in streams:
+            s_.sync()
+    sizes = [{"N": scenes[i].num_control_points, "M": int(scenes[i].pts.shape[0]),
+              "K": int(frames_np[i][0][1].shape[0])} for i in idx]
+    for s_ in streams:
+        s_.destroy()
+    log(f"batched assembly run: config {cfg}, {len(idx)} streams, {1 + args.assembly_batched_frames} frames")
+    return {"config": cfg, "streams": sizes, "frames": 1 + args.assembly_batched_frames}
+
+
+def assembly_batched_summary(trace_csv, run_json, out_path, cmd):
+    """HBM fraction of the assembly phase of whole-frame batches from a rocprofv3 kernel trace of
+    `bench.py --assembly-batched C`: per LM round (the assembly kernels of every stream that run
+    before that round's factorisation), the algorithmic bytes of all streams' assemblies over the
+    round's window (first assembly kernel start to last assembly kernel end; kernels of other phases
+    that overlap it are counted in it). The first (warm) frame is left out."""
+    import csv
+    import re
+    run = json.loads(open(run_json).read().strip().splitlines()[-1])["assembly_batched"]
+    asm = ("k_rows_arap", "k_arap_assemble", "k_data_rows", "k_data_assemble")
+    rows = []
+    for r in csv.DictReader(open(trace_csv)):
+        k = re.sub(r"\(anonymous namespace\)::", "", r["Kernel_Name"]).replace("void ", "").split("(")[0].split("<")[0]
+        rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), k))
+    rows.sort()
+    rounds, cur = [], []
+    for st, en, k in rows:
+        if k in asm:
+            cur.append((st, en))
+        elif k == "k_chol_dataflow" and cur:
+            rounds.append((min(a for a, _ in cur), max(b for _, b in cur)))
+            cur = []
+    per_frame = 10  # LM iterations per frame
+    rounds = rounds[per_frame:]  # the warm frame
+    nbytes = sum(_assembly_bytes(x["N"], x["M"], x["K"]) for x in run["streams"])
+    us = [(b - a) / 1e3 for a, b in rounds]
+    gbs = [nbytes / (u * 1e-6) / 1e9 for u in us]
+    rec = {"config": run["config"], "streams": len(run["streams"]), "rounds": len(us),
+           "algorithmic_bytes_per_round": nbytes, "mean_window_us": float(np.mean(us)),
+           "mean_achieved_GBps": float(np.mean(gbs)), "frac_of_hbm_peak": float(np.mean(gbs)) / 8000.0,
+           "min_window_us": float(np.min(us)), "max_window_us": float(np.max(us)), "command": cmd,
+           "note": ("per LM round: all streams' rows, dense ARAP and data-block assemblies (algorithmic bytes "
+                    "as for one stream, summed) over the window from the first assembly kernel's start to "
+                    "the last one's end before the round's factorisation")}
+    open(out_path, "w").write(json.dumps(rec, indent=1) + "\n")
+    print(json.dumps(rec, indent=1))
+
+
 def drift_study(args, torch, tt):
     """Tracking over a long warm-started sequence: config 2's frames 1..F in order, each started from
     the previous frame's warps (no reset, no teacher forcing), 10 LM iterations per frame, FP32 dense
@@ -703,6 +783,9 @@ def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--pmc-summary":
         pmc_summary(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5])
         return
+    if len(sys.argv) > 1 and sys.argv[1] == "--assembly-batched-summary":
+        assembly_batched_summary(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--pmc-assembly-summary":
         pmc_assembly_summary(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6], sys.argv[7])
         return
@@ -716,6 +799,9 @@ def main():
                     help="run the library's autotuner (tt_autotune) on the first frame before the warm-up")
     ap.add_argument("--precision-only", type=int, default=0,
                     help="only config 3 in the FP32 then the BF16-IR form, two frames each (for the counter runs)")
+    ap.add_argument("--assembly-batched", type=int, default=0, choices=(0, 4, 5),
+                    help="only run whole-frame FP32 batches of the config 4 or 5 mix (for a kernel trace)")
+    ap.add_argument("--assembly-batched-frames", type=int, default=2)
     ap.add_argument("--assembly-only", type=int, default=0,
                     help="only the assembly roofline of configs 2 and 3 (for the counter runs); no headline line")
     ap.add_argument("--cpu-lm-sample", type=int, default=3)
@@ -782,6 +868,10 @@ def main():
             log(f"config3 {name}: {len(dfr3)} frames in {res[name]['seconds']:.3f} s")
         _copy_calibration(args, torch)
         print(json.dumps({"precision_config3": res}), flush=True)
+        return
+
+    if args.assembly_batched:
+        print(json.dumps({"assembly_batched": assembly_batched_run(args, torch, tt)}), flush=True)
         return
 
     if args.assembly_only:
