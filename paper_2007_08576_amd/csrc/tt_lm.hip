@@ -732,25 +732,39 @@ __global__ __launch_bounds__(kDataThreads) void k_data_assemble(const int2* __re
 __global__ __launch_bounds__(1024) void k_damp(float* __restrict__ A, const float* __restrict__ g, int n, int npad,
                                                int ld, float* __restrict__ dscale, const double* __restrict__ part,
                                                Parts P, LMScalars* sc) {
-  __shared__ float shm[1024];
-  __shared__ double shd[1024];
+  __shared__ float shm[16];
+  __shared__ double shd[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // the loads are independent, so the unrolled loops keep several in flight at once
   float m = 0.0f;
-  for (int k = threadIdx.x; k < n; k += 1024) m = fmaxf(m, A[(size_t)k * ld + k]);
-  shm[threadIdx.x] = m;
+#pragma unroll 4
+  for (int k = tid; k < n; k += 1024) m = fmaxf(m, A[(size_t)k * ld + k]);
   double e = 0.0;
-  for (int b = threadIdx.x; b < P.nbp; b += 1024) e += part[P.pts + 2 * b + 1];
-  for (int b = threadIdx.x; b < P.nbf; b += 1024) e += part[P.feat + 2 * b + 1];
-  for (int b = threadIdx.x; b < P.cdata - P.arap; b += 1024) e += part[P.arap + b];
-  shd[threadIdx.x] = e;
-  __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      shm[threadIdx.x] = fmaxf(shm[threadIdx.x], shm[threadIdx.x + s]);
-      shd[threadIdx.x] += shd[threadIdx.x + s];
-    }
-    __syncthreads();
+#pragma unroll 2
+  for (int b = tid; b < P.nbp; b += 1024) e += part[P.pts + 2 * b + 1];
+  for (int b = tid; b < P.nbf; b += 1024) e += part[P.feat + 2 * b + 1];
+#pragma unroll 2
+  for (int b = tid; b < P.cdata - P.arap; b += 1024) e += part[P.arap + b];
+  // within each wavefront by a butterfly, then the sixteen wavefront values in order (the same
+  // order on every run)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    m = fmaxf(m, __shfl_xor(m, off));
+    e += __shfl_xor(e, off);
   }
-  const float eps = 1e-12f * shm[0];
+  if (lane == 0) {
+    shm[wv] = m;
+    shd[wv] = e;
+  }
+  __syncthreads();
+  float mx = shm[0];
+  double es = shd[0];
+#pragma unroll
+  for (int q = 1; q < 16; q++) {
+    mx = fmaxf(mx, shm[q]);
+    es += shd[q];
+  }
+  const float eps = 1e-12f * mx;
   const float lam = (float)sc->lambda;
   for (int k = threadIdx.x; k < npad; k += 1024) {
     float d = 1.0f;
@@ -764,7 +778,7 @@ __global__ __launch_bounds__(1024) void k_damp(float* __restrict__ A, const floa
     A[(size_t)npad * ld + k] = (k < n) ? -g[k] * d : 0.0f;
   }
   if (threadIdx.x == 0) {
-    sc->e_old = shd[0];
+    sc->e_old = es;
     sc->eps = (double)eps;
     sc->chol_fail = 0;
     sc->solve_epoch = (sc->solve_epoch == 0x7FFFFFFF) ? 1 : sc->solve_epoch + 1;
