@@ -71,13 +71,15 @@ def _ir_iters(args, precision):
     return 2 if precision == 0 else args.mixed_ir_iters
 
 
-def _streams_for(tt, scenes, precision, budget, ir_iters=2):
+def _streams_for(tt, scenes, precision, budget, ir_iters=2, graph=1):
     """Library streams for the scenes (templates set), admitted while the device bytes fit budget;
-    returns the streams, the indices of the admitted scenes and the bytes used."""
+    returns the streams, the indices of the admitted scenes and the bytes used. graph = 1: each
+    frame's LM iterations replay as a graph (per stream, or per batch when every stream of a batch
+    asks for it)."""
     streams, idx, used = [], [], 0
     for i, sc in enumerate(scenes):
         s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=4, precision=precision,
-                                        ir_iters=ir_iters),
+                                        ir_iters=ir_iters, graph=graph),
                       tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy))
         s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
         b = s.device_bytes()
@@ -129,7 +131,7 @@ def _serving_compare(args, torch, tt, scenes, frames_np, order, hz_list, seconds
                         raise
             used = sv.stats()["reserved_bytes"]
         else:
-            streams, idx, used = _streams_for(tt, scenes, prec, budget, _ir_iters(args, prec))
+            streams, idx, used = _streams_for(tt, scenes, prec, budget, _ir_iters(args, prec), args.serving_graph)
         S = len(streams)
         used_bytes[name] = used
         outs = [(torch.empty((scenes[i].pts.shape[0], 3), dtype=torch.float32, device=dev),
@@ -812,6 +814,8 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=6.0)
     ap.add_argument("--serving-hz", type=float, default=15.0)
     ap.add_argument("--serving-hbm-gib", type=float, default=200.0)
+    ap.add_argument("--serving-graph", type=int, default=1,
+                    help="plain and batched serving forms replay each frame's LM iterations as graphs")
     ap.add_argument("--mixed-ir-iters", type=int, default=1,
                     help="refinement steps per solve of the serving runs' mixed form")
     ap.add_argument("--mixed-precision", choices=("bf16", "fp16"), default="fp16",

@@ -100,7 +100,8 @@ typedef struct {
   int graph;               /* 0 (default): the LM iterations of each frame are launched kernel by
                               kernel; 1: they are captured once per front-buffer parity into a HIP
                               graph and replayed on later frames (single-stream calls without
-                              debug taps or stage timers; the results are the same bit for bit) */
+                              debug taps or stage timers, and whole-frame batches whose streams
+                              all set it; the results are the same bit for bit)               */
   int assoc_kdtree;        /* 0 (default): projective association (Sec. 2's re-projection); 1: the
                               closest-point comparator the paper contrasts it with -- each deformed
                               template point corresponds to the nearest frame point in 3D (float32
@@ -210,8 +211,11 @@ typedef struct {
  * refinement of all S normal systems run on streams[0]'s HIP stream as one launch each per LM
  * iteration, ordered against the per-stream work by events. The batch starts after all work
  * already queued on every stream's HIP stream, and later work on those HIP streams runs after it
- * (tt_sync on a stream waits for its frame). Each stream's result is the same as when it is
- * tracked alone. Returns without waiting. TT_EINVAL: bad arguments or a stream listed twice;
+ * (tt_sync on a stream waits for its frame). When every stream sets graph = 1 (and no stage timer
+ * is on), the LM set-up and iterations of the batch are captured as one HIP graph per ordered set of
+ * streams and pattern of their front-buffer parities, kept until one of its streams is destroyed,
+ * gets a new template or new launch shapes, and replayed. Each stream's result is the same as when
+ * it is tracked alone. Returns without waiting. TT_EINVAL: bad arguments or a stream listed twice;
  * TT_EBUSY: a stream is in use by another call (no stream is then touched); TT_ESTATE: a stream
  * has no template. */
 int tt_track_batch_device(tt_stream* const* streams, int S, const tt_frame_device* frames);

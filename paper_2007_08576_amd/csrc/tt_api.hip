@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -49,9 +50,38 @@ void free_list(std::vector<void*>& list, uint64_t& bytes) {
   bytes = 0;
 }
 
+// ---- captured LM rounds of whole-frame batches
+// One executable graph per ordered set of streams and pattern of their front-buffer parities (the
+// rounds read only the streams' own buffers and the parities' front outputs, as the single-stream
+// graphs do). Entries that hold a stream are dropped when its buffers are freed or its launch
+// shapes change; the list is short (the batches a caller alternates between), oldest out first.
+struct BatchGraph {
+  std::vector<tt_stream*> ss;
+  std::vector<int> parity;
+  hipGraphExec_t exec = nullptr;
+};
+static std::mutex g_bg_mu;
+static std::vector<BatchGraph> g_bg;
+constexpr size_t kMaxBatchGraphs = 16;
+
+static void drop_batch_graphs_of(tt_stream* s) {
+  std::lock_guard<std::mutex> lk(g_bg_mu);
+  for (size_t i = 0; i < g_bg.size();) {
+    if (std::find(g_bg[i].ss.begin(), g_bg[i].ss.end(), s) != g_bg[i].ss.end()) {
+      // every member queue waits on its launches' completion (the fork after each launch)
+      for (tt_stream* t : g_bg[i].ss) (void)hipStreamSynchronize(t->st);
+      (void)hipGraphExecDestroy(g_bg[i].exec);
+      g_bg.erase(g_bg.begin() + (long)i);
+    } else {
+      i++;
+    }
+  }
+}
+
 void free_template(tt_stream* s) {
   if (s->st) (void)hipStreamSynchronize(s->st);
   if (s->st_front) (void)hipStreamSynchronize(s->st_front);
+  drop_batch_graphs_of(s);
   for (int f = 0; f < 2; f++)  // captured against the buffers freed below
     if (s->lm_graph[f]) {
       (void)hipGraphExecDestroy(s->lm_graph[f]);
@@ -474,10 +504,7 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
     return TT_OK;
   };
   int rc = fork();
-  for (int q = 0; q < S && !rc; q++) {
-    rc = enqueue_front(ss[q], dd[q], fr[q].K2, qs[q], fr[q].inputs_ready);
-    if (!rc && launch_lm_begin(ss[q]->d, ss[q]->P.lm_lambda0, qs[q]) != hipSuccess) rc = TT_EDEVICE;
-  }
+  for (int q = 0; q < S && !rc; q++) rc = enqueue_front(ss[q], dd[q], fr[q].K2, qs[q], fr[q].inputs_ready);
   // the streams whose systems go to the batched factorisation
   std::vector<tt_stream*> cs;
   std::vector<DevState*> cp;
@@ -486,16 +513,64 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
       cs.push_back(ss[q]);
       cp.push_back(dp[q]);
     }
-  for (int it = 0; it < ss[0]->P.lm_iters && !rc; it++) {
-    for (int q = 0; q < S && !rc; q++) {
-      rc = enqueue_assemble(ss[q], dd[q], it, false, qs[q]);
-      if (rc) break;
-      if (ss[q]->P.solver == TT_SOLVE_NODE) rc = enqueue_node_solve(ss[q], dd[q], qs[q]);
+  // LM set-up and iterations of every stream (each stream's set-up follows its front in queue order)
+  auto lm_rounds = [&]() -> int {
+    int r = TT_OK;
+    for (int q = 0; q < S && !r; q++)
+      if (launch_lm_begin(ss[q]->d, ss[q]->P.lm_lambda0, qs[q]) != hipSuccess) r = TT_EDEVICE;
+    for (int it = 0; it < ss[0]->P.lm_iters && !r; it++) {
+      for (int q = 0; q < S && !r; q++) {
+        r = enqueue_assemble(ss[q], dd[q], it, false, qs[q]);
+        if (r) break;
+        if (ss[q]->P.solver == TT_SOLVE_NODE) r = enqueue_node_solve(ss[q], dd[q], qs[q]);
+      }
+      if (!r) r = join();
+      if (!r && !cs.empty()) r = enqueue_solve(cs.data(), cp.data(), (int)cs.size(), batch_st);
+      if (!r) r = fork();
+      for (int q = 0; q < S && !r; q++) r = enqueue_finish(ss[q], dd[q], qs[q]);
     }
-    if (!rc) rc = join();
-    if (!rc && !cs.empty()) rc = enqueue_solve(cs.data(), cp.data(), (int)cs.size(), batch_st);
-    if (!rc) rc = fork();
-    for (int q = 0; q < S && !rc; q++) rc = enqueue_finish(ss[q], dd[q], qs[q]);
+    return r;
+  };
+  bool graph = true;  // replay the rounds as one graph when every stream asks for graph replay
+  for (int q = 0; q < S; q++) graph = graph && ss[q]->P.graph == 1 && ss[q]->timing == 0;
+  if (!rc && graph) {
+    std::vector<tt_stream*> key(ss, ss + S);
+    std::vector<int> par(S);
+    for (int q = 0; q < S; q++) par[q] = (int)(ss[q]->frame & 1);
+    hipGraphExec_t exec = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_bg_mu);
+      for (const BatchGraph& b : g_bg)
+        if (b.ss == key && b.parity == par) exec = b.exec;
+    }
+    rc = join();  // the fronts, before the captured rounds
+    if (!rc && !exec) {
+      hipGraph_t g = nullptr;
+      if (hipStreamBeginCapture(batch_st, hipStreamCaptureModeThreadLocal) != hipSuccess) return TT_EDEVICE;
+      int rcc = fork();  // every per-stream queue joins the capture
+      if (!rcc) rcc = lm_rounds();
+      if (!rcc) rcc = join();
+      const hipError_t e = hipStreamEndCapture(batch_st, &g);
+      if (rcc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rcc ? rcc : TT_EDEVICE;
+      }
+      const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) return TT_EDEVICE;
+      std::lock_guard<std::mutex> lk(g_bg_mu);
+      if (g_bg.size() >= kMaxBatchGraphs) {
+        // every member queue waits on its launches' completion (the fork after each launch)
+        for (tt_stream* t : g_bg.front().ss) (void)hipStreamSynchronize(t->st);
+        (void)hipGraphExecDestroy(g_bg.front().exec);
+        g_bg.erase(g_bg.begin());
+      }
+      g_bg.push_back(BatchGraph{key, par, exec});
+    }
+    if (!rc && hipGraphLaunch(exec, batch_st) != hipSuccess) rc = TT_EDEVICE;
+    if (!rc) rc = fork();  // the per-stream tails after the rounds
+  } else if (!rc) {
+    rc = lm_rounds();
   }
   for (int q = 0; q < S && !rc; q++) {
     HIPCHK(launch_deform_out(ss[q]->d, fr[q].out_vertices, fr[q].out_dq, qs[q]));
@@ -1236,6 +1311,7 @@ static bool tuning_ok(const tt_tuning* t) {
 
 // The captured LM graphs hold the launch shapes of the tuning they were captured with.
 static void drop_graphs(tt_stream* s) {
+  drop_batch_graphs_of(s);
   for (int f = 0; f < 2; f++)
     if (s->lm_graph[f]) {
       (void)hipStreamSynchronize(s->st);

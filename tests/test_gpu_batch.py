@@ -230,3 +230,47 @@ def test_config4_mix_is_the_same_alone_concurrent_and_batched(env):
         for prec, v in first.items():
             rms = float(np.sqrt(((v[q].astype(np.float64) - vo) ** 2).sum(1).mean()))
             assert rms <= 0.01, f"stream {q}, precision {prec}: {rms:.3g} mm RMS from the oracle"
+
+
+def test_batch_graph_replay_equals_launches(env):
+    """Whole-frame batches with graph replay (every stream's graph = 1: the LM rounds of the batch
+    captured once per pattern of front-buffer parities, then replayed) give bit for bit the results
+    of the same batches launched kernel by kernel, across frames of both parities, a precision form
+    and a per-node stream in the mix, and after a tuning change on one stream drops the captured
+    graphs that hold it."""
+    tt, torch = env
+    dev = torch.device("cuda:0")
+    scenes = _scenes()
+    scenes.append(scenes[0])
+    forms = [(0, 0), (tt.TT_BF16_IR, 0), (0, 0), (0, tt.TT_SOLVE_NODE)]  # (precision, solver)
+    frames = [[_dev_frame(torch, sc.frame(t), dev) for t in (1, 2, 3)] for sc in scenes]
+    seq = [0, 1, 2, 1, 0, 2]  # frames replayed in this order (parities alternate)
+    outs = {}
+    for graph in (0, 1):
+        streams = []
+        for sc, (prec, solver) in zip(scenes, forms):
+            s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=5, precision=prec,
+                                            solver=solver, graph=graph),
+                          tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx,
+                                        sc.intr.cy))
+            s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+            streams.append(s)
+        ov = [torch.zeros((sc.pts.shape[0], 3), dtype=torch.float32, device=dev) for sc in scenes]
+        oq = [torch.zeros((sc.num_control_points, 8), dtype=torch.float32, device=dev) for sc in scenes]
+        res = []
+        for k, t in enumerate(seq):
+            if k == 4:  # new launch shapes on one stream: its captured graphs are dropped and recaptured
+                streams[1].set_tuning(chol_grid_pct=100)
+            tt.track_batch_device(streams, [(frames[q][t][0], frames[q][t][1], frames[q][t][2],
+                                             frames[q][t][1].shape[0], ov[q], oq[q]) for q in range(len(scenes))])
+            for s in streams:
+                s.sync()
+            res.append([(ov[q].cpu().numpy().copy(), oq[q].cpu().numpy().copy()) for q in range(len(scenes))])
+        for s in streams:
+            s.destroy()
+        outs[graph] = res
+    for k in range(len(seq)):
+        for q in range(len(scenes)):
+            a, b = outs[0][k][q], outs[1][k][q]
+            assert np.isfinite(a[0]).all()
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (k, q)
