@@ -48,7 +48,7 @@ def _track(tt, torch, sc, frames, tuning=None, autotune=False, graph=0):
 def test_launch_width_and_fusion_change_nothing(env):
     tt, torch, sc, frames = env
     ref, _, _ = _track(tt, torch, sc, frames)
-    for t in ({"chol_grid_pct": 50}, {"chol_grid_pct": 100, "fuse_rows_arap": 0},
+    for t in ({"chol_grid_pct": 25}, {"chol_grid_pct": 50}, {"chol_grid_pct": 100, "fuse_rows_arap": 0},
               {"chol_grid_pct": 400, "fuse_rows_arap": 1}):
         got, _, _ = _track(tt, torch, sc, frames, tuning=t)
         for k in range(len(frames)):
