@@ -59,18 +59,25 @@ struct BatchGraph {
   std::vector<tt_stream*> ss;
   std::vector<int> parity;
   hipGraphExec_t exec = nullptr;
+  LMMulti multi;  // argument table of the multi-system launches the graph replays
 };
 static std::mutex g_bg_mu;
 static std::vector<BatchGraph> g_bg;
 constexpr size_t kMaxBatchGraphs = 16;
 
+// Waits for the graph's last launch (every member queue waits on it: the fork after each launch),
+// then frees the graph and its table. g_bg_mu held.
+static void destroy_batch_graph(BatchGraph& b) {
+  for (tt_stream* t : b.ss) (void)hipStreamSynchronize(t->st);
+  (void)hipGraphExecDestroy(b.exec);
+  lm_multi_free(b.multi);
+}
+
 static void drop_batch_graphs_of(tt_stream* s) {
   std::lock_guard<std::mutex> lk(g_bg_mu);
   for (size_t i = 0; i < g_bg.size();) {
     if (std::find(g_bg[i].ss.begin(), g_bg[i].ss.end(), s) != g_bg[i].ss.end()) {
-      // every member queue waits on its launches' completion (the fork after each launch)
-      for (tt_stream* t : g_bg[i].ss) (void)hipStreamSynchronize(t->st);
-      (void)hipGraphExecDestroy(g_bg[i].exec);
+      destroy_batch_graph(g_bg[i]);
       g_bg.erase(g_bg.begin() + (long)i);
     } else {
       i++;
@@ -531,6 +538,37 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
     }
     return r;
   };
+  // Graph form: iteration 0 as above, then every round on batch_st, the streams in mq as
+  // multi-system launches and the others (sq) with their own launches.
+  LMMulti multi;
+  std::vector<int> mq, sq;
+  auto lm_rounds_multi = [&]() -> int {
+    int r = TT_OK;
+    for (int q = 0; q < S && !r; q++)
+      if (launch_lm_begin(ss[q]->d, ss[q]->P.lm_lambda0, qs[q]) != hipSuccess) r = TT_EDEVICE;
+    for (int it = 0; it < ss[0]->P.lm_iters && !r; it++) {
+      if (it == 0) {
+        for (int q = 0; q < S && !r; q++) {
+          r = enqueue_assemble(ss[q], dd[q], it, false, qs[q]);
+          if (!r && ss[q]->P.solver == TT_SOLVE_NODE) r = enqueue_node_solve(ss[q], dd[q], qs[q]);
+        }
+        if (!r) r = join();
+      } else {
+        for (int q : sq) {
+          if (!r) r = enqueue_assemble(ss[q], dd[q], it, false, batch_st);
+          if (!r && ss[q]->P.solver == TT_SOLVE_NODE) r = enqueue_node_solve(ss[q], dd[q], batch_st);
+        }
+        if (!r && launch_lm_multi_assemble(multi, it, batch_st) != hipSuccess) r = TT_EDEVICE;
+        for (int q : mq)
+          if (!r && ss[q]->d.prec != TT_FP32 && launch_ir_prepare(dd[q], batch_st) != hipSuccess) r = TT_EDEVICE;
+      }
+      if (!r && !cs.empty()) r = enqueue_solve(cs.data(), cp.data(), (int)cs.size(), batch_st);
+      if (!r && launch_lm_multi_finish(multi, batch_st) != hipSuccess) r = TT_EDEVICE;
+      for (int q : sq)
+        if (!r) r = enqueue_finish(ss[q], dd[q], batch_st);
+    }
+    return r;
+  };
   bool graph = true;  // replay the rounds as one graph when every stream asks for graph replay
   for (int q = 0; q < S; q++) graph = graph && ss[q]->P.graph == 1 && ss[q]->timing == 0;
   if (!rc && graph) {
@@ -545,27 +583,50 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
     }
     rc = join();  // the fronts, before the captured rounds
     if (!rc && !exec) {
+      // the coupled streams without launches of their own (per-node solve, z-buffer) and with the
+      // default ARAP workgroup run their iterations after the first as multi-system launches
+      for (int q = 0; q < S; q++) {
+        const DevState& d = ss[q]->d;
+        if (d.solver != TT_SOLVE_NODE && !d.zbuf && d.arap_threads == 256) mq.push_back(q);
+        else sq.push_back(q);
+      }
+      if (!mq.empty()) {
+        std::vector<DevState*> md;
+        std::vector<const tt_params*> mp;
+        std::vector<Intr> mk;
+        for (int q : mq) {
+          md.push_back(dp[q]);
+          mp.push_back(&ss[q]->P);
+          mk.push_back(intr_of(ss[q]));
+        }
+        if (lm_multi_build(md.data(), mp.data(), mk.data(), (int)mq.size(), &multi) != hipSuccess) return TT_EDEVICE;
+      }
       hipGraph_t g = nullptr;
-      if (hipStreamBeginCapture(batch_st, hipStreamCaptureModeThreadLocal) != hipSuccess) return TT_EDEVICE;
+      if (hipStreamBeginCapture(batch_st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        lm_multi_free(multi);
+        return TT_EDEVICE;
+      }
       int rcc = fork();  // every per-stream queue joins the capture
-      if (!rcc) rcc = lm_rounds();
+      if (!rcc) rcc = multi.jobs ? lm_rounds_multi() : lm_rounds();
       if (!rcc) rcc = join();
       const hipError_t e = hipStreamEndCapture(batch_st, &g);
       if (rcc || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
+        lm_multi_free(multi);
         return rcc ? rcc : TT_EDEVICE;
       }
       const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
-      if (ei != hipSuccess) return TT_EDEVICE;
+      if (ei != hipSuccess) {
+        lm_multi_free(multi);
+        return TT_EDEVICE;
+      }
       std::lock_guard<std::mutex> lk(g_bg_mu);
       if (g_bg.size() >= kMaxBatchGraphs) {
-        // every member queue waits on its launches' completion (the fork after each launch)
-        for (tt_stream* t : g_bg.front().ss) (void)hipStreamSynchronize(t->st);
-        (void)hipGraphExecDestroy(g_bg.front().exec);
+        destroy_batch_graph(g_bg.front());
         g_bg.erase(g_bg.begin());
       }
-      g_bg.push_back(BatchGraph{key, par, exec});
+      g_bg.push_back(BatchGraph{key, par, exec, multi});
     }
     if (!rc && hipGraphLaunch(exec, batch_st) != hipSuccess) rc = TT_EDEVICE;
     if (!rc) rc = fork();  // the per-stream tails after the rounds

@@ -247,6 +247,23 @@ hipError_t launch_node_solve(DevState& d, hipStream_t st);
 hipError_t launch_lm_finish(DevState& d, const tt_params& P, const Intr& K, hipStream_t st);
 hipError_t launch_deform_out(const DevState& d, float* out_xyz, float* out_dq, hipStream_t st);
 
+// Multi-system LM launches: the per-iteration stages of several coupled systems (no per-node solve,
+// no z-buffer) as one launch each, over a device table of their arguments (built from frame views,
+// so one table per batch composition and front-buffer parity). Each system's results are bit for
+// bit those of its own launches.
+struct LMMulti {
+  void* jobs = nullptr;       // device table, one entry per system
+  int nj = 0;
+  int blocks[3] = {0, 0, 0};  // workgroups of the update, row-shaped and data-block grids
+};
+// Synchronous (allocates and copies the table); hipErrorInvalidValue for a system it does not cover.
+hipError_t lm_multi_build(DevState* const* ds, const tt_params* const* P, const Intr* K, int S, LMMulti* out);
+void lm_multi_free(LMMulti& m);
+// rows + dense ARAP, data blocks, damping of every system (iterations after the first)
+hipError_t launch_lm_multi_assemble(const LMMulti& m, int it, hipStream_t st);
+// candidate, FP64 cost, accept / reject of every system
+hipError_t launch_lm_multi_finish(const LMMulti& m, hipStream_t st);
+
 // Ints of the flag area used by one Cholesky solve (tile flags, ticket counters, abort word).
 size_t chol_flag_ints(int nb);
 // Factorisation of the damped, equilibrated system (forward substitution included), then the back

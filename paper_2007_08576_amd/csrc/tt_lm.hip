@@ -30,6 +30,11 @@
 //   ARAP    per ordered pair (a, b): sqrt(w) (|b| - |e0|), sqrt(w w_angle) (a_hat - b_hat),
 //           sqrt(w w_rotation) (qr_a - qr_b), with w = w_ARAP w_ab, e0 = p_b^0 - p_a^0,
 //           a = R_a e0, b = p_b^t - p_a^t (the angle of Eq. (6) in chordal form |a_hat - b_hat|).
+// FMA contraction only inside one statement (decided by the source, not by the code around an
+// inlined body), so that a body compiles to the same arithmetic in every kernel that runs it: the
+// single-system and multi-system launches give bit for bit the same results.
+#pragma clang fp contract(on)
+
 #include <float.h>
 
 #include "tt_internal.h"
@@ -632,18 +637,13 @@ __global__ __launch_bounds__(kArapThreads) void k_rows_arap(ArapArgs aa, RowArgs
 
 constexpr int kDataThreads = 64;
 
-__global__ __launch_bounds__(kDataThreads) void k_data_assemble(const int2* __restrict__ blk_ab,
-                                                                const int* __restrict__ blk_ptr,
-                                                                const uint32_t* __restrict__ ent,
-                                                                const float* __restrict__ jac,
-                                                                const float* __restrict__ wres, int M,
-                                                                const float* __restrict__ jacF,
-                                                                const float* __restrict__ wresF, int K1,
-                                                                float* __restrict__ A, float* __restrict__ g, int ld,
-                                                                int diag_only) {
+__device__ __forceinline__ void data_block_body(const int2* __restrict__ blk_ab, const int* __restrict__ blk_ptr,
+                                                const uint32_t* __restrict__ ent, const float* __restrict__ jac,
+                                                const float* __restrict__ wres, const float* __restrict__ jacF,
+                                                const float* __restrict__ wresF, int K1, float* __restrict__ A,
+                                                float* __restrict__ g, int ld, int diag_only, int blk) {
   __shared__ float fin[42];
   __shared__ float red[42][kDataThreads + 1];
-  const int blk = blockIdx.x;
   const int2 ab = blk_ab[blk];
   if (diag_only && ab.x != ab.y) return;  // whole workgroup: the per-node solve reads no coupling block
   const int lane = threadIdx.x;
@@ -725,13 +725,24 @@ __global__ __launch_bounds__(kDataThreads) void k_data_assemble(const int2* __re
     g[6 * ab.x + lane - 36] += fin[lane];
   }
 }
+__global__ __launch_bounds__(kDataThreads) void k_data_assemble(const int2* __restrict__ blk_ab,
+                                                                const int* __restrict__ blk_ptr,
+                                                                const uint32_t* __restrict__ ent,
+                                                                const float* __restrict__ jac,
+                                                                const float* __restrict__ wres,
+                                                                const float* __restrict__ jacF,
+                                                                const float* __restrict__ wresF, int K1,
+                                                                float* __restrict__ A, float* __restrict__ g, int ld,
+                                                                int diag_only) {
+  data_block_body(blk_ab, blk_ptr, ent, jac, wres, jacF, wresF, K1, A, g, ld, diag_only, (int)blockIdx.x);
+}
 
 // Damping A_kk (1 + lambda) + eps, the symmetric diagonal equilibration d_k = 1/sqrt(that) (the
 // factorisation scales every entry by d_i d_j when it first reads it, so it factors D A D) and the
 // equilibrated right-hand side -d_k g_k. Also totals the cost of the iterate (FP64, fixed order).
-__global__ __launch_bounds__(1024) void k_damp(float* __restrict__ A, const float* __restrict__ g, int n, int npad,
-                                               int ld, float* __restrict__ dscale, const double* __restrict__ part,
-                                               Parts P, LMScalars* sc) {
+__device__ __forceinline__ void damp_body(float* __restrict__ A, const float* __restrict__ g, int n, int npad, int ld,
+                                          float* __restrict__ dscale, const double* __restrict__ part, Parts P,
+                                          LMScalars* sc) {
   __shared__ float shm[16];
   __shared__ double shd[16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -784,6 +795,11 @@ __global__ __launch_bounds__(1024) void k_damp(float* __restrict__ A, const floa
     sc->solve_epoch = (sc->solve_epoch == 0x7FFFFFFF) ? 1 : sc->solve_epoch + 1;
   }
 }
+__global__ __launch_bounds__(1024) void k_damp(float* __restrict__ A, const float* __restrict__ g, int n, int npad,
+                                               int ld, float* __restrict__ dscale, const double* __restrict__ part,
+                                               Parts P, LMScalars* sc) {
+  damp_body(A, g, n, npad, ld, dscale, part, P, sc);
+}
 
 // Per-node step (Sec. 2, each warp W_i updated on its own): node i solves its 6 x 6 diagonal block
 // of the damped, equilibrated matrix D A D against its part of the equilibrated right-hand side, by
@@ -834,11 +850,10 @@ __global__ __launch_bounds__(64) void k_node_solve(const float* __restrict__ A, 
 }
 
 // Candidate warps from the solution D y of (A + damping) x = -g (y solves the equilibrated system).
-__global__ void k_update(const float* __restrict__ W, const float4* __restrict__ pos, const float4* __restrict__ c0,
-                         const float* __restrict__ x, const float* __restrict__ dscale, int N, float* __restrict__ Wc,
-                         float4* __restrict__ posc, float4* __restrict__ ndispc) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+__device__ __forceinline__ void update_body(const float* __restrict__ W, const float4* __restrict__ pos,
+                                            const float4* __restrict__ c0, const float* __restrict__ x,
+                                            const float* __restrict__ dscale, float* __restrict__ Wc,
+                                            float4* __restrict__ posc, float4* __restrict__ ndispc, int i) {
   float q[8], out[8];
   load_dq(W, i, q);
   float4 p = pos[i];
@@ -853,6 +868,12 @@ __global__ void k_update(const float* __restrict__ W, const float4* __restrict__
   f3 dc = dq_disp(out, mk3(c.x, c.y, c.z));
   posc[i] = make_float4(c.x + dc.x, c.y + dc.y, c.z + dc.z, 0.0f);
   ndispc[i] = make_float4(dc.x, dc.y, dc.z, 0.0f);
+}
+__global__ void k_update(const float* __restrict__ W, const float4* __restrict__ pos, const float4* __restrict__ c0,
+                         const float* __restrict__ x, const float* __restrict__ dscale, int N, float* __restrict__ Wc,
+                         float4* __restrict__ posc, float4* __restrict__ ndispc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) update_body(W, pos, c0, x, dscale, Wc, posc, ndispc, i);
 }
 
 // FP64 cost of the candidate with the correspondences, Tukey weights and feature weights of the
@@ -938,12 +959,12 @@ __global__ __launch_bounds__(kArapThreads) void k_cost(ArapArgs aa, RowArgs ra, 
 
 // Accept / reject on the device: accept iff the factorisation succeeded and the candidate's
 // cost is lower. lambda / 10 (>= 1e-10) on accept, * 10 (<= 1e10) on reject.
-__global__ __launch_bounds__(256) void k_accept(const double* __restrict__ part, Parts P, int N, LMScalars* sc,
-                                                float* __restrict__ W, const float* __restrict__ Wc,
-                                                float4* __restrict__ pos, const float4* __restrict__ posc,
-                                                float4* __restrict__ ndisp, const float4* __restrict__ ndispc,
-                                                double* log_old, double* log_new, double* log_lambda,
-                                                int* log_acc, double* log_w_arap, int* log_fail) {
+__device__ __forceinline__ void accept_body(const double* __restrict__ part, Parts P, int N, LMScalars* sc,
+                                            float* __restrict__ W, const float* __restrict__ Wc,
+                                            float4* __restrict__ pos, const float4* __restrict__ posc,
+                                            float4* __restrict__ ndisp, const float4* __restrict__ ndispc,
+                                            double* log_old, double* log_new, double* log_lambda, int* log_acc,
+                                            double* log_w_arap, int* log_fail) {
   __shared__ double sh[256];
   __shared__ int acc_s;
   double e = 0.0;
@@ -975,6 +996,15 @@ __global__ __launch_bounds__(256) void k_accept(const double* __restrict__ part,
       ndisp[t] = ndispc[t];
     }
   }
+}
+__global__ __launch_bounds__(256) void k_accept(const double* __restrict__ part, Parts P, int N, LMScalars* sc,
+                                                float* __restrict__ W, const float* __restrict__ Wc,
+                                                float4* __restrict__ pos, const float4* __restrict__ posc,
+                                                float4* __restrict__ ndisp, const float4* __restrict__ ndispc,
+                                                double* log_old, double* log_new, double* log_lambda,
+                                                int* log_acc, double* log_w_arap, int* log_fail) {
+  accept_body(part, P, N, sc, W, Wc, pos, posc, ndisp, ndispc, log_old, log_new, log_lambda, log_acc, log_w_arap,
+              log_fail);
 }
 
 __global__ void k_lm_begin(LMScalars* sc, double lambda0) {
@@ -1039,7 +1069,149 @@ ArapArgs arap_args(DevState& d, const tt_params& P) {
   return a;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Multi-system launches: one launch of a stage over every coupled system of a batch. Each system
+// owns a contiguous range of the grid; a workgroup finds its system in the device table by block
+// index and runs the single-system kernel's body with the same block-local index, so every system
+// gets exactly the results of its own launch. The table is built once per batch composition and
+// never changes while launches that read it can run.
+
+struct LMJob {
+  ArapArgs aa;
+  RowArgs ra;
+  float* W;
+  float4 *pos, *ndisp;
+  const float4* c0;
+  const float* x;
+  float *dscale, *Wc;
+  float4 *posc, *ndispc;
+  LMScalars* sc;
+  double* part;
+  Parts P;
+  int N, n, npad, ld;
+  float *A, *g;
+  const int2* blk_ab;
+  const int* blk_ptr;
+  const uint32_t* ent;
+  const float *jac, *wres, *jacF, *wresF;
+  int K1;
+  double *log_old, *log_new, *log_lambda, *log_w_arap;
+  int *log_acc, *log_fail;
+  int start[3];  // first workgroup of the system in the update, row-shaped and data-block grids
+};
+
+// the system whose range of grid `kind` holds block b (ranges ascending; empty ranges skipped)
+__device__ __forceinline__ int job_of(const LMJob* __restrict__ J, int nj, int kind, int b) {
+  int lo = 0, hi = nj - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (J[mid].start[kind] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(64) void k_update_multi(const LMJob* __restrict__ J, int nj) {
+  const LMJob& j = J[job_of(J, nj, 0, (int)blockIdx.x)];
+  const int i = ((int)blockIdx.x - j.start[0]) * 64 + (int)threadIdx.x;
+  if (i < j.N) update_body(j.W, j.pos, j.c0, j.x, j.dscale, j.Wc, j.posc, j.ndispc, i);
+}
+
+__global__ __launch_bounds__(kArapThreads) void k_cost_multi(const LMJob* __restrict__ J, int nj) {
+  const LMJob& j = J[job_of(J, nj, 1, (int)blockIdx.x)];
+  const int bx = (int)blockIdx.x - j.start[1];
+  if (bx < j.N) cost_arap_body(j.aa, j.Wc, j.ndispc, bx);
+  else cost_data_body(j.ra, j.Wc, bx - j.N);
+}
+
+__global__ __launch_bounds__(256) void k_accept_multi(const LMJob* __restrict__ J) {
+  const LMJob& j = J[blockIdx.x];
+  accept_body(j.part, j.P, j.N, j.sc, j.W, j.Wc, j.pos, j.posc, j.ndisp, j.ndispc, j.log_old, j.log_new,
+              j.log_lambda, j.log_acc, j.log_w_arap, j.log_fail);
+}
+
+__global__ __launch_bounds__(kArapThreads) void k_rows_arap_multi(const LMJob* __restrict__ J, int nj, int it) {
+  const LMJob& j = J[job_of(J, nj, 1, (int)blockIdx.x)];
+  const int bx = (int)blockIdx.x - j.start[1];
+  if (bx < j.N) arap_body<true>(j.aa, bx);
+  else data_rows_body(j.ra, it, bx - j.N);
+}
+
+__global__ __launch_bounds__(kDataThreads) void k_data_multi(const LMJob* __restrict__ J, int nj) {
+  const LMJob& j = J[job_of(J, nj, 2, (int)blockIdx.x)];
+  data_block_body(j.blk_ab, j.blk_ptr, j.ent, j.jac, j.wres, j.jacF, j.wresF, j.K1, j.A, j.g, j.ld, 0,
+                  (int)blockIdx.x - j.start[2]);
+}
+
+__global__ __launch_bounds__(1024) void k_damp_multi(const LMJob* __restrict__ J) {
+  const LMJob& j = J[blockIdx.x];
+  damp_body(j.A, j.g, j.n, j.npad, j.ld, j.dscale, j.part, j.P, j.sc);
+}
+
 }  // namespace
+
+hipError_t lm_multi_build(DevState* const* ds, const tt_params* const* P, const Intr* K, int S, LMMulti* out) {
+  *out = LMMulti{};
+  if (S <= 0) return hipErrorInvalidValue;
+  std::vector<LMJob> J(S);
+  int b[3] = {0, 0, 0};
+  for (int q = 0; q < S; q++) {
+    DevState& d = *ds[q];
+    if (d.solver == TT_SOLVE_NODE || d.zbuf) return hipErrorInvalidValue;  // extra launches of their own
+    LMJob& j = J[q];
+    j.aa = arap_args(d, *P[q]);
+    j.ra = row_args(d, *P[q], K[q]);
+    j.W = d.W; j.pos = d.pos; j.ndisp = d.ndisp; j.c0 = d.c0;
+    j.x = d.x; j.dscale = d.dscale; j.Wc = d.Wc; j.posc = d.posc; j.ndispc = d.ndispc;
+    j.sc = d.sc; j.part = d.partial; j.P = parts_of(d.M, d.K1, d.N);
+    j.N = d.N; j.n = d.n; j.npad = d.npad; j.ld = d.ld; j.A = d.A; j.g = d.g;
+    j.blk_ab = d.blk_ab; j.blk_ptr = d.blk_ptr; j.ent = d.blk_ent;
+    j.jac = d.jac; j.wres = d.wres; j.jacF = d.jacF; j.wresF = d.wresF; j.K1 = d.K1;
+    j.log_old = d.log_cost_old; j.log_new = d.log_cost_new; j.log_lambda = d.log_lambda;
+    j.log_w_arap = d.log_w_arap; j.log_acc = d.log_accept; j.log_fail = d.log_fail;
+    j.start[0] = b[0];
+    b[0] += (d.N + 63) / 64;
+    j.start[1] = b[1];
+    b[1] += d.N + j.P.nbp + j.P.nbf;
+    j.start[2] = b[2];
+    b[2] += d.nblk;
+  }
+  void* dev = nullptr;
+  hipError_t e = hipMalloc(&dev, sizeof(LMJob) * (size_t)S);
+  if (e != hipSuccess) return e;
+  e = hipMemcpy(dev, J.data(), sizeof(LMJob) * (size_t)S, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dev);
+    return e;
+  }
+  out->jobs = dev;
+  out->nj = S;
+  for (int k = 0; k < 3; k++) out->blocks[k] = b[k];
+  return hipSuccess;
+}
+
+void lm_multi_free(LMMulti& m) {
+  if (m.jobs) (void)hipFree(m.jobs);
+  m = LMMulti{};
+}
+
+hipError_t launch_lm_multi_assemble(const LMMulti& m, int it, hipStream_t st) {
+  if (it == 0 || !m.jobs) return hipErrorInvalidValue;  // the ARAP weight comes from iteration 0's rows
+  const LMJob* J = static_cast<const LMJob*>(m.jobs);
+  hipLaunchKernelGGL(k_rows_arap_multi, dim3(m.blocks[1]), dim3(kArapThreads), 0, st, J, m.nj, it);
+  if (m.blocks[2] > 0) hipLaunchKernelGGL(k_data_multi, dim3(m.blocks[2]), dim3(kDataThreads), 0, st, J, m.nj);
+  hipLaunchKernelGGL(k_damp_multi, dim3(m.nj), dim3(1024), 0, st, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_lm_multi_finish(const LMMulti& m, hipStream_t st) {
+  if (!m.jobs) return hipErrorInvalidValue;
+  const LMJob* J = static_cast<const LMJob*>(m.jobs);
+  hipLaunchKernelGGL(k_update_multi, dim3(m.blocks[0]), dim3(64), 0, st, J, m.nj);
+  hipLaunchKernelGGL(k_cost_multi, dim3(m.blocks[1]), dim3(kArapThreads), 0, st, J, m.nj);
+  hipLaunchKernelGGL(k_accept_multi, dim3(m.nj), dim3(256), 0, st, J);
+  return hipGetLastError();
+}
 
 int partial_count(int M, int K1, int N) {
   Parts p = parts_of(M, K1, N);
@@ -1099,7 +1271,7 @@ hipError_t launch_lm_arap(DevState& d, const tt_params& P, hipStream_t st) {
 hipError_t launch_lm_data(DevState& d, hipStream_t st) {
   if (d.nblk > 0)
     hipLaunchKernelGGL(k_data_assemble, dim3(d.nblk), dim3(kDataThreads), 0, st, d.blk_ab, d.blk_ptr, d.blk_ent,
-                       d.jac, d.wres, d.M, d.jacF, d.wresF, d.K1, d.A, d.g, d.ld, (int)(d.solver == TT_SOLVE_NODE));
+                       d.jac, d.wres, d.jacF, d.wresF, d.K1, d.A, d.g, d.ld, (int)(d.solver == TT_SOLVE_NODE));
   return hipGetLastError();
 }
 
