@@ -538,30 +538,23 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
     }
     return r;
   };
-  // Graph form: iteration 0 as above, then every round on batch_st, the streams in mq as
-  // multi-system launches and the others (sq) with their own launches.
+  // Graph form: every stage on batch_st, the streams in mq as multi-system launches (one launch
+  // per stage for all of them) and the others (sq) with their own launches.
   LMMulti multi;
   std::vector<int> mq, sq;
   auto lm_rounds_multi = [&]() -> int {
     int r = TT_OK;
-    for (int q = 0; q < S && !r; q++)
-      if (launch_lm_begin(ss[q]->d, ss[q]->P.lm_lambda0, qs[q]) != hipSuccess) r = TT_EDEVICE;
+    for (int q : sq)
+      if (!r && launch_lm_begin(ss[q]->d, ss[q]->P.lm_lambda0, batch_st) != hipSuccess) r = TT_EDEVICE;
+    if (!r && launch_lm_multi_begin(multi, batch_st) != hipSuccess) r = TT_EDEVICE;
     for (int it = 0; it < ss[0]->P.lm_iters && !r; it++) {
-      if (it == 0) {
-        for (int q = 0; q < S && !r; q++) {
-          r = enqueue_assemble(ss[q], dd[q], it, false, qs[q]);
-          if (!r && ss[q]->P.solver == TT_SOLVE_NODE) r = enqueue_node_solve(ss[q], dd[q], qs[q]);
-        }
-        if (!r) r = join();
-      } else {
-        for (int q : sq) {
-          if (!r) r = enqueue_assemble(ss[q], dd[q], it, false, batch_st);
-          if (!r && ss[q]->P.solver == TT_SOLVE_NODE) r = enqueue_node_solve(ss[q], dd[q], batch_st);
-        }
-        if (!r && launch_lm_multi_assemble(multi, it, batch_st) != hipSuccess) r = TT_EDEVICE;
-        for (int q : mq)
-          if (!r && ss[q]->d.prec != TT_FP32 && launch_ir_prepare(dd[q], batch_st) != hipSuccess) r = TT_EDEVICE;
+      for (int q : sq) {
+        if (!r) r = enqueue_assemble(ss[q], dd[q], it, false, batch_st);
+        if (!r && ss[q]->P.solver == TT_SOLVE_NODE) r = enqueue_node_solve(ss[q], dd[q], batch_st);
       }
+      if (!r && launch_lm_multi_assemble(multi, it, batch_st) != hipSuccess) r = TT_EDEVICE;
+      for (int q : mq)
+        if (!r && ss[q]->d.prec != TT_FP32 && launch_ir_prepare(dd[q], batch_st) != hipSuccess) r = TT_EDEVICE;
       if (!r && !cs.empty()) r = enqueue_solve(cs.data(), cp.data(), (int)cs.size(), batch_st);
       if (!r && launch_lm_multi_finish(multi, batch_st) != hipSuccess) r = TT_EDEVICE;
       for (int q : sq)
@@ -584,7 +577,7 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
     rc = join();  // the fronts, before the captured rounds
     if (!rc && !exec) {
       // the coupled streams without launches of their own (per-node solve, z-buffer) and with the
-      // default ARAP workgroup run their iterations after the first as multi-system launches
+      // default ARAP workgroup run their LM set-up and iterations as multi-system launches
       for (int q = 0; q < S; q++) {
         const DevState& d = ss[q]->d;
         if (d.solver != TT_SOLVE_NODE && !d.zbuf && d.arap_threads == 256) mq.push_back(q);

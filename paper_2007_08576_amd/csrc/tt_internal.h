@@ -252,14 +252,17 @@ hipError_t launch_deform_out(const DevState& d, float* out_xyz, float* out_dq, h
 // so one table per batch composition and front-buffer parity). Each system's results are bit for
 // bit those of its own launches.
 struct LMMulti {
-  void* jobs = nullptr;       // device table, one entry per system
+  void* jobs = nullptr;  // device table, one entry per system
   int nj = 0;
-  int blocks[3] = {0, 0, 0};  // workgroups of the update, row-shaped and data-block grids
+  int blocks[5] = {};    // workgroups of the node-shaped, row-shaped, data-block, row-block and ARAP grids
 };
 // Synchronous (allocates and copies the table); hipErrorInvalidValue for a system it does not cover.
 hipError_t lm_multi_build(DevState* const* ds, const tt_params* const* P, const Intr* K, int S, LMMulti* out);
 void lm_multi_free(LMMulti& m);
-// rows + dense ARAP, data blocks, damping of every system (iterations after the first)
+// LM set-up of every system (launch_lm_begin)
+hipError_t launch_lm_multi_begin(const LMMulti& m, hipStream_t st);
+// rows and dense ARAP (at iteration 0: rows, ARAP weight, ARAP blocks), data blocks, damping of
+// every system
 hipError_t launch_lm_multi_assemble(const LMMulti& m, int it, hipStream_t st);
 // candidate, FP64 cost, accept / reject of every system
 hipError_t launch_lm_multi_finish(const LMMulti& m, hipStream_t st);

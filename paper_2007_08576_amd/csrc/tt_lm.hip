@@ -104,16 +104,19 @@ __device__ __forceinline__ void row_times_Q(const float* y, const float* q, f3 p
 
 // ---------------------------------------------------------------------------------------------
 
-__global__ void k_node_prep(const float* __restrict__ W, const float4* __restrict__ c0, int N,
-                            float4* __restrict__ pos, float4* __restrict__ ndisp) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+__device__ __forceinline__ void node_prep_body(const float* __restrict__ W, const float4* __restrict__ c0,
+                                               float4* __restrict__ pos, float4* __restrict__ ndisp, int i) {
   float q[8];
   load_dq(W, i, q);
   float4 c = c0[i];
   f3 dp = dq_disp(q, mk3(c.x, c.y, c.z));
   pos[i] = make_float4(c.x + dp.x, c.y + dp.y, c.z + dp.z, 0.0f);
   ndisp[i] = make_float4(dp.x, dp.y, dp.z, 0.0f);
+}
+__global__ void k_node_prep(const float* __restrict__ W, const float4* __restrict__ c0, int N,
+                            float4* __restrict__ pos, float4* __restrict__ ndisp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) node_prep_body(W, c0, pos, ndisp, i);
 }
 
 struct RowArgs {
@@ -354,8 +357,8 @@ __global__ __launch_bounds__(kRowThreads) void k_data_rows(RowArgs a, int it) { 
 
 // Dynamic ARAP weight, once per frame (iteration 0): lambda_arap times the summed ICP (Tukey)
 // and feature (w_ORB w_k) weights over the summed pair weights.
-__global__ __launch_bounds__(256) void k_lm_scalars(const double* __restrict__ part, Parts P, double lambda_arap,
-                                                    double w_orb, double s_arap, LMScalars* sc) {
+__device__ __forceinline__ void scalars_body(const double* __restrict__ part, Parts P, double lambda_arap,
+                                             double w_orb, double s_arap, LMScalars* sc) {
   __shared__ double sh[256];
   double so = 0.0, sw = 0.0;
   for (int b = threadIdx.x; b < P.nbp; b += 256) so += part[P.pts + 2 * b];
@@ -367,6 +370,10 @@ __global__ __launch_bounds__(256) void k_lm_scalars(const double* __restrict__ p
     sc->sum_orbw = sw;
     sc->w_arap = (s_arap > 0.0) ? lambda_arap * (so + w_orb * sw) / s_arap : 0.0;
   }
+}
+__global__ __launch_bounds__(256) void k_lm_scalars(const double* __restrict__ part, Parts P, double lambda_arap,
+                                                    double w_orb, double s_arap, LMScalars* sc) {
+  scalars_body(part, P, lambda_arap, w_orb, s_arap, sc);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1007,12 +1014,13 @@ __global__ __launch_bounds__(256) void k_accept(const double* __restrict__ part,
               log_fail);
 }
 
-__global__ void k_lm_begin(LMScalars* sc, double lambda0) {
+__device__ __forceinline__ void lm_begin_body(LMScalars* sc, double lambda0) {
   sc->lambda = lambda0;
   sc->it = 0;
   sc->chol_fail = 0;
   sc->accept = 0;
 }
+__global__ void k_lm_begin(LMScalars* sc, double lambda0) { lm_begin_body(sc, lambda0); }
 
 // Final deformed template (Sec. 2: interpolation of neighbouring control points) and warps.
 __global__ void k_deform_out(const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
@@ -1077,6 +1085,7 @@ ArapArgs arap_args(DevState& d, const tt_params& P) {
 // never changes while launches that read it can run.
 
 struct LMJob {
+  static constexpr int kMultiGrids = 5;
   ArapArgs aa;
   RowArgs ra;
   float* W;
@@ -1097,7 +1106,10 @@ struct LMJob {
   int K1;
   double *log_old, *log_new, *log_lambda, *log_w_arap;
   int *log_acc, *log_fail;
-  int start[3];  // first workgroup of the system in the update, row-shaped and data-block grids
+  double lambda0, lambda_arap, w_orb, s_arap;
+  // first workgroup of the system in the node-shaped (64 threads), row-shaped (ARAP rows then
+  // point / feature row blocks), data-block, row-block-only and ARAP-only grids
+  int start[kMultiGrids];
 };
 
 // the system whose range of grid `kind` holds block b (ranges ascending; empty ranges skipped)
@@ -1143,6 +1155,31 @@ __global__ __launch_bounds__(kDataThreads) void k_data_multi(const LMJob* __rest
                   (int)blockIdx.x - j.start[2]);
 }
 
+// LM set-up (k_lm_begin on the first workgroup of each system, k_node_prep)
+__global__ __launch_bounds__(64) void k_begin_multi(const LMJob* __restrict__ J, int nj) {
+  const LMJob& j = J[job_of(J, nj, 0, (int)blockIdx.x)];
+  const int lb = (int)blockIdx.x - j.start[0];
+  if (lb == 0 && threadIdx.x == 0) lm_begin_body(j.sc, j.lambda0);
+  const int i = lb * 64 + (int)threadIdx.x;
+  if (i < j.N) node_prep_body(j.W, j.c0, j.pos, j.ndisp, i);
+}
+
+// first iteration: the rows, the ARAP weight from them, then the dense ARAP blocks
+__global__ __launch_bounds__(kRowThreads) void k_rows_multi(const LMJob* __restrict__ J, int nj, int it) {
+  const LMJob& j = J[job_of(J, nj, 3, (int)blockIdx.x)];
+  data_rows_body(j.ra, it, (int)blockIdx.x - j.start[3]);
+}
+
+__global__ __launch_bounds__(256) void k_scalars_multi(const LMJob* __restrict__ J) {
+  const LMJob& j = J[blockIdx.x];
+  scalars_body(j.part, j.P, j.lambda_arap, j.w_orb, j.s_arap, j.sc);
+}
+
+__global__ __launch_bounds__(kArapThreads) void k_arap_multi(const LMJob* __restrict__ J, int nj) {
+  const LMJob& j = J[job_of(J, nj, 4, (int)blockIdx.x)];
+  arap_body<true>(j.aa, (int)blockIdx.x - j.start[4]);
+}
+
 __global__ __launch_bounds__(1024) void k_damp_multi(const LMJob* __restrict__ J) {
   const LMJob& j = J[blockIdx.x];
   damp_body(j.A, j.g, j.n, j.npad, j.ld, j.dscale, j.part, j.P, j.sc);
@@ -1154,7 +1191,7 @@ hipError_t lm_multi_build(DevState* const* ds, const tt_params* const* P, const 
   *out = LMMulti{};
   if (S <= 0) return hipErrorInvalidValue;
   std::vector<LMJob> J(S);
-  int b[3] = {0, 0, 0};
+  int b[LMJob::kMultiGrids] = {};
   for (int q = 0; q < S; q++) {
     DevState& d = *ds[q];
     if (d.solver == TT_SOLVE_NODE || d.zbuf) return hipErrorInvalidValue;  // extra launches of their own
@@ -1169,12 +1206,12 @@ hipError_t lm_multi_build(DevState* const* ds, const tt_params* const* P, const 
     j.jac = d.jac; j.wres = d.wres; j.jacF = d.jacF; j.wresF = d.wresF; j.K1 = d.K1;
     j.log_old = d.log_cost_old; j.log_new = d.log_cost_new; j.log_lambda = d.log_lambda;
     j.log_w_arap = d.log_w_arap; j.log_acc = d.log_accept; j.log_fail = d.log_fail;
-    j.start[0] = b[0];
-    b[0] += (d.N + 63) / 64;
-    j.start[1] = b[1];
-    b[1] += d.N + j.P.nbp + j.P.nbf;
-    j.start[2] = b[2];
-    b[2] += d.nblk;
+    j.lambda0 = P[q]->lm_lambda0; j.lambda_arap = P[q]->lambda_arap; j.w_orb = P[q]->w_orb; j.s_arap = d.s_arap;
+    const int cnt[LMJob::kMultiGrids] = {(d.N + 63) / 64, d.N + j.P.nbp + j.P.nbf, d.nblk, j.P.nbp + j.P.nbf, d.N};
+    for (int k = 0; k < LMJob::kMultiGrids; k++) {
+      j.start[k] = b[k];
+      b[k] += cnt[k];
+    }
   }
   void* dev = nullptr;
   hipError_t e = hipMalloc(&dev, sizeof(LMJob) * (size_t)S);
@@ -1186,7 +1223,7 @@ hipError_t lm_multi_build(DevState* const* ds, const tt_params* const* P, const 
   }
   out->jobs = dev;
   out->nj = S;
-  for (int k = 0; k < 3; k++) out->blocks[k] = b[k];
+  for (int k = 0; k < LMJob::kMultiGrids; k++) out->blocks[k] = b[k];
   return hipSuccess;
 }
 
@@ -1195,10 +1232,22 @@ void lm_multi_free(LMMulti& m) {
   m = LMMulti{};
 }
 
+hipError_t launch_lm_multi_begin(const LMMulti& m, hipStream_t st) {
+  if (!m.jobs) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_begin_multi, dim3(m.blocks[0]), dim3(64), 0, st, static_cast<const LMJob*>(m.jobs), m.nj);
+  return hipGetLastError();
+}
+
 hipError_t launch_lm_multi_assemble(const LMMulti& m, int it, hipStream_t st) {
-  if (it == 0 || !m.jobs) return hipErrorInvalidValue;  // the ARAP weight comes from iteration 0's rows
+  if (!m.jobs) return hipErrorInvalidValue;
   const LMJob* J = static_cast<const LMJob*>(m.jobs);
-  hipLaunchKernelGGL(k_rows_arap_multi, dim3(m.blocks[1]), dim3(kArapThreads), 0, st, J, m.nj, it);
+  if (it == 0) {  // the ARAP blocks need the ARAP weight from this iteration's rows
+    if (m.blocks[3] > 0) hipLaunchKernelGGL(k_rows_multi, dim3(m.blocks[3]), dim3(kRowThreads), 0, st, J, m.nj, it);
+    hipLaunchKernelGGL(k_scalars_multi, dim3(m.nj), dim3(256), 0, st, J);
+    hipLaunchKernelGGL(k_arap_multi, dim3(m.blocks[4]), dim3(kArapThreads), 0, st, J, m.nj);
+  } else {
+    hipLaunchKernelGGL(k_rows_arap_multi, dim3(m.blocks[1]), dim3(kArapThreads), 0, st, J, m.nj, it);
+  }
   if (m.blocks[2] > 0) hipLaunchKernelGGL(k_data_multi, dim3(m.blocks[2]), dim3(kDataThreads), 0, st, J, m.nj);
   hipLaunchKernelGGL(k_damp_multi, dim3(m.nj), dim3(1024), 0, st, J);
   return hipGetLastError();

@@ -174,7 +174,8 @@ def test_config4_mix_is_the_same_alone_concurrent_and_batched(env):
     binary16 form with one (the serving runs' mixed form): each stream's
     vertices and warps are bit for bit the same when it is tracked alone (synchronised after every
     frame), when all streams are queued at once on their own HIP streams (their persistent
-    factorisations then run side by side on the device), and in one batch. The smallest streams
+    factorisations then run side by side on the device), in one batch, and in one batch replayed as
+    a graph (every LM stage of the 16 streams as one multi-system launch). The smallest streams
     are then compared with the FP64 oracle (0.01 mm RMS, Sec. 2)."""
     from oracle import oracle as O
     tt, torch = env
@@ -185,9 +186,9 @@ def test_config4_mix_is_the_same_alone_concurrent_and_batched(env):
     first = {}
     for prec, ir in ((tt.TT_FP32, 2), (tt.TT_BF16_IR, 2), (tt.TT_FP16_IR, 1)):
         res = {}
-        for mode in ("alone", "concurrent", "batch"):
+        for mode in ("alone", "concurrent", "batch", "batch_graph"):
             streams = [tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=4, precision=prec,
-                                                   ir_iters=ir),
+                                                   ir_iters=ir, graph=int(mode == "batch_graph")),
                                  tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx,
                                                sc.intr.cy)) for sc in scenes]
             for s, sc in zip(streams, scenes):
@@ -198,7 +199,7 @@ def test_config4_mix_is_the_same_alone_concurrent_and_batched(env):
             for t in range(2):
                 args = [(frames[q][t][0], frames[q][t][1], frames[q][t][2], frames[q][t][1].shape[0], ov[q], oq[q])
                         for q in range(S)]
-                if mode == "batch":
+                if mode.startswith("batch"):
                     tt.track_batch_device(streams, args)
                 else:
                     for q in range(S):
@@ -211,7 +212,7 @@ def test_config4_mix_is_the_same_alone_concurrent_and_batched(env):
             res[mode] = out
             for s in streams:
                 s.destroy()
-        for mode in ("concurrent", "batch"):
+        for mode in ("concurrent", "batch", "batch_graph"):
             for t in range(2):
                 for q in range(S):
                     a, b = res["alone"][t][q], res[mode][t][q]
