@@ -308,7 +308,8 @@ int tt_cholesky_solve_noalloc(int n, const float* d_A, const float* d_b, float* 
  * node's diagonal block and gradient terms are summed (FP32 rounding only). */
 typedef struct {
   int chol_grid_pct;  /* workgroups of the factorisation launch, in percent of the compute units
-                         (25..400; default 200; at most one workgroup per task)               */
+                         (25..400; default 200; at most one workgroup per task); a batched
+                         launch takes the largest of its systems' values                       */
   int arap_threads;   /* 128 or 256 (default) threads per dense-ARAP workgroup                   */
   int fuse_rows_arap; /* 1 (default): rows and ARAP in one launch from the second LM iteration on
                          (needs arap_threads 256); 0: separate launches                          */

@@ -543,6 +543,9 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
   LMMulti multi;
   std::vector<int> mq, sq;
   auto lm_rounds_multi = [&]() -> int {
+    std::vector<DevState*> mir;  // the 16-bit systems among them: one refinement set-up launch
+    for (int q : mq)
+      if (ss[q]->d.prec != TT_FP32) mir.push_back(dp[q]);
     int r = TT_OK;
     for (int q : sq)
       if (!r && launch_lm_begin(ss[q]->d, ss[q]->P.lm_lambda0, batch_st) != hipSuccess) r = TT_EDEVICE;
@@ -553,8 +556,8 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
         if (!r && ss[q]->P.solver == TT_SOLVE_NODE) r = enqueue_node_solve(ss[q], dd[q], batch_st);
       }
       if (!r && launch_lm_multi_assemble(multi, it, batch_st) != hipSuccess) r = TT_EDEVICE;
-      for (int q : mq)
-        if (!r && ss[q]->d.prec != TT_FP32 && launch_ir_prepare(dd[q], batch_st) != hipSuccess) r = TT_EDEVICE;
+      if (!r && !mir.empty() && launch_ir_prepare_batch(mir.data(), (int)mir.size(), batch_st) != hipSuccess)
+        r = TT_EDEVICE;
       if (!r && !cs.empty()) r = enqueue_solve(cs.data(), cp.data(), (int)cs.size(), batch_st);
       if (!r && launch_lm_multi_finish(multi, batch_st) != hipSuccess) r = TT_EDEVICE;
       for (int q : sq)

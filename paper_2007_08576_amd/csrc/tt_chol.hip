@@ -1532,7 +1532,8 @@ __global__ __launch_bounds__(64) void k_ir_resid_sum(const BackBatch B) {
 }
 
 // A0 = the lower-triangle tiles of the damped matrix A (the only part the residual reads), before
-// the factorisation overwrites them; one workgroup per tile.
+// the factorisation overwrites them, one workgroup per tile; the workgroup of diagonal tile i also
+// keeps block i of the equilibrated right-hand side (row npad of A) in c.
 __global__ __launch_bounds__(256) void k_ir_copy_lower(const BackBatch B) {
   int t = (int)blockIdx.x;
   const CholArgs& P = B.p[lower_tile_system(B, t)];
@@ -1543,6 +1544,10 @@ __global__ __launch_bounds__(256) void k_ir_copy_lower(const BackBatch B) {
     const int e = threadIdx.x + 256 * u, r = e >> 4, c = 4 * (e & 15);
     const size_t o = (size_t)(NB * i + r) * P.ld + NB * k + c;
     *reinterpret_cast<float4*>(const_cast<float*>(P.A0) + o) = *reinterpret_cast<const float4*>(P.A + o);
+  }
+  if (i == k && threadIdx.x < NB) {
+    const size_t gi = (size_t)NB * i + threadIdx.x;
+    const_cast<float*>(P.c)[gi] = P.A[(size_t)P.npad * P.ld + gi];
   }
 }
 
@@ -1596,14 +1601,18 @@ hipError_t launch_cholesky_factor_batch(DevState* const* ds, int S, hipStream_t 
     CholBatch B;
     B.nprob = (S - b0 < kMaxCholBatch) ? S - b0 : kMaxCholBatch;
     int tasks = 0, cus = 256, khz = 100000;  // the constant clock runs at 100 MHz unless the device says otherwise
-    int pct = 200;                           // launch width in percent of the compute units (first system's tuning)
+    // launch width in percent of the compute units: the widest of the systems' tunings (a batch
+    // holds at least the work of its largest system)
+    int pct = 0;
     for (int q = 0; q < B.nprob; q++) {
       B.p[q] = chol_args(*ds[b0 + q], 0);
       tasks += B.p[q].ntasks;
       if (ds[b0 + q]->num_cus > 0) cus = ds[b0 + q]->num_cus;
       if (ds[b0 + q]->wall_khz > 0) khz = ds[b0 + q]->wall_khz;
+      const int t = ds[b0 + q]->chol_grid_pct;
+      if (t >= 25 && t <= 400 && t > pct) pct = t;
     }
-    if (ds[b0]->chol_grid_pct >= 25 && ds[b0]->chol_grid_pct <= 400) pct = ds[b0]->chol_grid_pct;
+    if (pct == 0) pct = 200;
     B.wait_ticks = (uint64_t)(kWaitSeconds * 1000.0 * khz);
     // any width is safe: a task waits only on smaller tickets, which running workgroups claimed
     const int width = (cus * pct + 99) / 100;
@@ -1651,13 +1660,15 @@ static int lower_tiles(const BackBatch& B) {
   return n;
 }
 
-hipError_t launch_ir_prepare(DevState& d, hipStream_t st) {
-  DevState* ds[1] = {&d};
-  hipError_t e = launch_rows_batch(ds, 0, 1, [&](const BackBatch& B) {
+hipError_t launch_ir_prepare_batch(DevState* const* ds, int S, hipStream_t st) {
+  return launch_rows_batch(ds, 0, S, [&](const BackBatch& B) {
     hipLaunchKernelGGL(k_ir_copy_lower, dim3(lower_tiles(B)), dim3(256), 0, st, B);
   });
-  if (e != hipSuccess) return e;
-  return hipMemcpyAsync(d.cvec, d.A + (size_t)d.npad * d.ld, sizeof(float) * d.npad, hipMemcpyDeviceToDevice, st);
+}
+
+hipError_t launch_ir_prepare(DevState& d, hipStream_t st) {
+  DevState* ds[1] = {&d};
+  return launch_ir_prepare_batch(ds, 1, st);
 }
 
 hipError_t launch_ir_step_batch(DevState* const* ds, int step, int S, hipStream_t st) {

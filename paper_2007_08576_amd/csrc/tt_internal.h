@@ -284,6 +284,7 @@ hipError_t launch_cholesky_backsolve_batch(DevState* const* ds, int which, int S
 // doubles of the refinement's xd buffer: the solution and the residual's per-tile partial sums
 inline size_t ir_xd_count(int npad, int nb) { return (size_t)npad + (size_t)nb * nb * TT_NB; }
 hipError_t launch_ir_prepare(DevState& d, hipStream_t st);
+hipError_t launch_ir_prepare_batch(DevState* const* ds, int S, hipStream_t st);
 hipError_t launch_ir_accum_batch(DevState* const* ds, int S, int mode, hipStream_t st);
 hipError_t launch_ir_step_batch(DevState* const* ds, int step, int S, hipStream_t st);
 
