@@ -25,6 +25,12 @@ bool finite3(const float* p) { return isfinite(p[0]) && isfinite(p[1]) && isfini
 
 Intr intr_of(const tt_stream* s) { return Intr{s->K.width, s->K.height, s->K.fx, s->K.fy, s->K.cx, s->K.cy}; }
 
+// The stream's LM stages can run as multi-system launches: a coupled solve with no stage of its own
+// (per-node solve, z-buffer), the default ARAP workgroup and no stage timers.
+bool multi_ok(const tt_stream* s) {
+  return s->P.solver != TT_SOLVE_NODE && !s->d.zbuf && s->d.arap_threads == 256 && s->timing == 0;
+}
+
 template <typename T>
 int dalloc(tt_stream* s, std::vector<void*>& list, uint64_t& bytes, T** out, size_t count) {
   size_t nbytes = sizeof(T) * (count ? count : 1);
@@ -582,8 +588,7 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
       // the coupled streams without launches of their own (per-node solve, z-buffer) and with the
       // default ARAP workgroup run their LM set-up and iterations as multi-system launches
       for (int q = 0; q < S; q++) {
-        const DevState& d = ss[q]->d;
-        if (d.solver != TT_SOLVE_NODE && !d.zbuf && d.arap_threads == 256) mq.push_back(q);
+        if (multi_ok(ss[q])) mq.push_back(q);
         else sq.push_back(q);
       }
       if (!mq.empty()) {
@@ -1502,6 +1507,8 @@ int enqueue_front(tt_stream* s, DevState& dd, int K2, hipStream_t st, const void
   return ::enqueue_front(s, dd, K2, st, inputs_ready);
 }
 hipEvent_t front_done_event(tt_stream* s) { return s->ev_front_done[s->frame & 1]; }
+bool multi_ok(const tt_stream* s) { return ::multi_ok(s); }
+Intr intr(const tt_stream* s) { return intr_of(s); }
 int enqueue_lm_begin(tt_stream* s, hipStream_t st) {
   return launch_lm_begin(s->d, s->P.lm_lambda0, st) == hipSuccess ? TT_OK : TT_EDEVICE;
 }

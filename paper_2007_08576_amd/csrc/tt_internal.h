@@ -258,6 +258,12 @@ struct LMMulti {
 };
 // Synchronous (allocates and copies the table); hipErrorInvalidValue for a system it does not cover.
 hipError_t lm_multi_build(DevState* const* ds, const tt_params* const* P, const Intr* K, int S, LMMulti* out);
+// Bytes of a table of S systems.
+size_t lm_multi_bytes(int S);
+// Writes the table into host memory (lm_multi_bytes(S) bytes) and describes it as living at dev;
+// the caller copies host to dev before the launches read it.
+hipError_t lm_multi_fill(DevState* const* ds, const tt_params* const* P, const Intr* K, int S, void* host,
+                         void* dev, LMMulti* out);
 void lm_multi_free(LMMulti& m);
 // LM set-up of every system (launch_lm_begin)
 hipError_t launch_lm_multi_begin(const LMMulti& m, hipStream_t st);
@@ -297,6 +303,8 @@ DevState frame_view(tt_stream* s, const float* depth, const float* xyz, const ui
 int ensure_k2(tt_stream* s, int K2);
 int enqueue_front(tt_stream* s, DevState& dd, int K2, hipStream_t st, const void* inputs_ready);
 hipEvent_t front_done_event(tt_stream* s);  // the event enqueue_front recorded for the stream's current frame
+bool multi_ok(const tt_stream* s);          // LM stages may run as multi-system launches
+Intr intr(const tt_stream* s);
 int enqueue_lm_begin(tt_stream* s, hipStream_t st);
 int enqueue_assemble(tt_stream* s, DevState& dd, int it, hipStream_t st);
 int enqueue_solve(tt_stream* const* ss, DevState* const* dp, int S, hipStream_t st);

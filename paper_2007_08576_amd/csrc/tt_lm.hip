@@ -1187,15 +1187,19 @@ __global__ __launch_bounds__(1024) void k_damp_multi(const LMJob* __restrict__ J
 
 }  // namespace
 
-hipError_t lm_multi_build(DevState* const* ds, const tt_params* const* P, const Intr* K, int S, LMMulti* out) {
+size_t lm_multi_bytes(int S) { return sizeof(LMJob) * (size_t)(S > 0 ? S : 0); }
+
+hipError_t lm_multi_fill(DevState* const* ds, const tt_params* const* P, const Intr* K, int S, void* host,
+                         void* dev, LMMulti* out) {
   *out = LMMulti{};
-  if (S <= 0) return hipErrorInvalidValue;
-  std::vector<LMJob> J(S);
+  if (S <= 0 || !host || !dev) return hipErrorInvalidValue;
+  LMJob* J = static_cast<LMJob*>(host);
   int b[LMJob::kMultiGrids] = {};
   for (int q = 0; q < S; q++) {
     DevState& d = *ds[q];
     if (d.solver == TT_SOLVE_NODE || d.zbuf) return hipErrorInvalidValue;  // extra launches of their own
     LMJob& j = J[q];
+    j = LMJob{};
     j.aa = arap_args(d, *P[q]);
     j.ra = row_args(d, *P[q], K[q]);
     j.W = d.W; j.pos = d.pos; j.ndisp = d.ndisp; j.c0 = d.c0;
@@ -1213,18 +1217,26 @@ hipError_t lm_multi_build(DevState* const* ds, const tt_params* const* P, const 
       b[k] += cnt[k];
     }
   }
-  void* dev = nullptr;
-  hipError_t e = hipMalloc(&dev, sizeof(LMJob) * (size_t)S);
-  if (e != hipSuccess) return e;
-  e = hipMemcpy(dev, J.data(), sizeof(LMJob) * (size_t)S, hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(dev);
-    return e;
-  }
   out->jobs = dev;
   out->nj = S;
   for (int k = 0; k < LMJob::kMultiGrids; k++) out->blocks[k] = b[k];
   return hipSuccess;
+}
+
+hipError_t lm_multi_build(DevState* const* ds, const tt_params* const* P, const Intr* K, int S, LMMulti* out) {
+  *out = LMMulti{};
+  if (S <= 0) return hipErrorInvalidValue;
+  std::vector<LMJob> J(S);
+  void* dev = nullptr;
+  hipError_t e = hipMalloc(&dev, lm_multi_bytes(S));
+  if (e != hipSuccess) return e;
+  e = lm_multi_fill(ds, P, K, S, J.data(), dev, out);
+  if (e == hipSuccess) e = hipMemcpy(dev, J.data(), lm_multi_bytes(S), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dev);
+    *out = LMMulti{};
+  }
+  return e;
 }
 
 void lm_multi_free(LMMulti& m) {

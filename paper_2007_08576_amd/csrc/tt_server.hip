@@ -3,10 +3,12 @@
 // the one the single-stream path queues, step for step; only the interleaving of streams differs.
 //
 // One scheduler thread per server queues the work in rounds. A round takes every frame whose front
-// stage (normal map, matching, pre-selection) has completed and that still has LM iterations to go:
-// each assembles its system on its stream's HIP stream, the coupled systems are factored and solved
-// together on the server's HIP stream (joined and forked by events), each frame takes its update,
-// and a frame that has done its last iteration queues its outputs and an event. The thread keeps at
+// stage (normal map, matching, pre-selection) has completed and that still has LM iterations to go.
+// Frames of coupled streams with no stage of their own run the round on the server's HIP stream,
+// each stage one multi-system launch over all of them (argument tables written per round); the
+// others assemble on their stream's HIP stream and join by events. All coupled systems are factored
+// and solved together on the server's HIP stream, each frame takes its update, and a frame that
+// has done its last iteration queues its outputs (on its stream's HIP stream) and an event. The thread keeps at
 // most `ahead` rounds queued beyond the device, so that a frame whose front stage finishes joins
 // within that many rounds, and it notices completions by querying the frames' events between
 // rounds.
@@ -73,6 +75,11 @@ struct tt_server {
   std::vector<Frame*> fronting, active, tailing;
   std::deque<hipEvent_t> inflight_rounds;
   std::vector<hipEvent_t> round_ev_free;
+  // argument tables of the rounds' multi-system launches: a ring of pinned staging slots and their
+  // device copies, one slot per round (scheduler thread)
+  std::vector<void*> tab_host, tab_dev;
+  size_t tab_cap = 0;  // bytes per slot
+  size_t tab_next = 0;
   std::thread worker;
 };
 
@@ -129,8 +136,81 @@ int end_frame(Frame* fr) {
   return TT_OK;
 }
 
+void free_tables(tt_server* sv) {
+  for (void* h : sv->tab_host) (void)hipHostFree(h);
+  for (void* d : sv->tab_dev) (void)hipFree(d);
+  sv->tab_host.clear();
+  sv->tab_dev.clear();
+  sv->tab_cap = 0;
+}
+
+// A slot of at least `bytes` for this round's tables. The ring has ahead + 2 slots: the scheduler
+// keeps at most `ahead` rounds queued beyond the device and waits for older ones, so a slot's
+// staging copy has run before the slot comes round again (and the device copy is written on the
+// server's queue, behind every earlier round that reads it). Growing waits for the queue first.
+int table_slot(tt_server* sv, size_t bytes, void** host, void** dev) {
+  const size_t nslot = (size_t)sv->ahead + 2;
+  if (bytes > sv->tab_cap || sv->tab_host.size() != nslot) {
+    if (hipStreamSynchronize(sv->st) != hipSuccess) return TT_EDEVICE;
+    free_tables(sv);
+    const size_t cap = std::max<size_t>((bytes + 65535) / 65536 * 65536, 65536);
+    for (size_t i = 0; i < nslot; i++) {
+      void *h = nullptr, *d = nullptr;
+      if (hipHostMalloc(&h, cap, 0) != hipSuccess) return TT_ENOMEM;
+      sv->tab_host.push_back(h);
+      if (hipMalloc(&d, cap) != hipSuccess) return TT_ENOMEM;
+      sv->tab_dev.push_back(d);
+    }
+    sv->tab_cap = cap;
+  }
+  const size_t i = sv->tab_next++ % nslot;
+  *host = sv->tab_host[i];
+  *dev = sv->tab_dev[i];
+  return TT_OK;
+}
+
+// The tables of the frames entering the rounds (m0) and of those continuing (m1), written to a
+// slot and copied to the device on the server's queue.
+int write_tables(tt_server* sv, const std::vector<Frame*>& m0, const std::vector<Frame*>& m1, LMMulti* t0,
+                 LMMulti* t1) {
+  const size_t b0 = (lm_multi_bytes((int)m0.size()) + 255) / 256 * 256, b1 = lm_multi_bytes((int)m1.size());
+  void *h = nullptr, *d = nullptr;
+  int rc = table_slot(sv, b0 + b1, &h, &d);
+  if (rc) return rc;
+  const std::vector<Frame*>* grp[2] = {&m0, &m1};
+  LMMulti* tab[2] = {t0, t1};
+  const size_t off[2] = {0, b0};
+  for (int k = 0; k < 2; k++) {
+    if (grp[k]->empty()) continue;
+    std::vector<DevState*> ds;
+    std::vector<const tt_params*> ps;
+    std::vector<Intr> ks;
+    for (Frame* fr : *grp[k]) {
+      ds.push_back(&fr->dd);
+      ps.push_back(&fr->s->P);
+      ks.push_back(ttx::intr(fr->s));
+    }
+    if (lm_multi_fill(ds.data(), ps.data(), ks.data(), (int)ds.size(), static_cast<char*>(h) + off[k],
+                      static_cast<char*>(d) + off[k], tab[k]) != hipSuccess)
+      return TT_EDEVICE;
+  }
+  return hipMemcpyAsync(d, h, b0 + b1, hipMemcpyHostToDevice, sv->st) == hipSuccess ? TT_OK : TT_EDEVICE;
+}
+
+// Work queued on queue `from` so far runs before work queued on `to` from now on.
+int order_after(tt_stream* s, hipStream_t from, hipStream_t to) {
+  hipEvent_t ev = nullptr;
+  if (ttx::ev_sync_get(s, &ev) != hipSuccess) return TT_EDEVICE;
+  const bool good = hipEventRecord(ev, from) == hipSuccess && hipStreamWaitEvent(to, ev, 0) == hipSuccess;
+  ttx::ev_sync_put(s, ev);
+  return good ? TT_OK : TT_EDEVICE;
+}
+
 // One LM-iteration round over the frames in sv->active (scheduler thread, mu not held). Frames that
 // fail to queue, and frames done with their iterations, move to `out` (state F_TAIL, rc set).
+// Frames of streams whose stages can run as multi-system launches run the whole round on the
+// server's queue, one launch per stage for all of them; the others assemble and update on their
+// own stream's queue.
 int queue_round(tt_server* sv, std::vector<Frame*>& out) {
   std::vector<Frame*> act;
   act.swap(sv->active);
@@ -140,10 +220,12 @@ int queue_round(tt_server* sv, std::vector<Frame*>& out) {
     fr->state = F_TAIL;
     out.push_back(fr);
   };
-  // entering frames: LM set-up; frames with no iterations end here
+  // entering frames: LM set-up (multi-system frames: in the round's launch below); frames with no
+  // iterations end here
+  auto multi = [](const Frame* fr) { return ttx::multi_ok(fr->s) && fr->s->P.lm_iters > 0; };
   std::vector<Frame*> work;
   for (Frame* fr : act) {
-    if (fr->it == 0) {
+    if (fr->it == 0 && !multi(fr)) {
       const int rc = ttx::enqueue_lm_begin(fr->s, fr->s->st);
       if (rc) {
         fail(fr, rc);
@@ -161,10 +243,13 @@ int queue_round(tt_server* sv, std::vector<Frame*>& out) {
     }
     work.push_back(fr);
   }
-  // assemble (per-node solver streams also solve here, on their own queue)
-  std::vector<Frame*> coupled;
-  std::vector<Frame*> ok;
+  // the other frames assemble on their own queues (per-node solver streams also solve there)
+  std::vector<Frame*> m0, m1, coupled, ok;
   for (Frame* fr : work) {
+    if (multi(fr)) {
+      (fr->it == 0 ? m0 : m1).push_back(fr);
+      continue;
+    }
     int rc = ttx::enqueue_assemble(fr->s, fr->dd, fr->it, fr->s->st);
     if (!rc && fr->s->P.solver == TT_SOLVE_NODE) rc = ttx::enqueue_node_solve(fr->s, fr->dd, fr->s->st);
     if (rc) {
@@ -174,41 +259,59 @@ int queue_round(tt_server* sv, std::vector<Frame*>& out) {
     ok.push_back(fr);
     if (fr->s->P.solver != TT_SOLVE_NODE) coupled.push_back(fr);
   }
+  // multi-system frames: those entering the rounds after their front stage and their stream's
+  // earlier work; then set-up, assembly and damping on the server's queue, one launch per stage
+  LMMulti t0, t1;
+  int mrc = TT_OK;
+  for (Frame* fr : m0)
+    if (!mrc) mrc = order_after(fr->s, fr->s->st, sv->st);
+  if (!m0.empty() || !m1.empty()) {
+    if (!mrc) mrc = write_tables(sv, m0, m1, &t0, &t1);
+    if (!mrc && t0.jobs &&
+        (launch_lm_multi_begin(t0, sv->st) != hipSuccess || launch_lm_multi_assemble(t0, 0, sv->st) != hipSuccess))
+      mrc = TT_EDEVICE;
+    if (!mrc && t1.jobs && launch_lm_multi_assemble(t1, 1, sv->st) != hipSuccess) mrc = TT_EDEVICE;
+    std::vector<DevState*> ir;
+    for (Frame* fr : m0)
+      if (fr->s->d.prec != TT_FP32) ir.push_back(&fr->dd);
+    for (Frame* fr : m1)
+      if (fr->s->d.prec != TT_FP32) ir.push_back(&fr->dd);
+    if (!mrc && !ir.empty() && launch_ir_prepare_batch(ir.data(), (int)ir.size(), sv->st) != hipSuccess)
+      mrc = TT_EDEVICE;
+  }
+  // the coupled frames on their own queues before the server's queue; every coupled system
+  // factored and solved in one batched launch there
   int brc = TT_OK;
-  if (!coupled.empty()) {
-    // every coupled stream's queue -> the server's queue; batched solve; back again
-    for (Frame* fr : coupled) {
-      hipEvent_t ev = nullptr;
-      if (ttx::ev_sync_get(fr->s, &ev) != hipSuccess) {
-        brc = TT_EDEVICE;
-        break;
+  for (Frame* fr : coupled)
+    if (!brc) brc = order_after(fr->s, fr->s->st, sv->st);
+  std::vector<tt_stream*> ss;
+  std::vector<DevState*> dp;
+  for (Frame* fr : coupled) {
+    ss.push_back(fr->s);
+    dp.push_back(&fr->dd);
+  }
+  if (!mrc)
+    for (const std::vector<Frame*>* g : {&m0, &m1})
+      for (Frame* fr : *g) {
+        ss.push_back(fr->s);
+        dp.push_back(&fr->dd);
       }
-      const bool good = hipEventRecord(ev, fr->s->st) == hipSuccess && hipStreamWaitEvent(sv->st, ev, 0) == hipSuccess;
-      ttx::ev_sync_put(fr->s, ev);
-      if (!good) {
-        brc = TT_EDEVICE;
-        break;
-      }
-    }
-    std::vector<tt_stream*> ss;
-    std::vector<DevState*> dp;
-    for (Frame* fr : coupled) {
-      ss.push_back(fr->s);
-      dp.push_back(&fr->dd);
-    }
-    if (!brc) brc = ttx::enqueue_solve(ss.data(), dp.data(), (int)ss.size(), sv->st);
-    if (!brc) {
-      hipEvent_t ev = nullptr;
-      if (ttx::ev_sync_get(coupled[0]->s, &ev) != hipSuccess) {
-        brc = TT_EDEVICE;
-      } else {
-        if (hipEventRecord(ev, sv->st) != hipSuccess) brc = TT_EDEVICE;
-        for (Frame* fr : coupled)
-          if (!brc && hipStreamWaitEvent(fr->s->st, ev, 0) != hipSuccess) brc = TT_EDEVICE;
-        ttx::ev_sync_put(coupled[0]->s, ev);
-      }
+  if (!brc && !ss.empty()) brc = ttx::enqueue_solve(ss.data(), dp.data(), (int)ss.size(), sv->st);
+  if (!brc && !coupled.empty()) {  // back to the coupled frames' own queues
+    hipEvent_t ev = nullptr;
+    if (ttx::ev_sync_get(coupled[0]->s, &ev) != hipSuccess) {
+      brc = TT_EDEVICE;
+    } else {
+      if (hipEventRecord(ev, sv->st) != hipSuccess) brc = TT_EDEVICE;
+      for (Frame* fr : coupled)
+        if (!brc && hipStreamWaitEvent(fr->s->st, ev, 0) != hipSuccess) brc = TT_EDEVICE;
+      ttx::ev_sync_put(coupled[0]->s, ev);
     }
   }
+  if (!mrc) mrc = brc;
+  // multi-system frames: candidate, cost, accept / reject
+  if (!mrc && t0.jobs && launch_lm_multi_finish(t0, sv->st) != hipSuccess) mrc = TT_EDEVICE;
+  if (!mrc && t1.jobs && launch_lm_multi_finish(t1, sv->st) != hipSuccess) mrc = TT_EDEVICE;
   for (Frame* fr : ok) {
     if (brc && fr->s->P.solver != TT_SOLVE_NODE) {
       fail(fr, brc);
@@ -231,6 +334,26 @@ int queue_round(tt_server* sv, std::vector<Frame*>& out) {
       keep.push_back(fr);
     }
   }
+  for (const std::vector<Frame*>* g : {&m0, &m1})
+    for (Frame* fr : *g) {
+      if (mrc) {
+        fail(fr, mrc);
+        continue;
+      }
+      fr->it += 1;
+      if (fr->it < fr->s->P.lm_iters) {
+        keep.push_back(fr);
+        continue;
+      }
+      // outputs on the stream's own queue, after the server's queue
+      int rc = order_after(fr->s, sv->st, fr->s->st);
+      if (!rc) rc = end_frame(fr);
+      if (rc) fail(fr, rc);
+      else {
+        fr->state = F_TAIL;
+        out.push_back(fr);
+      }
+    }
   sv->rounds += 1;
   sv->frame_iters += (int64_t)work.size();
   sv->active.swap(keep);
@@ -583,6 +706,8 @@ int tt_server_destroy(tt_server* sv) {
     (void)hipEventDestroy(e);
   }
   for (hipEvent_t e : sv->round_ev_free) (void)hipEventDestroy(e);
+  (void)hipStreamSynchronize(sv->st);
+  free_tables(sv);
   for (auto& kv : sv->frames) give_back(sv, kv.second);
   sv->frames.clear();
   for (hipEvent_t e : sv->ev_free) (void)hipEventDestroy(e);
