@@ -336,9 +336,11 @@ int tt_destroy(tt_stream* s);
  * The per-frame solve of Sec. 2 for many independent streams at once. A server owns the streams it
  * opens (other calls on them return TT_EBUSY until tt_server_close) and runs one scheduler thread
  * that queues the streams' work in rounds of one LM iteration: in a round every frame in flight
- * assembles its normal system on its stream's HIP stream, all those systems are factored and solved
- * together (one batched launch per up to 32 systems, on the server's HIP stream), and every frame
- * takes its update. A submitted frame first has its normal map, matching and pre-selection queued on
+ * assembles its normal system, all those systems are factored and solved together (one batched
+ * launch per up to 32 systems, on the server's HIP stream), and every frame takes its update. The
+ * frames of coupled streams with no stage of their own (no per-node solve, z-buffer, 128-thread
+ * ARAP workgroups or stage timers) run every stage of the round on the server's HIP stream as one
+ * launch over all of them; the others assemble and update on their stream's HIP stream. A submitted frame first has its normal map, matching and pre-selection queued on
  * its stream's side queue; it joins the rounds at the first LM-iteration boundary after that stage
  * has finished, and leaves after its lm_iters-th iteration, so frames of different streams enter
  * and leave at iteration boundaries rather than in whole-frame batches. Frames of one stream run in

@@ -186,3 +186,59 @@ def test_owned_stream_refuses_single_stream_calls(env):
         sv.submit(s, d[0], bxyz, big, 600)
     sv.close(s)
     sv.destroy()
+
+
+def test_config4_served_equals_alone_with_rounds_ahead(env):
+    """The 16-stream serving mix (control points 123-772, uneven images and feature counts) through
+    the serving loop with three rounds queued ahead of the device, so that the per-round argument
+    tables of the multi-system launches cycle through their ring of slots many times, and with the
+    streams arriving one after another (frames entering and frames continuing share rounds); in FP32
+    and in the binary16 form with one refinement step: every frame equals the stream's result when
+    tracked alone, bit for bit."""
+    tt, torch = env
+    dev = torch.device("cuda:0")
+    scenes = synth.make_config4(seed=4, n_streams=16, n_frames=300)
+    ts = (1, 2, 3)
+    frames = [_dev_frames(torch, sc, ts, dev) for sc in scenes]
+    for prec, ir in ((tt.TT_FP32, 2), (tt.TT_FP16_IR, 1)):
+        def params(sc):
+            return tt.default_params(num_control_points=sc.num_control_points, seed=4, precision=prec, ir_iters=ir)
+
+        ref = []
+        for q, sc in enumerate(scenes):
+            s = tt.Stream(params(sc), _intr(tt, sc))
+            s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+            ov = torch.zeros((sc.pts.shape[0], 3), dtype=torch.float32, device=dev)
+            oq = torch.zeros((sc.num_control_points, 8), dtype=torch.float32, device=dev)
+            r = []
+            for d in frames[q]:
+                s.track_frame_device(d[0], d[1], d[2], d[1].shape[0], ov, oq)
+                s.sync()
+                r.append((ov.cpu().numpy().copy(), oq.cpu().numpy().copy()))
+            s.destroy()
+            ref.append(r)
+        sv = tt.Server(max_rounds_ahead=3)
+        streams = [sv.open(params(sc), _intr(tt, sc), sc.pts, sc.feat_xyz, sc.feat_desc,
+                           K2max=max(d[1].shape[0] for d in frames[q])) for q, sc in enumerate(scenes)]
+        outs = [[(torch.zeros((sc.pts.shape[0], 3), dtype=torch.float32, device=dev),
+                  torch.zeros((sc.num_control_points, 8), dtype=torch.float32, device=dev)) for _ in ts]
+                for sc in scenes]
+        tickets = []
+        for q in range(len(scenes)):
+            for k in range(len(ts)):
+                d = frames[q][k]
+                ov, oq = outs[q][k]
+                tickets.append(sv.submit(streams[q], d[0], d[1], d[2], d[1].shape[0], ov, oq))
+            time.sleep(0.001)
+        for t in tickets:
+            sv.wait(t, 60.0)
+        st = sv.stats()
+        assert st["frames_done"] == len(tickets) and st["frame_iterations"] > st["rounds"]
+        for q in range(len(scenes)):
+            for k in range(len(ts)):
+                ov, oq = outs[q][k]
+                assert np.array_equal(ov.cpu().numpy(), ref[q][k][0]), f"precision {prec}: stream {q} frame {k}"
+                assert np.array_equal(oq.cpu().numpy(), ref[q][k][1]), f"precision {prec}: stream {q} frame {k}"
+        for s in streams:
+            sv.close(s)
+        sv.destroy()
