@@ -301,15 +301,18 @@ def _poisson_served(sv, streams, frame_of, S, hz, dur):
 def precision_study(args, torch, tt, sc2, dframes2, vo_oracle):
     """Each solve form on config 2 (frames/s; vertices of frame 1 after 3 LM iterations from the
     identity against the FP64 oracle's when it ran) and on config 3 (1,500 control points, 9,000
-    unknowns: frames/s, factorisation time, vertices of frame 1 against the FP32 form's)."""
+    unknowns: frames/s, factorisation time, vertices of frame 1 against the FP32 form's). The 16-bit
+    forms take the library's default of two refinement steps; fp16_ir1 is the serving runs' mixed
+    form, binary16 with one."""
     from paper_2007_08576_amd import synth
     dev = torch.device("cuda:0")
-    forms = (("fp32", tt.TT_FP32), ("bf16_ir", tt.TT_BF16_IR), ("fp16_ir", tt.TT_FP16_IR))
+    forms = (("fp32", tt.TT_FP32, 2), ("bf16_ir", tt.TT_BF16_IR, 2), ("fp16_ir", tt.TT_FP16_IR, 2),
+             ("fp16_ir1", tt.TT_FP16_IR, 1))
     out = {"config2": {}, "config3": {}}
 
-    def run(sc, dfr, prec, steps, lm_iters=10):
+    def run(sc, dfr, prec, ir, steps, lm_iters=10):
         s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=2, precision=prec,
-                                        lm_iters=lm_iters),
+                                        lm_iters=lm_iters, ir_iters=ir),
                       tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx, sc.intr.cy))
         s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
         ov = torch.empty((sc.pts.shape[0], 3), dtype=torch.float32, device=dev)
@@ -333,11 +336,12 @@ def precision_study(args, torch, tt, sc2, dframes2, vo_oracle):
         s.destroy()
         return fps, first, (fac, sol) if steps else (None, None)
 
-    for name, prec in forms:
-        fps, _, (fac, sol) = run(sc2, dframes2, prec, args.precision_steps)
-        entry = {"frames_per_s": fps, "factor_us": fac, "damp_substitutions_refinement_us": sol}
+    for name, prec, ir in forms:
+        fps, _, (fac, sol) = run(sc2, dframes2, prec, ir, args.precision_steps)
+        entry = {"frames_per_s": fps, "factor_us": fac, "damp_substitutions_refinement_us": sol,
+                 "refinement_steps": ir if prec else 0}
         if vo_oracle is not None:
-            _, v3, _ = run(sc2, dframes2, prec, 0, lm_iters=args.cpu_lm_sample)
+            _, v3, _ = run(sc2, dframes2, prec, ir, 0, lm_iters=args.cpu_lm_sample)
             entry["rms_vs_fp64_oracle_mm"] = float(np.sqrt(((v3 - vo_oracle) ** 2).sum(1).mean()))
         out["config2"][name] = entry
         log(f"  config2 {name:8s} {fps:7.1f} frames/s, factor {fac:7.1f} us, solve+refine {sol:7.1f} us"
@@ -350,11 +354,12 @@ def precision_study(args, torch, tt, sc2, dframes2, vo_oracle):
         torch.cuda.synchronize()  # the uploads are complete before the library's stream reads them
         log(f"config 3 generated in {time.time() - t0:.1f} s")
         ref = None
-        for name, prec in forms:
-            fps, v1, (fac, sol) = run(sc3, dfr3, prec, 2)
+        for name, prec, ir in forms:
+            fps, v1, (fac, sol) = run(sc3, dfr3, prec, ir, 2)
             if ref is None:
                 ref = v1
             entry = {"frames_per_s": fps, "factor_us": fac, "damp_substitutions_refinement_us": sol,
+                     "refinement_steps": ir if prec else 0,
                      "rms_vs_fp32_form_mm": float(np.sqrt(((v1 - ref) ** 2).sum(1).mean()))}
             if name == "fp32":
                 entry["roofline"] = chol_roofline(6 * sc3.num_control_points, fac * 1e-3)
