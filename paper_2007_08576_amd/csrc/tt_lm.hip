@@ -1112,6 +1112,8 @@ struct LMJob {
   int start[kMultiGrids];
 };
 
+static_assert(LMJob::kMultiGrids == sizeof(LMMulti{}.blocks) / sizeof(int), "one block count per grid");
+
 // the system whose range of grid `kind` holds block b (ranges ascending; empty ranges skipped)
 __device__ __forceinline__ int job_of(const LMJob* __restrict__ J, int nj, int kind, int b) {
   int lo = 0, hi = nj - 1;
