@@ -214,11 +214,11 @@ typedef struct {
  * (tt_sync on a stream waits for its frame). When every stream sets graph = 1 (and no stage timer
  * is on), the LM set-up and iterations of the batch are captured as one HIP graph per ordered set of
  * streams and pattern of their front-buffer parities, kept until one of its streams is destroyed,
- * gets a new template or new launch shapes, and replayed; in that form every LM stage of the
- * coupled streams with the default ARAP workgroup and no z-buffer runs as one launch over all of
- * them (a small device table of their arguments lives with the graph), the other streams' stages
- * as their own launches on streams[0]'s HIP stream. Each stream's result is the same as when it is
- * tracked alone. Returns without waiting. TT_EINVAL: bad arguments or a stream listed twice;
+ * gets a new template or new launch shapes, and replayed. Every LM stage of the coupled streams
+ * with the default ARAP workgroup, no z-buffer and no stage timer runs as one launch over all of
+ * them on streams[0]'s HIP stream, over a small device table of their arguments (kept with the
+ * graph, or written per call into a ring of four slots held by streams[0]); the other streams'
+ * stages run as their own launches. Each stream's result is the same as when it is tracked alone. Returns without waiting. TT_EINVAL: bad arguments or a stream listed twice;
  * TT_EBUSY: a stream is in use by another call (no stream is then touched); TT_ESTATE: a stream
  * has no template. */
 int tt_track_batch_device(tt_stream* const* streams, int S, const tt_frame_device* frames);

@@ -79,6 +79,46 @@ static void destroy_batch_graph(BatchGraph& b) {
   lm_multi_free(b.multi);
 }
 
+constexpr size_t kBatchTableSlots = 4;
+
+static void free_batch_tables(tt_stream* s) {
+  for (hipEvent_t e : s->bt_ev) (void)hipEventSynchronize(e);
+  for (void* h : s->bt_host) (void)hipHostFree(h);
+  for (void* d : s->bt_dev) (void)hipFree(d);
+  for (hipEvent_t e : s->bt_ev) (void)hipEventDestroy(e);
+  s->bt_host.clear();
+  s->bt_dev.clear();
+  s->bt_ev.clear();
+  s->bt_cap = 0;
+}
+
+// The next slot of the leading stream's table ring, at least `bytes` large, once the copy that last
+// used it has run. Growing waits for the stream first (queued launches may read the old slots).
+static int batch_table_slot(tt_stream* s, size_t bytes, void** host, void** dev, hipEvent_t* ev) {
+  if (bytes > s->bt_cap || s->bt_host.size() != kBatchTableSlots) {
+    if (hipStreamSynchronize(s->st) != hipSuccess) return TT_EDEVICE;
+    free_batch_tables(s);
+    const size_t cap = std::max<size_t>((bytes + 65535) / 65536 * 65536, 65536);
+    for (size_t i = 0; i < kBatchTableSlots; i++) {
+      void *h = nullptr, *d = nullptr;
+      hipEvent_t e = nullptr;
+      if (hipHostMalloc(&h, cap, 0) != hipSuccess) return TT_ENOMEM;
+      s->bt_host.push_back(h);
+      if (hipMalloc(&d, cap) != hipSuccess) return TT_ENOMEM;
+      s->bt_dev.push_back(d);
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return TT_EDEVICE;
+      s->bt_ev.push_back(e);
+    }
+    s->bt_cap = cap;
+  }
+  const size_t i = s->bt_next++ % kBatchTableSlots;
+  if (hipEventSynchronize(s->bt_ev[i]) != hipSuccess) return TT_EDEVICE;
+  *host = s->bt_host[i];
+  *dev = s->bt_dev[i];
+  *ev = s->bt_ev[i];
+  return TT_OK;
+}
+
 static void drop_batch_graphs_of(tt_stream* s) {
   std::lock_guard<std::mutex> lk(g_bg_mu);
   for (size_t i = 0; i < g_bg.size();) {
@@ -544,8 +584,9 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
     }
     return r;
   };
-  // Graph form: every stage on batch_st, the streams in mq as multi-system launches (one launch
-  // per stage for all of them) and the others (sq) with their own launches.
+  // Multi-system form (graph-replayed or launched): every stage on batch_st, the streams in mq as
+  // multi-system launches (one launch per stage for all of them) and the others (sq) with their
+  // own launches.
   LMMulti multi;
   std::vector<int> mq, sq;
   auto lm_rounds_multi = [&]() -> int {
@@ -571,6 +612,18 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
     }
     return r;
   };
+  for (int q = 0; q < S; q++) {
+    if (multi_ok(ss[q])) mq.push_back(q);
+    else sq.push_back(q);
+  }
+  std::vector<DevState*> md;
+  std::vector<const tt_params*> mp;
+  std::vector<Intr> mk;
+  for (int q : mq) {
+    md.push_back(dp[q]);
+    mp.push_back(&ss[q]->P);
+    mk.push_back(intr_of(ss[q]));
+  }
   bool graph = true;  // replay the rounds as one graph when every stream asks for graph replay
   for (int q = 0; q < S; q++) graph = graph && ss[q]->P.graph == 1 && ss[q]->timing == 0;
   if (!rc && graph) {
@@ -586,22 +639,11 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
     rc = join();  // the fronts, before the captured rounds
     if (!rc && !exec) {
       // the coupled streams without launches of their own (per-node solve, z-buffer) and with the
-      // default ARAP workgroup run their LM set-up and iterations as multi-system launches
-      for (int q = 0; q < S; q++) {
-        if (multi_ok(ss[q])) mq.push_back(q);
-        else sq.push_back(q);
-      }
-      if (!mq.empty()) {
-        std::vector<DevState*> md;
-        std::vector<const tt_params*> mp;
-        std::vector<Intr> mk;
-        for (int q : mq) {
-          md.push_back(dp[q]);
-          mp.push_back(&ss[q]->P);
-          mk.push_back(intr_of(ss[q]));
-        }
-        if (lm_multi_build(md.data(), mp.data(), mk.data(), (int)mq.size(), &multi) != hipSuccess) return TT_EDEVICE;
-      }
+      // default ARAP workgroup run their LM set-up and iterations as multi-system launches, over a
+      // table that lives with the graph
+      if (!mq.empty() &&
+          lm_multi_build(md.data(), mp.data(), mk.data(), (int)mq.size(), &multi) != hipSuccess)
+        return TT_EDEVICE;
       hipGraph_t g = nullptr;
       if (hipStreamBeginCapture(batch_st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         lm_multi_free(multi);
@@ -630,6 +672,21 @@ int enqueue_batch(tt_stream* const* ss, int S, const tt_frame_device* fr, hipStr
       g_bg.push_back(BatchGraph{key, par, exec, multi});
     }
     if (!rc && hipGraphLaunch(exec, batch_st) != hipSuccess) rc = TT_EDEVICE;
+    if (!rc) rc = fork();  // the per-stream tails after the rounds
+  } else if (!rc && !mq.empty()) {
+    // the same multi-system rounds, over a table written for this call: a slot of the leading
+    // stream's ring, copied on batch_st after the fronts
+    rc = join();
+    void *h = nullptr, *d = nullptr;
+    hipEvent_t ev = nullptr;
+    if (!rc) rc = batch_table_slot(ss[0], lm_multi_bytes((int)mq.size()), &h, &d, &ev);
+    if (!rc && lm_multi_fill(md.data(), mp.data(), mk.data(), (int)mq.size(), h, d, &multi) != hipSuccess)
+      rc = TT_EDEVICE;
+    if (!rc && (hipMemcpyAsync(d, h, lm_multi_bytes((int)mq.size()), hipMemcpyHostToDevice, batch_st) != hipSuccess ||
+                hipEventRecord(ev, batch_st) != hipSuccess))
+      rc = TT_EDEVICE;
+    if (!rc) rc = lm_rounds_multi();
+    multi = LMMulti{};  // the slot stays with the ring
     if (!rc) rc = fork();  // the per-stream tails after the rounds
   } else if (!rc) {
     rc = lm_rounds();
@@ -990,6 +1047,8 @@ int tt_destroy(tt_stream* s) {
     s->ev_pool.clear();
     for (hipEvent_t e : s->ev_sync_pool) (void)hipEventDestroy(e);
     s->ev_sync_pool.clear();
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    free_batch_tables(s);
     if (s->st_front) (void)hipStreamSynchronize(s->st_front);
     free_template(s);
     free_list(s->allocs_k2, s->bytes_k2);

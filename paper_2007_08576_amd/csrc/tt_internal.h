@@ -186,6 +186,13 @@ struct tt_stream {
   unsigned timing = 0;  // bit i set: stage i is timed
   std::vector<hipEvent_t> ev_pool;       // timing events
   std::vector<hipEvent_t> ev_sync_pool;  // ordering events between HIP streams (batched path)
+  // argument tables of the multi-system launches of the batches this stream leads (streams[0])
+  // that are not graph-replayed: a ring of pinned staging slots, their device copies (written on
+  // this stream's HIP stream, behind every earlier batch that reads them) and an event after each
+  // slot's copy, waited on before the slot is written again
+  std::vector<void*> bt_host, bt_dev;
+  std::vector<hipEvent_t> bt_ev;
+  size_t bt_cap = 0, bt_next = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   double stage_ms[TT_NSTAGES] = {};
   int64_t stage_n[TT_NSTAGES] = {};
