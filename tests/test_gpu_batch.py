@@ -275,3 +275,45 @@ def test_batch_graph_replay_equals_launches(env):
             a, b = outs[0][k][q], outs[1][k][q]
             assert np.isfinite(a[0]).all()
             assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (k, q)
+
+
+def test_launched_batches_back_to_back(env):
+    """Launched batches (no graph replay) write their multi-system argument tables into a ring of
+    four slots held by the leading stream. Six batches queued back to back, with no wait between
+    them, wrap the ring, so a slot is written again only after its earlier copy has run: every
+    batch equals the same batch run with a wait after each, bit for bit."""
+    tt, torch = env
+    dev = torch.device("cuda:0")
+    scenes = _scenes()
+    forms = [(0, 0), (tt.TT_BF16_IR, 0), (tt.TT_FP16_IR, 0)]
+    frames = [[_dev_frame(torch, sc.frame(t), dev) for t in (1, 2, 3)] for sc in scenes]
+    seq = [0, 1, 2, 1, 0, 2]
+    outs = {}
+    for wait in (True, False):
+        streams = []
+        for sc, (prec, solver) in zip(scenes, forms):
+            s = tt.Stream(tt.default_params(num_control_points=sc.num_control_points, seed=5, precision=prec,
+                                            solver=solver),
+                          tt.intrinsics(sc.intr.width, sc.intr.height, sc.intr.fx, sc.intr.fy, sc.intr.cx,
+                                        sc.intr.cy))
+            s.set_template(sc.pts, sc.feat_xyz, sc.feat_desc)
+            streams.append(s)
+        ov = [[torch.zeros((sc.pts.shape[0], 3), dtype=torch.float32, device=dev) for sc in scenes] for _ in seq]
+        oq = [[torch.zeros((sc.num_control_points, 8), dtype=torch.float32, device=dev) for sc in scenes] for _ in seq]
+        for k, t in enumerate(seq):
+            tt.track_batch_device(streams, [(frames[q][t][0], frames[q][t][1], frames[q][t][2],
+                                             frames[q][t][1].shape[0], ov[k][q], oq[k][q]) for q in range(len(scenes))])
+            if wait:
+                for s in streams:
+                    s.sync()
+        for s in streams:
+            s.sync()
+        outs[wait] = [[(ov[k][q].cpu().numpy().copy(), oq[k][q].cpu().numpy().copy()) for q in range(len(scenes))]
+                      for k in range(len(seq))]
+        for s in streams:
+            s.destroy()
+    for k in range(len(seq)):
+        for q in range(len(scenes)):
+            a, b = outs[True][k][q], outs[False][k][q]
+            assert np.isfinite(a[0]).all()
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (k, q)
