@@ -488,7 +488,8 @@ def assembly_batched_summary(trace_csv, run_json, out_path, cmd):
     import csv
     import re
     run = json.loads(open(run_json).read().strip().splitlines()[-1])["assembly_batched"]
-    asm = ("k_rows_arap", "k_arap_assemble", "k_data_rows", "k_data_assemble", "k_rows_arap_multi", "k_data_multi")
+    asm = ("k_rows_arap", "k_arap_assemble", "k_data_rows", "k_data_assemble", "k_rows_arap_multi", "k_rows_multi",
+           "k_arap_multi", "k_data_multi")
     rows = []
     for r in csv.DictReader(open(trace_csv)):
         k = re.sub(r"\(anonymous namespace\)::", "", r["Kernel_Name"]).replace("void ", "").split("(")[0].split("<")[0]
